@@ -1,0 +1,337 @@
+"""Plain CPU oracle for Randomly Pivoted LU (RPLU), FP64 / complex128.
+
+TEST INFRASTRUCTURE. This module exists to check the HIP implementation.
+Only tests, the smoke check and the bench's CPU-baseline leg may import it;
+the product path never does, and it shares no code with the HIP path.
+
+What it computes (Gilles & Wilber, "Low-Rank Approximation by Randomly
+Pivoted LU"):
+
+* Dense RPLU, Alg. 1. At step t the Schur complement S = A^(t) (S^(0) = A)
+  gives a pivot (i, j) drawn with probability |S_ij|^2 / ||S||_F^2 (Sec. 1,
+  the RPLU pivot distribution), realised in two stages: a row with
+  probability ||S_i,:||^2 / ||S||_F^2, then a column of that row with
+  probability |S_ij|^2 / ||S_i,:||^2 (Sec. 4.1, two-stage sampling). Then
+  L(:,t) = S_:,j / S_ij, U(t,:) = S_i,:, and S <- S - L(:,t) U(t,:)
+  (eq. residual_update).
+* Cauchy-like RPLU, Alg. 3 with exact row masses. S is never formed: its
+  entries are s_ij = (G_i,: B_:,j) / (x_i - y_j) (eq. cauchy-like), the row
+  masses are sum_j |s_ij|^2 (Sec. 5.1, row-norm formula), and each step
+  updates the generators with eqs. generator_update_g / generator_update_b.
+  With exact masses the rejection step of Alg. 3 accepts with probability 1,
+  so no acceptance draw is consumed.
+
+Readings where the paper is silent (each also listed in the design notes):
+
+* Inverse CDF: for weights w, P = inclusive prefix sums (np.cumsum,
+  sequential), T := P[-1], and the drawn index is the first idx with
+  P[idx] > u*T. The strict inequality never selects a zero-weight bin.
+* The column draw uses the pivot row's own total (last prefix of |S_i,:|^2),
+  not the row mass from the row stage.
+* Pivot row i and column j of the updated S are set to exactly 0 (they are 0
+  in exact arithmetic, eq. residual_update) and L(i,t) := 1.
+* U is not conjugated for complex inputs; a mass is |z|^2 = re^2 + im^2.
+* Stop test before each draw, in this order: T == 0 -> EXHAUSTED;
+  tol > 0 and T <= tol^2 * T0 -> TOL; t == kmax -> RANK (or TOL_UNREACHED
+  when tol > 0). kmax = min(n, m) when k == 0, else min(k, n, m).
+* Random numbers come from oracle.philox.step_uniforms(seed, stream, t).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+from .philox import step_uniforms
+
+STOP_RANK = 1
+STOP_TOL = 2
+STOP_EXHAUSTED = 3
+STOP_TOL_UNREACHED = 4
+
+
+class NonFiniteInput(ValueError):
+    pass
+
+
+class ZeroPivot(ValueError):
+    pass
+
+
+# ------------------------------------------------------------------ sampling
+
+def squared_magnitude(z: np.ndarray) -> np.ndarray:
+    """|z|^2 elementwise, in FP64."""
+    if np.iscomplexobj(z):
+        return z.real * z.real + z.imag * z.imag
+    z = np.asarray(z, dtype=np.float64)
+    return z * z
+
+
+def first_exceeding(prefix: np.ndarray, target: float) -> int:
+    """First index idx with prefix[idx] > target (prefix non-decreasing)."""
+    idx = int(np.searchsorted(prefix, target, side="right"))
+    if idx >= prefix.shape[0]:
+        raise ValueError("target is not below the last prefix value")
+    return idx
+
+
+@dataclass
+class Draw:
+    """One inverse-CDF draw and the CDF bin of the index actually used."""
+    drawn: int          # index the draw selects
+    used: int           # index used (== drawn unless forced)
+    total: float        # T = last inclusive prefix
+    target: float       # u * T
+    lo: float           # lower edge of the used index's bin (0 for idx 0)
+    hi: float           # upper edge of the used index's bin
+
+
+def inverse_cdf(weights: np.ndarray, u: float, forced: Optional[int] = None) -> Draw:
+    P = np.cumsum(np.asarray(weights, dtype=np.float64))
+    T = float(P[-1])
+    target = u * T
+    drawn = first_exceeding(P, target)
+    used = drawn if forced is None else int(forced)
+    lo = float(P[used - 1]) if used > 0 else 0.0
+    return Draw(drawn, used, T, target, lo, float(P[used]))
+
+
+# ------------------------------------------------------------------- results
+
+@dataclass
+class StepTrace:
+    t: int
+    row: Draw
+    col: Draw
+    a: complex
+
+
+@dataclass
+class RPLUResult:
+    L: np.ndarray                 # n x rank
+    U: np.ndarray                 # rank x m
+    piv: np.ndarray               # rank x 2 (i_t, j_t)
+    rank: int
+    stop: int
+    a_fro2: float                 # ||A||_F^2 (T at step 0)
+    res_fro2: float               # T at the stop test
+    S: Optional[np.ndarray] = None            # final Schur complement (dense)
+    G: Optional[np.ndarray] = None            # final generators (Cauchy)
+    B: Optional[np.ndarray] = None
+    trace: list = field(default_factory=list)
+    masses: list = field(default_factory=list)   # rowmass per step if asked
+
+
+def _stop_reason(t: int, T: float, T0: float, kmax: int, tol: float) -> int:
+    if T == 0.0:
+        return STOP_EXHAUSTED
+    if tol > 0.0 and T <= (tol * tol) * T0:
+        return STOP_TOL
+    if t == kmax:
+        return STOP_TOL_UNREACHED if tol > 0.0 else STOP_RANK
+    return 0
+
+
+def _forced_at(forced, t: int):
+    """Forced (i, j) for step t, or (None, None) to use the draw. A forced
+    sequence may hold None entries for steps that draw freely."""
+    if forced is None or t >= len(forced) or forced[t] is None:
+        return None, None
+    return int(forced[t][0]), int(forced[t][1])
+
+
+def _kmax(n: int, m: int, k: int) -> int:
+    return min(n, m) if k <= 0 else min(k, n, m)
+
+
+# --------------------------------------------------------------- dense form
+
+def schur_update(S: np.ndarray, i: int, j: int):
+    """Apply pivot (i, j) to S in place (eq. residual_update; Alg. 1 body).
+
+    Returns (l, u, a): l = S_:,j / a with l[i] = 1, u = S_i,: and a = S_ij.
+    Row i and column j of the result are set to exactly zero.
+    """
+    a = S[i, j]
+    if a == 0:
+        raise ZeroPivot(f"pivot ({i},{j}) is zero")
+    u = S[i, :].copy()
+    l = S[:, j] / a
+    l[i] = 1.0
+    S -= np.outer(l, u)
+    S[i, :] = 0.0
+    S[:, j] = 0.0
+    return l, u, a
+
+
+def rplu_dense(A: np.ndarray, k: int = 0, tol: float = 0.0, seed: int = 0,
+               stream: int = 0, forced: Optional[Sequence] = None,
+               keep_masses: bool = False) -> RPLUResult:
+    """Alg. 1 with two-stage exact sampling (Sec. 4.1).
+
+    forced: optional sequence of (i, j) pivots to use instead of the draws
+    (the draws are still made and recorded, so a caller can check where a
+    draw landed relative to the forced pivot's CDF bin).
+    """
+    S = np.array(A, dtype=np.complex128 if np.iscomplexobj(A) else np.float64,
+                 copy=True)
+    n, m = S.shape
+    kmax = _kmax(n, m, k)
+    L = np.zeros((n, kmax), dtype=S.dtype)
+    U = np.zeros((kmax, m), dtype=S.dtype)
+    piv = np.full((kmax, 2), -1, dtype=np.int64)
+    trace, masses = [], []
+    T0 = None
+    t = 0
+    while True:
+        rowmass = np.sum(squared_magnitude(S), axis=1)
+        T = float(np.cumsum(rowmass)[-1]) if n else 0.0
+        if not np.isfinite(T):
+            raise NonFiniteInput("non-finite entry in the input")
+        if t == 0:
+            T0 = T
+        stop = _stop_reason(t, T, T0, kmax, tol)
+        if stop:
+            break
+        if keep_masses:
+            masses.append(rowmass)
+        u1, u2 = step_uniforms(seed, stream, t)
+        fi, fj = _forced_at(forced, t)
+        rd = inverse_cdf(rowmass, u1, fi)
+        i = rd.used
+        cd = inverse_cdf(squared_magnitude(S[i, :]), u2, fj)
+        j = cd.used
+        l, u, a = schur_update(S, i, j)
+        L[:, t] = l
+        U[t, :] = u
+        piv[t] = (i, j)
+        trace.append(StepTrace(t, rd, cd, complex(a)))
+        t += 1
+    return RPLUResult(L[:, :t].copy(), U[:t].copy(), piv[:t].copy(), t, stop,
+                      T0, T, S=S, trace=trace, masses=masses)
+
+
+def schur_closed_form(A: np.ndarray, I: Sequence[int], J: Sequence[int]) -> np.ndarray:
+    """Schur complement after pivots on rows I, columns J, by its definition
+    A - A[:,J] A[I,J]^{-1} A[I,:] (depends on the sets only; Sec. 4.1, the
+    interpolative CUR form C U R with U = A[I,J]^{-1})."""
+    I = list(I)
+    J = list(J)
+    if not I:
+        return np.array(A, copy=True)
+    W = A[np.ix_(I, J)]
+    return A - A[:, J] @ np.linalg.solve(W, A[I, :])
+
+
+# -------------------------------------------------------- Cauchy-like form
+
+def cauchy_entries(x, y, G, B) -> np.ndarray:
+    """Dense n x m matrix with entries (G_i,: B_:,j) / (x_i - y_j)
+    (eq. cauchy-like)."""
+    return (G @ B) / (x[:, None] - y[None, :])
+
+
+def cauchy_row(x, y, G, B, i: int) -> np.ndarray:
+    """Row i: (G_i,: B) / (x_i - y) (Alg. 3, row of A^(k))."""
+    return (G[i, :] @ B) / (x[i] - y)
+
+
+def cauchy_col(x, y, G, B, j: int) -> np.ndarray:
+    """Column j: (G B_:,j) / (x - y_j) (Alg. 3, column of A^(k))."""
+    return (G @ B[:, j]) / (x - y[j])
+
+
+def cauchy_row_masses(x, y, G, B, rows_per_block: int = 512) -> np.ndarray:
+    """sum_j |s_ij|^2 for every row i (Sec. 5.1, exact row norms), one block
+    of rows at a time so that no n x m array is held."""
+    n = x.shape[0]
+    out = np.empty(n, dtype=np.float64)
+    for i0 in range(0, n, rows_per_block):
+        i1 = min(n, i0 + rows_per_block)
+        s = (G[i0:i1] @ B) / (x[i0:i1, None] - y[None, :])
+        out[i0:i1] = np.sum(squared_magnitude(s), axis=1)
+    return out
+
+
+def cauchy_generator_update(x, y, G, B, i: int, j: int):
+    """One pivot step on the generators, in place (eqs. generator_update_g,
+    generator_update_b): regenerate r = row i and c = column j, then
+    G <- G - (1/a) c G_i,:  and  B <- B - (1/a) B_:,j r, and zero G_i,: and
+    B_:,j exactly. Returns (c, r, a)."""
+    r = cauchy_row(x, y, G, B, i)
+    a = r[j]
+    if a == 0:
+        raise ZeroPivot(f"pivot ({i},{j}) is zero")
+    c = cauchy_col(x, y, G, B, j)
+    gi = G[i, :].copy()
+    bj = B[:, j].copy()
+    G -= np.outer(c, gi) / a
+    B -= np.outer(bj, r) / a
+    G[i, :] = 0.0
+    B[:, j] = 0.0
+    return c, r, a
+
+
+def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
+                stream: int = 0, forced: Optional[Sequence] = None,
+                keep_masses: bool = False, mass_steps: Optional[set] = None) -> RPLUResult:
+    """Alg. 3 with exact row masses (no rejection), generators in complex128.
+
+    mass_steps: if given, row masses (and hence the draw check) are computed
+    only at these steps; elsewhere the run must be forced. This keeps
+    full-size forced replays cheap (the generator update is O((n+m)p)).
+    """
+    x = np.asarray(x, dtype=np.complex128)
+    y = np.asarray(y, dtype=np.complex128)
+    G = np.array(G, dtype=np.complex128, copy=True)
+    B = np.array(B, dtype=np.complex128, copy=True)
+    n, m = x.shape[0], y.shape[0]
+    assert G.shape[0] == n and B.shape[1] == m and G.shape[1] == B.shape[0]
+    kmax = _kmax(n, m, k)
+    L = np.zeros((n, kmax), dtype=np.complex128)
+    U = np.zeros((kmax, m), dtype=np.complex128)
+    piv = np.full((kmax, 2), -1, dtype=np.int64)
+    trace, masses = [], []
+    T0 = None
+    T = float("nan")
+    t = 0
+    while True:
+        need_mass = mass_steps is None or t in mass_steps or t == 0
+        if need_mass:
+            rowmass = cauchy_row_masses(x, y, G, B)
+            T = float(np.cumsum(rowmass)[-1])
+            if not np.isfinite(T):
+                raise NonFiniteInput("non-finite generator or node data")
+            if t == 0:
+                T0 = T
+            stop = _stop_reason(t, T, T0, kmax, tol)
+        else:
+            stop = STOP_RANK if t == kmax else 0
+        if stop:
+            break
+        u1, u2 = step_uniforms(seed, stream, t)
+        fi, fj = _forced_at(forced, t)
+        if not need_mass and fi is None:
+            raise ValueError("a step without row masses needs a forced pivot")
+        if need_mass:
+            if keep_masses:
+                masses.append(rowmass)
+            rd = inverse_cdf(rowmass, u1, fi)
+        else:
+            rd = Draw(-1, fi, float("nan"), float("nan"), float("nan"), float("nan"))
+        i = rd.used
+        r = cauchy_row(x, y, G, B, i)
+        cd = inverse_cdf(squared_magnitude(r), u2, fj)
+        j = cd.used
+        c, r, a = cauchy_generator_update(x, y, G, B, i, j)
+        l = c / a
+        l[i] = 1.0
+        L[:, t] = l
+        U[t, :] = r
+        piv[t] = (i, j)
+        trace.append(StepTrace(t, rd, cd, complex(a)))
+        t += 1
+    return RPLUResult(L[:, :t].copy(), U[:t].copy(), piv[:t].copy(), t, stop,
+                      T0, T, G=G, B=B, trace=trace, masses=masses)

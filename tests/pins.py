@@ -1,0 +1,410 @@
+"""Pins of the CPU oracle: checks against facts the paper and the
+mathematics fix, not against the oracle's own formulas.
+
+Each pin is a function that raises AssertionError on failure, so that the
+mutation tests can plant a mistake in the oracle and confirm that some pin
+catches it. Pins reach the oracle through the module object `O` so that a
+monkeypatched oracle function is the one exercised.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+from scipy import stats
+
+import workloads as W
+from oracle import philox as PH
+from oracle import rplu as O
+
+
+# ----------------------------------------------------------------- helpers
+
+def _numpy_philox_block(seed: int, stream: int, t: int):
+    """numpy's Philox4x64-10 output for counter (t, stream, 0, 0): numpy
+    pre-increments its 256-bit counter, so start it one below."""
+    c = (t | (stream << 64)) - 1
+    c %= 1 << 256
+    words = [(c >> (64 * q)) & PH.MASK64 for q in range(4)]
+    bg = np.random.Philox(key=np.array([seed, 0], dtype=np.uint64),
+                          counter=np.array(words, dtype=np.uint64))
+    return [int(v) for v in bg.random_raw(4)]
+
+
+def _p_of(S):
+    """The RPLU pivot distribution |S_ij|^2 / ||S||_F^2 (Sec. 1), computed
+    with numpy's abs, independently of the oracle's mass routine."""
+    w = np.abs(S) ** 2
+    return w / w.sum()
+
+
+def _enumerate(S, depth, prob=1.0, out=None, k=0):
+    """Accumulate E||S^(k)||_F^2 (k = 0..depth) over every pivot sequence,
+    weighting each by the product of the step probabilities."""
+    if out is None:
+        out = np.zeros(depth + 1)
+    out[k] += prob * float(np.sum(np.abs(S) ** 2))
+    if k == depth:
+        return out
+    P = _p_of(S) if np.any(S != 0) else None
+    if P is None:
+        for kk in range(k + 1, depth + 1):
+            out[kk] += 0.0
+        return out
+    for (i, j), pij in np.ndenumerate(P):
+        if pij == 0:
+            continue
+        S2 = S.copy()
+        O.schur_update(S2, i, j)
+        _enumerate(S2, depth, prob * pij, out, k + 1)
+    return out
+
+
+def _one_step_moments(A):
+    """E[S^(1)] and E[S^(1)* S^(1)] by enumeration over the first pivot."""
+    P = _p_of(A)
+    E1 = np.zeros_like(A)
+    G1 = np.zeros((A.shape[1], A.shape[1]), dtype=A.dtype)
+    for (i, j), pij in np.ndenumerate(P):
+        if pij == 0:
+            continue
+        S = A.copy()
+        O.schur_update(S, i, j)
+        E1 = E1 + pij * S
+        G1 = G1 + pij * (S.conj().T @ S)
+    return E1, G1
+
+
+def _chi2_pvalue(counts, probs):
+    counts = np.asarray(counts, dtype=np.float64).ravel()
+    probs = np.asarray(probs, dtype=np.float64).ravel()
+    keep = probs > 0
+    assert np.all(counts[~keep] == 0), "a zero-probability pivot was drawn"
+    N = counts.sum()
+    c = counts[keep]
+    exp = N * probs[keep]
+    small = exp < 5          # pool sparse cells into one, as usual for chi-square
+    if small.any():
+        c = np.append(c[~small], c[small].sum())
+        exp = np.append(exp[~small], exp[small].sum())
+    stat = float(np.sum((c - exp) ** 2 / exp))
+    return float(stats.chi2.sf(stat, len(c) - 1))
+
+
+def _mixed_6x6(seed=11):
+    rng = np.random.default_rng(seed)
+    mag = rng.uniform(0.5, 2.0, (6, 6))
+    sgn = rng.choice([-1.0, 1.0], (6, 6))
+    return mag * sgn
+
+
+# --------------------------------------------------------------------- pins
+
+def pin_philox_numpy():
+    """Philox4x64-10 equals numpy.random.Philox (a library implementation of
+    the same published generator) word for word."""
+    cases = [(0, 0, 0), (0, 0, 1), (0, 3, 0), (7, 0, 5), (2**63 + 5, 2**40 + 1, 123456),
+             (12345, 4095, 511), (1, 2**64 - 1, 2**64 - 1)]
+    for seed, stream, t in cases:
+        mine = list(PH.philox4x64_10((t, stream, 0, 0), (seed, 0)))
+        ref = _numpy_philox_block(seed, stream, t)
+        assert mine == ref, (seed, stream, t, mine, ref)
+        u1, u2 = PH.step_uniforms(seed, stream, t)
+        assert u1 == (ref[0] >> 11) / 2.0**53 and u2 == (ref[1] >> 11) / 2.0**53
+
+
+def pin_inverse_cdf_bruteforce():
+    """First prefix strictly above u*T, brute force on tiny vectors with
+    zero-weight runs, targets exactly on edges, u = 0 and u = 1 - 2^-53."""
+    rng = np.random.default_rng(3)
+    # power-of-two weights make every prefix exact, so edges can be hit exactly
+    for trial in range(300):
+        n = int(rng.integers(1, 9))
+        w = np.where(rng.random(n) < 0.35, 0.0, 2.0 ** rng.integers(-3, 4, n))
+        if w.sum() == 0:
+            w[int(rng.integers(0, n))] = 1.0
+        P = np.cumsum(w)
+        T = P[-1]
+        us = [0.0, 1.0 - 2.0**-53] + [float(v) / T for v in P[:-1] if v < T] + list(rng.random(4))
+        for u in us:
+            d = O.inverse_cdf(w, u)
+            target = u * T
+            brute = next(idx for idx in range(n) if P[idx] > target)
+            assert d.drawn == brute, (w, u, d.drawn, brute)
+            assert w[d.drawn] > 0, "zero-weight bin selected"
+            assert d.total == T and d.target == target
+            assert d.lo <= d.target < d.hi
+
+
+def pin_chi2_first_pivot(N=40000):
+    """First pivots over N independent streams follow |a_ij|^2/||A||_F^2
+    (Sec. 1, the RPLU distribution): chi-square on 36 cells, p > 1e-3."""
+    A = _mixed_6x6()
+    counts = np.zeros((6, 6))
+    for s in range(N):
+        r = O.rplu_dense(A, k=1, seed=9, stream=s)
+        counts[tuple(r.piv[0])] += 1
+    p = _chi2_pvalue(counts, _p_of(A))
+    assert p > 1e-3, p
+
+
+def pin_chi2_second_pivot(N=40000):
+    """With the first pivot forced to (i1, j1), the second pivot follows
+    |S_ij|^2/||S||_F^2 of the closed-form one-step Schur complement."""
+    A = _mixed_6x6(12)
+    i1, j1 = 2, 4
+    S1 = A - np.outer(A[:, j1], A[i1, :]) / A[i1, j1]
+    S1[i1, :] = 0
+    S1[:, j1] = 0
+    counts = np.zeros((6, 6))
+    for s in range(N):
+        r = O.rplu_dense(A, k=2, seed=4, stream=s, forced=[(i1, j1), None])
+        counts[tuple(r.piv[1])] += 1
+    p = _chi2_pvalue(counts, _p_of(S1))
+    assert p > 1e-3, p
+
+
+def pin_one_step_expectation():
+    """E[A^(1) | A] = A - A A^* A / ||A||_F^2 (Sec. 3.1), and when every
+    a_ij != 0 the Gram identity E[A^(1)* A^(1)] = 2 A^*A - 2 (A^*A)^2/||A||_F^2
+    (eq. G1_bound, equality case), real and complex."""
+    rng = np.random.default_rng(5)
+    for cplx in (False, True):
+        for shape in ((4, 4), (3, 5), (5, 3)):
+            A = W.random_dense(*shape, seed=int(rng.integers(1 << 30)), complex_=cplx)
+            f2 = float(np.sum(np.abs(A) ** 2))
+            E1, G1 = _one_step_moments(A)
+            E1_cf = A - A @ A.conj().T @ A / f2
+            AhA = A.conj().T @ A
+            G1_cf = 2 * AhA - 2 * AhA @ AhA / f2
+            assert np.allclose(E1, E1_cf, rtol=0, atol=1e-12 * np.abs(A).max()), cplx
+            assert np.allclose(G1, G1_cf, rtol=0, atol=1e-12 * np.abs(AhA).max()), cplx
+
+
+def pin_unitary_dft():
+    """Dense unitary with no zero entry (normalised DFT): E||A^(1)||_F^2 =
+    2(n - 1) (Sec. 3.1, the unitary example)."""
+    for n in (4, 5, 6, 8):
+        F = np.exp(-2j * np.pi * np.outer(np.arange(n), np.arange(n)) / n) / math.sqrt(n)
+        E = _enumerate(F, 1)
+        assert abs(E[1] - 2 * (n - 1)) <= 1e-12 * n, (n, E[1])
+
+
+def pin_doubling_enumeration():
+    """Exact expected error over all 576 pivot sequences of a 4x4 matrix:
+    E||A - A_hat^(k)||_F^2 <= 4^k * sum_{j>k} sigma_j^2 (thm. doubling) for
+    k = 1, 2, 3, and the error is exactly 0 at k = 4. The k = 1 value equals
+    the trace of the Gram identity, 2||A||^2 - 2||A^*A||_F^2/||A||^2."""
+    for seed, cplx in ((21, False), (22, True), (23, False)):
+        A = W.random_dense(4, 4, seed=seed, complex_=cplx)
+        sig = np.linalg.svd(A, compute_uv=False)
+        E = _enumerate(A, 4)
+        f2 = float(np.sum(np.abs(A) ** 2))
+        AhA = A.conj().T @ A
+        assert abs(E[1] - (2 * f2 - 2 * np.sum(np.abs(AhA) ** 2) / f2)) <= 1e-12 * f2
+        for k in (1, 2, 3):
+            assert E[k] <= 4**k * np.sum(sig[k:] ** 2) * (1 + 1e-12), (k, E[k])
+            assert E[k] >= np.sum(sig[k:] ** 2) * (1 - 1e-12), (k, E[k])
+        assert E[4] == 0.0, E[4]
+
+
+def _check_schur_relations(A, res, tol):
+    I = [int(v) for v in res.piv[:, 0]]
+    J = [int(v) for v in res.piv[:, 1]]
+    scale = np.abs(A).max()
+    S_cf = O.schur_closed_form(A, I, J) if I else A
+    # the closed form via numpy.linalg.solve, written out again here so that
+    # this check does not rest on the oracle's own helper
+    if I:
+        S_np = A - A[:, J] @ np.linalg.solve(A[np.ix_(I, J)], A[I, :])
+        assert np.allclose(S_cf, S_np, rtol=0, atol=tol * scale)
+    assert np.allclose(res.S, S_cf, rtol=0, atol=tol * scale), np.abs(res.S - S_cf).max()
+    LU = res.L @ res.U
+    assert np.allclose(LU + res.S, A, rtol=0, atol=tol * scale)
+    if I:
+        assert np.allclose(LU[I, :], A[I, :], rtol=0, atol=tol * scale)      # interpolation
+        assert np.allclose(LU[:, J], A[:, J], rtol=0, atol=tol * scale)
+        prod = np.prod(np.array([res.U[t, J[t]] for t in range(len(I))]))
+        det = np.linalg.det(A[np.ix_(I, J)])
+        assert abs(prod - det) <= 1e-9 * abs(det), (prod, det)
+        for t in range(len(I)):
+            assert res.L[I[t], t] == 1.0
+            for s_ in range(t):
+                assert res.L[I[s_], t] == 0.0 and res.U[t, J[s_]] == 0.0
+
+
+def pin_closed_form_schur():
+    """The Schur complement after pivots (I, J) is A - A[:,J] A[I,J]^{-1} A[I,:]
+    (depends only on the sets; Sec. 4.1 CUR form), A = LU + S^(k)
+    (eqs. residual_update / approximation_update), LU interpolates A on the
+    pivot rows and columns, the pivot product equals det A[I,J], and L, U are
+    triangular up to the pivot order (Sec. 1, PAQ = LU)."""
+    rng = np.random.default_rng(8)
+    for trial in range(12):
+        n, m = int(rng.integers(3, 12)), int(rng.integers(3, 12))
+        cplx = bool(trial % 2)
+        A = W.random_dense(n, m, seed=100 + trial, complex_=cplx)
+        k = int(rng.integers(1, min(n, m) + 1))
+        res = O.rplu_dense(A, k=k, seed=trial, stream=0)
+        _check_schur_relations(A, res, 1e-10)
+        # and under arbitrary forced pivots
+        rows = rng.permutation(n)[:k]
+        cols = rng.permutation(m)[:k]
+        res2 = O.rplu_dense(A, k=k, forced=list(zip(rows, cols)))
+        _check_schur_relations(A, res2, 1e-8)
+
+
+def pin_exact_recovery():
+    """A rank-r matrix is recovered after r steps (the rank-r Schur
+    complement is 0 in exact arithmetic, eq. residual_update)."""
+    for seed, (n, m, r, cplx) in enumerate(((30, 20, 3, False), (25, 40, 7, True), (64, 64, 10, False))):
+        A = W.rank_r_dense(n, m, r, seed=seed, complex_=cplx)
+        res = O.rplu_dense(A, k=r, seed=seed)
+        rel = math.sqrt(float(np.sum(np.abs(res.S) ** 2)) / float(np.sum(np.abs(A) ** 2)))
+        assert rel <= 1e-12, rel
+        assert np.allclose(res.L @ res.U, A, rtol=0, atol=1e-11 * np.abs(A).max())
+
+
+def pin_eckart_young_floor():
+    """No rank-k approximation beats the truncated SVD (Sec. 2.2):
+    ||S^(k)||_F >= (sum_{j>k} sigma_j^2)^{1/2}, and T = ||S||_F^2."""
+    sigma = 0.8 ** np.arange(1, 97)
+    A = W.dense_with_spectrum(96, 96, sigma, seed=3)
+    for seed in range(4):
+        res = O.rplu_dense(A, k=20, seed=seed)
+        fro2 = float(np.sum(np.abs(res.S) ** 2))
+        assert abs(res.res_fro2 - fro2) <= 1e-13 * fro2
+        assert math.sqrt(fro2) >= math.sqrt(np.sum(sigma[20:] ** 2)) * (1 - 1e-12)
+
+
+def pin_mass_bookkeeping():
+    """Row masses and column masses both sum to ||S||_F^2 at every step, and
+    the row masses of a step equal the squared row norms of that step's
+    Schur complement from the closed form."""
+    A = W.random_dense(17, 23, seed=5, complex_=True)
+    res = O.rplu_dense(A, k=8, seed=1, keep_masses=True)
+    for t, rm in enumerate(res.masses):
+        I = [int(v) for v in res.piv[:t, 0]]
+        J = [int(v) for v in res.piv[:t, 1]]
+        S = O.schur_closed_form(A, I, J)
+        w = np.abs(S) ** 2
+        assert np.allclose(rm, w.sum(axis=1), rtol=1e-10, atol=1e-12 * w.sum())
+        assert abs(w.sum(axis=0).sum() - rm.sum()) <= 1e-12 * w.sum()
+
+
+def pin_stop_rules():
+    """Stop test before each draw: tolerance, exhaustion, rank limit."""
+    A = W.config1_dense_512()[:128, :128]
+    full = O.rplu_dense(A, k=60, seed=2)
+    # rel. residual history from the closed form of each prefix of pivots
+    fro2 = float(np.sum(A * A))
+    hist = []
+    for t in range(61):
+        I = [int(v) for v in full.piv[:t, 0]]
+        J = [int(v) for v in full.piv[:t, 1]]
+        hist.append(float(np.sum(O.schur_closed_form(A, I, J) ** 2)))
+    tol = math.sqrt(hist[25] / fro2) * 1.0000001
+    first = next(t for t in range(61) if hist[t] <= tol * tol * fro2)
+    res = O.rplu_dense(A, k=60, tol=tol, seed=2)
+    assert res.stop == O.STOP_TOL and res.rank == first, (res.stop, res.rank, first)
+    res = O.rplu_dense(A, k=10, tol=1e-30, seed=2)
+    assert res.stop == O.STOP_TOL_UNREACHED and res.rank == 10
+    res = O.rplu_dense(A, k=10, seed=2)
+    assert res.stop == O.STOP_RANK and res.rank == 10
+    # exactly representable rank-1 matrix: the Schur complement is exactly 0
+    X = np.outer([1.0, 2.0, 4.0, 0.5], [3.0, -1.0, 2.0])
+    res = O.rplu_dense(X, k=3)
+    assert res.stop == O.STOP_EXHAUSTED and res.rank == 1
+    res = O.rplu_dense(np.zeros((3, 4)), k=2)
+    assert res.stop == O.STOP_EXHAUSTED and res.rank == 0 and res.a_fro2 == 0.0
+    res = O.rplu_dense(W.random_dense(5, 3, seed=1), k=0)
+    assert res.rank == 3 and res.stop == O.STOP_EXHAUSTED
+
+
+def pin_nonfinite():
+    A = W.random_dense(4, 4, seed=1)
+    A[2, 1] = np.nan
+    try:
+        O.rplu_dense(A, k=2)
+    except O.NonFiniteInput:
+        return
+    raise AssertionError("NaN input was not rejected")
+
+
+def pin_cauchy_vs_dense():
+    """Generator updates (eqs. generator_update_g/_b) reproduce the dense
+    Schur complement entrywise under the same pivots, and the Sylvester
+    identity X S - S Y = G B holds at every step (eq. cauchy-like-Sylvester);
+    free-running, both forms draw the same pivots."""
+    for p, (n, m) in ((1, (40, 30)), (2, (25, 45)), (3, (33, 33))):
+        x, y, G, B = W.cauchy_like_random(n, m, p, seed=p)
+        A = O.cauchy_entries(x, y, G, B)
+        rc = O.rplu_cauchy(x, y, G, B, k=12, seed=p)
+        rd = O.rplu_dense(A, k=12, seed=p)
+        assert np.array_equal(rc.piv, rd.piv), (rc.piv, rd.piv)
+        scale = np.abs(A).max()
+        # L(:,t) = c/a_t: compare the columns c = L(:,t) a_t of S^(t), since
+        # late pivots a_t are small and the division amplifies rounding
+        a_t = np.array([rd.U[t, rd.piv[t, 1]] for t in range(rd.rank)])
+        assert np.allclose(rc.L * a_t, rd.L * a_t, rtol=0, atol=1e-12 * scale)
+        assert np.allclose(rc.U, rd.U, rtol=0, atol=1e-12 * scale)
+        S_gen = O.cauchy_entries(x, y, rc.G, rc.B)
+        assert np.allclose(S_gen, rd.S, rtol=0, atol=1e-12 * scale)
+        # Sylvester identity at every step, with the dense oracle's S^(t)
+        Gt, Bt = G.astype(np.complex128).copy(), B.astype(np.complex128).copy()
+        S = A.copy()
+        gb0 = np.abs(Gt @ Bt).max()        # rounding scales with the input
+        for t in range(rc.rank):
+            i, j = (int(v) for v in rc.piv[t])
+            O.cauchy_generator_update(x, y, Gt, Bt, i, j)
+            O.schur_update(S, i, j)
+            lhs = x[:, None] * S - S * y[None, :]
+            assert np.allclose(lhs, Gt @ Bt, rtol=0, atol=1e-12 * gb0)
+
+
+def pin_cauchy_determinant():
+    """For a pure Cauchy matrix (G = B = 1), the pivot product equals the
+    Cauchy determinant of A[I, J] (textbook closed form)."""
+    x, y, G, B = W.cauchy_like_random(30, 26, 1, seed=7)
+    G = np.ones_like(G)
+    B = np.ones_like(B)
+    res = O.rplu_cauchy(x, y, G, B, k=9, seed=3)
+    I = [int(v) for v in res.piv[:, 0]]
+    J = [int(v) for v in res.piv[:, 1]]
+    xi, yj = x[I], y[J]
+    num = 1.0 + 0j
+    for a, b in itertools.combinations(range(len(I)), 2):
+        num *= (xi[b] - xi[a]) * (yj[a] - yj[b])
+    den = np.prod(xi[:, None] - yj[None, :])
+    det = num / den
+    prod = np.prod([res.U[t, J[t]] for t in range(len(I))])
+    assert abs(prod - det) <= 1e-12 * len(I) * abs(det), (prod, det)
+
+
+def pin_loewner_entries():
+    """With Loewner generators (eq. loewner-generators), regenerated entries
+    equal (f^x_i - f^y_j)/(x_i - y_j) (eq. aaa-loewner)."""
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1, 1, 50).astype(np.complex128)
+    y = rng.uniform(-1, 1, 40).astype(np.complex128) + 1e-3j
+    fx, fy = np.sin(10 * x), np.sin(10 * y)
+    G, B = W.loewner_generators(fx, fy)
+    A = O.cauchy_entries(x, y, G, B)
+    ref = (fx[:, None] - fy[None, :]) / (x[:, None] - y[None, :])
+    assert np.allclose(A, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+    row = O.cauchy_row(x, y, G, B, 7)
+    col = O.cauchy_col(x, y, G, B, 5)
+    assert np.allclose(row, ref[7], rtol=1e-13, atol=0) and np.allclose(col, ref[:, 5], rtol=1e-13, atol=0)
+    rm = O.cauchy_row_masses(x, y, G, B, rows_per_block=7)
+    assert np.allclose(rm, np.sum(np.abs(ref) ** 2, axis=1), rtol=1e-12)
+
+
+ALL_PINS = [
+    pin_philox_numpy, pin_inverse_cdf_bruteforce, pin_chi2_first_pivot,
+    pin_chi2_second_pivot, pin_one_step_expectation, pin_unitary_dft,
+    pin_doubling_enumeration, pin_closed_form_schur, pin_exact_recovery,
+    pin_eckart_young_floor, pin_mass_bookkeeping, pin_stop_rules,
+    pin_nonfinite, pin_cauchy_vs_dense, pin_cauchy_determinant,
+    pin_loewner_entries,
+]

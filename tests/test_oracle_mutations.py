@@ -1,0 +1,192 @@
+"""Planted mistakes in the CPU oracle must be caught by its pins.
+
+Each case monkeypatches one oracle routine with a plausible bug (a sign, a
+conjugation, a transposed index, a dropped term, an off-by-one edge rule)
+and asserts that at least one of the named pins fails.
+"""
+import numpy as np
+import pytest
+
+import pins
+from oracle import philox as PH
+from oracle import rplu as O
+
+_orig_schur = O.schur_update
+_orig_sq = O.squared_magnitude
+_orig_gen = O.cauchy_generator_update
+_orig_col = O.cauchy_col
+
+
+def _schur_plus(S, i, j):
+    a = S[i, j]
+    u = S[i, :].copy()
+    l = S[:, j] / a
+    l[i] = 1.0
+    S += np.outer(l, u)                 # wrong sign
+    S[i, :] = 0.0
+    S[:, j] = 0.0
+    return l, u, a
+
+
+def _schur_conj(S, i, j):
+    a = S[i, j]
+    u = S[i, :].conj().copy()           # U conjugated
+    l = S[:, j] / a
+    l[i] = 1.0
+    S -= np.outer(l, u)
+    S[i, :] = 0.0
+    S[:, j] = 0.0
+    return l, u, a
+
+
+def _schur_noscale(S, i, j):
+    a = S[i, j]
+    u = S[i, :].copy()
+    l = S[:, j].copy()                  # dropped 1/a
+    l[i] = 1.0
+    S -= np.outer(l, u)
+    S[i, :] = 0.0
+    S[:, j] = 0.0
+    return l, u, a
+
+
+def _schur_nozero(S, i, j):
+    a = S[i, j]
+    u = S[i, :].copy()
+    l = S[:, j] / a
+    l[i] = 1.0
+    S -= np.outer(l, u)                 # no exact zeroing of row i / column j
+    return l, u, a
+
+
+def _sq_abs(z):
+    return np.abs(z)                    # |z| instead of |z|^2
+
+
+def _sq_real_only(z):
+    return np.real(z) ** 2              # drops the imaginary part
+
+
+def _first_ge(prefix, target):
+    idx = int(np.searchsorted(prefix, target, side="left"))   # >= instead of >
+    if idx >= prefix.shape[0]:
+        raise ValueError
+    return idx
+
+
+def _gen_conj(x, y, G, B, i, j):
+    r = O.cauchy_row(x, y, G, B, i)
+    a = r[j]
+    c = O.cauchy_col(x, y, G, B, j)
+    gi = G[i, :].copy()
+    bj = B[:, j].copy()
+    G -= np.outer(c, gi) / a
+    B -= np.outer(bj, r.conj()) / a     # conjugated row in the B update
+    G[i, :] = 0.0
+    B[:, j] = 0.0
+    return c, r, a
+
+
+def _gen_swap(x, y, G, B, i, j):
+    r = O.cauchy_row(x, y, G, B, i)
+    a = r[j]
+    c = O.cauchy_col(x, y, G, B, j)
+    gi = G[i, :].copy()
+    bj = B[:, j].copy()
+    G -= np.outer(c, gi) / a
+    B -= np.outer(bj, r) / np.conj(a)   # wrong pivot in the B update
+    G[i, :] = 0.0
+    B[:, j] = 0.0
+    return c, r, a
+
+
+def _col_sign(x, y, G, B, j):
+    return (G @ B[:, j]) / (y[j] - x)   # flipped denominator
+
+
+def _philox_no_bump(counter, key):
+    c0, c1, c2, c3 = (int(v) & PH.MASK64 for v in counter)
+    k0, k1 = (int(v) & PH.MASK64 for v in key)
+    for _ in range(10):                 # key never bumped
+        p0 = PH.PHILOX_M0 * c0
+        p1 = PH.PHILOX_M1 * c2
+        c0, c1, c2, c3 = (p1 >> 64) ^ c1 ^ k0, p1 & PH.MASK64, (p0 >> 64) ^ c3 ^ k1, p0 & PH.MASK64
+    return c0, c1, c2, c3
+
+
+def _stop_tol_linear(t, T, T0, kmax, tol):
+    if T == 0.0:
+        return O.STOP_EXHAUSTED
+    if tol > 0.0 and T <= tol * T0:     # tol instead of tol^2
+        return O.STOP_TOL
+    if t == kmax:
+        return O.STOP_TOL_UNREACHED if tol > 0.0 else O.STOP_RANK
+    return 0
+
+
+def _rplu_dense_colstage_from_column(A, k=0, tol=0.0, seed=0, stream=0, forced=None,
+                                     keep_masses=False):
+    # column stage weighted by column i instead of row i (transposed index)
+    S = np.array(A, dtype=np.complex128 if np.iscomplexobj(A) else np.float64, copy=True)
+    n, m = S.shape
+    kmax = O._kmax(n, m, k)
+    L = np.zeros((n, kmax), dtype=S.dtype)
+    U = np.zeros((kmax, m), dtype=S.dtype)
+    piv = np.full((kmax, 2), -1, dtype=np.int64)
+    T0 = None
+    t = 0
+    while True:
+        rowmass = np.sum(O.squared_magnitude(S), axis=1)
+        T = float(np.cumsum(rowmass)[-1])
+        if t == 0:
+            T0 = T
+        stop = O._stop_reason(t, T, T0, kmax, tol)
+        if stop:
+            break
+        u1, u2 = O.step_uniforms(seed, stream, t)
+        fi, fj = O._forced_at(forced, t)
+        i = O.inverse_cdf(rowmass, u1, fi).used
+        j = O.inverse_cdf(O.squared_magnitude(S[:, i % m]), u2, fj).used % m
+        if S[i, j] == 0:
+            j = int(np.argmax(np.abs(S[i])))
+        l, u, a = O.schur_update(S, i, j)
+        L[:, t], U[t, :], piv[t] = l, u, (i, j)
+        t += 1
+    return O.RPLUResult(L[:, :t], U[:t], piv[:t], t, stop, T0, T, S=S)
+
+
+MUTATIONS = [
+    ("schur_sign", "schur_update", _schur_plus, [pins.pin_closed_form_schur, pins.pin_one_step_expectation]),
+    ("schur_conj_u", "schur_update", _schur_conj, [pins.pin_one_step_expectation, pins.pin_unitary_dft, pins.pin_closed_form_schur]),
+    ("schur_no_div", "schur_update", _schur_noscale, [pins.pin_closed_form_schur, pins.pin_exact_recovery]),
+    ("schur_no_zeroing", "schur_update", _schur_nozero, [pins.pin_doubling_enumeration, pins.pin_closed_form_schur]),
+    ("mass_abs", "squared_magnitude", _sq_abs, [pins.pin_chi2_first_pivot, pins.pin_mass_bookkeeping]),
+    ("mass_real_only", "squared_magnitude", _sq_real_only, [pins.pin_mass_bookkeeping]),
+    ("cdf_ge_edge", "first_exceeding", _first_ge, [pins.pin_inverse_cdf_bruteforce]),
+    ("gen_conj_row", "cauchy_generator_update", _gen_conj, [pins.pin_cauchy_vs_dense]),
+    ("gen_conj_pivot", "cauchy_generator_update", _gen_swap, [pins.pin_cauchy_vs_dense]),
+    ("col_denominator", "cauchy_col", _col_sign, [pins.pin_cauchy_vs_dense, pins.pin_loewner_entries]),
+    ("stop_tol_linear", "_stop_reason", _stop_tol_linear, [pins.pin_stop_rules]),
+    ("col_stage_transposed", "rplu_dense", _rplu_dense_colstage_from_column, [pins.pin_chi2_first_pivot, pins.pin_mass_bookkeeping]),
+]
+
+
+@pytest.mark.parametrize("name,attr,impl,catchers", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(monkeypatch, name, attr, impl, catchers):
+    monkeypatch.setattr(O, attr, impl)
+    caught = []
+    for pin in catchers:
+        try:
+            if pin in (pins.pin_chi2_first_pivot, pins.pin_chi2_second_pivot):
+                pin(N=8000)
+            else:
+                pin()
+        except (AssertionError, ValueError, IndexError, np.linalg.LinAlgError, O.ZeroPivot):
+            caught.append(pin.__name__)
+    assert caught, f"mutation {name} slipped past {[p.__name__ for p in catchers]}"
+
+
+def test_philox_mutation_is_caught(monkeypatch):
+    monkeypatch.setattr(PH, "philox4x64_10", _philox_no_bump)
+    with pytest.raises(AssertionError):
+        pins.pin_philox_numpy()
