@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""RPLU throughput on one MI355X: rank-k approximations per second.
+
+A step is one complete RPLU run (every per-step kernel of the method, k
+times) on one synthetic input that is already resident in device memory; the
+input buffers the run overwrites are restored from a device copy inside the
+step. Workloads:
+
+  cauchy20k  Cauchy matrix 1/(x_i - y_j), n = m = 20000, complex128, p = 1,
+             k = 200, x on two interleaved spirals, y a Gaussian cluster with
+             5% outliers; generator form, no matrix stored      (default)
+  dense32k   dense FP32 32768 x 32768, sigma_i = i^-2, U and V exactly
+             orthogonal products of 256 Householder reflectors, k = 512
+  dense512   dense FP64 512 x 512, sigma_i = 0.8^i, Haar U and V, k = 50
+
+Prints one JSON line. The hot kernel's average launch duration is measured
+with HIP events on the library's stream over the timed region; the CPU
+baseline times the oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RPLU rank-k approximations/sec and GB/s at rel err ≤1e-6; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_VECTOR_PEAK_TF = 78.6     # MI355X FP64 vector, TFLOP/s
+CAUCHY_FLOP_PER_PAIR = 7       # complex difference 2, |d|^2 3, divide 1, accumulate 1 (p = 1)
+KERNEL_SOURCES = ["common.hpp", "cdf.hpp", "dense.hip", "cauchy.hip"]
+
+
+def _source_sha() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2601_22344_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(workload: str, launches: int):
+    """Counter-measured HBM bytes per launch of the hot kernel, from the
+    committed rocprofv3 --pmc summary, if it was taken on the current kernel
+    sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            tab = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = tab.get(workload)
+    if not e or e.get("source_sha") != _source_sha():
+        return None
+    return e.get("bytes_per_launch")
+
+
+# ------------------------------------------------------------------ workloads
+
+def _setup_cauchy20k(torch, rplu):
+    import numpy as np
+    import workloads as W
+    x, y, G, B = W.config2_cauchy_spirals()
+    dev = "cuda:0"
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
+    xd, yd, G0, B0 = t(x), t(y), t(G), t(B)
+    G1, B1 = G0.clone(), B0.clone()
+    n, m, k = x.shape[0], y.shape[0], 200
+
+    def step():
+        G1.copy_(G0)
+        B1.copy_(B0)
+        return rplu.rplu_cauchy(xd, yd, G1, B1, k=k, seed=0)
+
+    # all-pairs mass launches at steps t = 0..k (the stop test at k included)
+    pairs = sum((n - s) * (m - s) for s in range(k + 1)) / (k + 1)
+    return dict(step=step, k=k, n=n, m=m, kind="cauchy", dtype="c128",
+                per_launch=pairs * CAUCHY_FLOP_PER_PAIR,
+                config={"workload": "cauchy n=m=20000 complex128 p=1 k=200 "
+                                    "spirals-vs-cluster (generator form, no stored matrix)",
+                        "n": n, "m": m, "k": k, "p": 1, "seed": 0})
+
+
+def _setup_dense(torch, rplu, which):
+    import numpy as np
+    import workloads as W
+    dev = "cuda:0"
+    if which == "dense512":
+        A = torch.from_numpy(W.config1_dense_512()).to(dev)
+        n = m = 512
+        k = 50
+        es = 8
+        desc = "dense fp64 512x512 sigma_i=0.8^i Haar U,V k=50"
+        dtype = "f64"
+    else:
+        n = m = 32768
+        k = 512
+        es = 4
+        A = W.dense_reflector_matrix_device(n, sigma_power=-2.0, q=256, seed=3,
+                                            device=dev, dtype=torch.float32)
+        desc = "dense fp32 32768x32768 sigma_i=i^-2 (256-reflector U,V) k=512"
+        dtype = "f32"
+    A0 = A
+    A1 = torch.empty_like(A0)
+
+    def step():
+        A1.copy_(A0)
+        return rplu.rplu_dense(A1, k=k, seed=0)
+
+    live = sum(2 * (n - s) * (m - s) * es for s in range(k)) / k
+    return dict(step=step, k=k, n=n, m=m, kind="dense", dtype=dtype, per_launch=live,
+                live_total=sum(2 * (n - s) * (m - s) * es for s in range(k)) + n * m * es,
+                config={"workload": desc, "n": n, "m": m, "k": k, "seed": 0})
+
+
+# --------------------------------------------------------------- CPU baseline
+
+_CPU_SAMPLE = r"""
+import sys, time, json
+sys.path.insert(0, {root!r})
+import numpy as np, workloads as W
+from oracle import rplu as O
+wl = {wl!r}
+if wl == "cauchy20k":
+    x, y, G, B = W.config2_cauchy_spirals()
+    t0 = time.perf_counter()
+    r = O.rplu_cauchy(x, y, G, B, k=2, seed=0)
+    el = time.perf_counter() - t0
+    print(json.dumps({{"elapsed": el, "passes": 3, "k": 200}}))
+elif wl == "dense512":
+    A = W.config1_dense_512()
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < 10.0:
+        O.rplu_dense(A, k=50, seed=0)
+        reps += 1
+    el = time.perf_counter() - t0
+    print(json.dumps({{"elapsed": el / reps, "passes": 51, "k": 50, "reps": reps}}))
+else:
+    n = 8192
+    A = W.dense_with_spectrum(n, n, np.arange(1, n + 1, dtype=np.float64) ** -2.0, seed=3).astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    O.rplu_dense(A, k=3, seed=0)
+    el = time.perf_counter() - t0
+    print(json.dumps({{"elapsed": el, "passes": 4, "k": 512, "sub_n": n}}))
+"""
+
+
+def cpu_baseline(workload: str):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    code = _CPU_SAMPLE.format(root=ROOT, wl=workload)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    if workload == "cauchy20k":
+        per_pass = d["elapsed"] / d["passes"]
+        full = per_pass * (d["k"] + 1)
+        sample = ("oracle rplu_cauchy on the full 20000x20000 input, k=2 (3 exact all-pairs "
+                  "mass passes), extrapolated to k=200 (201 passes)")
+    elif workload == "dense512":
+        full = d["elapsed"]
+        sample = f"oracle rplu_dense on the full 512x512 input, k=50, {d['reps']} repetitions"
+    else:
+        per_pass = d["elapsed"] / d["passes"]
+        full = per_pass * (32768 / d["sub_n"]) ** 2 * (d["k"] + 1)
+        sample = ("oracle rplu_dense, k=3 on an 8192x8192 matrix of the same spectrum, "
+                  "scaled by (32768/8192)^2 per step and to k=512")
+    return {"value": 1.0 / full, "unit": "approximations/s", "cores": 1, "kind": "oracle",
+            "sample": sample, "seconds_per_approximation": full}
+
+
+# ------------------------------------------------------------------------ main
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cauchy20k", choices=["cauchy20k", "dense32k", "dense512"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the method runs on a single device here)", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2601_22344_amd as rplu
+
+    torch.cuda.set_device(0)
+    if args.workload == "cauchy20k":
+        wl = _setup_cauchy20k(torch, rplu)
+    else:
+        wl = _setup_dense(torch, rplu, args.workload)
+    ctx = rplu.default_context(0)
+    res = None
+    for _ in range(args.warmup):
+        res = wl["step"]()
+    torch.cuda.synchronize()
+    rplu.rplu_profile_begin(ctx)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = wl["step"]()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = rplu.rplu_profile_end(ctx)
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+    hot_launches = prof["launches"][0]
+    hot_ms = prof["ms"][0] / max(1, hot_launches)
+    achieved = wl["per_launch"] / (hot_ms * 1e-3)
+    if wl["kind"] == "cauchy":
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK_TF,
+                "unit": "TFLOP/s", "frac": achieved / 1e12 / FP64_VECTOR_PEAK_TF}
+        kernel = "k_cauchy_mass<1>"
+    else:
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / 1e9 / HBM_PEAK_GBS}
+        kernel = "k_dense_sweep"
+    roof["traffic"] = _traffic(args.workload, hot_launches)
+    roof["kernel"] = kernel
+    roof["avg_launch_us"] = hot_ms * 1e3
+    roof["launches"] = hot_launches
+    out = {
+        "metric": METRIC, "value": value, "unit": "approximations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"],
+        "data": "synthetic", "config": wl["config"], "roofline": roof,
+        "achieved_rel_residual": math.sqrt(res.res_fro2 / res.a_fro2) if res and res.a_fro2 else None,
+        "rank": res.rank if res else None,
+        "kernel_ms_per_step": {"hot": prof["ms"][0] / args.steps, "sampler": prof["ms"][1] / args.steps,
+                               "update": prof["ms"][2] / args.steps, "init": prof["ms"][3] / args.steps},
+    }
+    if wl["kind"] == "dense":
+        out["GB_per_s_live"] = wl["live_total"] / (elapsed / args.steps) / 1e9
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

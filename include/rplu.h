@@ -1,0 +1,260 @@
+/*
+ * rplu.h -- C ABI of the MI355X (gfx950) Randomly Pivoted LU library.
+ *
+ * Randomly Pivoted LU (Gilles & Wilber, "Low-Rank Approximation by Randomly
+ * Pivoted LU") builds a rank-k approximation A ~ L U by k steps of Gaussian
+ * elimination in which the pivot (i, j) of step t is drawn with probability
+ * |S_ij|^2 / ||S||_F^2 from the current Schur complement S = A^(t)
+ * (Sec. 1, the RPLU distribution; Alg. 1). The library runs each step on the
+ * device in four parts: reduce |S_ij|^2 into row masses; draw the row, then
+ * the column of that row, by inverse-CDF sampling on a counter-based Philox
+ * stream (two-stage sampling, Sec. 4.1); copy the pivot row into U and the
+ * scaled pivot column into L; apply the rank-1 update
+ * S <- S - L(:,t) U(t,:) (eq. residual_update) while accumulating the next
+ * step's masses in the same pass.
+ *
+ * Two forms:
+ *   rplu_dense   S is stored in device memory and swept once per step.
+ *   rplu_cauchy  S is Cauchy-like (eq. cauchy-like): s_ij = (G_i,: B_:,j) /
+ *                (x_i - y_j). Only the generators G, B are stored and updated
+ *                (eqs. generator_update_g/_b, Alg. 3); entries are regenerated
+ *                on the fly and the row masses are computed exactly.
+ * plus rplu_batched (many independent dense instances in one persistent
+ * launch) and a continuous-batching server (rplu_server_*).
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers owned by the caller; the
+ *     library never frees them. Host pointers are named *_host.
+ *   - Indices are 0-based. piv[2t] = i_t, piv[2t+1] = j_t.
+ *   - L is n x k column-major: column t starts at L + t*ldl (ldl >= n).
+ *   - U is k x m row-major: row t starts at U + t*ldu (ldu >= m).
+ *   - A is n x m row-major with leading dimension lda >= m. It is
+ *     OVERWRITTEN with the final Schur complement S^(rank).
+ *   - Complex data are interleaved (re, im) pairs. Masses are |z|^2, U is not
+ *     conjugated, L(:,t) = S_:,j / S_ij with L(i_t, t) = 1.
+ *   - Pivot row and column of each update are set to exactly 0.
+ *   - Random numbers: Philox4x64-10 with key (seed, 0) and counter
+ *     (t, stream, 0, 0); u1 = (w0 >> 11) 2^-53 draws the row, u2 =
+ *     (w1 >> 11) 2^-53 the column. A drawn index is the first whose
+ *     inclusive prefix of masses exceeds u * (last prefix), so an index of
+ *     zero mass is never drawn.
+ *   - Stop test, before each draw, with T = ||S^(t)||_F^2 and T0 = ||A||_F^2:
+ *     T == 0 -> EXHAUSTED; rel_tol > 0 and T <= rel_tol^2 T0 -> TOL;
+ *     t == kmax -> RANK (TOL_UNREACHED if rel_tol > 0), where
+ *     kmax = min(n, m) if max_rank == 0, else min(max_rank, n, m).
+ *   - Calls that take a hip_stream (a hipStream_t; NULL = default stream)
+ *     enqueue on it and synchronise with it once at the end to fill info.
+ *   - Errors return a negative rplu_status; rplu_last_error() gives a
+ *     thread-local message. No call aborts or throws across the ABI.
+ */
+#ifndef RPLU_H
+#define RPLU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rplu_status;
+
+enum {
+    RPLU_OK = 0,
+    RPLU_PENDING = 1,          /* server: job admitted or queued, not done  */
+    RPLU_E_ARG = -1,           /* invalid argument (shape, pointer, dtype)  */
+    RPLU_E_NOMEM = -2,         /* device workspace could not be allocated   */
+    RPLU_E_HIP = -3,           /* a HIP runtime call failed                 */
+    RPLU_E_NONFINITE = -4,     /* NaN/Inf in the input or a pivot           */
+    RPLU_E_BUSY = -5,          /* server queue full                         */
+    RPLU_E_UNSUPPORTED = -6,   /* valid but not implemented combination     */
+    RPLU_E_ZERO_PIVOT = -7     /* a forced pivot has S_ij == 0              */
+};
+
+typedef enum {
+    RPLU_R32 = 1,    /* float                       */
+    RPLU_R64 = 2,    /* double                      */
+    RPLU_C64 = 3,    /* complex float  (re, im)     */
+    RPLU_C128 = 4    /* complex double (re, im)     */
+} rplu_dtype;
+
+enum {
+    RPLU_STOP_RANK = 1,
+    RPLU_STOP_TOL = 2,
+    RPLU_STOP_EXHAUSTED = 3,
+    RPLU_STOP_TOL_UNREACHED = 4
+};
+
+enum {
+    RPLU_FLAG_COLMASS = 1u << 0,  /* also reduce column masses in each sweep  */
+    RPLU_FLAG_GRAPH = 1u << 1,    /* replay the step loop as a hipGraph        */
+    RPLU_FLAG_NO_GRAPH = 1u << 2  /* never use a hipGraph (plain launches)     */
+};
+
+/* Per-step trace words (opts.trace, RPLU_TRACE_WORDS doubles per step t):
+ *  0 T        total mass ||S^(t)||_F^2 (last row prefix)
+ *  1 u1*T     row draw target
+ *  2 lo_i     lower CDF edge of the row bin used (prefix before i)
+ *  3 hi_i     upper CDF edge of the row bin used (prefix at i)
+ *  4 T_i      pivot row's own total (last prefix of |S_i,:|^2)
+ *  5 u2*T_i   column draw target
+ *  6 lo_j     lower CDF edge of the column bin used
+ *  7 hi_j     upper CDF edge of the column bin used
+ *  8 a.re     pivot entry S_ij (real part)
+ *  9 a.im     pivot entry (imaginary part, 0 for real dtypes)
+ * 10 i        pivot row (as a double)
+ * 11 j        pivot column (as a double)                                   */
+#define RPLU_TRACE_WORDS 12
+
+typedef struct {
+    int64_t max_rank;       /* k; 0 => min(n, m)                                */
+    double rel_tol;         /* stop when ||S||_F <= rel_tol ||A||_F; 0 => off   */
+    uint64_t seed;          /* Philox key word 0                                */
+    uint64_t stream;        /* Philox counter word 1 (instance / request id)    */
+    uint32_t flags;         /* RPLU_FLAG_*                                      */
+    uint32_t reserved;
+    const int32_t* forced;  /* device, 2*kmax ints: use (i_t, j_t) instead of the
+                               draws (draws are still traced); NULL = sample    */
+    double* trace;          /* device, kmax*RPLU_TRACE_WORDS doubles, or NULL   */
+    double* rowmass_out;    /* device, kmax*n doubles: the row masses each draw
+                               used (dense: per row; Cauchy: per row), or NULL  */
+    double* colmass_out;    /* device, kmax*m doubles: column masses of S^(t),
+                               needs RPLU_FLAG_COLMASS (dense only), or NULL     */
+} rplu_opts;
+
+typedef struct {
+    int64_t rank;           /* pivots taken                                     */
+    int32_t stop;           /* RPLU_STOP_*                                      */
+    int32_t reserved;
+    double a_fro2;          /* ||A||_F^2 as reduced on the device               */
+    double res_fro2;        /* ||S^(rank)||_F^2 at the final stop test          */
+} rplu_info;
+
+typedef struct rplu_ctx_s* rplu_ctx;
+
+/* Context: device workspace (row masses, step state, partial sums), a pinned
+ * host staging word and the batched-launch tuning table. Not thread-safe; use
+ * one context per host thread. */
+rplu_status rplu_create(int device, rplu_ctx* out);
+rplu_status rplu_destroy(rplu_ctx ctx);
+
+/* Dense RPLU (Alg. 1 with two-stage exact sampling, Sec. 4.1).
+ * A: n x m, dtype, row-major, lda >= m; overwritten by S^(rank).
+ * piv: 2*kmax int32. L: n x kmax col-major (ldl >= n). U: kmax x m row-major
+ * (ldu >= m). L or U may be NULL to skip storing that factor (the update still
+ * runs; U row t is then kept in workspace). info: host pointer, required.
+ * Real dtypes R32/R64 and complex C64/C128 are supported; R32/C64 sweep in
+ * single precision with FP64 masses, prefix sums, totals and pivot reciprocal. */
+rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m,
+                       void* A, int64_t lda, const rplu_opts* opts,
+                       int32_t* piv, void* L, int64_t ldl, void* U, int64_t ldu,
+                       rplu_info* info, void* hip_stream);
+
+/* Cauchy-like RPLU (Alg. 3 with exact row masses, Sec. 5.1), C128 only.
+ * x: n complex nodes, y: m complex nodes (x_i != y_j required), G: n x p
+ * row-major, B: p x m row-major, 1 <= p <= 4. G and B are OVERWRITTEN with the
+ * generators of S^(rank) (eqs. generator_update_g/_b). L, U, piv as for
+ * rplu_dense; U(t,:) is the regenerated pivot row, L(:,t) the pivot column
+ * divided by the pivot. No n x m array is ever stored. */
+rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m,
+                        int32_t p, const void* x, const void* y, void* G, void* B,
+                        const rplu_opts* opts, int32_t* piv, void* L, int64_t ldl,
+                        void* U, int64_t ldu, rplu_info* info, void* hip_stream);
+
+/* ------------------------------------------------------------- batched */
+
+enum { RPLU_JOB_DENSE = 1, RPLU_JOB_CAUCHY = 2 };
+
+/* One independent problem. Dense fields: A, lda. Cauchy fields: p, x, y, G, B.
+ * Outputs piv/L/U as for the single-instance calls (device pointers). */
+typedef struct {
+    int32_t kind;           /* RPLU_JOB_DENSE or RPLU_JOB_CAUCHY               */
+    int32_t dtype;          /* rplu_dtype                                      */
+    int64_t n, m;
+    void* A;                /* dense input, overwritten by S^(rank)            */
+    int64_t lda;
+    int32_t p;              /* Cauchy displacement rank                        */
+    int32_t reserved;
+    const void* x;          /* Cauchy nodes and generators                     */
+    const void* y;
+    void* G;
+    void* B;
+    int32_t* piv;           /* outputs                                         */
+    void* L;
+    int64_t ldl;
+    void* U;
+    int64_t ldu;
+    int64_t max_rank;
+    double rel_tol;
+    uint64_t seed;
+    uint64_t stream;
+} rplu_job;
+
+/* Runs `count` dense jobs (host array `jobs`) in ONE persistent launch: every
+ * workgroup takes instances from a device work queue (largest estimated cost
+ * first) and runs each instance's whole step loop. R32 and R64 instances with
+ * n, m <= 4096 are supported; all jobs must share one dtype. Results are the
+ * same as running rplu_dense on each job alone (pivots identical, factors
+ * bitwise equal, because an instance's reduction order depends only on its
+ * shape). infos_host: count entries, filled at the end. */
+rplu_status rplu_batched(rplu_ctx ctx, int64_t count, const rplu_job* jobs,
+                         rplu_info* infos_host, void* hip_stream);
+
+/* ------------------------------------------------------------- server */
+
+typedef struct {
+    size_t hbm_budget_bytes;   /* admit jobs while their device footprint fits */
+    int32_t max_slots;         /* most jobs resident on the device at once     */
+    int32_t queue_capacity;    /* most jobs waiting; beyond -> RPLU_E_BUSY     */
+} rplu_server_cfg;
+
+typedef struct {
+    int64_t submitted, completed, rejected, queued, active;
+    double p50_ms, p99_ms;             /* submit -> completion latency       */
+    double p50_dense_ms, p99_dense_ms;
+    double p50_cauchy_ms, p99_cauchy_ms;
+    double busy_s;                     /* wall time with >= 1 active job     */
+    size_t hbm_in_use;
+} rplu_server_stats_t;
+
+typedef struct rplu_server_s* rplu_server;
+
+/* A server owns a worker thread and its own device stream(s). Jobs are copied
+ * into server-owned device slot memory at admission, so a job's input buffers
+ * may be reused as soon as poll returns something other than RPLU_PENDING for
+ * the admission (see rplu_server_poll); outputs are written at completion. */
+rplu_status rplu_server_create(rplu_ctx ctx, const rplu_server_cfg* cfg,
+                               rplu_server* out);
+/* Non-blocking. Copies the descriptor; returns a ticket. */
+rplu_status rplu_server_submit(rplu_server srv, const rplu_job* job,
+                               uint64_t* ticket);
+/* RPLU_PENDING until the job finished; then its status (RPLU_OK or an error)
+ * and info. Thread-safe. */
+rplu_status rplu_server_poll(rplu_server srv, uint64_t ticket, rplu_info* info);
+rplu_status rplu_server_stats(rplu_server srv, rplu_server_stats_t* out);
+/* Drains every submitted job, stops the worker and frees slot memory. */
+rplu_status rplu_server_destroy(rplu_server srv);
+
+/* ------------------------------------------------------------- profiling */
+
+/* Device time per kernel class, measured with HIP events recorded on the
+ * caller's stream around every launch between rplu_profile_begin and
+ * rplu_profile_end (plain launches only; graph replays are not timed).
+ * Class 0: the hot kernel (dense sweep / Cauchy all-pairs mass), 1: the
+ * samplers, 2: updates and reductions, 3: initial mass pass. */
+#define RPLU_PROFILE_CLASSES 4
+typedef struct {
+    int64_t launches[RPLU_PROFILE_CLASSES];
+    double ms[RPLU_PROFILE_CLASSES];
+} rplu_profile;
+rplu_status rplu_profile_begin(rplu_ctx ctx);
+/* Synchronises with the recorded events and returns the sums. */
+rplu_status rplu_profile_end(rplu_ctx ctx, rplu_profile* out);
+
+const char* rplu_status_str(rplu_status s);
+const char* rplu_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPLU_H */

@@ -1,0 +1,12 @@
+"""Randomly Pivoted LU on MI355X (gfx950): Python binding of librplu.
+
+The binding marshals torch device tensors and the current HIP stream into the
+C ABI of include/rplu.h; all computation runs in the library's HIP kernels.
+Importing fails if the library has not been built (there is no CPU path).
+"""
+from ._binding import (  # noqa: F401
+    RPLU_C64, RPLU_C128, RPLU_FLAG_COLMASS, RPLU_FLAG_GRAPH, RPLU_FLAG_NO_GRAPH, RPLU_R32,
+    RPLU_R64, RPLU_STOP_EXHAUSTED, RPLU_STOP_RANK, RPLU_STOP_TOL, RPLU_STOP_TOL_UNREACHED,
+    RPLU_TRACE_WORDS, Context, Result, RPLUError, default_context, lib, rplu_cauchy,
+    rplu_create, rplu_dense, rplu_profile_begin, rplu_profile_end,
+)

@@ -1,0 +1,261 @@
+"""ctypes binding of librplu.so (the C ABI declared in include/rplu.h).
+
+Argument marshalling only: tensors supply device memory and the current HIP
+stream; every step of the method runs in the library's HIP kernels. There is
+no fallback: if the library is missing or fails to load, importing this
+module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librplu.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python paper_2601_22344_amd/build.py` "
+        "(the RPLU path has no CPU fallback)")
+lib = C.CDLL(LIB_PATH)
+
+# ------------------------------------------------------------------ constants
+RPLU_OK, RPLU_PENDING = 0, 1
+RPLU_E_ARG, RPLU_E_NOMEM, RPLU_E_HIP, RPLU_E_NONFINITE = -1, -2, -3, -4
+RPLU_E_BUSY, RPLU_E_UNSUPPORTED, RPLU_E_ZERO_PIVOT = -5, -6, -7
+RPLU_R32, RPLU_R64, RPLU_C64, RPLU_C128 = 1, 2, 3, 4
+RPLU_STOP_RANK, RPLU_STOP_TOL, RPLU_STOP_EXHAUSTED, RPLU_STOP_TOL_UNREACHED = 1, 2, 3, 4
+RPLU_FLAG_COLMASS, RPLU_FLAG_GRAPH, RPLU_FLAG_NO_GRAPH = 1, 2, 4
+RPLU_TRACE_WORDS = 12
+RPLU_JOB_DENSE, RPLU_JOB_CAUCHY = 1, 2
+
+_DTYPES = {torch.float32: RPLU_R32, torch.float64: RPLU_R64,
+           torch.complex64: RPLU_C64, torch.complex128: RPLU_C128}
+
+
+class rplu_opts(C.Structure):
+    _fields_ = [("max_rank", C.c_int64), ("rel_tol", C.c_double), ("seed", C.c_uint64),
+                ("stream", C.c_uint64), ("flags", C.c_uint32), ("reserved", C.c_uint32),
+                ("forced", C.c_void_p), ("trace", C.c_void_p), ("rowmass_out", C.c_void_p),
+                ("colmass_out", C.c_void_p)]
+
+
+class rplu_info(C.Structure):
+    _fields_ = [("rank", C.c_int64), ("stop", C.c_int32), ("reserved", C.c_int32),
+                ("a_fro2", C.c_double), ("res_fro2", C.c_double)]
+
+
+class rplu_job(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("n", C.c_int64), ("m", C.c_int64),
+                ("A", C.c_void_p), ("lda", C.c_int64), ("p", C.c_int32), ("reserved", C.c_int32),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("G", C.c_void_p), ("B", C.c_void_p),
+                ("piv", C.c_void_p), ("L", C.c_void_p), ("ldl", C.c_int64), ("U", C.c_void_p),
+                ("ldu", C.c_int64), ("max_rank", C.c_int64), ("rel_tol", C.c_double),
+                ("seed", C.c_uint64), ("stream", C.c_uint64)]
+
+
+class rplu_server_cfg(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32),
+                ("queue_capacity", C.c_int32)]
+
+
+class rplu_profile(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 4), ("ms", C.c_double * 4)]
+
+
+class rplu_server_stats_t(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("queued", C.c_int64), ("active", C.c_int64), ("p50_ms", C.c_double),
+                ("p99_ms", C.c_double), ("p50_dense_ms", C.c_double),
+                ("p99_dense_ms", C.c_double), ("p50_cauchy_ms", C.c_double),
+                ("p99_cauchy_ms", C.c_double), ("busy_s", C.c_double),
+                ("hbm_in_use", C.c_size_t)]
+
+
+_P = C.c_void_p
+_I64 = C.c_int64
+lib.rplu_create.argtypes = [C.c_int, C.POINTER(_P)]
+lib.rplu_destroy.argtypes = [_P]
+lib.rplu_dense.argtypes = [_P, C.c_int, _I64, _I64, _P, _I64, C.POINTER(rplu_opts), _P, _P, _I64,
+                           _P, _I64, C.POINTER(rplu_info), _P]
+lib.rplu_cauchy.argtypes = [_P, C.c_int, _I64, _I64, C.c_int32, _P, _P, _P, _P,
+                            C.POINTER(rplu_opts), _P, _P, _I64, _P, _I64, C.POINTER(rplu_info), _P]
+lib.rplu_batched.argtypes = [_P, _I64, C.POINTER(rplu_job), C.POINTER(rplu_info), _P]
+lib.rplu_server_create.argtypes = [_P, C.POINTER(rplu_server_cfg), C.POINTER(_P)]
+lib.rplu_server_submit.argtypes = [_P, C.POINTER(rplu_job), C.POINTER(C.c_uint64)]
+lib.rplu_server_poll.argtypes = [_P, C.c_uint64, C.POINTER(rplu_info)]
+lib.rplu_server_stats.argtypes = [_P, C.POINTER(rplu_server_stats_t)]
+lib.rplu_server_destroy.argtypes = [_P]
+lib.rplu_profile_begin.argtypes = [_P]
+lib.rplu_profile_end.argtypes = [_P, C.POINTER(rplu_profile)]
+lib.rplu_status_str.argtypes = [C.c_int32]
+lib.rplu_status_str.restype = C.c_char_p
+lib.rplu_last_error.restype = C.c_char_p
+for _fn in ("rplu_create", "rplu_destroy", "rplu_dense", "rplu_cauchy", "rplu_batched",
+            "rplu_server_create", "rplu_server_submit", "rplu_server_poll",
+            "rplu_server_stats", "rplu_server_destroy", "rplu_profile_begin", "rplu_profile_end"):
+    getattr(lib, _fn).restype = C.c_int32
+
+
+class RPLUError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib.rplu_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {lib.rplu_status_str(status).decode()} ({msg})")
+
+
+def _check(status: int, where: str) -> int:
+    if status < 0:
+        raise RPLUError(status, where)
+    return status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _cur_stream(device: torch.device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """Owns an rplu_ctx (device workspace) for one device."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib.rplu_create(int(device), C.byref(h)), "rplu_create")
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if self.handle:
+            lib.rplu_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx: dict = {}
+
+
+def rplu_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def default_context(device: int = 0) -> Context:
+    ctx = _default_ctx.get(device)
+    if ctx is None:
+        ctx = _default_ctx[device] = Context(device)
+    return ctx
+
+
+@dataclass
+class Result:
+    piv: torch.Tensor              # rank x 2 int32 (device)
+    L: Optional[torch.Tensor]      # n x rank (column-major view)
+    U: Optional[torch.Tensor]      # rank x m
+    rank: int
+    stop: int
+    a_fro2: float
+    res_fro2: float
+    trace: Optional[torch.Tensor] = None      # rank x 12 float64
+    rowmass: Optional[torch.Tensor] = None    # rank x n float64
+    colmass: Optional[torch.Tensor] = None    # rank x m float64
+
+
+def _opts(k, tol, seed, stream, flags, forced, trace, rowmass_out, colmass_out):
+    return rplu_opts(int(k), float(tol), int(seed) & (2**64 - 1), int(stream) & (2**64 - 1),
+                     int(flags), 0, _ptr(forced), _ptr(trace), _ptr(rowmass_out),
+                     _ptr(colmass_out))
+
+
+def rplu_dense(A: torch.Tensor, k: int = 0, tol: float = 0.0, seed: int = 0, stream: int = 0,
+               flags: int = 0, forced: Optional[torch.Tensor] = None, want_trace: bool = False,
+               want_rowmass: bool = False, want_colmass: bool = False, store_L: bool = True,
+               store_U: bool = True, ctx: Optional[Context] = None) -> Result:
+    """Dense RPLU of A (n x m CUDA tensor, row stride >= m, overwritten by the
+    final Schur complement). Returns device factors sliced to the rank."""
+    if A.dim() != 2 or A.stride(1) != 1 or A.dtype not in _DTYPES or not A.is_cuda:
+        raise ValueError("A must be a 2-D CUDA tensor (float32/64, complex64/128), unit column stride")
+    n, m = A.shape
+    dev = A.device
+    ctx = ctx or default_context(dev.index or 0)
+    kmax = min(n, m) if k <= 0 else min(k, n, m)
+    piv = torch.empty((kmax, 2), dtype=torch.int32, device=dev)
+    Lt = torch.empty((kmax, n), dtype=A.dtype, device=dev) if store_L else None
+    U = torch.empty((kmax, m), dtype=A.dtype, device=dev) if store_U else None
+    trace = torch.empty((kmax, RPLU_TRACE_WORDS), dtype=torch.float64, device=dev) if want_trace else None
+    rmo = torch.empty((kmax, n), dtype=torch.float64, device=dev) if want_rowmass else None
+    cmo = torch.empty((kmax, m), dtype=torch.float64, device=dev) if want_colmass else None
+    if want_colmass:
+        flags |= RPLU_FLAG_COLMASS
+    if forced is not None:
+        forced = forced.to(device=dev, dtype=torch.int32).contiguous()
+        if forced.numel() < 2 * kmax:
+            raise ValueError("forced needs 2*kmax entries")
+    opts = _opts(k, tol, seed, stream, flags, forced, trace, rmo, cmo)
+    info = rplu_info()
+    st = lib.rplu_dense(ctx.handle, _DTYPES[A.dtype], n, m, _ptr(A), A.stride(0), C.byref(opts),
+                        _ptr(piv), _ptr(Lt), n, _ptr(U), m, C.byref(info), _cur_stream(dev))
+    _check(st, "rplu_dense")
+    r = int(info.rank)
+    return Result(piv[:r], Lt[:r].T if Lt is not None else None, U[:r] if U is not None else None,
+                  r, int(info.stop), float(info.a_fro2), float(info.res_fro2),
+                  trace[:r] if trace is not None else None, rmo[:r] if rmo is not None else None,
+                  cmo[:r] if cmo is not None else None)
+
+
+def rplu_cauchy(x: torch.Tensor, y: torch.Tensor, G: torch.Tensor, B: torch.Tensor, k: int = 0,
+                tol: float = 0.0, seed: int = 0, stream: int = 0, flags: int = 0,
+                forced: Optional[torch.Tensor] = None, want_trace: bool = False,
+                want_rowmass: bool = False, store_L: bool = True, store_U: bool = True,
+                ctx: Optional[Context] = None) -> Result:
+    """Cauchy-like RPLU from nodes x (n), y (m) and generators G (n x p),
+    B (p x m), complex128 CUDA tensors; G and B are overwritten by the
+    generators of the final Schur complement."""
+    for t_ in (x, y, G, B):
+        if t_.dtype != torch.complex128 or not t_.is_cuda or not t_.is_contiguous():
+            raise ValueError("x, y, G, B must be contiguous complex128 CUDA tensors")
+    n, m, p = x.shape[0], y.shape[0], G.shape[1]
+    if G.shape != (n, p) or B.shape != (p, m):
+        raise ValueError("G must be n x p and B p x m")
+    dev = x.device
+    ctx = ctx or default_context(dev.index or 0)
+    kmax = min(n, m) if k <= 0 else min(k, n, m)
+    piv = torch.empty((kmax, 2), dtype=torch.int32, device=dev)
+    Lt = torch.empty((kmax, n), dtype=torch.complex128, device=dev) if store_L else None
+    U = torch.empty((kmax, m), dtype=torch.complex128, device=dev) if store_U else None
+    trace = torch.empty((kmax, RPLU_TRACE_WORDS), dtype=torch.float64, device=dev) if want_trace else None
+    rmo = torch.empty((kmax, n), dtype=torch.float64, device=dev) if want_rowmass else None
+    if forced is not None:
+        forced = forced.to(device=dev, dtype=torch.int32).contiguous()
+    opts = _opts(k, tol, seed, stream, flags, forced, trace, rmo, None)
+    info = rplu_info()
+    st = lib.rplu_cauchy(ctx.handle, RPLU_C128, n, m, p, _ptr(x), _ptr(y), _ptr(G), _ptr(B),
+                         C.byref(opts), _ptr(piv), _ptr(Lt), n, _ptr(U), m, C.byref(info),
+                         _cur_stream(dev))
+    _check(st, "rplu_cauchy")
+    r = int(info.rank)
+    return Result(piv[:r], Lt[:r].T if Lt is not None else None, U[:r] if U is not None else None,
+                  r, int(info.stop), float(info.a_fro2), float(info.res_fro2),
+                  trace[:r] if trace is not None else None, rmo[:r] if rmo is not None else None)
+
+
+def rplu_profile_begin(ctx: Context) -> None:
+    _check(lib.rplu_profile_begin(ctx.handle), "rplu_profile_begin")
+
+
+def rplu_profile_end(ctx: Context) -> dict:
+    """{'launches': [4 ints], 'ms': [4 floats]}: device time per kernel class
+    (0 hot sweep/mass, 1 sampler, 2 update/reduce, 3 initial mass)."""
+    out = rplu_profile()
+    _check(lib.rplu_profile_end(ctx.handle, C.byref(out)), "rplu_profile_end")
+    return {"launches": list(out.launches), "ms": list(out.ms)}

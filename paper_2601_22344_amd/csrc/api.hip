@@ -1,0 +1,394 @@
+// C ABI of the RPLU library: argument checks, device workspace, and the host
+// step loop that enqueues the per-step kernels.
+//
+// Step loop. Every kernel reads the step index from the device-side
+// StepState, so a chunk of steps is the same sequence of launches whatever t
+// is. The host enqueues chunks of CH steps and reads the state's `done` word
+// back once per chunk; after the stop test fires on the device, the kernels
+// that remain in the chunk return at once. With RPLU_FLAG_GRAPH the chunk is
+// captured once into a hipGraph and replayed. One synchronisation with the
+// caller's stream per chunk is the only host/device round trip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "common.hpp"
+#include "launch.hpp"
+#include "runtime.hpp"
+
+namespace rplu {
+
+static thread_local std::string g_last_error;
+
+rplu_status fail(rplu_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+rplu_status hip_fail(hipError_t e, const char* what) {
+    return fail(RPLU_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t dtype_size(int dt) {
+    switch (dt) {
+        case RPLU_R32: return 4;
+        case RPLU_R64: return 8;
+        case RPLU_C64: return 8;
+        case RPLU_C128: return 16;
+        default: return 0;
+    }
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+rplu_status ws_reserve(rplu_ctx_s* ctx, size_t bytes, hipStream_t s) {
+    if (bytes <= ctx->ws_cap) return RPLU_OK;
+    if (ctx->ws) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_cap = 0;
+    }
+    size_t cap = std::max(bytes, (size_t)1 << 20);
+    hipError_t e = hipMalloc(&ctx->ws, cap);
+    if (e != hipSuccess) {
+        ctx->ws = nullptr;
+        return fail(RPLU_E_NOMEM, "workspace of %zu bytes: %s", cap, hipGetErrorString(e));
+    }
+    ctx->ws_cap = cap;
+    return RPLU_OK;
+}
+
+// Carves consecutive 256-byte aligned regions out of the context workspace.
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    }
+};
+
+static rplu_status read_state(rplu_ctx_s* ctx, const StepState* st, hipStream_t s,
+                              StepState* out) {
+    hipError_t e = hipMemcpyAsync(ctx->host_state, st, sizeof(StepState),
+                                  hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(state)");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    std::memcpy(out, ctx->host_state, sizeof(StepState));
+    return RPLU_OK;
+}
+
+static rplu_status finish(const StepState& hs, rplu_info* info) {
+    info->rank = hs.t;
+    info->stop = hs.stop;
+    info->reserved = 0;
+    info->a_fro2 = hs.T0;
+    info->res_fro2 = hs.T;
+    switch (hs.error) {
+        case 0: return RPLU_OK;
+        case RPLU_E_NONFINITE: return fail(RPLU_E_NONFINITE, "non-finite mass or pivot at step %d", hs.t);
+        case RPLU_E_ZERO_PIVOT: return fail(RPLU_E_ZERO_PIVOT, "forced pivot is zero at step %d", hs.t);
+        case RPLU_E_ARG: return fail(RPLU_E_ARG, "forced pivot out of range at step %d", hs.t);
+        default: return fail(hs.error, "device error %d at step %d", hs.error, hs.t);
+    }
+}
+
+// Runs `steps_total` steps of `enqueue_step` in chunks, optionally as a graph.
+template <class F>
+static rplu_status run_loop(rplu_ctx_s* ctx, StepState* st, int64_t steps_total, bool use_graph,
+                            hipStream_t s, F&& enqueue_step) {
+    const int64_t CH = steps_total <= 64 ? steps_total : 32;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (use_graph && s != nullptr && CH > 0) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        for (int64_t q = 0; q < CH; ++q) enqueue_step();
+        e = hipStreamEndCapture(s, &graph);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) { (void)hipGraphDestroy(graph); return hip_fail(e, "hipGraphInstantiate"); }
+    }
+    rplu_status rc = RPLU_OK;
+    for (int64_t done_steps = 0; done_steps < steps_total; done_steps += CH) {
+        if (exec) {
+            hipError_t e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) { rc = hip_fail(e, "hipGraphLaunch"); break; }
+        } else {
+            const int64_t todo = std::min(CH, steps_total - done_steps);
+            for (int64_t q = 0; q < todo; ++q) enqueue_step();
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) { rc = hip_fail(e, "kernel launch"); break; }
+        }
+        if (done_steps + CH >= steps_total) break;
+        hipError_t e = hipMemcpyAsync(&ctx->host_state->done, &st->done, sizeof(int32_t),
+                                      hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) { rc = hip_fail(e, "hipMemcpyAsync(done)"); break; }
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { rc = hip_fail(e, "hipStreamSynchronize"); break; }
+        if (ctx->host_state->done) break;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+}
+
+static int64_t kmax_of(int64_t n, int64_t m, int64_t k) {
+    const int64_t mn = std::min(n, m);
+    return k <= 0 ? mn : std::min(k, mn);
+}
+
+}  // namespace rplu
+
+using namespace rplu;
+
+extern "C" {
+
+const char* rplu_last_error(void) { return g_last_error.c_str(); }
+
+const char* rplu_status_str(rplu_status s) {
+    switch (s) {
+        case RPLU_OK: return "RPLU_OK";
+        case RPLU_PENDING: return "RPLU_PENDING";
+        case RPLU_E_ARG: return "RPLU_E_ARG";
+        case RPLU_E_NOMEM: return "RPLU_E_NOMEM";
+        case RPLU_E_HIP: return "RPLU_E_HIP";
+        case RPLU_E_NONFINITE: return "RPLU_E_NONFINITE";
+        case RPLU_E_BUSY: return "RPLU_E_BUSY";
+        case RPLU_E_UNSUPPORTED: return "RPLU_E_UNSUPPORTED";
+        case RPLU_E_ZERO_PIVOT: return "RPLU_E_ZERO_PIVOT";
+        default: return "RPLU_E_UNKNOWN";
+    }
+}
+
+rplu_status rplu_create(int device, rplu_ctx* out) {
+    if (out == nullptr) return fail(RPLU_E_ARG, "rplu_create: out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count)
+        return fail(RPLU_E_ARG, "rplu_create: device %d not in [0, %d)", device, count);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    rplu_ctx_s* c = new rplu_ctx_s();
+    c->device = device;
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDeviceProperties"); }
+    c->cu_count = prop.multiProcessorCount;
+    e = hipHostMalloc((void**)&c->host_state, sizeof(StepState), hipHostMallocDefault);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "hipHostMalloc"); }
+    *out = c;
+    return RPLU_OK;
+}
+
+rplu_status rplu_profile_begin(rplu_ctx ctx) {
+    if (ctx == nullptr) return fail(RPLU_E_ARG, "rplu_profile_begin: ctx is NULL");
+    ctx->prof.clear();
+    ctx->ev_used = 0;
+    ctx->prof_on = true;
+    return RPLU_OK;
+}
+
+rplu_status rplu_profile_end(rplu_ctx ctx, rplu_profile* out) {
+    if (ctx == nullptr || out == nullptr) return fail(RPLU_E_ARG, "rplu_profile_end: NULL argument");
+    std::memset(out, 0, sizeof *out);
+    ctx->prof_on = false;
+    rplu_status rc = RPLU_OK;
+    for (const rplu_prof_rec& r : ctx->prof) {
+        hipError_t e = hipEventSynchronize(r.b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) { rc = hip_fail(e, "hipEventElapsedTime"); break; }
+        out->launches[r.cls] += 1;
+        out->ms[r.cls] += ms;
+    }
+    ctx->prof.clear();
+    ctx->ev_used = 0;
+    return rc;
+}
+
+rplu_status rplu_destroy(rplu_ctx ctx) {
+    if (ctx == nullptr) return RPLU_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t ev : ctx->ev_pool) (void)hipEventDestroy(ev);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->batch_ws) (void)hipFree(ctx->batch_ws);
+    if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+    delete ctx;
+    return RPLU_OK;
+}
+
+rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, void* A,
+                       int64_t lda, const rplu_opts* opts, int32_t* piv, void* L, int64_t ldl,
+                       void* U, int64_t ldu, rplu_info* info, void* hip_stream) {
+    if (ctx == nullptr || opts == nullptr || info == nullptr)
+        return fail(RPLU_E_ARG, "rplu_dense: ctx, opts and info are required");
+    const size_t es = dtype_size(dtype);
+    if (es == 0) return fail(RPLU_E_ARG, "rplu_dense: unknown dtype %d", (int)dtype);
+    if (n < 1 || m < 1 || n > INT32_MAX || m > INT32_MAX)
+        return fail(RPLU_E_ARG, "rplu_dense: shape %lld x %lld out of range", (long long)n,
+                    (long long)m);
+    if (A == nullptr || lda < m) return fail(RPLU_E_ARG, "rplu_dense: A NULL or lda < m");
+    if (piv == nullptr) return fail(RPLU_E_ARG, "rplu_dense: piv is required");
+    if (L != nullptr && ldl < n) return fail(RPLU_E_ARG, "rplu_dense: ldl < n");
+    if (U != nullptr && ldu < m) return fail(RPLU_E_ARG, "rplu_dense: ldu < m");
+    if (opts->rel_tol < 0 || !(opts->rel_tol == opts->rel_tol))
+        return fail(RPLU_E_ARG, "rplu_dense: rel_tol must be >= 0");
+    if (opts->colmass_out != nullptr && !(opts->flags & RPLU_FLAG_COLMASS))
+        return fail(RPLU_E_ARG, "rplu_dense: colmass_out needs RPLU_FLAG_COLMASS");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t kmax = kmax_of(n, m, opts->max_rank);
+    const bool colmass = (opts->flags & RPLU_FLAG_COLMASS) != 0;
+
+    Carver cv;
+    const size_t o_st = cv.take(sizeof(StepState));
+    const size_t o_rm = cv.take((size_t)n * 8);
+    const int nbc = (int)((n + DENSE_ROWS_COLMASS - 1) / DENSE_ROWS_COLMASS);
+    const size_t o_cp = colmass ? cv.take((size_t)nbc * m * 8) : 0;
+    const size_t o_u = (U == nullptr) ? cv.take((size_t)m * es) : 0;
+    rplu_status rc = ws_reserve(ctx, cv.off, s);
+    if (rc) return rc;
+    char* ws = (char*)ctx->ws;
+
+    DenseArgs a{};
+    a.dtype = dtype;
+    a.n = n;
+    a.m = m;
+    a.S = A;
+    a.lda = lda;
+    a.U = U ? U : (void*)(ws + o_u);
+    a.ldu = U ? ldu : 0;          // a single workspace row, reused every step
+    a.L = L;
+    a.ldl = ldl;
+    a.piv = piv;
+    a.st = (StepState*)(ws + o_st);
+    a.rowmass = (double*)(ws + o_rm);
+    a.colpart = colmass ? (double*)(ws + o_cp) : nullptr;
+    a.colmass = colmass;
+    a.vec_ok = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)es) % 16 == 0) &&
+               ((uintptr_t)a.U % 16 == 0) && ((a.ldu * (int64_t)es) % 16 == 0);
+    a.colmass_out = opts->colmass_out;
+    a.rowmass_out = opts->rowmass_out;
+    a.trace = opts->trace;
+    a.forced = opts->forced;
+    a.seed = opts->seed;
+    a.stream = opts->stream;
+    a.kmax = kmax;
+    a.tol2 = opts->rel_tol * opts->rel_tol;
+
+    launch_state_init(a.st, s);
+    timed(ctx, 3, s, [&] { launch_dense_sweep(a, /*init=*/true, s); });
+    if (colmass && a.colmass_out) launch_colmass_reduce(a, false, s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "initial mass launch");
+
+    const bool graph = (opts->flags & RPLU_FLAG_GRAPH) && !(opts->flags & RPLU_FLAG_NO_GRAPH) &&
+                       !ctx->prof_on;
+    rc = run_loop(ctx, a.st, kmax + 1, graph, s, [&]() {
+        timed(ctx, 1, s, [&] { launch_dense_sample(a, s); });
+        timed(ctx, 0, s, [&] { launch_dense_sweep(a, /*init=*/false, s); });
+        if (colmass && a.colmass_out)
+            timed(ctx, 2, s, [&] { launch_colmass_reduce(a, true, s); });
+    });
+    if (rc) return rc;
+    StepState hs;
+    rc = read_state(ctx, a.st, s, &hs);
+    if (rc) return rc;
+    return finish(hs, info);
+}
+
+rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, int32_t p,
+                        const void* x, const void* y, void* G, void* B, const rplu_opts* opts,
+                        int32_t* piv, void* L, int64_t ldl, void* U, int64_t ldu,
+                        rplu_info* info, void* hip_stream) {
+    if (ctx == nullptr || opts == nullptr || info == nullptr)
+        return fail(RPLU_E_ARG, "rplu_cauchy: ctx, opts and info are required");
+    if (dtype != RPLU_C128) return fail(RPLU_E_UNSUPPORTED, "rplu_cauchy: only RPLU_C128");
+    if (n < 1 || m < 1 || n > INT32_MAX || m > INT32_MAX)
+        return fail(RPLU_E_ARG, "rplu_cauchy: shape out of range");
+    if (p < 1 || p > 4) return fail(RPLU_E_UNSUPPORTED, "rplu_cauchy: p must be in [1, 4]");
+    if (!x || !y || !G || !B || !piv)
+        return fail(RPLU_E_ARG, "rplu_cauchy: x, y, G, B and piv are required");
+    if (L != nullptr && ldl < n) return fail(RPLU_E_ARG, "rplu_cauchy: ldl < n");
+    if (U != nullptr && ldu < m) return fail(RPLU_E_ARG, "rplu_cauchy: ldu < m");
+    if (opts->rel_tol < 0 || !(opts->rel_tol == opts->rel_tol))
+        return fail(RPLU_E_ARG, "rplu_cauchy: rel_tol must be >= 0");
+    if (opts->colmass_out != nullptr || (opts->flags & RPLU_FLAG_COLMASS))
+        return fail(RPLU_E_UNSUPPORTED, "rplu_cauchy: column masses are not provided");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t kmax = kmax_of(n, m, opts->max_rank);
+
+    CauchyArgs a{};
+    const int64_t nbr = (n + cauchy_rows_per_block() - 1) / cauchy_rows_per_block();
+    // enough workgroups to fill every CU a few times over
+    int64_t splits = (4 * (int64_t)ctx->cu_count + nbr - 1) / nbr;
+    splits = std::max<int64_t>(1, std::min<int64_t>(splits, std::max<int64_t>(1, m / 256)));
+    a.splits = (int)splits;
+    Carver cv;
+    const size_t o_st = cv.take(sizeof(StepState));
+    const size_t o_rm = cv.take((size_t)n * 8);
+    const size_t o_pa = cv.take((size_t)n * splits * 8);
+    const size_t o_u = (U == nullptr) ? cv.take((size_t)m * 16) : 0;
+    rplu_status rc = ws_reserve(ctx, cv.off, s);
+    if (rc) return rc;
+    char* ws = (char*)ctx->ws;
+    a.n = n;
+    a.m = m;
+    a.p = p;
+    a.x = x;
+    a.y = y;
+    a.G = G;
+    a.B = B;
+    a.U = U ? U : (void*)(ws + o_u);
+    a.ldu = U ? ldu : 0;
+    a.L = L;
+    a.ldl = ldl;
+    a.piv = piv;
+    a.st = (StepState*)(ws + o_st);
+    a.partial = (double*)(ws + o_pa);
+    a.rowmass = (double*)(ws + o_rm);
+    a.rowmass_out = opts->rowmass_out;
+    a.trace = opts->trace;
+    a.forced = opts->forced;
+    a.seed = opts->seed;
+    a.stream = opts->stream;
+    a.kmax = kmax;
+    a.tol2 = opts->rel_tol * opts->rel_tol;
+
+    launch_state_init(a.st, s);
+    const bool graph = (opts->flags & RPLU_FLAG_GRAPH) && !(opts->flags & RPLU_FLAG_NO_GRAPH) &&
+                       !ctx->prof_on;
+    rc = run_loop(ctx, a.st, kmax + 1, graph, s, [&]() {
+        timed(ctx, 0, s, [&] { launch_cauchy_mass(a, s); });
+        timed(ctx, 1, s, [&] { launch_cauchy_sample(a, s); });
+        timed(ctx, 2, s, [&] { launch_cauchy_update(a, s); });
+    });
+    if (rc) return rc;
+    StepState hs;
+    rc = read_state(ctx, a.st, s, &hs);
+    if (rc) return rc;
+    return finish(hs, info);
+}
+
+}  // extern "C"

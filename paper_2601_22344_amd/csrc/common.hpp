@@ -1,0 +1,182 @@
+// Device-side building blocks shared by the RPLU kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rplu.h"
+
+#define RPLU_WAVE 64
+
+namespace rplu {
+
+// ---------------------------------------------------------------- complex
+
+struct cf32 { float re, im; };
+struct cf64 { double re, im; };
+
+// Scalar traits: storage type T, its FP64 "wide" form W (double or cf64),
+// |z|^2 in FP64, and the FMA-form update s - l*u in the storage precision.
+template <class T> struct Sc;
+
+template <> struct Sc<float> {
+    using W = double;
+    static constexpr bool cplx = false;
+    __device__ __host__ static inline double mag2(float v) { double d = v; return d * d; }
+    __device__ static inline W widen(float v) { return (double)v; }
+    __device__ static inline float narrow(W v) { return (float)v; }
+    __device__ static inline float zero() { return 0.f; }
+    __device__ static inline float one() { return 1.f; }
+    __device__ static inline float fms(float s, float l, float u) { return fmaf(-l, u, s); }
+    __device__ static inline double re(float v) { return v; }
+    __device__ static inline double im(float) { return 0.0; }
+};
+
+template <> struct Sc<double> {
+    using W = double;
+    static constexpr bool cplx = false;
+    __device__ __host__ static inline double mag2(double v) { return v * v; }
+    __device__ static inline W widen(double v) { return v; }
+    __device__ static inline double narrow(W v) { return v; }
+    __device__ static inline double zero() { return 0.0; }
+    __device__ static inline double one() { return 1.0; }
+    __device__ static inline double fms(double s, double l, double u) { return fma(-l, u, s); }
+    __device__ static inline double re(double v) { return v; }
+    __device__ static inline double im(double) { return 0.0; }
+};
+
+template <> struct Sc<cf32> {
+    using W = cf64;
+    static constexpr bool cplx = true;
+    __device__ __host__ static inline double mag2(cf32 v) {
+        double a = v.re, b = v.im;
+        return a * a + b * b;
+    }
+    __device__ static inline W widen(cf32 v) { return {(double)v.re, (double)v.im}; }
+    __device__ static inline cf32 narrow(W v) { return {(float)v.re, (float)v.im}; }
+    __device__ static inline cf32 zero() { return {0.f, 0.f}; }
+    __device__ static inline cf32 one() { return {1.f, 0.f}; }
+    // s - l*u = (s.re - l.re u.re + l.im u.im, s.im - l.re u.im - l.im u.re)
+    __device__ static inline cf32 fms(cf32 s, cf32 l, cf32 u) {
+        float r = fmaf(-l.re, u.re, s.re);
+        r = fmaf(l.im, u.im, r);
+        float i = fmaf(-l.re, u.im, s.im);
+        i = fmaf(-l.im, u.re, i);
+        return {r, i};
+    }
+    __device__ static inline double re(cf32 v) { return v.re; }
+    __device__ static inline double im(cf32 v) { return v.im; }
+};
+
+template <> struct Sc<cf64> {
+    using W = cf64;
+    static constexpr bool cplx = true;
+    __device__ __host__ static inline double mag2(cf64 v) { return v.re * v.re + v.im * v.im; }
+    __device__ static inline W widen(cf64 v) { return v; }
+    __device__ static inline cf64 narrow(W v) { return v; }
+    __device__ static inline cf64 zero() { return {0.0, 0.0}; }
+    __device__ static inline cf64 one() { return {1.0, 0.0}; }
+    __device__ static inline cf64 fms(cf64 s, cf64 l, cf64 u) {
+        double r = fma(-l.re, u.re, s.re);
+        r = fma(l.im, u.im, r);
+        double i = fma(-l.re, u.im, s.im);
+        i = fma(-l.im, u.re, i);
+        return {r, i};
+    }
+    __device__ static inline double re(cf64 v) { return v.re; }
+    __device__ static inline double im(cf64 v) { return v.im; }
+};
+
+__device__ inline double wmul(double a, double b) { return a * b; }
+__device__ inline cf64 wmul(cf64 a, cf64 b) {
+    return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+__device__ inline cf64 cadd(cf64 a, cf64 b) { return {a.re + b.re, a.im + b.im}; }
+__device__ inline cf64 csub(cf64 a, cf64 b) { return {a.re - b.re, a.im - b.im}; }
+
+// 1/a in FP64. Complex: Smith's scaling avoids overflow/underflow of |a|^2.
+__device__ inline double winv(double a) { return 1.0 / a; }
+__device__ inline cf64 winv(cf64 a) {
+    if (fabs(a.re) >= fabs(a.im)) {
+        double r = a.im / a.re, d = a.re + a.im * r;
+        return {1.0 / d, -r / d};
+    } else {
+        double r = a.re / a.im, d = a.re * r + a.im;
+        return {r / d, -1.0 / d};
+    }
+}
+// a / b, complex, Smith's algorithm.
+__device__ inline cf64 cdiv(cf64 a, cf64 b) {
+    if (fabs(b.re) >= fabs(b.im)) {
+        double r = b.im / b.re, d = b.re + b.im * r;
+        return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+    } else {
+        double r = b.re / b.im, d = b.re * r + b.im;
+        return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+    }
+}
+
+// ------------------------------------------------------------------ Philox
+
+// Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64x64->128-bit
+// multiplications with key bumps by 64-bit Weyl constants between rounds.
+struct Philox4 { uint64_t w[4]; };
+
+__device__ inline Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                        uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += W0; k1 += W1; }
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    return {{c0, c1, c2, c3}};
+}
+
+__device__ inline double unit_from_word(uint64_t w) {
+    return (double)(w >> 11) * 0x1.0p-53;
+}
+
+// ------------------------------------------------------------ reductions
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, RPLU_WAVE);
+    return v;
+}
+
+// Inclusive scan across the 64 lanes of a wave (Hillis-Steele).
+__device__ inline double wave_incl_scan(double v, int lane) {
+#pragma unroll
+    for (int off = 1; off < RPLU_WAVE; off <<= 1) {
+        double o = __shfl_up(v, off, RPLU_WAVE);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// --------------------------------------------------------------- state
+
+// Per-run device state. The sampler of step t reads t, writes cur = t and
+// t = t + 1 (unless it stops); the sweep/update of that step reads cur. No
+// kernel other than the single-workgroup sampler writes the state.
+struct StepState {
+    int32_t t;          // pivots taken so far
+    int32_t cur;        // step the current sweep/update applies
+    int32_t done;       // 1 once the stop test fired or an error occurred
+    int32_t stop;       // RPLU_STOP_*
+    int32_t error;      // 0 or an RPLU_E_* code raised on the device
+    int32_t i, j;       // current pivot
+    int32_t pad;
+    double T0, T;       // ||A||_F^2 and the latest total
+    double a_re, a_im;  // pivot entry
+    double inv_re, inv_im;  // 1/a in FP64
+    double gi[8];       // Cauchy: copy of G_i,: (p <= 4 complex)
+    double bj[8];       // Cauchy: copy of B_:,j
+};
+
+}  // namespace rplu

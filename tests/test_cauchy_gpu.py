@@ -1,0 +1,129 @@
+"""Cauchy-like RPLU on the GPU against the FP64 oracle (Alg. 3, exact masses).
+
+Small cases: pivots match the oracle's draws (within 1e-12 T at bin edges),
+L, U and the final generators agree within 1e-10. Full size (n = m = 20000,
+p = 1, k = 200, spiral/cluster geometry): the oracle replays the GPU pivots
+on the generators (O((n+m)p) per step), checks the draws at sampled steps
+with its own exact row masses, and the pivot product is checked against the
+closed-form Cauchy determinant in log form.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import parity
+import workloads as W
+from oracle import rplu as O
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _dev(*arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(DEV) for a in arrs]
+
+
+def _check_small(rplu, x, y, G, B, k, seed, stream=0, tol=0.0):
+    xd, yd, Gd, Bd = _dev(x, y, G, B)
+    res = rplu.rplu_cauchy(xd, yd, Gd, Bd, k=k, tol=tol, seed=seed, stream=stream,
+                           want_trace=True, want_rowmass=True)
+    piv = res.piv.cpu().numpy()
+    orc = O.rplu_cauchy(x, y, G, B, k=k, tol=tol, seed=seed, stream=stream,
+                        forced=[tuple(p) for p in piv], keep_masses=True)
+    assert orc.rank == res.rank
+    parity.check_trace_self(res.trace.cpu().numpy(), piv)
+    exact, steps = parity.check_draws(orc, tau=1e-12)
+    assert exact == steps
+    scale = np.abs(O.cauchy_entries(x, y, G, B)).max()
+    a_t = np.array([orc.U[t, orc.piv[t, 1]] for t in range(orc.rank)])
+    # L(:,t) a_t is column j_t of S^(t); compare on the input's scale
+    assert parity.fro(res.L.cpu().numpy() * a_t - orc.L * a_t) <= 1e-10 * scale * math.sqrt(x.size * max(1, k))
+    assert parity.rel(res.U.cpu().numpy(), orc.U) <= 1e-10
+    S_g = O.cauchy_entries(x, y, Gd.cpu().numpy(), Bd.cpu().numpy())
+    S_o = O.cauchy_entries(x, y, orc.G, orc.B)
+    assert parity.fro(S_g - S_o) <= 1e-10 * math.sqrt(orc.a_fro2)
+    # row masses of every step against the oracle's exact generator-form
+    # masses; rounding in the generators is on the scale of the input, so the
+    # absolute allowance is sqrt(T_t T0) * 1e-12 per step
+    rm = res.rowmass.cpu().numpy()
+    for t in range(res.rank):
+        ref = orc.masses[t]
+        allow = 1e-12 * math.sqrt(ref.sum() * orc.a_fro2)
+        assert np.allclose(rm[t], ref, rtol=1e-10, atol=allow), t
+    return res, orc
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("n,m", [(40, 30), (300, 257), (1000, 2000), (2049, 1500)])
+def test_cauchy_small(rplu_lib, p, n, m):
+    x, y, G, B = W.cauchy_like_random(n, m, p, seed=n + p)
+    k = min(n, m, 25)
+    _check_small(rplu_lib, x, y, G, B, k, seed=p, stream=m)
+
+
+def test_cauchy_loewner_p2(rplu_lib):
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1, 1, 400).astype(np.complex128)
+    y = rng.uniform(-1, 1, 300).astype(np.complex128) + 0.05j
+    G, B = W.loewner_generators(np.sin(10 * x), np.sin(10 * y))
+    # stop well above the rounding floor: the numerical rank of this Loewner
+    # matrix is small, and pivots drawn from rounding noise are not comparable
+    _check_small(rplu_lib, x, y, G, B, 40, seed=2, tol=1e-9)
+
+
+def test_cauchy_matches_dense_gpu(rplu_lib):
+    """The generator path and the dense path on the same matrix pick the same
+    pivots and the same factors (both on the GPU)."""
+    x, y, G, B = W.cauchy_like_random(500, 700, 2, seed=3)
+    A = O.cauchy_entries(x, y, G, B)
+    xd, yd, Gd, Bd = _dev(x, y, G, B)
+    rc = rplu_lib.rplu_cauchy(xd, yd, Gd, Bd, k=30, seed=8)
+    rd = rplu_lib.rplu_dense(torch.from_numpy(A).to(DEV), k=30, seed=8)
+    assert torch.equal(rc.piv.cpu(), rd.piv.cpu())
+    assert parity.rel(rc.U.cpu().numpy(), rd.U.cpu().numpy()) <= 1e-11
+
+
+def test_cauchy_tolerance_and_errors(rplu_lib):
+    x, y, G, B = W.cauchy_like_random(800, 600, 1, seed=5)
+    xd, yd, Gd, Bd = _dev(x, y, G, B)
+    r = rplu_lib.rplu_cauchy(xd, yd, Gd, Bd, k=0, tol=1e-8, seed=1)
+    assert r.stop == rplu_lib.RPLU_STOP_TOL and r.res_fro2 <= 1e-16 * r.a_fro2
+    orc = O.rplu_cauchy(x, y, G, B, k=0, tol=1e-8, seed=1, forced=[tuple(p) for p in r.piv.cpu().numpy()])
+    assert orc.rank == r.rank and orc.stop == O.STOP_TOL
+    yb = y.copy()
+    yb[5] = x[7]                      # x_i == y_j: infinite entry
+    xd, yd, Gd, Bd = _dev(x, yb, G, B)
+    with pytest.raises(rplu_lib.RPLUError) as e:
+        rplu_lib.rplu_cauchy(xd, yd, Gd, Bd, k=3)
+    assert e.value.status == -4
+
+
+@pytest.mark.slow
+def test_config2_full_size(rplu_lib):
+    """n = m = 20000 Cauchy matrix 1/(x_i - y_j) (spirals vs cluster), k = 200."""
+    x, y, G, B = W.config2_cauchy_spirals()
+    xd, yd, Gd, Bd = _dev(x, y, G, B)
+    res = rplu_lib.rplu_cauchy(xd, yd, Gd, Bd, k=200, seed=0, want_trace=True)
+    assert res.rank == 200
+    piv = res.piv.cpu().numpy()
+    parity.check_trace_self(res.trace.cpu().numpy(), piv)
+    sampled = {0, 1, 199}
+    orc = O.rplu_cauchy(x, y, G, B, k=200, seed=0, forced=[tuple(p) for p in piv],
+                        mass_steps=sampled)
+    exact, _ = parity.check_draws(orc, tau=1e-12)
+    assert exact == len(sampled)
+    assert parity.rel(res.U.cpu().numpy(), orc.U) <= 1e-10
+    Gg, Bg = Gd.cpu().numpy(), Bd.cpu().numpy()
+    assert parity.rel(Gg, orc.G, scale=parity.fro(G)) <= 1e-10
+    assert parity.rel(Bg, orc.B, scale=parity.fro(B)) <= 1e-10
+    # pivot product vs the Cauchy determinant of A[I, J], in logs
+    I, J = piv[:, 0], piv[:, 1]
+    xi, yj = x[I], y[J]
+    logdet = 0.0
+    for a in range(200):
+        logdet += np.sum(np.log(np.abs(xi[a + 1:] - xi[a]))) + np.sum(np.log(np.abs(yj[a] - yj[a + 1:])))
+    logdet -= np.sum(np.log(np.abs(xi[:, None] - yj[None, :])))
+    logprod = np.sum(np.log(np.abs(res.trace[:, 8].cpu().numpy() + 1j * res.trace[:, 9].cpu().numpy())))
+    assert abs(logprod - logdet) <= 1e-9 * abs(logdet)

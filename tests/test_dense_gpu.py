@@ -1,0 +1,207 @@
+"""Dense RPLU on the GPU (C ABI via the binding) against the FP64 oracle.
+
+FP64 / complex128 (protocol P1): every GPU pivot is the oracle's draw or
+lands in the oracle's CDF bin within 1e-12 T; L, U and the final Schur
+complement agree within 1e-10 relative. FP32 / complex64 (protocol P2): the
+oracle replays the GPU pivots in FP64 on the single-precision input; the
+GPU's own draws are exact in its own masses, the oracle's draws land in the
+GPU bins within the measured mass discrepancy, and the Schur complements
+agree within 1e-5 relative to ||A||_F.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import parity
+import workloads as W
+from oracle import rplu as O
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TORCH = {"r64": torch.float64, "c128": torch.complex128, "r32": torch.float32, "c64": torch.complex64}
+WIDE = {"r64": torch.float64, "c128": torch.complex128, "r32": torch.float64, "c64": torch.complex128}
+
+
+def _input(n, m, dt, seed, lda_pad=0):
+    A = W.random_dense(n, m, seed=seed, complex_=dt in ("c128", "c64"))
+    t = torch.from_numpy(A).to(TORCH[dt])
+    if lda_pad:
+        buf = torch.zeros((n, m + lda_pad), dtype=TORCH[dt])
+        buf[:, :m] = t
+        return buf.to(DEV)[:, :m], t
+    return t.to(DEV), t
+
+
+def _run_and_check(rplu, Ad, A_host, dt, k, seed, stream=0, tol=0.0, flags=0):
+    A_in = A_host.to(WIDE[dt]).numpy()          # the exact values the GPU starts from
+    res = rplu.rplu_dense(Ad, k=k, tol=tol, seed=seed, stream=stream, flags=flags,
+                          want_trace=True, want_rowmass=True)
+    piv = res.piv.cpu().numpy()
+    orc = O.rplu_dense(A_in, k=k, tol=tol, seed=seed, stream=stream, forced=[tuple(p) for p in piv])
+    assert orc.rank == res.rank or (tol > 0 and abs(orc.rank - res.rank) <= 1)
+    parity.check_trace_self(res.trace.cpu().numpy(), piv)
+    S_g = Ad.cpu().to(WIDE[dt]).numpy()
+    fa = math.sqrt(orc.a_fro2)
+    if dt in ("r64", "c128"):
+        exact, steps = parity.check_draws(orc, tau=1e-12)
+        assert exact == steps, f"{steps - exact} edge-tolerant pivot mismatches"
+        if res.rank:
+            # L(:,t) a_t is column j_t of S^(t): compared on the scale of A,
+            # since a late pivot a_t is small and 1/a_t amplifies rounding
+            a_t = np.array([orc.U[t, orc.piv[t, 1]] for t in range(orc.rank)])
+            assert parity.fro((res.L.cpu().numpy() - orc.L) * a_t) <= 1e-10 * fa
+            assert parity.rel(res.U.cpu().numpy(), orc.U) <= 1e-10
+        assert parity.rel(S_g, orc.S, scale=fa) <= 1e-10
+        assert abs(res.a_fro2 - orc.a_fro2) <= 1e-12 * orc.a_fro2
+    else:
+        # measured mass discrepancy per step, for the draw-agreement window
+        om = O.rplu_dense(A_in, k=k, tol=tol, seed=seed, stream=stream,
+                          forced=[tuple(p) for p in piv], keep_masses=True).masses
+        gm = res.rowmass.cpu().numpy()
+        delta = [float(np.sum(np.abs(gm[t] - om[t])) / np.sum(om[t])) for t in range(len(om))]
+        parity.check_draws(orc, tau=1e-12, delta=delta)
+        # single-precision forward error of k rank-1 updates: each step adds
+        # at most ~u32 (|S| + |L(:,t)| |U(t,:)|) per entry; 1e-5 of ||A||_F is
+        # the stated target, and the a-priori bound governs inputs with growth
+        u32 = 2.0 ** -24
+        bound = 4 * u32 * sum(fa + parity.fro(orc.L[:, t]) * parity.fro(orc.U[t]) for t in range(orc.rank))
+        tol_abs = max(1e-5 * fa, bound)
+        assert parity.fro(S_g - orc.S) <= tol_abs
+        if res.rank:
+            LU_g = res.L.cpu().to(WIDE[dt]).numpy() @ res.U.cpu().to(WIDE[dt]).numpy()
+            assert parity.fro(LU_g - orc.L @ orc.U) <= tol_abs
+    return res, orc
+
+
+SHAPES = [(1, 1), (1, 7), (7, 1), (2, 3), (17, 17), (50, 2500), (100, 64), (513, 257), (300, 1000)]
+
+
+@pytest.mark.parametrize("dt", ["r64", "c128", "r32", "c64"])
+@pytest.mark.parametrize("n,m", SHAPES)
+def test_dense_small_shapes(rplu_lib, dt, n, m):
+    seed = 1000 * n + m
+    Ad, Ah = _input(n, m, dt, seed)
+    k = 0 if min(n, m) <= 17 else min(n, m) // 3
+    _run_and_check(rplu_lib, Ad, Ah, dt, k, seed=seed % 97, stream=n)
+
+
+@pytest.mark.parametrize("dt", ["r64", "r32", "c128"])
+def test_dense_unaligned_rows(rplu_lib, dt):
+    """Row stride not a multiple of 16 bytes: the scalar (unvectorised) sweep."""
+    Ad, Ah = _input(37, 301, dt, 5, lda_pad=3)
+    _run_and_check(rplu_lib, Ad, Ah, dt, 20, seed=3)
+
+
+def test_config1_dense_512_fp64(rplu_lib):
+    """512 x 512 FP64, sigma_i = 0.8^i, k = 50, seed 0: every pivot equals the
+    oracle's draw and the factors agree within 1e-10."""
+    A = W.config1_dense_512()
+    Ad = torch.from_numpy(A).to(DEV)
+    res, orc = _run_and_check(rplu_lib, Ad, torch.from_numpy(A), "r64", 50, seed=0)
+    assert res.rank == 50 and res.stop == rplu_lib.RPLU_STOP_RANK
+    assert parity.rel(res.L.cpu().numpy(), orc.L) <= 1e-10
+    assert parity.rel(res.U.cpu().numpy(), orc.U) <= 1e-10
+    sig = np.linalg.svd(A, compute_uv=False)
+    assert math.sqrt(res.res_fro2) >= math.sqrt(np.sum(sig[50:] ** 2)) * (1 - 1e-12)
+
+
+def test_free_running_matches_oracle(rplu_lib):
+    """Free-running oracle (its own draws) and GPU produce the same pivots."""
+    A = W.random_dense(96, 80, seed=7)
+    res = rplu_lib.rplu_dense(torch.from_numpy(A).to(DEV), k=40, seed=11, stream=2)
+    orc = O.rplu_dense(A, k=40, seed=11, stream=2)
+    assert np.array_equal(res.piv.cpu().numpy(), orc.piv)
+
+
+def test_tolerance_stop(rplu_lib):
+    sigma = 0.5 ** np.arange(1, 65)
+    A = W.dense_with_spectrum(64, 64, sigma, seed=9)
+    res, orc = _run_and_check(rplu_lib, torch.from_numpy(A).to(DEV), torch.from_numpy(A), "r64",
+                              0, seed=4, tol=1e-6)
+    assert res.stop == rplu_lib.RPLU_STOP_TOL and orc.stop == O.STOP_TOL
+    assert res.res_fro2 <= 1e-12 * res.a_fro2
+
+
+def test_rank_r_recovery(rplu_lib):
+    A = W.rank_r_dense(200, 150, 12, seed=3)
+    Ad = torch.from_numpy(A).to(DEV)
+    res = rplu_lib.rplu_dense(Ad, k=12, seed=1)
+    assert math.sqrt(res.res_fro2 / res.a_fro2) <= 1e-12
+    LU = (res.L @ res.U).cpu().numpy()
+    assert parity.rel(LU, A) <= 1e-12
+
+
+def test_degenerate_inputs(rplu_lib):
+    Z = torch.zeros((5, 9), dtype=torch.float64, device=DEV)
+    r = rplu_lib.rplu_dense(Z, k=3)
+    assert r.rank == 0 and r.stop == rplu_lib.RPLU_STOP_EXHAUSTED and r.a_fro2 == 0.0
+    X = torch.tensor(np.outer([1.0, 2.0, 4.0, 0.5], [3.0, -1.0, 2.0]), device=DEV)
+    r = rplu_lib.rplu_dense(X, k=3)
+    assert r.rank == 1 and r.stop == rplu_lib.RPLU_STOP_EXHAUSTED
+    Y = torch.from_numpy(W.random_dense(6, 4, seed=2)).to(DEV)
+    r = rplu_lib.rplu_dense(Y, k=0)
+    assert r.rank == 4 and r.stop == rplu_lib.RPLU_STOP_EXHAUSTED
+    N = torch.from_numpy(W.random_dense(6, 4, seed=2)).to(DEV)
+    N[3, 1] = float("nan")
+    with pytest.raises(rplu_lib.RPLUError) as e:
+        rplu_lib.rplu_dense(N, k=2)
+    assert e.value.status == -4
+    F = torch.from_numpy(W.random_dense(6, 6, seed=2)).to(DEV)
+    F[2, 3] = 0.0
+    with pytest.raises(rplu_lib.RPLUError) as e:
+        rplu_lib.rplu_dense(F, k=1, forced=torch.tensor([2, 3]))
+    assert e.value.status == -7
+    with pytest.raises(rplu_lib.RPLUError) as e:
+        rplu_lib.rplu_dense(F, k=1, forced=torch.tensor([9, 0]))
+    assert e.value.status == -1
+
+
+def test_column_masses(rplu_lib):
+    """Column masses reduced by the sweep equal the oracle's column masses of
+    each S^(t), and row and column masses sum to the same total."""
+    A = W.random_dense(70, 2100, seed=12)
+    res = rplu_lib.rplu_dense(torch.from_numpy(A).to(DEV), k=9, seed=2, want_colmass=True,
+                              want_rowmass=True)
+    piv = res.piv.cpu().numpy()
+    cm = res.colmass.cpu().numpy()
+    rm = res.rowmass.cpu().numpy()
+    S = A.copy()
+    for t in range(res.rank):
+        ref = np.sum(S * S, axis=0)
+        assert np.allclose(cm[t], ref, rtol=1e-12, atol=1e-14 * ref.sum())
+        assert abs(cm[t].sum() - rm[t].sum()) <= 1e-12 * rm[t].sum()
+        O.schur_update(S, int(piv[t, 0]), int(piv[t, 1]))
+
+
+def test_deterministic_and_graph(rplu_lib):
+    """Two runs, and a run replayed as a hipGraph, are bitwise identical."""
+    A = W.random_dense(257, 1100, seed=21).astype(np.float32)
+    outs = []
+    for flags in (0, 0, rplu_lib.RPLU_FLAG_GRAPH):
+        Ad = torch.from_numpy(A).to(DEV)
+        r = rplu_lib.rplu_dense(Ad, k=70, seed=5, flags=flags)
+        torch.cuda.synchronize()
+        outs.append((r.piv.cpu(), r.L.cpu(), r.U.cpu(), Ad.cpu()))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert torch.equal(a, b)
+
+
+def test_chi2_first_pivot_gpu(rplu_lib):
+    """First pivots over 20000 streams follow |a_ij|^2/||A||_F^2 (6x6)."""
+    from scipy import stats
+    rng = np.random.default_rng(11)
+    A = rng.uniform(0.5, 2.0, (6, 6)) * rng.choice([-1.0, 1.0], (6, 6))
+    Ad0 = torch.from_numpy(A).to(DEV)
+    counts = np.zeros(36)
+    N = 20000
+    for s in range(N):
+        r = rplu_lib.rplu_dense(Ad0.clone(), k=1, seed=9, stream=s, store_L=False, store_U=False)
+        i, j = r.piv[0].tolist()
+        counts[6 * i + j] += 1
+    p = (A * A).ravel() / np.sum(A * A)
+    stat = np.sum((counts - N * p) ** 2 / (N * p))
+    assert stats.chi2.sf(stat, 35) > 1e-3

@@ -29,7 +29,7 @@ __all__ = [
     "random_dense", "rank_r_dense", "spiral_cluster_points",
     "config2_cauchy_spirals", "cauchy_like_random", "loewner_generators",
     "batched_instance_specs", "batched_instance", "serving_arrivals",
-    "dense_reflector_factors",
+    "dense_reflector_matrix_device",
 ]
 
 
@@ -89,13 +89,55 @@ def rank_r_dense(n: int, m: int, r: int, seed, complex_: bool = False) -> np.nda
     return X @ Y
 
 
-def dense_reflector_factors(n: int, q: int, seed) -> np.ndarray:
-    """q full-support Gaussian Householder vectors (q x n, FP64). The product
-    of the q reflectors I - 2 w w^T / (w^T w) is an exactly orthogonal n x n
-    matrix; it is used to build large test matrices A = U diag(sigma) V^T on
-    the device without a full-size QR."""
+def _compact_wy(Wm: np.ndarray) -> np.ndarray:
+    """T of the compact WY form H_1 H_2 ... H_q = I - W T W^T of the
+    reflectors H_l = I - tau_l w_l w_l^T, tau_l = 2 / (w_l^T w_l) (T upper
+    triangular, built column by column)."""
+    q = Wm.shape[1]
+    tau = 2.0 / np.sum(Wm * Wm, axis=0)
+    gram = Wm.T @ Wm
+    T = np.zeros((q, q))
+    for j in range(q):
+        T[j, j] = tau[j]
+        if j:
+            T[:j, j] = -tau[j] * (T[:j, :j] @ gram[:j, j])
+    return T
+
+
+def dense_reflector_matrix_device(n: int, sigma_power: float = -2.0, q: int = 256,
+                                  seed: int = 3, device="cuda:0", dtype=None):
+    """Large square test matrix A = U diag(sigma) V^T, sigma_i = i^sigma_power,
+    built on `device` with torch (FP64, then cast to dtype). U and V are
+    exactly orthogonal products of q seeded full-support Householder
+    reflectors, applied in compact WY form with three GEMMs per side, so no
+    n x n QR is needed. (With q << n the singular vectors stay close to the
+    coordinate axes; the spectrum is exact.)"""
+    import torch
     rng = np.random.default_rng(seed)
-    return rng.standard_normal((q, n))
+    Wu = rng.standard_normal((n, q))
+    Wv = rng.standard_normal((n, q))
+    Tu, Tv = _compact_wy(Wu), _compact_wy(Wv)
+    f64 = torch.float64
+    sig = torch.arange(1, n + 1, dtype=f64, device=device) ** sigma_power
+    Wu_d = torch.from_numpy(Wu).to(device)
+    Wv_d = torch.from_numpy(Wv).to(device)
+    Tu_d = torch.from_numpy(Tu).to(device)
+    Tv_d = torch.from_numpy(Tv).to(device)
+    # U diag(sigma) = diag(sigma) - Wu (Tu (Wu^T diag(sigma)))
+    R = (Tu_d @ (Wu_d.T.contiguous() * sig[None, :])).contiguous()
+    M = -(Wu_d @ R)
+    del R
+    M.diagonal().add_(sig)
+    # A = M V^T with V^T = I - Wv Tv^T Wv^T
+    P = (M @ Wv_d).contiguous()
+    Q = (Tv_d.T.contiguous() @ Wv_d.T.contiguous()).contiguous()
+    M -= P @ Q
+    del P, Q
+    if dtype is not None and dtype != f64:
+        out = M.to(dtype)
+        del M
+        return out
+    return M
 
 
 # --------------------------------------------------------------- Cauchy inputs
