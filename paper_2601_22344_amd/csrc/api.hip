@@ -16,6 +16,7 @@
 #include <cstring>
 #include <string>
 
+#include "cdf.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 #include "runtime.hpp"
@@ -49,6 +50,10 @@ size_t dtype_size(int dt) {
 }
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Largest n or m: the sampler chains at most CDF_MAX_GROUPS groups of
+// CDF_GROUP chunks of CDF_CHUNK elements.
+constexpr int64_t RPLU_MAX_DIM = (int64_t)CDF_MAX_GROUPS * CDF_GROUP * CDF_CHUNK;
 
 rplu_status ws_reserve(rplu_ctx_s* ctx, size_t bytes, hipStream_t s) {
     if (bytes <= ctx->ws_cap) return RPLU_OK;
@@ -259,9 +264,13 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, voi
     const int64_t kmax = kmax_of(n, m, opts->max_rank);
     const bool colmass = (opts->flags & RPLU_FLAG_COLMASS) != 0;
 
+    if (n > RPLU_MAX_DIM || m > RPLU_MAX_DIM)
+        return fail(RPLU_E_UNSUPPORTED, "rplu_dense: n and m must be <= %d", RPLU_MAX_DIM);
     Carver cv;
     const size_t o_st = cv.take(sizeof(StepState));
     const size_t o_rm = cv.take((size_t)n * 8);
+    const size_t o_ctr = cv.take((size_t)cdf_chunks((int)n) * 8);
+    const size_t o_ctc = cv.take((size_t)cdf_chunks((int)m) * 8);
     const int nbc = (int)((n + DENSE_ROWS_COLMASS - 1) / DENSE_ROWS_COLMASS);
     const size_t o_cp = colmass ? cv.take((size_t)nbc * m * 8) : 0;
     const size_t o_u = (U == nullptr) ? cv.take((size_t)m * es) : 0;
@@ -282,6 +291,7 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, voi
     a.piv = piv;
     a.st = (StepState*)(ws + o_st);
     a.rowmass = (double*)(ws + o_rm);
+    a.ct_col = (double*)(ws + o_ctc);
     a.colpart = colmass ? (double*)(ws + o_cp) : nullptr;
     a.colmass = colmass;
     a.vec_ok = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)es) % 16 == 0) &&
@@ -301,10 +311,35 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, voi
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "initial mass launch");
 
+    SampleArgs sa{};
+    sa.dtype = dtype;
+    sa.p = 0;
+    sa.n = n;
+    sa.m = m;
+    sa.rowmass = a.rowmass;
+    sa.ct_row = (double*)(ws + o_ctr);
+    sa.ct_col = a.ct_col;
+    sa.st = a.st;
+    sa.piv = piv;
+    sa.U = a.U;
+    sa.ldu = a.ldu;
+    sa.seed = opts->seed;
+    sa.stream = opts->stream;
+    sa.kmax = kmax;
+    sa.tol2 = a.tol2;
+    sa.forced = opts->forced;
+    sa.trace = opts->trace;
+    sa.rowmass_out = opts->rowmass_out;
+
     const bool graph = (opts->flags & RPLU_FLAG_GRAPH) && !(opts->flags & RPLU_FLAG_NO_GRAPH) &&
                        !ctx->prof_on;
     rc = run_loop(ctx, a.st, kmax + 1, graph, s, [&]() {
-        timed(ctx, 1, s, [&] { launch_dense_sample(a, s); });
+        timed(ctx, 1, s, [&] {
+            launch_ct_vec(a.rowmass, n, sa.ct_row, a.st, s);
+            launch_sample_row(sa, s);
+            launch_dense_rowchunks(a, s);
+            launch_sample_col(sa, s);
+        });
         timed(ctx, 0, s, [&] { launch_dense_sweep(a, /*init=*/false, s); });
         if (colmass && a.colmass_out)
             timed(ctx, 2, s, [&] { launch_colmass_reduce(a, true, s); });
@@ -339,6 +374,8 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     hipStream_t s = (hipStream_t)hip_stream;
     const int64_t kmax = kmax_of(n, m, opts->max_rank);
 
+    if (n > RPLU_MAX_DIM || m > RPLU_MAX_DIM)
+        return fail(RPLU_E_UNSUPPORTED, "rplu_cauchy: n and m must be <= %d", RPLU_MAX_DIM);
     CauchyArgs a{};
     const int64_t nbr = (n + cauchy_rows_per_block() - 1) / cauchy_rows_per_block();
     // enough workgroups to fill every CU a few times over
@@ -349,6 +386,8 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     const size_t o_st = cv.take(sizeof(StepState));
     const size_t o_rm = cv.take((size_t)n * 8);
     const size_t o_pa = cv.take((size_t)n * splits * 8);
+    const size_t o_ctr = cv.take((size_t)cdf_chunks((int)n) * 8);
+    const size_t o_ctc = cv.take((size_t)cdf_chunks((int)m) * 8);
     const size_t o_u = (U == nullptr) ? cv.take((size_t)m * 16) : 0;
     rplu_status rc = ws_reserve(ctx, cv.off, s);
     if (rc) return rc;
@@ -368,7 +407,7 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     a.st = (StepState*)(ws + o_st);
     a.partial = (double*)(ws + o_pa);
     a.rowmass = (double*)(ws + o_rm);
-    a.rowmass_out = opts->rowmass_out;
+    a.ct_col = (double*)(ws + o_ctc);
     a.trace = opts->trace;
     a.forced = opts->forced;
     a.seed = opts->seed;
@@ -379,9 +418,36 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     launch_state_init(a.st, s);
     const bool graph = (opts->flags & RPLU_FLAG_GRAPH) && !(opts->flags & RPLU_FLAG_NO_GRAPH) &&
                        !ctx->prof_on;
+    SampleArgs sa{};
+    sa.dtype = RPLU_C128;
+    sa.p = p;
+    sa.n = n;
+    sa.m = m;
+    sa.rowmass = a.rowmass;
+    sa.ct_row = (double*)(ws + o_ctr);
+    sa.ct_col = a.ct_col;
+    sa.st = a.st;
+    sa.piv = piv;
+    sa.U = a.U;
+    sa.ldu = a.ldu;
+    sa.G = G;
+    sa.B = B;
+    sa.seed = opts->seed;
+    sa.stream = opts->stream;
+    sa.kmax = kmax;
+    sa.tol2 = a.tol2;
+    sa.forced = opts->forced;
+    sa.trace = opts->trace;
+    sa.rowmass_out = opts->rowmass_out;
     rc = run_loop(ctx, a.st, kmax + 1, graph, s, [&]() {
         timed(ctx, 0, s, [&] { launch_cauchy_mass(a, s); });
-        timed(ctx, 1, s, [&] { launch_cauchy_sample(a, s); });
+        timed(ctx, 2, s, [&] { launch_cauchy_reduce(a, s); });
+        timed(ctx, 1, s, [&] {
+            launch_ct_vec(a.rowmass, n, sa.ct_row, a.st, s);
+            launch_sample_row(sa, s);
+            launch_cauchy_rowgen(a, s);
+            launch_sample_col(sa, s);
+        });
         timed(ctx, 2, s, [&] { launch_cauchy_update(a, s); });
     });
     if (rc) return rc;

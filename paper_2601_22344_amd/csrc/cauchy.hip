@@ -10,10 +10,13 @@
 //                    workgroup stages tiles of source columns (y_j, B_:,j) in
 //                    LDS and every lane reads them as broadcasts. Columns are
 //                    split over `splits` workgroup columns; the partial sums
-//                    are added in split order by the sampler (deterministic).
-//   k_cauchy_sample  stop test; row draw; regenerate the pivot row
-//                    r = (G_i,: B) ./ (x_i - y) into U(t,:); column draw over
-//                    |r|^2; pivot a = r_j and its reciprocal.
+//                    are added in split order by k_cauchy_reduce
+//                    (deterministic).
+//   k_cauchy_reduce  row masses from the split partials (fixed order)
+//   k_cauchy_rowgen  after the row draw: regenerate the pivot row
+//                    r = (G_i,: B) ./ (x_i - y) into U(t,:) with the chunk
+//                    totals of |r|^2 for the column draw (the draws are in
+//                    sample.hip)
 //   k_cauchy_update  column c = (G B_:,j) ./ (x - y_j), L(:,t) = c / a with
 //                    L(i,t) = 1; G <- G - (1/a) c G_i,: and
 //                    B <- B - (1/a) B_:,j r (eqs. generator_update_g/_b),
@@ -25,29 +28,43 @@
 namespace rplu {
 
 constexpr int CM_THREADS = 256;
-constexpr int CM_RT = 2;                       // target rows per thread
+constexpr int CM_RT = 4;                       // target rows per thread
 constexpr int CM_ROWS = CM_THREADS * CM_RT;    // target rows per workgroup
 constexpr int CM_TILE = 256;                   // source columns per LDS tile
 
-// 1/d for d > 0 in FP64: hardware reciprocal estimate refined by two Newton
-// steps r <- r + r (1 - d r), each of which roughly doubles the correct bits.
-__device__ inline double rcp_refined(double d) {
-    double r = __builtin_amdgcn_rcp(d);
-    double e = fma(-d, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-d, r, 1.0);
-    return fma(r, e, r);
+// |G_i,: B_:,j|^2 for one target row (registers) and one source column (LDS).
+template <int P>
+__device__ inline double gb_mag2(const cf64* g, const cf64 (*sb)[CM_TILE], int e) {
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        const cf64 b = sb[l][e];
+        sr = fma(g[l].re, b.re, sr);
+        sr = fma(-g[l].im, b.im, sr);
+        si = fma(g[l].re, b.im, si);
+        si = fma(g[l].im, b.re, si);
+    }
+    return fma(sr, sr, si * si);
 }
 
+// Row masses sum_j |G_i,: B_:,j|^2 / |x_i - y_j|^2 (for p = 1 the factor
+// |g_i|^2 is taken out of the sum and |b_j|^2 is staged per column).
+//
+// Four columns share one reciprocal: w0/d0 + w1/d1 + w2/d2 + w3/d3 = N / D
+// with D = (d0 d1)(d2 d3) and N = (w0 d1 + w1 d0)(d2 d3) + (w2 d3 + w3 d2)(d0 d1),
+// which takes the per-pair cost from one reciprocal plus its Newton steps to
+// a quarter of that. A group whose D or N leaves [2^-1000, 2^1000] (or is not
+// a number, e.g. when x_i == y_j) is summed term by term instead, so the
+// result is the plain sum for every input.
 template <int P>
 __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass(
     const cf64* __restrict__ x, const cf64* __restrict__ y, const cf64* __restrict__ G,
     const cf64* __restrict__ B, int n, int m, int cols_per_split,
     const StepState* __restrict__ st, double* __restrict__ partial) {
     if (st->done) return;
-    __shared__ double sy_re[CM_TILE], sy_im[CM_TILE];
+    __shared__ cf64 sy[CM_TILE];
     __shared__ double sw[P == 1 ? CM_TILE : 1];                 // |b_j|^2 (p = 1)
-    __shared__ cf64 sb[P == 1 ? 1 : P][P == 1 ? 1 : CM_TILE];   // b_lj (p > 1)
+    __shared__ cf64 sb[P == 1 ? 1 : P][CM_TILE];                // b_lj (p > 1)
     const int tid = threadIdx.x;
     const int split = blockIdx.y;
     const int c_beg = split * cols_per_split;
@@ -59,7 +76,7 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass(
     for (int q = 0; q < CM_RT; ++q) {
         const int r = blockIdx.x * CM_ROWS + q * CM_THREADS + tid;
         const bool ok = r < n;
-        cf64 xv = ok ? x[r] : cf64{0.0, 0.0};
+        const cf64 xv = ok ? x[r] : cf64{0.0, 0.0};
         xr[q] = xv.re;
         xi[q] = xv.im;
         acc[q] = 0.0;
@@ -76,9 +93,7 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass(
         const int nt = min(CM_TILE, c_end - c0);
         __syncthreads();
         for (int e = tid; e < nt; e += CM_THREADS) {
-            const cf64 yv = y[c0 + e];
-            sy_re[e] = yv.re;
-            sy_im[e] = yv.im;
+            sy[e] = y[c0 + e];
             if constexpr (P == 1) {
                 const cf64 b = B[c0 + e];
                 sw[e] = b.re * b.re + b.im * b.im;
@@ -88,27 +103,64 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass(
             }
         }
         __syncthreads();
-        for (int e = 0; e < nt; ++e) {
-            const double yr = sy_re[e], yi = sy_im[e];
+        const int n4 = nt & ~3;
+        for (int e = 0; e < n4; e += 4) {
+            const cf64 y0 = sy[e], y1 = sy[e + 1], y2 = sy[e + 2], y3 = sy[e + 3];
+            double w[CM_RT][4];
+            if constexpr (P == 1) {
+#pragma unroll
+                for (int q = 0; q < CM_RT; ++q) {
+                    w[q][0] = sw[e]; w[q][1] = sw[e + 1]; w[q][2] = sw[e + 2]; w[q][3] = sw[e + 3];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < CM_RT; ++q)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) w[q][u] = gb_mag2<P>(g[q], sb, e + u);
+            }
+            double Dq[CM_RT], Nq[CM_RT];
+            bool ok = true;
 #pragma unroll
             for (int q = 0; q < CM_RT; ++q) {
-                const double dr = xr[q] - yr, di = xi[q] - yi;
-                const double d2 = fma(dr, dr, di * di);
-                const double rinv = rcp_refined(d2);
-                if constexpr (P == 1) {
-                    acc[q] = fma(sw[e], rinv, acc[q]);
-                } else {
-                    double sr = 0.0, si = 0.0;
+                double a, b;
+                a = xr[q] - y0.re; b = xi[q] - y0.im; const double d0 = fma(a, a, b * b);
+                a = xr[q] - y1.re; b = xi[q] - y1.im; const double d1 = fma(a, a, b * b);
+                a = xr[q] - y2.re; b = xi[q] - y2.im; const double d2 = fma(a, a, b * b);
+                a = xr[q] - y3.re; b = xi[q] - y3.im; const double d3 = fma(a, a, b * b);
+                const double d01 = d0 * d1, d23 = d2 * d3;
+                Dq[q] = d01 * d23;
+                const double n01 = fma(w[q][0], d1, w[q][1] * d0);
+                const double n23 = fma(w[q][2], d3, w[q][3] * d2);
+                Nq[q] = fma(n01, d23, n23 * d01);
+                ok = ok && (Dq[q] >= 0x1p-1000) && (Dq[q] <= 0x1p+1000) && (fabs(Nq[q]) <= 0x1p+1000);
+            }
+            if (__builtin_expect(ok, 1)) {
 #pragma unroll
-                    for (int l = 0; l < P; ++l) {
-                        const cf64 b = sb[l][e];
-                        sr = fma(g[q][l].re, b.re, sr);
-                        sr = fma(-g[q][l].im, b.im, sr);
-                        si = fma(g[q][l].re, b.im, si);
-                        si = fma(g[q][l].im, b.re, si);
+                for (int q = 0; q < CM_RT; ++q) acc[q] = fma(Nq[q], rcp_refined(Dq[q]), acc[q]);
+            } else {
+                // term by term (extreme magnitudes or x_i == y_j)
+                const cf64 yy[4] = {y0, y1, y2, y3};
+#pragma unroll
+                for (int q = 0; q < CM_RT; ++q) {
+                    double s4 = 0.0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const double a = xr[q] - yy[u].re, b = xi[q] - yy[u].im;
+                        s4 = fma(w[q][u], rcp_refined(fma(a, a, b * b)), s4);
                     }
-                    acc[q] = fma(fma(sr, sr, si * si), rinv, acc[q]);
+                    acc[q] += s4;
                 }
+            }
+        }
+        for (int e = n4; e < nt; ++e) {
+            const cf64 yv = sy[e];
+#pragma unroll
+            for (int q = 0; q < CM_RT; ++q) {
+                double w;
+                if constexpr (P == 1) w = sw[e];
+                else w = gb_mag2<P>(g[q], sb, e);
+                const double a = xr[q] - yv.re, b = xi[q] - yv.im;
+                acc[q] = fma(w, rcp_refined(fma(a, a, b * b)), acc[q]);
             }
         }
     }
@@ -136,98 +188,35 @@ __device__ inline cf64 gen_dot(const cf64* g, const cf64* __restrict__ B, int m,
 // rowmass[e] = sum over splits s, in order, of partial[s][e].
 __global__ __launch_bounds__(256) void k_cauchy_reduce(
     const double* __restrict__ partial, int splits, int n, const StepState* __restrict__ st,
-    int kmax, double* __restrict__ rowmass, double* __restrict__ rowmass_out) {
+    double* __restrict__ rowmass) {
     if (st->done) return;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     double v = 0.0;
+#pragma unroll 8
     for (int s = 0; s < splits; ++s) v += partial[(int64_t)s * n + e];
     rowmass[e] = v;
-    const int t = st->t;
-    if (rowmass_out != nullptr && t < kmax) rowmass_out[(int64_t)t * n + e] = v;
 }
 
+// Wide: regenerates the pivot row r = (G_i,: B) ./ (x_i - y) into U(t,:)
+// (Alg. 3, row of A^(k)) and writes the chunk totals of |r|^2.
 template <int P>
-__global__ __launch_bounds__(CDF_THREADS) void k_cauchy_sample(
+__global__ __launch_bounds__(256) void k_cauchy_rowgen(
     const cf64* __restrict__ x, const cf64* __restrict__ y, const cf64* __restrict__ G,
-    const cf64* __restrict__ B, int n, int m, const double* __restrict__ rowmass,
-    StepState* __restrict__ st, int32_t* __restrict__ piv,
-    cf64* __restrict__ U, int64_t ldu, uint64_t seed, uint64_t stream, int kmax, double tol2,
-    const int32_t* __restrict__ forced, double* __restrict__ trace) {
-    __shared__ CdfShared sh;
-    __shared__ int s_flag;
-    __shared__ cf64 s_gi[P];
+    const cf64* __restrict__ B, int m, const StepState* __restrict__ st, cf64* __restrict__ U,
+    int64_t ldu, double* __restrict__ ct) {
     if (st->done) return;
-    const int t = st->t;
-    const int tid = threadIdx.x;
-    const double T = cdf_total(sh, n, [&](int e) { return rowmass[e]; });
-    if (tid == 0) {
-        int stop = 0, err = 0;
-        const double T0 = (t == 0) ? T : st->T0;
-        if (!isfinite(T)) err = RPLU_E_NONFINITE;
-        else if (T == 0.0) stop = RPLU_STOP_EXHAUSTED;
-        else if (tol2 > 0.0 && T <= tol2 * T0) stop = RPLU_STOP_TOL;
-        else if (t >= kmax) stop = tol2 > 0.0 ? RPLU_STOP_TOL_UNREACHED : RPLU_STOP_RANK;
-        st->T = T;
-        if (t == 0) st->T0 = T;
-        if (err || stop) { st->error = err; st->stop = stop; st->done = 1; }
-        s_flag = (err || stop) ? 1 : 0;
-    }
-    __syncthreads();
-    if (s_flag) return;
-    const Philox4 rnd = philox4x64_10((uint64_t)t, stream, 0, 0, seed, 0);
-    const double u1 = unit_from_word(rnd.w[0]), u2 = unit_from_word(rnd.w[1]);
-    const double tgt_i = u1 * T;
-    const CdfPick pr = cdf_select(sh, n, [&](int e) { return rowmass[e]; }, tgt_i);
-    const int i = forced ? forced[2 * t] : pr.idx;
-    const int j_forced = forced ? forced[2 * t + 1] : 0;
-    if (i < 0 || i >= n || j_forced < 0 || j_forced >= m) {
-        if (tid == 0) { st->error = RPLU_E_ARG; st->done = 1; }
-        return;
-    }
-    if (tid < P) s_gi[tid] = G[(int64_t)i * P + tid];
-    __syncthreads();
+    const int i = st->i;
     cf64 gi[P];
 #pragma unroll
-    for (int l = 0; l < P; ++l) gi[l] = s_gi[l];
+    for (int l = 0; l < P; ++l) gi[l] = G[(int64_t)i * P + l];
     const cf64 xi = x[i];
-    cf64* Ut = U + (int64_t)t * ldu;
-    for (int c = tid; c < m; c += CDF_THREADS) Ut[c] = cdiv(gen_dot<P>(gi, B, m, c), csub(xi, y[c]));
-    __syncthreads();
-    auto cm = [&](int e) { const cf64 v = Ut[e]; return v.re * v.re + v.im * v.im; };
-    const double Ti = cdf_total(sh, m, cm);
-    const double tgt_j = u2 * Ti;
-    CdfPick pc{0, 0.0, 0.0};
-    if (Ti > 0.0 && isfinite(Ti)) pc = cdf_select(sh, m, cm, tgt_j);
-    const int j = forced ? j_forced : pc.idx;
-    if (tid == 0) {
-        const cf64 a = Ut[j];
-        const double a2 = a.re * a.re + a.im * a.im;
-        if (!(a2 > 0.0)) {
-            st->error = isfinite(a2) ? RPLU_E_ZERO_PIVOT : RPLU_E_NONFINITE;
-            st->done = 1;
-        } else {
-            const cf64 inv = winv(a);
-            st->i = i; st->j = j;
-            st->a_re = a.re; st->a_im = a.im;
-            st->inv_re = inv.re; st->inv_im = inv.im;
-            for (int l = 0; l < P; ++l) {
-                st->gi[2 * l] = gi[l].re; st->gi[2 * l + 1] = gi[l].im;
-                const cf64 b = B[(int64_t)l * m + j];
-                st->bj[2 * l] = b.re; st->bj[2 * l + 1] = b.im;
-            }
-            st->cur = t;
-            st->t = t + 1;
-            piv[2 * t] = i;
-            piv[2 * t + 1] = j;
-            if (trace != nullptr) {
-                double* tr = trace + (int64_t)t * RPLU_TRACE_WORDS;
-                tr[0] = T; tr[1] = tgt_i; tr[2] = pr.lo; tr[3] = pr.hi;
-                tr[4] = Ti; tr[5] = tgt_j; tr[6] = pc.lo; tr[7] = pc.hi;
-                tr[8] = a.re; tr[9] = a.im; tr[10] = (double)i; tr[11] = (double)j;
-            }
-        }
-    }
+    cf64* Ut = U + (int64_t)st->cur * ldu;
+    cdf_chunk_totals_wave(m, ct, [&](int c) {
+        const cf64 r = cdiv_fast(gen_dot<P>(gi, B, m, c), csub(xi, y[c]));
+        Ut[c] = r;
+        return Sc<cf64>::mag2(r);
+    });
 }
 
 template <int P>
@@ -251,7 +240,7 @@ __global__ __launch_bounds__(256) void k_cauchy_update(
         cf64 s{0.0, 0.0};
 #pragma unroll
         for (int l = 0; l < P; ++l) s = cadd(s, wmul(g[l], bj[l]));
-        const cf64 c = cdiv(s, csub(x[r], y[pj]));
+        const cf64 c = cdiv_fast(s, csub(x[r], y[pj]));
         const cf64 l_r = wmul(c, inv);
         if (L != nullptr) L[(int64_t)t * ldl + r] = (r == pi) ? cf64{1.0, 0.0} : l_r;
 #pragma unroll
@@ -287,14 +276,16 @@ static void mass_p(const CauchyArgs& a, hipStream_t s) {
 }
 
 template <int P>
-static void sample_p(const CauchyArgs& a, hipStream_t s) {
+static void rowgen_p(const CauchyArgs& a, hipStream_t s) {
+    const int waves = cdf_chunks((int)a.m);
+    hipLaunchKernelGGL(k_cauchy_rowgen<P>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
+                       (const cf64*)a.x, (const cf64*)a.y, (const cf64*)a.G, (const cf64*)a.B,
+                       (int)a.m, a.st, (cf64*)a.U, a.ldu, a.ct_col);
+}
+
+void launch_cauchy_reduce(const CauchyArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_cauchy_reduce, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s,
-                       a.partial, a.splits, (int)a.n, a.st, (int)a.kmax, a.rowmass,
-                       a.rowmass_out);
-    hipLaunchKernelGGL(k_cauchy_sample<P>, dim3(1), dim3(CDF_THREADS), 0, s, (const cf64*)a.x,
-                       (const cf64*)a.y, (const cf64*)a.G, (const cf64*)a.B, (int)a.n, (int)a.m,
-                       a.rowmass, a.st, a.piv, (cf64*)a.U, a.ldu, a.seed,
-                       a.stream, (int)a.kmax, a.tol2, a.forced, a.trace);
+                       a.partial, a.splits, (int)a.n, a.st, a.rowmass);
 }
 
 template <int P>
@@ -314,7 +305,7 @@ static void update_p(const CauchyArgs& a, hipStream_t s) {
     }
 
 void launch_cauchy_mass(const CauchyArgs& a, hipStream_t s) { RPLU_DISPATCH_P(mass_p) }
-void launch_cauchy_sample(const CauchyArgs& a, hipStream_t s) { RPLU_DISPATCH_P(sample_p) }
+void launch_cauchy_rowgen(const CauchyArgs& a, hipStream_t s) { RPLU_DISPATCH_P(rowgen_p) }
 void launch_cauchy_update(const CauchyArgs& a, hipStream_t s) { RPLU_DISPATCH_P(update_p) }
 
 }  // namespace rplu

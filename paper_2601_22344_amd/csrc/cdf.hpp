@@ -1,120 +1,205 @@
-// Inverse-CDF sampling over a mass vector inside one 1024-thread workgroup.
+// Two-level inverse-CDF sampling over a mass vector.
 //
 // The index drawn for a target u*T is the first index e whose inclusive
 // prefix P(e) of the masses exceeds u*T (two-stage exact sampling draws a row
 // by its mass, then a column of that row by |S_ij|^2; Sec. 4.1).
 //
-// Prefix structure (two levels, deterministic for a given length):
-//   * wave w of the 16 waves owns the contiguous range [w*Rw, (w+1)*Rw),
-//     Rw a multiple of 64, walked in 64-element chunks; inside a chunk the
-//     lanes form an inclusive Hillis-Steele scan with shuffles and a running
-//     carry links the chunks, giving the wave-local prefix p(e) and the wave
-//     total tot_w = p(last);
-//   * the wave offsets are chained sequentially: off_0 = 0,
-//     off_{w+1} = off_w + tot_w, and the total is T := off_16. The wave
-//     intervals [off_w, off_{w+1}) therefore tile [0, T) with no gap.
-// The drawn index lies in the first wave with off_{w+1} > u*T; in that wave
-// the global prefix is P(e) = off_w + p(e), and P(last) == off_{w+1}
-// bit for bit, so a hit always exists. A hit must also have positive mass;
-// if rounding in off_w + p(e) leaves only zero-mass hits, the last
-// positive-mass index of the wave is taken (the wave has one, as its total
-// is positive). This keeps a zero-mass index from ever being drawn.
+// The vector (length len) is cut into chunks of CDF_CHUNK = 64 lanes x E
+// consecutive elements. Prefix structure, deterministic for a given len:
+//   * inside chunk k, lane l sums its E elements in order (local prefix loc,
+//     lane total lt); the lane totals are scanned across the wave
+//     (Hillis-Steele) and the exclusive scan ex gives each lane's offset;
+//     the chunk total is ct_k = ex_L + lt_L (L = last lane holding data);
+//   * chunks are grouped by CDF_GROUP; inside group g the chunk offsets are
+//     a sequential chain io_k (io = 0 at the group start, io += ct_k), the
+//     group total gt_g is the chain's end;
+//   * the group offsets are a sequential chain goff_0 = 0,
+//     goff_{g+1} = goff_g + gt_g, and the total is T := goff_G.
+// The prefix of element e in chunk k of group g is
+//     P(e) = goff_g + (io_k + (ex_l + loc_l(e))),
+// so the last element of chunk k has P = goff_g + io_{k+1} and the last of
+// group g has P = goff_{g+1}, bit for bit: the chunk and group intervals
+// tile [0, T) with no gap, and the first group (then chunk) whose upper end
+// exceeds u*T always holds a hit. A hit must also have positive mass; if
+// rounding at a lane boundary leaves only zero-mass hits in the chunk, its
+// last positive-mass element is taken (the chunk has one, as its total is
+// positive). A zero-mass index is never drawn.
+//
+// The chunk totals are computed by wide kernels (one wave per chunk, spread
+// over the whole GPU, fused with whatever produces the masses); the chains,
+// the stop test and the draw run in one workgroup, and one wave of it
+// re-walks the selected chunk.
 #pragma once
 
 #include "common.hpp"
 
 namespace rplu {
 
-constexpr int CDF_THREADS = 1024;
-constexpr int CDF_WAVES = CDF_THREADS / RPLU_WAVE;
+constexpr int CDF_E = 8;                           // consecutive elements per lane
+constexpr int CDF_CHUNK = RPLU_WAVE * CDF_E;       // elements per chunk (one wave)
+constexpr int CDF_GROUP = 32;                      // chunks per group
+constexpr int CDF_THREADS = 1024;                  // sampler workgroup
+constexpr int CDF_MAX_GROUPS = CDF_THREADS;        // => len <= 2^24 elements
 
-struct CdfShared {
-    double tot[CDF_WAVES];
-    double off[CDF_WAVES + 1];
-    double bcast[4];
-    int ibcast[4];
+__device__ __host__ inline int cdf_chunks(int len) { return (len + CDF_CHUNK - 1) / CDF_CHUNK; }
+
+// One chunk as seen by one wave: the lane's E masses (0 beyond len), its
+// exclusive offset ex, its total lt and the chunk total ct (same in every
+// lane). Indices are clamped into range and the values masked afterwards, so
+// every mass() call is unconditional and the loads issue back to back; a
+// callback that also stores (a row copy) rewrites element len-1 with the
+// value it already holds.
+struct CdfChunk {
+    double v[CDF_E];
+    double ex, lt, ct;
 };
+
+template <class MassFn>
+__device__ inline void cdf_chunk(CdfChunk& c, int chunk, int len, int lane, MassFn& mass) {
+    const int s0 = chunk * CDF_CHUNK + lane * CDF_E;
+    double x[CDF_E];
+#pragma unroll
+    for (int u = 0; u < CDF_E; ++u) x[u] = mass(min(s0 + u, len - 1));
+    double l = 0.0;
+#pragma unroll
+    for (int u = 0; u < CDF_E; ++u) {
+        c.v[u] = (s0 + u < len) ? x[u] : 0.0;
+        l += c.v[u];
+    }
+    const double incl = wave_incl_scan(l, lane);
+    double ex = __shfl_up(incl, 1, RPLU_WAVE);
+    if (lane == 0) ex = 0.0;
+    c.ex = ex;
+    c.lt = l;
+    const int L = min(RPLU_WAVE - 1, (len - 1 - chunk * CDF_CHUNK) / CDF_E);
+    c.ct = __shfl(ex + l, L, RPLU_WAVE);
+}
 
 struct CdfPick {
     int idx;        // drawn index
     double lo, hi;  // CDF edges of the drawn bin: P(idx-1), P(idx)
 };
 
-__device__ inline int cdf_wave_range(int len) {
-    int r = (len + CDF_WAVES - 1) / CDF_WAVES;
-    return (r + RPLU_WAVE - 1) / RPLU_WAVE * RPLU_WAVE;
+// Within chunk `chunk` (whole wave): the first element with positive mass
+// whose prefix goff + (io + (ex + loc)) exceeds target; `before` is the prefix
+// just before the chunk's first element.
+template <class MassFn>
+__device__ inline CdfPick cdf_chunk_select(int chunk, int len, int lane, MassFn& mass, double goff,
+                                           double io, double before, double target) {
+    CdfChunk c;
+    cdf_chunk(c, chunk, len, lane, mass);
+    double prev = __shfl_up(goff + (io + (c.ex + c.lt)), 1, RPLU_WAVE);
+    if (lane == 0) prev = before;
+    int hit_u = -1, pos_u = -1;
+    double hlo = 0.0, hhi = 0.0, plo = 0.0, phi = 0.0, loc = 0.0;
+#pragma unroll
+    for (int u = 0; u < CDF_E; ++u) {
+        loc += c.v[u];                          // the same sequence as c.lt
+        const double P = goff + (io + (c.ex + loc));
+        if (c.v[u] > 0.0) {
+            if (hit_u < 0 && P > target) { hit_u = u; hlo = prev; hhi = P; }
+            pos_u = u; plo = prev; phi = P;
+        }
+        prev = P;
+    }
+    const unsigned long long bal = __ballot(hit_u >= 0);
+    CdfPick r{-1, 0.0, 0.0};
+    if (bal) {
+        const int fl = __ffsll(bal) - 1;
+        r.idx = chunk * CDF_CHUNK + fl * CDF_E + __shfl(hit_u, fl, RPLU_WAVE);
+        r.lo = __shfl(hlo, fl, RPLU_WAVE);
+        r.hi = __shfl(hhi, fl, RPLU_WAVE);
+    } else {
+        const unsigned long long pos = __ballot(pos_u >= 0);
+        if (pos) {
+            const int lp = 63 - __clzll(pos);
+            r.idx = chunk * CDF_CHUNK + lp * CDF_E + __shfl(pos_u, lp, RPLU_WAVE);
+            r.lo = __shfl(plo, lp, RPLU_WAVE);
+            r.hi = __shfl(phi, lp, RPLU_WAVE);
+        }
+    }
+    return r;
 }
 
-// Pass 1: returns T (same value in every thread). MassFn: double(int e),
-// called only for 0 <= e < len.
+// Wide kernel body: wave w of the grid computes chunk w's total.
 template <class MassFn>
-__device__ double cdf_total(CdfShared& sh, int len, MassFn mass) {
-    const int lane = threadIdx.x % RPLU_WAVE, w = threadIdx.x / RPLU_WAVE;
-    const int Rw = cdf_wave_range(len);
-    const int b = w * Rw, e_end = min(len, b + Rw);
-    double carry = 0.0;
-    for (int c = b; c < e_end; c += RPLU_WAVE) {
-        int e = c + lane;
-        double v = e < e_end ? mass(e) : 0.0;
-        double s = wave_incl_scan(v, lane);
-        // link chunks through the last VALID lane, so that p(last) == tot_w
-        carry += __shfl(s, min(RPLU_WAVE, e_end - c) - 1, RPLU_WAVE);
+__device__ inline void cdf_chunk_totals_wave(int len, double* __restrict__ ct, MassFn mass) {
+    const int lane = threadIdx.x % RPLU_WAVE;
+    const int chunk = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / RPLU_WAVE);
+    if (chunk >= cdf_chunks(len)) return;
+    CdfChunk c;
+    cdf_chunk(c, chunk, len, lane, mass);
+    if (lane == 0) ct[chunk] = c.ct;
+}
+
+// ------------------------------------------------------ sampler workgroup
+
+struct CdfShared {
+    double goff[CDF_MAX_GROUPS + 1];
+    int flag[CDF_THREADS / RPLU_WAVE];
+    double bcast[4];
+    int ibcast[4];
+};
+
+// Group totals and offsets from the chunk totals ct[0..K); returns T in every
+// thread. Thread g sums group g's chunks in order; thread 0 chains groups.
+__device__ inline double cdf_levels(CdfShared& sh, const double* __restrict__ ct, int K) {
+    const int G = (K + CDF_GROUP - 1) / CDF_GROUP;
+    const int g = threadIdx.x;
+    if (g < G) {
+        double x[CDF_GROUP];                       // loads issued together
+#pragma unroll
+        for (int q = 0; q < CDF_GROUP; ++q) x[q] = ct[min(g * CDF_GROUP + q, K - 1)];
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < CDF_GROUP; ++q)
+            if (g * CDF_GROUP + q < K) s = s + x[q];
+        sh.goff[g + 1] = s;                        // group total, for now
     }
-    if (lane == 0) sh.tot[w] = carry;
     __syncthreads();
     if (threadIdx.x == 0) {
         double o = 0.0;
-        sh.off[0] = 0.0;
-        for (int q = 0; q < CDF_WAVES; ++q) { o = o + sh.tot[q]; sh.off[q + 1] = o; }
+        sh.goff[0] = 0.0;
+        for (int q = 0; q < G; ++q) { o = o + sh.goff[q + 1]; sh.goff[q + 1] = o; }
     }
     __syncthreads();
-    return sh.off[CDF_WAVES];
+    return sh.goff[G];
 }
 
-// Pass 2, after cdf_total on the same data: the drawn index for `target`
-// (0 <= target < T), its bin edges, same result in every thread.
+// After cdf_levels: the drawn index for target (0 <= target < T), same in
+// every thread. MassFn gives the masses of the vector (re-walks one chunk).
 template <class MassFn>
-__device__ CdfPick cdf_select(CdfShared& sh, int len, MassFn mass, double target) {
+__device__ CdfPick cdf_draw(CdfShared& sh, const double* __restrict__ ct, int K, int len,
+                            MassFn mass, double target) {
+    const int G = (K + CDF_GROUP - 1) / CDF_GROUP;
     const int lane = threadIdx.x % RPLU_WAVE, w = threadIdx.x / RPLU_WAVE;
-    int ww = 0;
-    while (ww < CDF_WAVES - 1 && !(sh.off[ww + 1] > target)) ++ww;
-    if (w == ww) {
-        const int Rw = cdf_wave_range(len);
-        const int b = w * Rw, e_end = min(len, b + Rw);
-        const double base = sh.off[w];
-        double carry = 0.0;
-        int found = -1, last_pos = -1;
-        double flo = 0.0, fhi = 0.0, plo = base, phi = base;
-        for (int c = b; c < e_end; c += RPLU_WAVE) {
-            int e = c + lane;
-            double v = e < e_end ? mass(e) : 0.0;
-            double s = wave_incl_scan(v, lane);
-            double P = base + (carry + s);
-            double Pprev = __shfl_up(P, 1, RPLU_WAVE);
-            if (lane == 0) Pprev = (c == b) ? base : base + carry;
-            bool hit = (e < e_end) && (v > 0.0) && (P > target);
-            unsigned long long bal = __ballot(hit);
-            unsigned long long pos = __ballot((e < e_end) && (v > 0.0));
-            if (pos) {
-                int lp = 63 - __clzll(pos);
-                int cand = c + lp;
-                double lo = __shfl(Pprev, lp, RPLU_WAVE), hi = __shfl(P, lp, RPLU_WAVE);
-                last_pos = cand; plo = lo; phi = hi;
-            }
-            if (bal) {
-                int fl = __ffsll(bal) - 1;
-                found = c + fl;
-                flo = __shfl(Pprev, fl, RPLU_WAVE);
-                fhi = __shfl(P, fl, RPLU_WAVE);
-                break;
-            }
-            carry += __shfl(s, min(RPLU_WAVE, e_end - c) - 1, RPLU_WAVE);
+    // first group whose upper end exceeds the target
+    const bool above = threadIdx.x < G && sh.goff[threadIdx.x + 1] > target;
+    const unsigned long long b = __ballot(above);
+    if (lane == 0) sh.flag[w] = b ? w * RPLU_WAVE + (__ffsll(b) - 1) : 0x7fffffff;
+    __syncthreads();
+    if (w == 0) {
+        int g = lane < CDF_THREADS / RPLU_WAVE ? sh.flag[lane] : 0x7fffffff;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) g = min(g, __shfl_xor(g, off, RPLU_WAVE));
+        g = min(g, G - 1);                         // T > target: always found
+        // chunk inside the group: sequential chain, same order as cdf_levels
+        const double goff = sh.goff[g];
+        const int k0 = g * CDF_GROUP, k1 = min(K, k0 + CDF_GROUP);
+        const double myct = ct[min(k0 + lane, K - 1)];   // lane q holds ct[k0 + q]
+        double io = 0.0;
+        int k = k0;
+        for (; k < k1 - 1; ++k) {
+            const double nio = io + __shfl(myct, k - k0, RPLU_WAVE);
+            if (goff + nio > target) break;
+            io = nio;
         }
-        if (found < 0) { found = last_pos; flo = plo; fhi = phi; }
-        if (lane == 0) { sh.ibcast[0] = found; sh.bcast[0] = flo; sh.bcast[1] = fhi; }
+        const double before = (k == k0) ? goff : goff + io;
+        const CdfPick p = cdf_chunk_select(k, len, lane, mass, goff, io, before, target);
+        if (lane == 0) { sh.ibcast[0] = p.idx; sh.bcast[0] = p.lo; sh.bcast[1] = p.hi; }
     }
     __syncthreads();
-    CdfPick r{sh.ibcast[0], sh.bcast[0], sh.bcast[1]};
+    const CdfPick r{sh.ibcast[0], sh.bcast[0], sh.bcast[1]};
     __syncthreads();
     return r;
 }

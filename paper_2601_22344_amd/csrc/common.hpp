@@ -48,9 +48,10 @@ template <> struct Sc<double> {
 template <> struct Sc<cf32> {
     using W = cf64;
     static constexpr bool cplx = true;
+    // explicit fma: every call site rounds |z|^2 the same way
     __device__ __host__ static inline double mag2(cf32 v) {
         double a = v.re, b = v.im;
-        return a * a + b * b;
+        return fma(a, a, b * b);
     }
     __device__ static inline W widen(cf32 v) { return {(double)v.re, (double)v.im}; }
     __device__ static inline cf32 narrow(W v) { return {(float)v.re, (float)v.im}; }
@@ -71,7 +72,7 @@ template <> struct Sc<cf32> {
 template <> struct Sc<cf64> {
     using W = cf64;
     static constexpr bool cplx = true;
-    __device__ __host__ static inline double mag2(cf64 v) { return v.re * v.re + v.im * v.im; }
+    __device__ __host__ static inline double mag2(cf64 v) { return fma(v.re, v.re, v.im * v.im); }
     __device__ static inline W widen(cf64 v) { return v; }
     __device__ static inline cf64 narrow(W v) { return v; }
     __device__ static inline cf64 zero() { return {0.0, 0.0}; }
@@ -114,6 +115,27 @@ __device__ inline cf64 cdiv(cf64 a, cf64 b) {
         double r = b.re / b.im, d = b.re * r + b.im;
         return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
     }
+}
+
+// 1/d for d > 0 in FP64: hardware reciprocal estimate refined by two Newton
+// steps r <- r + r (1 - d r), each of which roughly doubles the correct bits.
+__device__ inline double rcp_refined(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
+// a / b as a conj(b) / |b|^2 with one refined reciprocal when |b|^2 lies well
+// inside the FP64 range; Smith's algorithm otherwise.
+__device__ inline cf64 cdiv_fast(cf64 a, cf64 b) {
+    const double d2 = fma(b.re, b.re, b.im * b.im);
+    if (d2 >= 0x1p-1000 && d2 <= 0x1p+1000) {
+        const double r = rcp_refined(d2);
+        return {fma(a.re, b.re, a.im * b.im) * r, fma(a.im, b.re, -a.re * b.im) * r};
+    }
+    return cdiv(a, b);
 }
 
 // ------------------------------------------------------------------ Philox
@@ -161,9 +183,10 @@ __device__ inline double wave_incl_scan(double v, int lane) {
 
 // --------------------------------------------------------------- state
 
-// Per-run device state. The sampler of step t reads t, writes cur = t and
-// t = t + 1 (unless it stops); the sweep/update of that step reads cur. No
-// kernel other than the single-workgroup sampler writes the state.
+// Per-run device state. The row sampler of step t reads t, runs the stop
+// test, and records cur = t and the row i; the column sampler records j, the
+// pivot and its reciprocal and sets t = t + 1; the other kernels of the step
+// read cur, i, j. Only the two single-workgroup samplers write the state.
 struct StepState {
     int32_t t;          // pivots taken so far
     int32_t cur;        // step the current sweep/update applies
@@ -175,6 +198,7 @@ struct StepState {
     double T0, T;       // ||A||_F^2 and the latest total
     double a_re, a_im;  // pivot entry
     double inv_re, inv_im;  // 1/a in FP64
+    double row_tgt, row_lo, row_hi;   // row draw: target u1*T and its bin edges
     double gi[8];       // Cauchy: copy of G_i,: (p <= 4 complex)
     double bj[8];       // Cauchy: copy of B_:,j
 };

@@ -10,9 +10,12 @@ namespace rplu {
 
 struct StepState;
 
-// Rows per workgroup of the dense sweep (row masses only / with column masses).
-constexpr int DENSE_ROWS = 8;
+// Rows and threads per workgroup of the dense sweep (row masses only / with
+// column masses, whose per-row-block partials favour taller blocks).
+constexpr int DENSE_ROWS = 4;
+constexpr int DENSE_THREADS = 512;
 constexpr int DENSE_ROWS_COLMASS = 16;
+constexpr int DENSE_THREADS_COLMASS = 256;
 
 struct DenseArgs {
     int dtype;
@@ -26,6 +29,7 @@ struct DenseArgs {
     int32_t* piv;
     StepState* st;
     double* rowmass;     // n
+    double* ct_col;      // chunk totals of the pivot row's masses
     double* colpart;     // ceil(n / DENSE_ROWS_COLMASS) * m, when colmass
     bool colmass;
     bool vec_ok;         // 16-byte packs are aligned for S and U
@@ -38,9 +42,35 @@ struct DenseArgs {
     double tol2;
 };
 
+// Pivot sampling (sample.hip), shared by both forms.
+struct SampleArgs {
+    int dtype;           // element type of U
+    int p;               // 0: dense; >= 1: Cauchy-like displacement rank
+    int64_t n, m;
+    const double* rowmass;
+    double* ct_row;      // chunk totals of the row masses
+    double* ct_col;      // chunk totals of the pivot row's masses
+    StepState* st;
+    int32_t* piv;
+    void* U;
+    int64_t ldu;
+    const void* G;       // Cauchy: generators (copies of G_i,: and B_:,j)
+    const void* B;
+    uint64_t seed, stream;
+    int64_t kmax;
+    double tol2;
+    const int32_t* forced;
+    double* trace;
+    double* rowmass_out;
+};
+
 void launch_state_init(StepState* st, hipStream_t s);
+void launch_ct_vec(const double* v, int64_t len, double* ct, StepState* st, hipStream_t s);
+void launch_sample_row(const SampleArgs& a, hipStream_t s);
+void launch_sample_col(const SampleArgs& a, hipStream_t s);
+
 void launch_dense_sweep(const DenseArgs& a, bool init, hipStream_t s);
-void launch_dense_sample(const DenseArgs& a, hipStream_t s);
+void launch_dense_rowchunks(const DenseArgs& a, hipStream_t s);
 void launch_colmass_reduce(const DenseArgs& a, bool after_step, hipStream_t s);
 int dense_row_block(bool colmass);
 
@@ -59,8 +89,8 @@ struct CauchyArgs {
     StepState* st;
     double* partial;     // splits * n
     int splits;
-    double* rowmass;     // n (reduced masses, written by the sampler)
-    double* rowmass_out;
+    double* rowmass;     // n (reduced masses)
+    double* ct_col;      // chunk totals of the regenerated pivot row
     double* trace;
     const int32_t* forced;
     uint64_t seed, stream;
@@ -69,7 +99,8 @@ struct CauchyArgs {
 };
 
 void launch_cauchy_mass(const CauchyArgs& a, hipStream_t s);
-void launch_cauchy_sample(const CauchyArgs& a, hipStream_t s);
+void launch_cauchy_reduce(const CauchyArgs& a, hipStream_t s);
+void launch_cauchy_rowgen(const CauchyArgs& a, hipStream_t s);
 void launch_cauchy_update(const CauchyArgs& a, hipStream_t s);
 int cauchy_rows_per_block();
 
