@@ -43,7 +43,12 @@
  *     t == kmax -> RANK (TOL_UNREACHED if rel_tol > 0), where
  *     kmax = min(n, m) if max_rank == 0, else min(max_rank, n, m).
  *   - Calls that take a hip_stream (a hipStream_t; NULL = default stream)
- *     enqueue on it and synchronise with it once at the end to fill info.
+ *     enqueue on it and synchronise with it once per chunk of steps (to stop
+ *     early) and at the end (to fill info). By default the step loop is
+ *     captured once into hipGraphs (a chunk of steps and the remainder) on a
+ *     context-owned stream and replayed on hip_stream; the instantiated
+ *     graphs are cached in the context and reused by calls with the same
+ *     buffers, sizes and options.
  *   - Errors return a negative rplu_status; rplu_last_error() gives a
  *     thread-local message. No call aborts or throws across the ABI.
  */
@@ -87,8 +92,9 @@ enum {
 
 enum {
     RPLU_FLAG_COLMASS = 1u << 0,  /* also reduce column masses in each sweep  */
-    RPLU_FLAG_GRAPH = 1u << 1,    /* replay the step loop as a hipGraph        */
-    RPLU_FLAG_NO_GRAPH = 1u << 2  /* never use a hipGraph (plain launches)     */
+    RPLU_FLAG_GRAPH = 1u << 1,    /* replay the step loop as a hipGraph (the
+                                     default; accepted for clarity)            */
+    RPLU_FLAG_NO_GRAPH = 1u << 2  /* plain kernel launches, no hipGraph        */
 };
 
 /* Per-step trace words (opts.trace, RPLU_TRACE_WORDS doubles per step t):
@@ -239,7 +245,8 @@ rplu_status rplu_server_destroy(rplu_server srv);
 
 /* Device time per kernel class, measured with HIP events recorded on the
  * caller's stream around every launch between rplu_profile_begin and
- * rplu_profile_end (plain launches only; graph replays are not timed).
+ * rplu_profile_end. While profiling is on, runs use plain launches (events
+ * time individual kernels; a replayed graph cannot be timed per kernel).
  * Class 0: the hot kernel (dense sweep / Cauchy all-pairs mass), 1: the
  * samplers, 2: updates and reductions, 3: initial mass pass. */
 #define RPLU_PROFILE_CLASSES 4

@@ -62,6 +62,7 @@ rplu_status ws_reserve(rplu_ctx_s* ctx, size_t bytes, hipStream_t s) {
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
         e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        graph_cache_clear(ctx);           // captured graphs point into the old workspace
         (void)hipFree(ctx->ws);
         ctx->ws = nullptr;
         ctx->ws_cap = 0;
@@ -112,44 +113,112 @@ static rplu_status finish(const StepState& hs, rplu_info* info) {
     }
 }
 
-// Runs `steps_total` steps of `enqueue_step` in chunks, optionally as a graph.
+static void destroy_entry(rplu_graph_entry& g) {
+    if (g.main) (void)hipGraphExecDestroy(g.main);
+    if (g.rest) (void)hipGraphExecDestroy(g.rest);
+    g = rplu_graph_entry{};
+}
+
+void graph_cache_clear(rplu_ctx_s* ctx) {
+    for (rplu_graph_entry& g : ctx->graphs) destroy_entry(g);
+}
+
+template <class F>
+static rplu_status capture(rplu_ctx_s* ctx, int64_t steps, F& enqueue_step, hipGraphExec_t* out) {
+    hipStream_t cs = ctx->cap_stream;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    for (int64_t q = 0; q < steps; ++q) enqueue_step(cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) { *out = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
+    return RPLU_OK;
+}
+
+// Runs `steps_total` steps of `enqueue_step(stream)`.
+//
+// Graph path (default): the loop is captured once as a chunk of CH steps and
+// a tail of the remaining steps, on the context's capture stream, and the
+// instantiated graphs are replayed on the caller's stream; `key` identifies
+// the launch arguments, so repeated calls on the same buffers reuse them.
+// Plain path (RPLU_FLAG_NO_GRAPH, or while profiling, whose events time
+// individual launches): the same launches issued directly. Either way the host reads
+// the device `done` word after each chunk and stops early once the stop test
+// has fired; the kernels left in a chunk return at once.
 template <class F>
 static rplu_status run_loop(rplu_ctx_s* ctx, StepState* st, int64_t steps_total, bool use_graph,
-                            hipStream_t s, F&& enqueue_step) {
+                            uint64_t key, hipStream_t s, F&& enqueue_step) {
+    if (steps_total <= 0) return RPLU_OK;
     const int64_t CH = steps_total <= 64 ? steps_total : 32;
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
-    if (use_graph && s != nullptr && CH > 0) {
-        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        for (int64_t q = 0; q < CH; ++q) enqueue_step();
-        e = hipStreamEndCapture(s, &graph);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) { (void)hipGraphDestroy(graph); return hip_fail(e, "hipGraphInstantiate"); }
-    }
-    rplu_status rc = RPLU_OK;
-    for (int64_t done_steps = 0; done_steps < steps_total; done_steps += CH) {
-        if (exec) {
-            hipError_t e = hipGraphLaunch(exec, s);
-            if (e != hipSuccess) { rc = hip_fail(e, "hipGraphLaunch"); break; }
-        } else {
-            const int64_t todo = std::min(CH, steps_total - done_steps);
-            for (int64_t q = 0; q < todo; ++q) enqueue_step();
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) { rc = hip_fail(e, "kernel launch"); break; }
-        }
-        if (done_steps + CH >= steps_total) break;
+    auto done_after_sync = [&](bool& done) -> rplu_status {
         hipError_t e = hipMemcpyAsync(&ctx->host_state->done, &st->done, sizeof(int32_t),
                                       hipMemcpyDeviceToHost, s);
-        if (e != hipSuccess) { rc = hip_fail(e, "hipMemcpyAsync(done)"); break; }
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(done)");
         e = hipStreamSynchronize(s);
-        if (e != hipSuccess) { rc = hip_fail(e, "hipStreamSynchronize"); break; }
-        if (ctx->host_state->done) break;
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        done = ctx->host_state->done != 0;
+        return RPLU_OK;
+    };
+
+    rplu_graph_entry* g = nullptr;
+    if (use_graph && !ctx->prof_on && ctx->cap_stream != nullptr) {
+        key = fnv1a(&steps_total, sizeof steps_total, key);
+        for (rplu_graph_entry& c : ctx->graphs)
+            if (c.valid && c.key == key) g = &c;
+        if (g == nullptr) {
+            rplu_graph_entry* victim = &ctx->graphs[0];
+            for (rplu_graph_entry& c : ctx->graphs)
+                if (!c.valid || c.last_use < victim->last_use) victim = &c;
+            destroy_entry(*victim);
+            victim->ch = CH;
+            victim->reps = steps_total / CH;
+            victim->tail = steps_total - victim->reps * CH;
+            rplu_status rc = capture(ctx, CH, enqueue_step, &victim->main);
+            if (rc == RPLU_OK && victim->tail > 0)
+                rc = capture(ctx, victim->tail, enqueue_step, &victim->rest);
+            if (rc == RPLU_OK) {
+                victim->key = key;
+                victim->valid = true;
+                g = victim;
+            } else {
+                destroy_entry(*victim);    // fall back to plain launches
+            }
+        }
+        if (g != nullptr) g->last_use = ++ctx->use_clock;
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    return rc;
+
+    if (g != nullptr) {
+        for (int64_t r = 0; r < g->reps; ++r) {
+            hipError_t e = hipGraphLaunch(g->main, s);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+            if ((r == g->reps - 1) && g->tail == 0) return RPLU_OK;
+            bool done = false;
+            rplu_status rc = done_after_sync(done);
+            if (rc) return rc;
+            if (done) return RPLU_OK;
+        }
+        if (g->tail > 0) {
+            hipError_t e = hipGraphLaunch(g->rest, s);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        }
+        return RPLU_OK;
+    }
+
+    for (int64_t done_steps = 0; done_steps < steps_total; done_steps += CH) {
+        const int64_t todo = std::min(CH, steps_total - done_steps);
+        for (int64_t q = 0; q < todo; ++q) enqueue_step(s);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        if (done_steps + CH >= steps_total) break;
+        bool done = false;
+        rplu_status rc = done_after_sync(done);
+        if (rc) return rc;
+        if (done) break;
+    }
+    return RPLU_OK;
 }
 
 static int64_t kmax_of(int64_t n, int64_t m, int64_t k) {
@@ -198,6 +267,9 @@ rplu_status rplu_create(int device, rplu_ctx* out) {
     c->cu_count = prop.multiProcessorCount;
     e = hipHostMalloc((void**)&c->host_state, sizeof(StepState), hipHostMallocDefault);
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipHostMalloc"); }
+    // capture only (never executes work); default priority
+    e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) c->cap_stream = nullptr;   // graphs disabled, plain launches
     *out = c;
     return RPLU_OK;
 }
@@ -233,6 +305,8 @@ rplu_status rplu_destroy(rplu_ctx ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (hipEvent_t ev : ctx->ev_pool) (void)hipEventDestroy(ev);
+    graph_cache_clear(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->batch_ws) (void)hipFree(ctx->batch_ws);
     if (ctx->host_state) (void)hipHostFree(ctx->host_state);
@@ -278,7 +352,8 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, voi
     if (rc) return rc;
     char* ws = (char*)ctx->ws;
 
-    DenseArgs a{};
+    DenseArgs a;
+    std::memset(&a, 0, sizeof a);        // padding too: the struct keys the graph cache
     a.dtype = dtype;
     a.n = n;
     a.m = m;
@@ -311,7 +386,8 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, voi
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "initial mass launch");
 
-    SampleArgs sa{};
+    SampleArgs sa;
+    std::memset(&sa, 0, sizeof sa);
     sa.dtype = dtype;
     sa.p = 0;
     sa.n = n;
@@ -331,18 +407,18 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, voi
     sa.trace = opts->trace;
     sa.rowmass_out = opts->rowmass_out;
 
-    const bool graph = (opts->flags & RPLU_FLAG_GRAPH) && !(opts->flags & RPLU_FLAG_NO_GRAPH) &&
-                       !ctx->prof_on;
-    rc = run_loop(ctx, a.st, kmax + 1, graph, s, [&]() {
-        timed(ctx, 1, s, [&] {
-            launch_ct_vec(a.rowmass, n, sa.ct_row, a.st, s);
-            launch_sample_row(sa, s);
-            launch_dense_rowchunks(a, s);
-            launch_sample_col(sa, s);
+    const bool graph = !(opts->flags & RPLU_FLAG_NO_GRAPH);
+    const uint64_t key = fnv1a(&sa, sizeof sa, fnv1a(&a, sizeof a, 0x64656e7365ull));
+    rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
+        timed(ctx, 1, q, [&] {
+            launch_ct_vec(a.rowmass, n, sa.ct_row, a.st, q);
+            launch_sample_row(sa, q);
+            launch_dense_rowchunks(a, q);
+            launch_sample_col(sa, q);
         });
-        timed(ctx, 0, s, [&] { launch_dense_sweep(a, /*init=*/false, s); });
+        timed(ctx, 0, q, [&] { launch_dense_sweep(a, /*init=*/false, q); });
         if (colmass && a.colmass_out)
-            timed(ctx, 2, s, [&] { launch_colmass_reduce(a, true, s); });
+            timed(ctx, 2, q, [&] { launch_colmass_reduce(a, true, q); });
     });
     if (rc) return rc;
     StepState hs;
@@ -376,12 +452,18 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
 
     if (n > RPLU_MAX_DIM || m > RPLU_MAX_DIM)
         return fail(RPLU_E_UNSUPPORTED, "rplu_cauchy: n and m must be <= %d", RPLU_MAX_DIM);
-    CauchyArgs a{};
+    CauchyArgs a;
+    std::memset(&a, 0, sizeof a);        // padding too: the struct keys the graph cache
     const int64_t nbr = (n + cauchy_rows_per_block() - 1) / cauchy_rows_per_block();
     // enough workgroups to fill every CU a few times over
     int64_t splits = (4 * (int64_t)ctx->cu_count + nbr - 1) / nbr;
     splits = std::max<int64_t>(1, std::min<int64_t>(splits, std::max<int64_t>(1, m / 256)));
+    // columns per split: a multiple of the 8-column reciprocal group
+    int64_t cps = (m + splits - 1) / splits;
+    cps = (cps + 7) / 8 * 8;
+    splits = (m + cps - 1) / cps;
     a.splits = (int)splits;
+    a.cols_per_split = (int)cps;
     Carver cv;
     const size_t o_st = cv.take(sizeof(StepState));
     const size_t o_rm = cv.take((size_t)n * 8);
@@ -416,9 +498,8 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     a.tol2 = opts->rel_tol * opts->rel_tol;
 
     launch_state_init(a.st, s);
-    const bool graph = (opts->flags & RPLU_FLAG_GRAPH) && !(opts->flags & RPLU_FLAG_NO_GRAPH) &&
-                       !ctx->prof_on;
-    SampleArgs sa{};
+    SampleArgs sa;
+    std::memset(&sa, 0, sizeof sa);
     sa.dtype = RPLU_C128;
     sa.p = p;
     sa.n = n;
@@ -439,16 +520,18 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     sa.forced = opts->forced;
     sa.trace = opts->trace;
     sa.rowmass_out = opts->rowmass_out;
-    rc = run_loop(ctx, a.st, kmax + 1, graph, s, [&]() {
-        timed(ctx, 0, s, [&] { launch_cauchy_mass(a, s); });
-        timed(ctx, 2, s, [&] { launch_cauchy_reduce(a, s); });
-        timed(ctx, 1, s, [&] {
-            launch_ct_vec(a.rowmass, n, sa.ct_row, a.st, s);
-            launch_sample_row(sa, s);
-            launch_cauchy_rowgen(a, s);
-            launch_sample_col(sa, s);
+    const bool graph = !(opts->flags & RPLU_FLAG_NO_GRAPH);
+    const uint64_t key = fnv1a(&sa, sizeof sa, fnv1a(&a, sizeof a, 0x636175636879ull));
+    rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
+        timed(ctx, 0, q, [&] { launch_cauchy_mass(a, q); });
+        timed(ctx, 2, q, [&] { launch_cauchy_reduce(a, q); });
+        timed(ctx, 1, q, [&] {
+            launch_ct_vec(a.rowmass, n, sa.ct_row, a.st, q);
+            launch_sample_row(sa, q);
+            launch_cauchy_rowgen(a, q);
+            launch_sample_col(sa, q);
         });
-        timed(ctx, 2, s, [&] { launch_cauchy_update(a, s); });
+        timed(ctx, 2, q, [&] { launch_cauchy_update(a, q); });
     });
     if (rc) return rc;
     StepState hs;

@@ -8,7 +8,8 @@
 //                    G_i,: B_:,j, its |.|^2 and one reciprocal. Each thread
 //                    keeps RT target rows (x_i, G_i,:) in registers; the
 //                    workgroup stages tiles of source columns (y_j, B_:,j) in
-//                    LDS and every lane reads them as broadcasts. Columns are
+//                    LDS and every lane reads them as broadcasts; eight
+//                    columns share one reciprocal. Columns are
 //                    split over `splits` workgroup columns; the partial sums
 //                    are added in split order by k_cauchy_reduce
 //                    (deterministic).
@@ -27,10 +28,18 @@
 
 namespace rplu {
 
-constexpr int CM_THREADS = 256;
-constexpr int CM_RT = 4;                       // target rows per thread
+constexpr int CM_THREADS = 512;
+constexpr int CM_RT = 2;                       // target rows per thread
 constexpr int CM_ROWS = CM_THREADS * CM_RT;    // target rows per workgroup
 constexpr int CM_TILE = 256;                   // source columns per LDS tile
+constexpr int CM_GRP = 8;                      // columns sharing one reciprocal
+
+// 1/d for d > 0 to about 2^-48 relative: the hardware estimate (~24 bits)
+// refined by one Newton step. Enough for masses, which only feed the draws.
+__device__ inline double rcp_1nr(double d) {
+    const double r = __builtin_amdgcn_rcp(d);
+    return fma(r, fma(-d, r, 1.0), r);
+}
 
 // |G_i,: B_:,j|^2 for one target row (registers) and one source column (LDS).
 template <int P>
@@ -48,14 +57,32 @@ __device__ inline double gb_mag2(const cf64* g, const cf64 (*sb)[CM_TILE], int e
 }
 
 // Row masses sum_j |G_i,: B_:,j|^2 / |x_i - y_j|^2 (for p = 1 the factor
-// |g_i|^2 is taken out of the sum and |b_j|^2 is staged per column).
+// |g_i|^2 is taken out of the sum and w_j = |b_j|^2 is staged per column).
 //
-// Four columns share one reciprocal: w0/d0 + w1/d1 + w2/d2 + w3/d3 = N / D
-// with D = (d0 d1)(d2 d3) and N = (w0 d1 + w1 d0)(d2 d3) + (w2 d3 + w3 d2)(d0 d1),
-// which takes the per-pair cost from one reciprocal plus its Newton steps to
-// a quarter of that. A group whose D or N leaves [2^-1000, 2^1000] (or is not
-// a number, e.g. when x_i == y_j) is summed term by term instead, so the
-// result is the plain sum for every input.
+// Eight columns share one reciprocal: sum_u w_u / d_u = N / D with
+// D = prod_u d_u and N = sum_u w_u prod_{v != u} d_v, formed as a pairwise
+// tree (N01 = w0 d1 + w1 d0, D01 = d0 d1, and so on up the tree). This takes
+// the per-pair cost from one reciprocal and its Newton step to an eighth of
+// that. A tile is first summed this way while recording, without branching,
+// whether any group had D outside [2^-1000, 2^1000] or a non-finite N
+// (extreme magnitudes, or x_i == y_j); only then is that thread's tile sum
+// for the row recomputed term by term, so the result is the plain sum for
+// every input.
+template <int P>
+__device__ inline void mass_tile_exact(double& acc_t, double xr, double xi, const cf64* sy,
+                                       const double* sw, const cf64* g, const cf64 (*sb)[CM_TILE],
+                                       int nt) {
+    double s = 0.0;
+    for (int e = 0; e < nt; ++e) {
+        double w;
+        if constexpr (P == 1) w = sw[e];
+        else w = gb_mag2<P>(g, sb, e);
+        const double a = xr - sy[e].re, b = xi - sy[e].im;
+        s = fma(w, rcp_refined(fma(a, a, b * b)), s);
+    }
+    acc_t = s;
+}
+
 template <int P>
 __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass(
     const cf64* __restrict__ x, const cf64* __restrict__ y, const cf64* __restrict__ G,
@@ -103,65 +130,50 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass(
             }
         }
         __syncthreads();
-        const int n4 = nt & ~3;
-        for (int e = 0; e < n4; e += 4) {
-            const cf64 y0 = sy[e], y1 = sy[e + 1], y2 = sy[e + 2], y3 = sy[e + 3];
-            double w[CM_RT][4];
-            if constexpr (P == 1) {
+        double acc_t[CM_RT];
+        bool ok[CM_RT];
 #pragma unroll
-                for (int q = 0; q < CM_RT; ++q) {
-                    w[q][0] = sw[e]; w[q][1] = sw[e + 1]; w[q][2] = sw[e + 2]; w[q][3] = sw[e + 3];
-                }
-            } else {
+        for (int q = 0; q < CM_RT; ++q) { acc_t[q] = 0.0; ok[q] = true; }
+        const int ng = nt / CM_GRP * CM_GRP;
+        for (int e = 0; e < ng; e += CM_GRP) {
+            cf64 yy[CM_GRP];
 #pragma unroll
-                for (int q = 0; q < CM_RT; ++q)
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) w[q][u] = gb_mag2<P>(g[q], sb, e + u);
-            }
-            double Dq[CM_RT], Nq[CM_RT];
-            bool ok = true;
+            for (int u = 0; u < CM_GRP; ++u) yy[u] = sy[e + u];
 #pragma unroll
             for (int q = 0; q < CM_RT; ++q) {
-                double a, b;
-                a = xr[q] - y0.re; b = xi[q] - y0.im; const double d0 = fma(a, a, b * b);
-                a = xr[q] - y1.re; b = xi[q] - y1.im; const double d1 = fma(a, a, b * b);
-                a = xr[q] - y2.re; b = xi[q] - y2.im; const double d2 = fma(a, a, b * b);
-                a = xr[q] - y3.re; b = xi[q] - y3.im; const double d3 = fma(a, a, b * b);
-                const double d01 = d0 * d1, d23 = d2 * d3;
-                Dq[q] = d01 * d23;
-                const double n01 = fma(w[q][0], d1, w[q][1] * d0);
-                const double n23 = fma(w[q][2], d3, w[q][3] * d2);
-                Nq[q] = fma(n01, d23, n23 * d01);
-                ok = ok && (Dq[q] >= 0x1p-1000) && (Dq[q] <= 0x1p+1000) && (fabs(Nq[q]) <= 0x1p+1000);
-            }
-            if (__builtin_expect(ok, 1)) {
+                double d[CM_GRP], w[CM_GRP];
 #pragma unroll
-                for (int q = 0; q < CM_RT; ++q) acc[q] = fma(Nq[q], rcp_refined(Dq[q]), acc[q]);
-            } else {
-                // term by term (extreme magnitudes or x_i == y_j)
-                const cf64 yy[4] = {y0, y1, y2, y3};
-#pragma unroll
-                for (int q = 0; q < CM_RT; ++q) {
-                    double s4 = 0.0;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const double a = xr[q] - yy[u].re, b = xi[q] - yy[u].im;
-                        s4 = fma(w[q][u], rcp_refined(fma(a, a, b * b)), s4);
-                    }
-                    acc[q] += s4;
+                for (int u = 0; u < CM_GRP; ++u) {
+                    const double a = xr[q] - yy[u].re, b = xi[q] - yy[u].im;
+                    d[u] = fma(a, a, b * b);
+                    if constexpr (P == 1) w[u] = sw[e + u];
+                    else w[u] = gb_mag2<P>(g[q], sb, e + u);
                 }
+                const double d01 = d[0] * d[1], d23 = d[2] * d[3];
+                const double d45 = d[4] * d[5], d67 = d[6] * d[7];
+                const double D03 = d01 * d23, D47 = d45 * d67;
+                const double D = D03 * D47;
+                const double N03 = fma(fma(w[0], d[1], w[1] * d[0]), d23,
+                                       fma(w[2], d[3], w[3] * d[2]) * d01);
+                const double N47 = fma(fma(w[4], d[5], w[5] * d[4]), d67,
+                                       fma(w[6], d[7], w[7] * d[6]) * d45);
+                const double N = fma(N03, D47, N47 * D03);
+                ok[q] = ok[q] & (D >= 0x1p-1000) & (D <= 0x1p+1000) & (fabs(N) <= 0x1p+1000);
+                acc_t[q] = fma(N, rcp_1nr(D), acc_t[q]);
             }
         }
-        for (int e = n4; e < nt; ++e) {
-            const cf64 yv = sy[e];
 #pragma unroll
-            for (int q = 0; q < CM_RT; ++q) {
+        for (int q = 0; q < CM_RT; ++q) {
+            if (__builtin_expect(!ok[q], 0))      // rare: recompute this tile term by term
+                mass_tile_exact<P>(acc_t[q], xr[q], xi[q], sy, sw, g[q], sb, ng);
+            for (int e = ng; e < nt; ++e) {       // ragged tail of the tile
                 double w;
                 if constexpr (P == 1) w = sw[e];
                 else w = gb_mag2<P>(g[q], sb, e);
-                const double a = xr[q] - yv.re, b = xi[q] - yv.im;
-                acc[q] = fma(w, rcp_refined(fma(a, a, b * b)), acc[q]);
+                const double a = xr[q] - sy[e].re, b = xi[q] - sy[e].im;
+                acc_t[q] = fma(w, rcp_refined(fma(a, a, b * b)), acc_t[q]);
             }
+            acc[q] += acc_t[q];
         }
     }
 #pragma unroll
@@ -268,7 +280,7 @@ int cauchy_rows_per_block() { return CM_ROWS; }
 
 template <int P>
 static void mass_p(const CauchyArgs& a, hipStream_t s) {
-    const int cps = (int)((a.m + a.splits - 1) / a.splits);
+    const int cps = a.cols_per_split;
     dim3 grid((unsigned)((a.n + CM_ROWS - 1) / CM_ROWS), (unsigned)a.splits);
     hipLaunchKernelGGL(k_cauchy_mass<P>, grid, dim3(CM_THREADS), 0, s, (const cf64*)a.x,
                        (const cf64*)a.y, (const cf64*)a.G, (const cf64*)a.B, (int)a.n, (int)a.m,

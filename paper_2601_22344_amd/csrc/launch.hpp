@@ -89,6 +89,7 @@ struct CauchyArgs {
     StepState* st;
     double* partial;     // splits * n
     int splits;
+    int cols_per_split;  // columns of y per workgroup column of the mass kernel
     double* rowmass;     // n (reduced masses)
     double* ct_col;      // chunk totals of the regenerated pivot row
     double* trace;

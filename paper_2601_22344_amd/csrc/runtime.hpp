@@ -3,6 +3,9 @@
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
 
 #include "rplu.h"
 
@@ -10,12 +13,23 @@ namespace rplu {
 struct StepState;
 }
 
-#include <vector>
-
 struct rplu_prof_rec {
     int cls;
     hipEvent_t a, b;
 };
+
+// An instantiated step-loop graph: a chunk of `ch` steps replayed `reps`
+// times, then a tail graph of the remaining steps. `key` fingerprints every
+// launch argument, so a call with the same buffers and sizes reuses it.
+struct rplu_graph_entry {
+    uint64_t key = 0;
+    bool valid = false;
+    uint64_t last_use = 0;
+    int64_t ch = 0, reps = 0, tail = 0;
+    hipGraphExec_t main = nullptr, rest = nullptr;
+};
+
+constexpr int RPLU_GRAPH_CACHE = 6;
 
 struct rplu_ctx_s {
     int device = 0;
@@ -25,10 +39,14 @@ struct rplu_ctx_s {
     void* batch_ws = nullptr;       // batched-launch descriptors and queue
     size_t batch_ws_cap = 0;
     rplu::StepState* host_state = nullptr;   // pinned staging for state read-back
+    hipStream_t cap_stream = nullptr;        // stream the step loop is captured on
+    // profiling
     bool prof_on = false;                    // record events around launches
-    std::vector<hipEvent_t> ev_pool;         // reusable events
+    std::vector<hipEvent_t> ev_pool;         // reusable events (plain launches)
     size_t ev_used = 0;
-    std::vector<rplu_prof_rec> prof;
+    std::vector<rplu_prof_rec> prof;         // pending event records
+    rplu_graph_entry graphs[RPLU_GRAPH_CACHE];
+    uint64_t use_clock = 0;
 };
 
 namespace rplu {
@@ -36,9 +54,11 @@ rplu_status fail(rplu_status code, const char* fmt, ...);
 rplu_status hip_fail(hipError_t e, const char* what);
 size_t dtype_size(int dt);
 rplu_status ws_reserve(rplu_ctx_s* ctx, size_t bytes, hipStream_t s);
+void graph_cache_clear(rplu_ctx_s* ctx);
 
-// Enqueues `launch` on stream s; while profiling is on, brackets it with two
-// events and remembers them under class `cls`.
+// Enqueues `launch` on stream s; while profiling is on (which also selects
+// plain launches over graph replay), brackets it with two events and
+// remembers them under class `cls`.
 template <class F>
 inline void timed(rplu_ctx_s* ctx, int cls, hipStream_t s, F&& launch) {
     if (!ctx->prof_on) { launch(); return; }
@@ -52,5 +72,12 @@ inline void timed(rplu_ctx_s* ctx, int cls, hipStream_t s, F&& launch) {
     launch();
     (void)hipEventRecord(b, s);
     ctx->prof.push_back({cls, a, b});
+}
+
+// FNV-1a over raw bytes, for graph cache keys.
+inline uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+    return h;
 }
 }  // namespace rplu

@@ -127,3 +127,19 @@ def test_config2_full_size(rplu_lib):
     logdet -= np.sum(np.log(np.abs(xi[:, None] - yj[None, :])))
     logprod = np.sum(np.log(np.abs(res.trace[:, 8].cpu().numpy() + 1j * res.trace[:, 9].cpu().numpy())))
     assert abs(logprod - logdet) <= 1e-9 * abs(logdet)
+
+
+def test_cauchy_graph_matches_plain(rplu_lib):
+    """The default step-loop graph (fresh and cached) and plain launches give
+    bitwise identical pivots, factors and generators."""
+    x, y, G, B = W.cauchy_like_random(900, 1300, 2, seed=9)
+    xd, yd = _dev(x, y)
+    outs = []
+    for flags in (rplu_lib.RPLU_FLAG_NO_GRAPH, 0, 0):
+        Gd, Bd = _dev(G, B)
+        r = rplu_lib.rplu_cauchy(xd, yd, Gd, Bd, k=40, seed=3, flags=flags)
+        torch.cuda.synchronize()
+        outs.append((r.piv.cpu(), r.L.cpu(), r.U.cpu(), Gd.cpu(), Bd.cpu()))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert torch.equal(a, b)

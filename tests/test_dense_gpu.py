@@ -177,14 +177,19 @@ def test_column_masses(rplu_lib):
 
 
 def test_deterministic_and_graph(rplu_lib):
-    """Two runs, and a run replayed as a hipGraph, are bitwise identical."""
+    """Plain launches, a freshly captured step-loop graph and replays of the
+    cached graph (same buffers, input restored in between, eager work and a
+    synchronisation between calls) give bitwise identical results."""
     A = W.random_dense(257, 1100, seed=21).astype(np.float32)
+    Ad = torch.empty((257, 1100), dtype=torch.float32, device=DEV)
     outs = []
-    for flags in (0, 0, rplu_lib.RPLU_FLAG_GRAPH):
-        Ad = torch.from_numpy(A).to(DEV)
+    for flags in (rplu_lib.RPLU_FLAG_NO_GRAPH, 0, 0, 0):
+        Ad.copy_(torch.from_numpy(A))
+        junk = torch.randn(1000, device=DEV).sum()          # eager work between replays
         r = rplu_lib.rplu_dense(Ad, k=70, seed=5, flags=flags)
         torch.cuda.synchronize()
         outs.append((r.piv.cpu(), r.L.cpu(), r.U.cpu(), Ad.cpu()))
+        del junk
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert torch.equal(a, b)
