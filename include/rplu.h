@@ -131,7 +131,8 @@ typedef struct {
 typedef struct {
     int64_t rank;           /* pivots taken                                     */
     int32_t stop;           /* RPLU_STOP_*                                      */
-    int32_t reserved;
+    int32_t status;         /* this run's rplu_status: RPLU_OK or an RPLU_E_*
+                               code (per instance for rplu_batched)            */
     double a_fro2;          /* ||A||_F^2 as reduced on the device               */
     double res_fro2;        /* ||S^(rank)||_F^2 at the final stop test          */
 } rplu_info;
@@ -196,15 +197,52 @@ typedef struct {
     uint64_t stream;
 } rplu_job;
 
+/* Batched launch configuration. None of these fields changes the arithmetic:
+ * an instance's reduction order depends only on its shape, so every
+ * configuration returns bitwise the same results.
+ *   rows_per_pass  rows a lane group of the workgroup sweeps at once: 1, 2, 4, 8
+ *   wg_per_cu      resident workgroups per compute unit (grid = CUs x this,
+ *                  at most the number of jobs), 1..8 within occupancy
+ *   order          queue order: RPLU_ORDER_AREA (n*m descending, the default),
+ *                  RPLU_ORDER_CUBE (n*m*kmax descending), RPLU_ORDER_GIVEN
+ * A field left 0 takes the tuned (or default) value. */
+enum { RPLU_ORDER_AREA = 1, RPLU_ORDER_CUBE = 2, RPLU_ORDER_GIVEN = 3 };
+typedef struct {
+    int32_t rows_per_pass;
+    int32_t wg_per_cu;
+    int32_t order;
+    int32_t reserved;
+} rplu_batch_cfg;
+
 /* Runs `count` dense jobs (host array `jobs`) in ONE persistent launch: every
  * workgroup takes instances from a device work queue (largest estimated cost
- * first) and runs each instance's whole step loop. R32 and R64 instances with
- * n, m <= 4096 are supported; all jobs must share one dtype. Results are the
- * same as running rplu_dense on each job alone (pivots identical, factors
- * bitwise equal, because an instance's reduction order depends only on its
- * shape). infos_host: count entries, filled at the end. */
+ * first) and runs each instance's whole step loop with workgroup barriers
+ * (Alg. 1 with two-stage sampling, Sec. 4.1). R32 or R64 jobs only, all of
+ * one dtype, 1 <= n, m <= 8192, and n * (8 + element size) bytes of LDS
+ * per workgroup; piv is required, L and U may be NULL; max_rank, rel_tol,
+ * seed and stream are per job. Results are bitwise those of rplu_dense on each
+ * job alone. infos_host: count entries, each with its own status; the call
+ * returns RPLU_OK, or the status of the first failing job (by index).
+ *
+ * rplu_batched picks the configuration from the context's tuning table,
+ * keyed by (dtype, count, largest n and m, mean n*m) rounded to powers of
+ * two; on the first call with a new key it runs rplu_batched_tune first.
+ * Tuning runs candidate configurations on device copies of the inputs (every
+ * job, or a cost-stratified subset when the copies would exceed 8 GiB or a
+ * quarter of free device memory), so the caller's buffers are untouched
+ * until the real run. */
 rplu_status rplu_batched(rplu_ctx ctx, int64_t count, const rplu_job* jobs,
                          rplu_info* infos_host, void* hip_stream);
+/* Same with an explicit configuration (NULL = as rplu_batched). */
+rplu_status rplu_batched_ex(rplu_ctx ctx, int64_t count, const rplu_job* jobs,
+                            rplu_info* infos_host, const rplu_batch_cfg* cfg,
+                            void* hip_stream);
+/* Autotuner: times the candidate configurations on copies of the jobs (inputs
+ * are not modified), stores the fastest in the context's table and returns it
+ * in best_out; best_ms_out (may be NULL) gets its device time. */
+rplu_status rplu_batched_tune(rplu_ctx ctx, int64_t count, const rplu_job* jobs,
+                              rplu_batch_cfg* best_out, double* best_ms_out,
+                              void* hip_stream);
 
 /* ------------------------------------------------------------- server */
 

@@ -32,6 +32,7 @@ RPLU_STOP_RANK, RPLU_STOP_TOL, RPLU_STOP_EXHAUSTED, RPLU_STOP_TOL_UNREACHED = 1,
 RPLU_FLAG_COLMASS, RPLU_FLAG_GRAPH, RPLU_FLAG_NO_GRAPH = 1, 2, 4
 RPLU_TRACE_WORDS = 12
 RPLU_JOB_DENSE, RPLU_JOB_CAUCHY = 1, 2
+RPLU_ORDER_AREA, RPLU_ORDER_CUBE, RPLU_ORDER_GIVEN = 1, 2, 3
 
 _DTYPES = {torch.float32: RPLU_R32, torch.float64: RPLU_R64,
            torch.complex64: RPLU_C64, torch.complex128: RPLU_C128}
@@ -45,7 +46,7 @@ class rplu_opts(C.Structure):
 
 
 class rplu_info(C.Structure):
-    _fields_ = [("rank", C.c_int64), ("stop", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("rank", C.c_int64), ("stop", C.c_int32), ("status", C.c_int32),
                 ("a_fro2", C.c_double), ("res_fro2", C.c_double)]
 
 
@@ -56,6 +57,11 @@ class rplu_job(C.Structure):
                 ("piv", C.c_void_p), ("L", C.c_void_p), ("ldl", C.c_int64), ("U", C.c_void_p),
                 ("ldu", C.c_int64), ("max_rank", C.c_int64), ("rel_tol", C.c_double),
                 ("seed", C.c_uint64), ("stream", C.c_uint64)]
+
+
+class rplu_batch_cfg(C.Structure):
+    _fields_ = [("rows_per_pass", C.c_int32), ("wg_per_cu", C.c_int32), ("order", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class rplu_server_cfg(C.Structure):
@@ -85,6 +91,10 @@ lib.rplu_dense.argtypes = [_P, C.c_int, _I64, _I64, _P, _I64, C.POINTER(rplu_opt
 lib.rplu_cauchy.argtypes = [_P, C.c_int, _I64, _I64, C.c_int32, _P, _P, _P, _P,
                             C.POINTER(rplu_opts), _P, _P, _I64, _P, _I64, C.POINTER(rplu_info), _P]
 lib.rplu_batched.argtypes = [_P, _I64, C.POINTER(rplu_job), C.POINTER(rplu_info), _P]
+lib.rplu_batched_ex.argtypes = [_P, _I64, C.POINTER(rplu_job), C.POINTER(rplu_info),
+                                C.POINTER(rplu_batch_cfg), _P]
+lib.rplu_batched_tune.argtypes = [_P, _I64, C.POINTER(rplu_job), C.POINTER(rplu_batch_cfg),
+                                  C.POINTER(C.c_double), _P]
 lib.rplu_server_create.argtypes = [_P, C.POINTER(rplu_server_cfg), C.POINTER(_P)]
 lib.rplu_server_submit.argtypes = [_P, C.POINTER(rplu_job), C.POINTER(C.c_uint64)]
 lib.rplu_server_poll.argtypes = [_P, C.c_uint64, C.POINTER(rplu_info)]
@@ -96,6 +106,7 @@ lib.rplu_status_str.argtypes = [C.c_int32]
 lib.rplu_status_str.restype = C.c_char_p
 lib.rplu_last_error.restype = C.c_char_p
 for _fn in ("rplu_create", "rplu_destroy", "rplu_dense", "rplu_cauchy", "rplu_batched",
+            "rplu_batched_ex", "rplu_batched_tune",
             "rplu_server_create", "rplu_server_submit", "rplu_server_poll",
             "rplu_server_stats", "rplu_server_destroy", "rplu_profile_begin", "rplu_profile_end"):
     getattr(lib, _fn).restype = C.c_int32
@@ -169,6 +180,7 @@ class Result:
     trace: Optional[torch.Tensor] = None      # rank x 12 float64
     rowmass: Optional[torch.Tensor] = None    # rank x n float64
     colmass: Optional[torch.Tensor] = None    # rank x m float64
+    status: int = 0                           # RPLU_OK or the job's RPLU_E_* code
 
 
 def _opts(k, tol, seed, stream, flags, forced, trace, rowmass_out, colmass_out):
@@ -259,3 +271,88 @@ def rplu_profile_end(ctx: Context) -> dict:
     out = rplu_profile()
     _check(lib.rplu_profile_end(ctx.handle, C.byref(out)), "rplu_profile_end")
     return {"launches": list(out.launches), "ms": list(out.ms)}
+
+
+def _per_job(v, count, name):
+    if isinstance(v, (list, tuple)):
+        if len(v) != count:
+            raise ValueError(f"{name}: expected {count} values")
+        return list(v)
+    return [v] * count
+
+
+def _batch_jobs(As, k, tol, seed, streams, store_L, store_U, kind_check=True):
+    count = len(As)
+    ks, tols, seeds = _per_job(k, count, "k"), _per_job(tol, count, "tol"), _per_job(seed, count, "seed")
+    streams = list(range(count)) if streams is None else _per_job(streams, count, "streams")
+    jobs = (rplu_job * max(count, 1))()
+    outs = []
+    for b, A in enumerate(As):
+        if A.dim() != 2 or A.stride(1) != 1 or A.dtype not in (torch.float32, torch.float64) \
+                or not A.is_cuda:
+            raise ValueError("batched jobs: 2-D float32/float64 CUDA tensors, unit column stride")
+        n, m = A.shape
+        kk = int(ks[b])
+        kmax = min(n, m) if kk <= 0 else min(kk, n, m)
+        piv = torch.empty((kmax, 2), dtype=torch.int32, device=A.device)
+        Lt = torch.empty((kmax, n), dtype=A.dtype, device=A.device) if store_L else None
+        U = torch.empty((kmax, m), dtype=A.dtype, device=A.device) if store_U else None
+        j = jobs[b]
+        j.kind, j.dtype, j.n, j.m = RPLU_JOB_DENSE, _DTYPES[A.dtype], n, m
+        j.A, j.lda = A.data_ptr(), A.stride(0)
+        j.piv = piv.data_ptr()
+        j.L, j.ldl = (Lt.data_ptr(), n) if Lt is not None else (None, 0)
+        j.U, j.ldu = (U.data_ptr(), m) if U is not None else (None, 0)
+        j.max_rank, j.rel_tol = kk, float(tols[b])
+        j.seed, j.stream = int(seeds[b]) & (2**64 - 1), int(streams[b]) & (2**64 - 1)
+        outs.append((piv, Lt, U))
+    return jobs, outs
+
+
+def rplu_batched(As, k=0, tol=0.0, seed=0, streams=None, store_L: bool = True,
+                 store_U: bool = True, cfg: Optional[dict] = None, raise_on_error: bool = True,
+                 ctx: Optional[Context] = None) -> list:
+    """Dense RPLU of every matrix in As (float32 or float64 CUDA tensors, one
+    dtype; each overwritten by its final Schur complement) in one persistent
+    launch. k, tol, seed may be scalars or per-job lists; streams defaults to
+    the job index. cfg: {'rows_per_pass', 'wg_per_cu', 'order'} (missing or 0
+    = tuned). Returns one Result per job."""
+    count = len(As)
+    if count == 0:
+        return []
+    dev = As[0].device
+    ctx = ctx or default_context(dev.index or 0)
+    jobs, outs = _batch_jobs(As, k, tol, seed, streams, store_L, store_U)
+    infos = (rplu_info * count)()
+    c = None
+    if cfg is not None:
+        c = rplu_batch_cfg(int(cfg.get("rows_per_pass", 0)), int(cfg.get("wg_per_cu", 0)),
+                           int(cfg.get("order", 0)), 0)
+    st = lib.rplu_batched_ex(ctx.handle, count, jobs, infos, C.byref(c) if c is not None else None,
+                             _cur_stream(dev))
+    if st < 0 and (raise_on_error or all(infos[b].status == 0 for b in range(count))):
+        raise RPLUError(st, "rplu_batched")
+    res = []
+    for b in range(count):
+        piv, Lt, U = outs[b]
+        r = int(infos[b].rank)
+        res.append(Result(piv[:r], Lt[:r].T if Lt is not None else None,
+                          U[:r] if U is not None else None, r, int(infos[b].stop),
+                          float(infos[b].a_fro2), float(infos[b].res_fro2),
+                          status=int(infos[b].status)))
+    return res
+
+
+def rplu_batched_tune(As, k=0, tol=0.0, seed=0, streams=None, store_L: bool = True,
+                      store_U: bool = True, ctx: Optional[Context] = None):
+    """Runs the autotuner on copies of As (not modified); returns (cfg, ms)."""
+    count = len(As)
+    dev = As[0].device
+    ctx = ctx or default_context(dev.index or 0)
+    jobs, _ = _batch_jobs(As, k, tol, seed, streams, store_L, store_U)
+    best = rplu_batch_cfg()
+    ms = C.c_double()
+    _check(lib.rplu_batched_tune(ctx.handle, count, jobs, C.byref(best), C.byref(ms),
+                                 _cur_stream(dev)), "rplu_batched_tune")
+    return ({"rows_per_pass": best.rows_per_pass, "wg_per_cu": best.wg_per_cu,
+             "order": best.order}, float(ms.value))

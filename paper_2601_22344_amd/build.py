@@ -19,7 +19,8 @@ OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "sample.hip", "dense.hip", "cauchy.hip", "stubs.cpp"]
+SOURCES = ["api.hip", "sample.hip", "dense.hip", "cauchy.hip", "batched.hip", "batch_api.cpp",
+           "stubs.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"-I{INCLUDE}", f"-I{CSRC}"]

@@ -101,7 +101,7 @@ static rplu_status read_state(rplu_ctx_s* ctx, const StepState* st, hipStream_t 
 static rplu_status finish(const StepState& hs, rplu_info* info) {
     info->rank = hs.t;
     info->stop = hs.stop;
-    info->reserved = 0;
+    info->status = hs.error;
     info->a_fro2 = hs.T0;
     info->res_fro2 = hs.T;
     switch (hs.error) {
@@ -265,6 +265,7 @@ rplu_status rplu_create(int device, rplu_ctx* out) {
     e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDeviceProperties"); }
     c->cu_count = prop.multiProcessorCount;
+    c->lds_per_block = prop.sharedMemPerBlock;
     e = hipHostMalloc((void**)&c->host_state, sizeof(StepState), hipHostMallocDefault);
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipHostMalloc"); }
     // capture only (never executes work); default priority

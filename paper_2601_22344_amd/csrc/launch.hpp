@@ -105,4 +105,43 @@ void launch_cauchy_rowgen(const CauchyArgs& a, hipStream_t s);
 void launch_cauchy_update(const CauchyArgs& a, hipStream_t s);
 int cauchy_rows_per_block();
 
+// Batched dense instances (batched.hip): one workgroup runs a whole instance.
+constexpr int RPLU_BATCH_MAX_DIM = 8192;
+
+struct BatchJob {
+    void* A;             // n x m row-major, lda
+    void* L;             // n x kmax col-major (ldl), or null
+    void* U;             // kmax x m row-major (ldu), or null: a per-workgroup row
+    int32_t* piv;        // 2 * kmax, or null
+    int64_t lda, ldl, ldu;
+    int32_t n, m, kmax;
+    int32_t vec;         // 16-byte packs aligned for A and U (as rplu_dense decides)
+    double tol2;
+    uint64_t seed, stream;
+};
+
+struct BatchInfo {
+    int64_t rank;
+    int32_t stop, error;
+    double a_fro2, res_fro2;
+};
+
+struct BatchLaunch {
+    int dtype;           // RPLU_R32 or RPLU_R64
+    int rows;            // rows per lane-group pass: 1, 2, 4 or 8
+    int grid;            // resident workgroups
+    int maxn;            // largest n in the batch (LDS rows)
+    int count;
+    const BatchJob* jobs;
+    const int32_t* order;   // queue position -> job index
+    int* queue;
+    void* uscratch;      // grid rows of uscr_ld elements
+    int64_t uscr_ld;
+    BatchInfo* infos;
+};
+
+void launch_batched(const BatchLaunch& a, hipStream_t s);
+size_t batched_lds_bytes(int dtype, int maxn);
+int batched_max_resident(int dtype, int rows, int maxn);
+
 }  // namespace rplu

@@ -31,9 +31,18 @@ struct rplu_graph_entry {
 
 constexpr int RPLU_GRAPH_CACHE = 6;
 
+// A tuned batched-launch configuration and the batch signature it was
+// measured for.
+struct rplu_tune_entry {
+    uint64_t key;
+    rplu_batch_cfg cfg;
+    double ms;
+};
+
 struct rplu_ctx_s {
     int device = 0;
     int cu_count = 0;
+    size_t lds_per_block = 0;       // bytes of LDS one workgroup may use
     void* ws = nullptr;             // grow-only device workspace
     size_t ws_cap = 0;
     void* batch_ws = nullptr;       // batched-launch descriptors and queue
@@ -47,6 +56,7 @@ struct rplu_ctx_s {
     std::vector<rplu_prof_rec> prof;         // pending event records
     rplu_graph_entry graphs[RPLU_GRAPH_CACHE];
     uint64_t use_clock = 0;
+    std::vector<rplu_tune_entry> tune;       // batched-launch tuning table
 };
 
 namespace rplu {

@@ -3,9 +3,6 @@
 #include "runtime.hpp"
 
 extern "C" {
-rplu_status rplu_batched(rplu_ctx, int64_t, const rplu_job*, rplu_info*, void*) {
-    return rplu::fail(RPLU_E_UNSUPPORTED, "rplu_batched: not available in this build");
-}
 rplu_status rplu_server_create(rplu_ctx, const rplu_server_cfg*, rplu_server* out) {
     if (out) *out = nullptr;
     return rplu::fail(RPLU_E_UNSUPPORTED, "rplu_server: not available in this build");

@@ -232,6 +232,31 @@ def batched_instance(spec: InstanceSpec, seed: int = 4) -> np.ndarray:
     return dense_with_spectrum(spec.n, spec.m, sigma, [seed, spec.index])
 
 
+def batched_instances_device(specs, seed: int = 4, device="cuda:0", dtype=None):
+    """The batched workload built on `device` (torch): for each spec,
+    A = U diag(r^i) V^T with U, V the sign-fixed reduced Q factors (FP64
+    QR on the device) of Gaussians drawn from torch's device generator seeded
+    with seed * 2^32 + index. Returns a list of tensors of `dtype`
+    (default float32)."""
+    import torch
+    dtype = dtype or torch.float32
+    out = []
+    g = torch.Generator(device=device)
+    for sp in specs:
+        k = min(sp.n, sp.m)
+        g.manual_seed(seed * (1 << 32) + sp.index)
+        Gu = torch.randn((sp.n, k), generator=g, device=device, dtype=torch.float64)
+        Gv = torch.randn((sp.m, k), generator=g, device=device, dtype=torch.float64)
+        Qu, Ru = torch.linalg.qr(Gu)
+        Qv, Rv = torch.linalg.qr(Gv)
+        Qu *= torch.sign(torch.diagonal(Ru))[None, :]
+        Qv *= torch.sign(torch.diagonal(Rv))[None, :]
+        sig = sp.r ** torch.arange(1, k + 1, device=device, dtype=torch.float64)
+        A = (Qu * sig[None, :]) @ Qv.T.contiguous()
+        out.append(A.to(dtype).contiguous())
+    return out
+
+
 @dataclass
 class Arrival:
     t: float                  # arrival time (s)
