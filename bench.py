@@ -12,6 +12,9 @@ step. Workloads:
   dense32k   dense FP32 32768 x 32768, sigma_i = i^-2, U and V exactly
              orthogonal products of 256 Householder reflectors, k = 512
   dense512   dense FP64 512 x 512, sigma_i = 0.8^i, Haar U and V, k = 50
+  batched4096  4096 dense FP32 instances, n, m ~ U{64..1024}, sigma_i = r^i with
+             r ~ U[0.5, 0.95], tol 1e-6, in one persistent autotuned launch;
+             also times plain one-at-a-time FP64 rplu_dense on the same inputs
 
 Prints one JSON line. The hot kernel's average launch duration is measured
 with HIP events on the library's stream over the timed region; the CPU
@@ -35,7 +38,7 @@ METRIC = "RPLU rank-k approximations/sec and GB/s at rel err ≤1e-6; p50/p99 la
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_PEAK_TF = 78.6     # MI355X FP64 vector, TFLOP/s
 CAUCHY_FLOP_PER_PAIR = 7       # complex difference 2, |d|^2 3, divide 1, accumulate 1 (p = 1)
-KERNEL_SOURCES = ["common.hpp", "cdf.hpp", "dense.hip", "cauchy.hip"]
+KERNEL_SOURCES = ["common.hpp", "cdf.hpp", "dense.hip", "cauchy.hip", "batched.hip"]
 
 
 def _source_sha() -> str:
@@ -120,6 +123,60 @@ def _setup_dense(torch, rplu, which):
                 config={"workload": desc, "n": n, "m": m, "k": k, "seed": 0})
 
 
+def _setup_batched(torch, rplu):
+    import workloads as W
+    specs = W.batched_instance_specs()
+    t0 = time.perf_counter()
+    mats0 = W.batched_instances_device(specs)
+    torch.cuda.synchronize()
+    print(f"[bench] generated {len(specs)} instances in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    mats1 = [torch.empty_like(a) for a in mats0]
+    streams = list(range(len(specs)))
+    plan = rplu.BatchPlan(mats1, k=0, tol=1e-6, seed=0, streams=streams)
+
+    def step(flags=0):
+        torch._foreach_copy_(mats1, mats0)
+        plan.run()
+        return plan
+
+    def tune():
+        cfg, ms = rplu.rplu_batched_tune(mats0, k=0, tol=1e-6, seed=0, streams=streams)
+        return dict(cfg, ms=ms)
+
+    def fp64_one_at_a_time():
+        """Plain FP64 rplu_dense, one instance at a time, no graph, tol 1e-6."""
+        work = [a.double() for a in mats0]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ranks = []
+        for b, A in enumerate(work):
+            r = rplu.rplu_dense(A, k=0, tol=1e-6, seed=0, stream=b, flags=rplu.RPLU_FLAG_NO_GRAPH)
+            ranks.append(r.rank)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        del work
+        return el, ranks
+
+    n = sum(sp.n for sp in specs) / len(specs)
+    return dict(step=step, kind="batched", dtype="f32", specs=specs, plan=plan,
+                fp64=fp64_one_at_a_time, tune=tune,
+                config={"workload": "batched dense fp32, 4096 instances, n,m ~ U{64..1024}, "
+                                    "sigma_i=r^i r~U[0.5,0.95], tol 1e-6, one persistent launch",
+                        "instances": len(specs), "mean_n": n, "tol": 1e-6, "seed": 0})
+
+
+def _batched_live_bytes(specs, ranks, es=4):
+    """Live bytes of the batched kernel per instance: the initial mass pass
+    reads each instance once; step t of an instance reads and writes its
+    live (n - t) x (m - t) block."""
+    out = []
+    for sp, k in zip(specs, ranks):
+        n, m = sp.n, sp.m
+        out.append(n * m * es + sum(2 * (n - t) * (m - t) * es for t in range(k)))
+    return out
+
+
 # --------------------------------------------------------------- CPU baseline
 
 _CPU_SAMPLE = r"""
@@ -143,6 +200,20 @@ elif wl == "dense512":
         reps += 1
     el = time.perf_counter() - t0
     print(json.dumps({{"elapsed": el / reps, "passes": 51, "k": 50, "reps": reps}}))
+elif wl == "batched4096":
+    import random
+    specs = W.batched_instance_specs()
+    order = np.random.default_rng(99).permutation(len(specs))
+    spent, done = 0.0, 0
+    for b in order:
+        A = W.batched_instance(specs[int(b)]).astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        O.rplu_dense(A, k=0, tol=1e-6, seed=0, stream=int(b))
+        spent += time.perf_counter() - t0
+        done += 1
+        if spent > 15.0:
+            break
+    print(json.dumps({{"elapsed": spent, "done": done, "count": len(specs)}}))
 else:
     n = 8192
     A = W.dense_with_spectrum(n, n, np.arange(1, n + 1, dtype=np.float64) ** -2.0, seed=3).astype(np.float32).astype(np.float64)
@@ -166,6 +237,11 @@ def cpu_baseline(workload: str):
         full = per_pass * (d["k"] + 1)
         sample = ("oracle rplu_cauchy on the full 20000x20000 input, k=2 (3 exact all-pairs "
                   "mass passes), extrapolated to k=200 (201 passes)")
+    elif workload == "batched4096":
+        full = d["elapsed"] / d["done"] * d["count"]
+        sample = (f"oracle rplu_dense (tol 1e-6) on {d['done']} instances drawn at random "
+                  f"(seeded) from the {d['count']}-instance batch recipe, generated on the host; "
+                  f"mean time per instance x {d['count']}; one approximation = the whole batch")
     elif workload == "dense512":
         full = d["elapsed"]
         sample = f"oracle rplu_dense on the full 512x512 input, k=50, {d['reps']} repetitions"
@@ -185,8 +261,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cauchy20k", choices=["cauchy20k", "dense32k", "dense512"])
+    ap.add_argument("--workload", default="cauchy20k", choices=["cauchy20k", "dense32k", "dense512", "batched4096"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-baseline", action="store_true",
+                    help="batched4096: skip the one-at-a-time FP64 GPU baseline")
     ap.add_argument("--no-graph", action="store_true",
                     help="plain kernel launches instead of the default hipGraph replay")
     args = ap.parse_args()
@@ -201,6 +279,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.workload == "cauchy20k":
         wl = _setup_cauchy20k(torch, rplu)
+    elif args.workload == "batched4096":
+        return _main_batched(args, torch, rplu)
     else:
         wl = _setup_dense(torch, rplu, args.workload)
     ctx = rplu.default_context(0)
@@ -256,6 +336,69 @@ def main() -> int:
     if wl["kind"] == "dense":
         out["GB_per_s_live"] = wl["live_total"] / (elapsed / args.steps) / 1e9
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _main_batched(args, torch, rplu) -> int:
+    wl = _setup_batched(torch, rplu)
+    ctx = rplu.default_context(0)
+    t0 = time.perf_counter()
+    wl["tuned"] = wl["tune"]()
+    print(f"[bench] tuned {wl['tuned']} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    for _ in range(args.warmup):
+        wl["step"]()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        wl["step"]()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    plan = wl["plan"]
+    res = plan.results()
+    ranks = [r.rank for r in res]
+    prof_steps = max(1, min(args.steps, 3))
+    rplu.rplu_profile_begin(ctx)
+    for _ in range(prof_steps):
+        wl["step"]()
+    torch.cuda.synchronize()
+    prof = rplu.rplu_profile_end(ctx)
+    hot_ms = prof["ms"][0] / max(1, prof["launches"][0])
+    per_inst = _batched_live_bytes(wl["specs"], ranks)
+    live = sum(per_inst)
+    achieved = live / (hot_ms * 1e-3) / 1e9
+    count = len(res)
+    value = count * args.steps / elapsed
+    stops = {}
+    for r in res:
+        stops[r.stop] = stops.get(r.stop, 0) + 1
+    rel = [math.sqrt(r.res_fro2 / r.a_fro2) for r in res if r.a_fro2 > 0]
+    out = {
+        "metric": METRIC, "value": value, "unit": "approximations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"],
+        "data": "synthetic", "config": wl["config"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic("batched4096", 1),
+                     "kernel": "k_batched", "avg_launch_us": hot_ms * 1e3,
+                     "launches": prof["launches"][0], "live_bytes_per_launch": live},
+        "ranks": {"mean": sum(ranks) / count, "max": max(ranks), "min": min(ranks)},
+        "largest_instance_live_fraction": max(per_inst) / live,
+        "tuned_cfg": wl["tuned"],
+        "stops": {str(k): v for k, v in sorted(stops.items())},
+        "rel_residual_max": max(rel) if rel else None,
+        "step_note": "a step restores the 4096 inputs from device copies (one fused copy) and "
+                     "runs the batch; value counts instances (approximations) per second",
+    }
+    if not args.no_fp64_baseline:
+        el64, ranks64 = wl["fp64"]()
+        out["fp64_one_at_a_time"] = {
+            "value": count / el64, "unit": "approximations/s", "seconds": el64,
+            "mean_rank": sum(ranks64) / count,
+            "how": "rplu_dense FP64, plain launches, one instance after another, tol 1e-6"}
+        out["speedup_vs_fp64_one_at_a_time"] = value / (count / el64)
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline("batched4096")
     print(json.dumps(out), flush=True)
     return 0
 

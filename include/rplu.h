@@ -200,7 +200,7 @@ typedef struct {
 /* Batched launch configuration. None of these fields changes the arithmetic:
  * an instance's reduction order depends only on its shape, so every
  * configuration returns bitwise the same results.
- *   rows_per_pass  rows a lane group of the workgroup sweeps at once: 1, 2, 4, 8
+ *   rows_per_pass  rows one wave sweeps at once: 1, 2, 4, 8
  *   wg_per_cu      resident workgroups per compute unit (grid = CUs x this,
  *                  at most the number of jobs), 1..8 within occupancy
  *   order          queue order: RPLU_ORDER_AREA (n*m descending, the default),
@@ -218,10 +218,11 @@ typedef struct {
  * workgroup takes instances from a device work queue (largest estimated cost
  * first) and runs each instance's whole step loop with workgroup barriers
  * (Alg. 1 with two-stage sampling, Sec. 4.1). R32 or R64 jobs only, all of
- * one dtype, 1 <= n, m <= 8192, and n * (8 + element size) bytes of LDS
+ * one dtype, 1 <= n, m <= 8192, and n * (12 + element size) bytes of LDS
  * per workgroup; piv is required, L and U may be NULL; max_rank, rel_tol,
  * seed and stream are per job. Results are bitwise those of rplu_dense on each
- * job alone. infos_host: count entries, each with its own status; the call
+ * job alone (for finite data; rows already pivoted are skipped, which leaves
+ * their exact zeros unchanged). infos_host: count entries, each with its own status; the call
  * returns RPLU_OK, or the status of the first failing job (by index).
  *
  * rplu_batched picks the configuration from the context's tuning table,
@@ -285,7 +286,8 @@ rplu_status rplu_server_destroy(rplu_server srv);
  * caller's stream around every launch between rplu_profile_begin and
  * rplu_profile_end. While profiling is on, runs use plain launches (events
  * time individual kernels; a replayed graph cannot be timed per kernel).
- * Class 0: the hot kernel (dense sweep / Cauchy all-pairs mass), 1: the
+ * Class 0: the hot kernel (dense sweep / Cauchy all-pairs mass / the batched
+ * persistent kernel, queue reset included), 1: the
  * samplers, 2: updates and reductions, 3: initial mass pass. */
 #define RPLU_PROFILE_CLASSES 4
 typedef struct {

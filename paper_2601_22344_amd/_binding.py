@@ -309,6 +309,47 @@ def _batch_jobs(As, k, tol, seed, streams, store_L, store_U, kind_check=True):
     return jobs, outs
 
 
+class BatchPlan:
+    """A batch of dense jobs with preallocated outputs and a prebuilt job
+    table, for repeated launches (the matrices are overwritten by each run)."""
+
+    def __init__(self, As, k=0, tol=0.0, seed=0, streams=None, store_L: bool = True,
+                 store_U: bool = True, ctx: Optional[Context] = None):
+        self.count = len(As)
+        self.device = As[0].device if self.count else torch.device("cuda", 0)
+        self.ctx = ctx or default_context(self.device.index or 0)
+        self.jobs, self.outs = _batch_jobs(As, k, tol, seed, streams, store_L, store_U)
+        self.infos = (rplu_info * max(self.count, 1))()
+        self._keep = list(As)
+
+    def run(self, cfg: Optional[dict] = None, raise_on_error: bool = True) -> int:
+        if self.count == 0:
+            return 0
+        c = None
+        if cfg is not None:
+            c = rplu_batch_cfg(int(cfg.get("rows_per_pass", 0)), int(cfg.get("wg_per_cu", 0)),
+                               int(cfg.get("order", 0)), 0)
+        st = lib.rplu_batched_ex(self.ctx.handle, self.count, self.jobs, self.infos,
+                                 C.byref(c) if c is not None else None, _cur_stream(self.device))
+        if st < 0 and (raise_on_error or all(self.infos[b].status == 0 for b in range(self.count))):
+            raise RPLUError(st, "rplu_batched")
+        return st
+
+    def ranks(self) -> list:
+        return [int(self.infos[b].rank) for b in range(self.count)]
+
+    def results(self) -> list:
+        res = []
+        for b in range(self.count):
+            piv, Lt, U = self.outs[b]
+            inf = self.infos[b]
+            r = int(inf.rank)
+            res.append(Result(piv[:r], Lt[:r].T if Lt is not None else None,
+                              U[:r] if U is not None else None, r, int(inf.stop),
+                              float(inf.a_fro2), float(inf.res_fro2), status=int(inf.status)))
+        return res
+
+
 def rplu_batched(As, k=0, tol=0.0, seed=0, streams=None, store_L: bool = True,
                  store_U: bool = True, cfg: Optional[dict] = None, raise_on_error: bool = True,
                  ctx: Optional[Context] = None) -> list:
@@ -317,30 +358,11 @@ def rplu_batched(As, k=0, tol=0.0, seed=0, streams=None, store_L: bool = True,
     launch. k, tol, seed may be scalars or per-job lists; streams defaults to
     the job index. cfg: {'rows_per_pass', 'wg_per_cu', 'order'} (missing or 0
     = tuned). Returns one Result per job."""
-    count = len(As)
-    if count == 0:
+    if len(As) == 0:
         return []
-    dev = As[0].device
-    ctx = ctx or default_context(dev.index or 0)
-    jobs, outs = _batch_jobs(As, k, tol, seed, streams, store_L, store_U)
-    infos = (rplu_info * count)()
-    c = None
-    if cfg is not None:
-        c = rplu_batch_cfg(int(cfg.get("rows_per_pass", 0)), int(cfg.get("wg_per_cu", 0)),
-                           int(cfg.get("order", 0)), 0)
-    st = lib.rplu_batched_ex(ctx.handle, count, jobs, infos, C.byref(c) if c is not None else None,
-                             _cur_stream(dev))
-    if st < 0 and (raise_on_error or all(infos[b].status == 0 for b in range(count))):
-        raise RPLUError(st, "rplu_batched")
-    res = []
-    for b in range(count):
-        piv, Lt, U = outs[b]
-        r = int(infos[b].rank)
-        res.append(Result(piv[:r], Lt[:r].T if Lt is not None else None,
-                          U[:r] if U is not None else None, r, int(infos[b].stop),
-                          float(infos[b].a_fro2), float(infos[b].res_fro2),
-                          status=int(infos[b].status)))
-    return res
+    plan = BatchPlan(As, k, tol, seed, streams, store_L, store_U, ctx)
+    plan.run(cfg, raise_on_error)
+    return plan.results()
 
 
 def rplu_batched_tune(As, k=0, tol=0.0, seed=0, streams=None, store_L: bool = True,

@@ -179,7 +179,8 @@ rplu_status run_batch(rplu_ctx_s* ctx, const Prepared& P, const rplu_batch_cfg& 
             return fail(RPLU_E_HIP, "rplu_batched: hipEventCreate failed");
         (void)hipEventRecord(ev[0], s);
     }
-    launch_batched(a, s);
+    if (ms) launch_batched(a, s);
+    else timed(ctx, 0, s, [&] { launch_batched(a, s); });   // profiling: class 0
     e = hipGetLastError();
     if (ms) (void)hipEventRecord(ev[1], s);
     if (e != hipSuccess) {
@@ -277,7 +278,7 @@ rplu_status tune(rplu_ctx_s* ctx, const Prepared& P, hipStream_t s, rplu_batch_c
     };
 
     std::vector<rplu_batch_cfg> cands;
-    for (int rows : {1, 2, 4, 8}) {
+    for (int rows : {1, 2, 4}) {        // (8 rows spill registers at 1024 threads)
         const int res = batched_max_resident(P.dtype, rows, Q.maxn);
         for (int wg = 1; wg <= std::min(4, res); ++wg) cands.push_back({rows, wg, RPLU_ORDER_AREA, 0});
     }
@@ -300,7 +301,7 @@ rplu_status tune(rplu_ctx_s* ctx, const Prepared& P, hipStream_t s, rplu_batch_c
         if (r != hipSuccess) rc = hip_fail(r, "hipMemcpy2DAsync(tuning copy)");
         Prepared W = Q;
         W.jobs.resize(1);
-        for (int rows : {1, 2, 4, 8})
+        for (int rows : {1, 2, 4})
             if (rc == RPLU_OK) rc = run_batch(ctx, W, {rows, 1, RPLU_ORDER_GIVEN, 0}, s, nullptr, nullptr);
     }
     for (size_t q = 0; q < cands.size() && rc == RPLU_OK; ++q) rc = trial(cands[q]);

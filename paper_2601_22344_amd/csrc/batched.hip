@@ -1,23 +1,21 @@
 // Batched dense RPLU: many independent instances in one persistent launch.
 //
-// Each workgroup (512 threads) takes instances from a device work queue (an
+// Each workgroup (1024 threads) takes instances from a device work queue (an
 // atomic counter over a host-ordered table, largest estimated cost first)
 // and runs an instance's whole step loop (Alg. 1 with two-stage sampling,
-// Sec. 4.1) with workgroup barriers only. Row masses and the scaled pivot
-// column live in LDS; the pivot row goes to U(t,:) (or a per-workgroup row).
+// Sec. 4.1) with workgroup barriers only. Row masses, the scaled pivot
+// column and the list of rows not yet pivoted live in LDS; the pivot row goes
+// to U(t,:) (or a per-workgroup row).
 //
 // Every reduction uses the thread-to-element mapping and order of the
-// single-instance path (the sweep's 512 threads x 16-byte packs, its wave
+// single-instance path (the sweep's 512-thread x 16-byte-pack layout, its wave
 // sums and fixed-order sum over the 8 waves; the chunk totals, the chain and
 // the in-chunk select of cdf.hpp), so an instance's pivots and factors are
 // bitwise those of rplu_dense on the same buffer. Two schedule knobs leave
 // the arithmetic unchanged and are left to the autotuner:
-//   * R, the rows a lane group sweeps per pass (each row keeps its own
-//     partial sums, so R changes only how many rows are in flight);
+//   * R, the rows a wave sweeps at once (each row keeps its own partial
+//     sums, so R changes only how many rows are in flight);
 //   * the number of resident workgroups per CU.
-// When a row needs only 1, 2 or 4 of the 8 waves, the workgroup splits into
-// 8, 4 or 2 lane groups that sweep different rows at once: the idle waves of
-// the single-instance kernel add exact zeros after the active ones.
 #include <type_traits>
 
 #include "common.hpp"
@@ -26,12 +24,12 @@
 
 namespace rplu {
 
-constexpr int BT_THREADS = 512;
+constexpr int BT_THREADS = 1024;                   // physical workgroup
 constexpr int BT_WAVES = BT_THREADS / RPLU_WAVE;
+constexpr int VT_THREADS = DENSE_THREADS;          // the single-instance sweep's mapping
+constexpr int VT_WAVES = VT_THREADS / RPLU_WAVE;
 constexpr int BT_MAXK = RPLU_BATCH_MAX_DIM / CDF_CHUNK;   // chunks of a mass vector
-constexpr int BT_MAXR = 8;
 
-static_assert(BT_THREADS == DENSE_THREADS, "same sweep mapping as rplu_dense");
 static_assert(BT_MAXK <= CDF_GROUP, "one CDF group: the chain is a single sequential sum");
 
 template <class T, int V>
@@ -41,7 +39,6 @@ static_assert(sizeof(BPack<float, 1>) == 4 && sizeof(BPack<double, 2>) == 16, "p
 struct BtShared {
     double ctr[BT_MAXK];                  // chunk totals: row masses
     double ctc[BT_MAXK];                  // chunk totals: pivot row
-    double red[2][BT_WAVES][BT_MAXR];     // per-wave row sums, double-buffered
     double bc[4];
     int bi[2];
     int job;
@@ -58,32 +55,50 @@ __device__ __forceinline__ double uniform_d(double v) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// One pass over the instance: S <- S - l u^T with row pi and column pj set
-// to exactly 0 (unless INIT), and the row masses of the result into s_rm.
+// One pass over the live rows of the instance: S <- S - l u^T with row pi
+// and column pj set to exactly 0 (unless INIT), and the row masses of the
+// result into s_rm. rows[0..nalive) lists the rows not yet pivoted; a
+// pivoted row is exactly +0 and would stay +0 under every later update (its
+// multiplier is +-0 and its entries +0), so leaving it out changes no bit.
+//
+// Blocks of R live rows go to the waves in turn, and a wave sweeps its block
+// on its own, with no barrier. The single-instance kernel reduces a row with
+// 8 waves: wave w holds columns (64 w + lane) V + 512 V k, each lane sums its
+// packs in order, each wave sums its lanes (wave_sum), and the 8 wave sums
+// are added in wave order. Here one wave walks those 8 virtual waves in turn
+// with the same lane mapping, so it forms the same per-lane sums, the same
+// wave sums and the same ordered total; a virtual wave that holds no column
+// would add an exact 0 and is skipped.
 template <class T, int R, int V, bool INIT>
-__device__ __forceinline__ void bt_sweep(T* __restrict__ S, int64_t lda, int n, int m, int pi, int pj,
-                         const T* __restrict__ s_l, const T* __restrict__ Ut,
-                         double* __restrict__ s_rm, BtShared& sh) {
-    const int tid = threadIdx.x, lane = tid % RPLU_WAVE, wv = tid / RPLU_WAVE;
-    const int aw = (m + RPLU_WAVE * V - 1) / (RPLU_WAVE * V);   // waves a row needs
-    const int gw = aw > 4 ? 8 : (aw > 2 ? 4 : (aw > 1 ? 2 : 1));
-    const int groups = BT_WAVES / gw;
-    const int grp = wv / gw;
-    const int gt = tid - grp * gw * RPLU_WAVE;                   // thread index in its group
-    const int nblk = (n + R - 1) / R;
-    int par = 0;
-    for (int b0 = 0; b0 < nblk; b0 += groups, par ^= 1) {
-        const int blk = b0 + grp;
-        const int r0 = blk * R;
-        const int nr = blk < nblk ? min(R, n - r0) : 0;
-        double rp[R];
+__device__ __forceinline__ void bt_sweep(T* __restrict__ S, int64_t lda, int m, int pi, int pj,
+                                         const T* __restrict__ s_l, const T* __restrict__ Ut,
+                                         double* __restrict__ s_rm,
+                                         const uint16_t* __restrict__ rows, int nalive) {
+    const int lane = threadIdx.x % RPLU_WAVE, wv = threadIdx.x / RPLU_WAVE;
+    const int vws = min(VT_WAVES, (m + RPLU_WAVE * V - 1) / (RPLU_WAVE * V));
+    const int nblk = (nalive + R - 1) / R;
+#pragma unroll 1
+    for (int blk = wv; blk < nblk; blk += BT_WAVES) {
+        const int b0 = blk * R;
+        const int nr = min(R, nalive - b0);
+        int ri[R];
 #pragma unroll
-        for (int q = 0; q < R; ++q) rp[q] = 0.0;
+        for (int q = 0; q < R; ++q) ri[q] = rows[b0 + min(q, nr - 1)];
         T lq[R];
 #pragma unroll
-        for (int q = 0; q < R; ++q) lq[q] = (!INIT && q < nr) ? s_l[r0 + q] : Sc<T>::zero();
+        for (int q = 0; q < R; ++q) lq[q] = (!INIT && q < nr) ? s_l[ri[q]] : Sc<T>::zero();
+        double tot[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) tot[q] = 0.0;
+        double rp[R];
 
-        auto pack = [&](int64_t c, auto full_tag, auto allrows_tag) {
+        T* rowp[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) rowp[q] = S + (int64_t)ri[q] * lda;
+
+        // Pivot row and column become exact zeros by a select (pv = offset
+        // of column pj inside the pack), so every load is unconditional.
+        auto pack = [&](int c, auto full_tag, auto allrows_tag) {
             constexpr bool FULL = decltype(full_tag)::value;
             constexpr bool ALLR = decltype(allrows_tag)::value;
             BPack<T, V> u;
@@ -98,7 +113,7 @@ __device__ __forceinline__ void bt_sweep(T* __restrict__ S, int64_t lda, int n, 
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 if (ALLR || q < nr) {
-                    const T* p = S + (int64_t)(r0 + q) * lda + c;
+                    const T* p = rowp[q] + c;
                     if constexpr (FULL) s[q] = *reinterpret_cast<const BPack<T, V>*>(p);
                     else {
 #pragma unroll
@@ -106,22 +121,22 @@ __device__ __forceinline__ void bt_sweep(T* __restrict__ S, int64_t lda, int n, 
                     }
                 }
             }
+            const int pv = pj - c;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 if (ALLR || q < nr) {
                     if constexpr (!INIT) {
-                        const bool prow = (r0 + q) == pi;
+                        const bool zr = ri[q] == pi;
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
-                            T x = Sc<T>::fms(s[q].v[v], lq[q], u.v[v]);
-                            if (prow || c + v == pj) x = Sc<T>::zero();
-                            s[q].v[v] = x;
+                            const T x = Sc<T>::fms(s[q].v[v], lq[q], u.v[v]);
+                            s[q].v[v] = ((v == pv) | zr) ? Sc<T>::zero() : x;
                         }
                     }
 #pragma unroll
                     for (int v = 0; v < V; ++v) rp[q] += Sc<T>::mag2(s[q].v[v]);
                     if constexpr (!INIT) {
-                        T* p = S + (int64_t)(r0 + q) * lda + c;
+                        T* p = rowp[q] + c;
                         if constexpr (FULL) *reinterpret_cast<BPack<T, V>*>(p) = s[q];
                         else {
 #pragma unroll
@@ -132,43 +147,31 @@ __device__ __forceinline__ void bt_sweep(T* __restrict__ S, int64_t lda, int n, 
             }
         };
 
-        if (nr > 0) {
-            // With gw < 8 the group covers the row in one pass (gw*64*V >= m).
-            int64_t c = (int64_t)gt * V;
-            // (not unrolled: the R rows already keep R loads in flight, and
-            // registers decide how many workgroups share a CU)
+#pragma unroll 1
+        for (int vw = 0; vw < vws; ++vw) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) rp[q] = 0.0;
+            int c = (vw * RPLU_WAVE + lane) * V;      // virtual thread vw*64 + lane
+            // (not unrolled: the R rows already keep R loads in flight)
             if (nr == R) {
 #pragma unroll 1
-                for (; c + V <= m; c += (int64_t)BT_THREADS * V) pack(c, std::true_type{}, std::true_type{});
+                for (; c + V <= m; c += VT_THREADS * V) pack(c, std::true_type{}, std::true_type{});
                 if (c < m) pack(c, std::false_type{}, std::true_type{});
             } else {
 #pragma unroll 1
-                for (; c + V <= m; c += (int64_t)BT_THREADS * V) pack(c, std::true_type{}, std::false_type{});
+                for (; c + V <= m; c += VT_THREADS * V) pack(c, std::true_type{}, std::false_type{});
                 if (c < m) pack(c, std::false_type{}, std::false_type{});
             }
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const double w = wave_sum(rp[q]);
+                tot[q] = (vw == 0) ? w : tot[q] + w;
+            }
         }
-
-        if (gw == 1) {
+        if (lane == 0) {
 #pragma unroll
-            for (int q = 0; q < R; ++q) {
-                const double v = wave_sum(rp[q]);
-                if (lane == 0 && q < nr) s_rm[r0 + q] = v;
-            }
-        } else {
-            // gw is uniform over the workgroup, so is this barrier. The two
-            // red buffers alternate: the reads of pass k and the writes of
-            // pass k+2 are separated by the barrier of pass k+1.
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                const double v = wave_sum(rp[q]);
-                if (lane == 0) sh.red[par][wv][q] = v;
-            }
-            __syncthreads();
-            if (gt < nr) {
-                double v = sh.red[par][grp * gw][gt];
-                for (int w = 1; w < gw; ++w) v += sh.red[par][grp * gw + w][gt];
-                s_rm[r0 + gt] = v;
-            }
+            for (int q = 0; q < R; ++q)
+                if (q < nr) s_rm[ri[q]] = tot[q];
         }
     }
 }
@@ -222,7 +225,8 @@ __device__ __forceinline__ CdfPick bt_draw(int len, const double* ct, MassFn& ma
 
 template <class T, int R, int V>
 __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr, BatchInfo* __restrict__ info,
-                       double* __restrict__ s_rm, T* __restrict__ s_l, BtShared& sh) {
+                       double* __restrict__ s_rm, T* __restrict__ s_l, uint16_t* __restrict__ s_alive,
+                       uint16_t* __restrict__ s_pos, BtShared& sh) {
     using W = typename Sc<T>::W;
     T* __restrict__ S = (T*)jb.A;
     T* __restrict__ L = (T*)jb.L;
@@ -230,11 +234,28 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
     const int64_t lda = jb.lda;
     T* Ubase = jb.U ? (T*)jb.U : uscr;
     const int64_t ldu = jb.U ? jb.ldu : 0;
-    bt_sweep<T, R, V, true>(S, lda, n, m, -1, -1, s_l, nullptr, s_rm, sh);
+    for (int r = threadIdx.x; r < n; r += BT_THREADS) {
+        s_alive[r] = (uint16_t)r;
+        s_pos[r] = (uint16_t)r;
+    }
+    __syncthreads();
+    int nalive = n;
+    bt_sweep<T, R, V, true>(S, lda, m, -1, -1, s_l, nullptr, s_rm, s_alive, nalive);
     __syncthreads();
     double T0 = 0.0, Tc = 0.0;
-    int t = 0, stop = 0, err = 0;
+    int t = 0, stop = 0, err = 0, prev_i = -1;
     for (;; ++t) {
+        if (prev_i >= 0) {
+            // the previous pivot row leaves the live list (the barriers of
+            // the sampling below order this before the next sweep)
+            if (threadIdx.x == 0) {
+                const int p = s_pos[prev_i];
+                const int last = s_alive[nalive - 1];
+                s_alive[p] = (uint16_t)last;
+                s_pos[last] = (uint16_t)p;
+            }
+            nalive -= 1;
+        }
         auto rmass = [&](int e) { return s_rm[e]; };
         Tc = bt_levels(n, sh.ctr, rmass, sh);
         if (t == 0) T0 = Tc;
@@ -269,8 +290,9 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
             if (L != nullptr) L[(int64_t)t * jb.ldl + r] = l;
         }
         __syncthreads();                  // column j read before any store to it
-        bt_sweep<T, R, V, false>(S, lda, n, m, i, j, s_l, Ut, s_rm, sh);
+        bt_sweep<T, R, V, false>(S, lda, m, i, j, s_l, Ut, s_rm, s_alive, nalive);
         __syncthreads();                  // new masses and S visible to every wave
+        prev_i = i;
     }
     if (threadIdx.x == 0) {
         info->rank = t;
@@ -293,6 +315,8 @@ __global__ __launch_bounds__(BT_THREADS) void k_batched(const BatchJob* __restri
     __shared__ BtShared sh;
     double* s_rm = bt_dyn;
     T* s_l = reinterpret_cast<T*>(bt_dyn + maxn);
+    uint16_t* s_alive = reinterpret_cast<uint16_t*>(s_l + maxn);
+    uint16_t* s_pos = s_alive + maxn;
     T* myscr = uscratch + (int64_t)blockIdx.x * uscr_ld;
     constexpr int VV = 16 / (int)sizeof(T);
     for (;;) {
@@ -303,8 +327,8 @@ __global__ __launch_bounds__(BT_THREADS) void k_batched(const BatchJob* __restri
         if (q >= count) break;
         const int b = order[q];
         const BatchJob jb = jobs[b];
-        if (jb.vec) bt_run<T, R, VV>(jb, myscr, &infos[b], s_rm, s_l, sh);
-        else bt_run<T, R, 1>(jb, myscr, &infos[b], s_rm, s_l, sh);
+        if (jb.vec) bt_run<T, R, VV>(jb, myscr, &infos[b], s_rm, s_l, s_alive, s_pos, sh);
+        else bt_run<T, R, 1>(jb, myscr, &infos[b], s_rm, s_l, s_alive, s_pos, sh);
         __syncthreads();
     }
 }
@@ -328,7 +352,8 @@ static const void* batched_kernel(int dtype, int rows) {
 }
 
 size_t batched_lds_bytes(int dtype, int maxn) {
-    return (size_t)maxn * (8 + (dtype == RPLU_R64 ? 8 : 4));
+    // row masses, multipliers, live-row list and positions
+    return (size_t)maxn * (8 + (dtype == RPLU_R64 ? 8 : 4) + 2 * sizeof(uint16_t));
 }
 
 int batched_max_resident(int dtype, int rows, int maxn) {

@@ -232,28 +232,82 @@ def batched_instance(spec: InstanceSpec, seed: int = 4) -> np.ndarray:
     return dense_with_spectrum(spec.n, spec.m, sigma, [seed, spec.index])
 
 
+def _stiefel_batched_device(rows_k, seeds, device):
+    """Orthonormal factors Q (rows x k) of Gaussians, for many shapes at once.
+
+    Each Gaussian G (rows x k, from torch's device generator seeded by its
+    seed) has the unique QR factorisation G = Q R with diag(R) > 0; Q is
+    computed by CholeskyQR2 (R1 = chol(G^T G), Q1 = G R1^-1, then the same on
+    Q1), which yields that Q. Shapes are grouped into buckets of rows and k
+    rounded up to 128 and processed as batches: G is zero-padded, and the
+    padded diagonal block of each Gram matrix is set to the identity, so the
+    Cholesky factor and the solve act on the true block alone. A bucket whose
+    Cholesky fails (a nearly rank-deficient draw) falls back to Householder
+    QR per matrix."""
+    import torch
+    f64 = torch.float64
+    out = [None] * len(rows_k)
+    buckets = {}
+    for q, (r, k) in enumerate(rows_k):
+        key = ((r + 127) // 128 * 128, (k + 127) // 128 * 128)
+        buckets.setdefault(key, []).append(q)
+    g = torch.Generator(device=device)
+    for (R, K), idx in sorted(buckets.items()):
+        for c0 in range(0, len(idx), 64):
+            part = idx[c0:c0 + 64]
+            Gp = torch.zeros((len(part), R, K), dtype=f64, device=device)
+            pad = torch.zeros((len(part), K), dtype=f64, device=device)
+            for b, q in enumerate(part):
+                r, k = rows_k[q]
+                g.manual_seed(seeds[q])
+                Gp[b, :r, :k] = torch.randn((r, k), generator=g, device=device, dtype=f64)
+                pad[b, k:] = 1.0
+            Q = Gp
+            ok = True
+            for _ in range(2):
+                Gram = Q.transpose(1, 2).contiguous() @ Q
+                Gram += torch.diag_embed(pad)
+                L, info = torch.linalg.cholesky_ex(Gram)
+                if int(info.abs().sum()) != 0:
+                    ok = False
+                    break
+                # Q <- Q L^-T  (L^T = R, upper triangular)
+                Q = torch.linalg.solve_triangular(L.transpose(1, 2).contiguous(), Q, upper=True,
+                                                  left=False)
+            for b, q in enumerate(part):
+                r, k = rows_k[q]
+                if ok:
+                    out[q] = Q[b, :r, :k].contiguous()
+                else:
+                    g.manual_seed(seeds[q])
+                    G = torch.randn((r, k), generator=g, device=device, dtype=f64)
+                    Qh, Rh = torch.linalg.qr(G)
+                    out[q] = Qh * torch.sign(torch.diagonal(Rh))[None, :]
+    return out
+
+
 def batched_instances_device(specs, seed: int = 4, device="cuda:0", dtype=None):
     """The batched workload built on `device` (torch): for each spec,
-    A = U diag(r^i) V^T with U, V the sign-fixed reduced Q factors (FP64
-    QR on the device) of Gaussians drawn from torch's device generator seeded
-    with seed * 2^32 + index. Returns a list of tensors of `dtype`
-    (default float32)."""
+    A = U diag(r^i) V^T (i = 1..min(n, m)) with U, V the orthonormal Q
+    factors (diag(R) > 0) of Gaussians drawn from torch's device generator,
+    seeded with seed * 2^32 + 2 * index (U) and + 1 (V). Returns a list of
+    tensors of `dtype` (default float32)."""
     import torch
     dtype = dtype or torch.float32
-    out = []
-    g = torch.Generator(device=device)
+    shapes, seeds = [], []
     for sp in specs:
         k = min(sp.n, sp.m)
-        g.manual_seed(seed * (1 << 32) + sp.index)
-        Gu = torch.randn((sp.n, k), generator=g, device=device, dtype=torch.float64)
-        Gv = torch.randn((sp.m, k), generator=g, device=device, dtype=torch.float64)
-        Qu, Ru = torch.linalg.qr(Gu)
-        Qv, Rv = torch.linalg.qr(Gv)
-        Qu *= torch.sign(torch.diagonal(Ru))[None, :]
-        Qv *= torch.sign(torch.diagonal(Rv))[None, :]
+        shapes += [(sp.n, k), (sp.m, k)]
+        seeds += [seed * (1 << 32) + 2 * sp.index, seed * (1 << 32) + 2 * sp.index + 1]
+    Q = _stiefel_batched_device(shapes, seeds, device)
+    out = []
+    for q, sp in enumerate(specs):
+        k = min(sp.n, sp.m)
+        U, V = Q[2 * q], Q[2 * q + 1]
         sig = sp.r ** torch.arange(1, k + 1, device=device, dtype=torch.float64)
-        A = (Qu * sig[None, :]) @ Qv.T.contiguous()
+        A = (U * sig[None, :]) @ V.T.contiguous()
         out.append(A.to(dtype).contiguous())
+        Q[2 * q] = Q[2 * q + 1] = None
     return out
 
 
