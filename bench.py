@@ -117,8 +117,25 @@ def _setup_dense(torch, rplu, which):
         A1.copy_(A0)
         return rplu.rplu_dense(A1, k=k, seed=0, flags=flags)
 
+    def verify(res):
+        """FP64 matrix-core check of the last run: ||A - L U|| and
+        ||A - L U - S||, timed with events on the current stream."""
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        v = rplu.rplu_verify(A0, res.L, res.U, A1)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        flop = 2.0 * n * m * res.rank
+        return {"kernel": "k_verify (v_mfma_f64_16x16x4f64)", "ms": ms,
+                "achieved_tflops": flop / (ms * 1e-3) / 1e12, "peak_tflops": FP64_VECTOR_PEAK_TF,
+                "frac": flop / (ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TF,
+                "rel_err": math.sqrt(v["err_fro2"] / v["a_fro2"]),
+                "rel_schur_gap": math.sqrt(v["schur_gap_fro2"] / v["a_fro2"]),
+                "note": "FP64 MFMA peak on MI355X equals the FP64 vector peak, 78.6 TFLOP/s"}
+
     live = sum(2 * (n - s) * (m - s) * es for s in range(k)) / k
-    return dict(step=step, k=k, n=n, m=m, kind="dense", dtype=dtype, per_launch=live,
+    return dict(step=step, k=k, n=n, m=m, kind="dense", dtype=dtype, per_launch=live, verify=verify,
                 live_total=sum(2 * (n - s) * (m - s) * es for s in range(k)) + n * m * es,
                 config={"workload": desc, "n": n, "m": m, "k": k, "seed": 0})
 
@@ -335,6 +352,7 @@ def main() -> int:
     }
     if wl["kind"] == "dense":
         out["GB_per_s_live"] = wl["live_total"] / (elapsed / args.steps) / 1e9
+        out["verify"] = wl["verify"](res)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
     return 0

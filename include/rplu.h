@@ -280,6 +280,27 @@ rplu_status rplu_server_stats(rplu_server srv, rplu_server_stats_t* out);
 /* Drains every submitted job, stops the worker and frees slot memory. */
 rplu_status rplu_server_destroy(rplu_server srv);
 
+/* -------------------------------------------------------- verification */
+
+/* Check of a rank-k factorisation with FP64 matrix cores (off the step loop).
+ * After k steps the residual is S = A - L U (eqs. residual_update and
+ * approximation_update), so ||A - L U||_F is the approximation error and
+ * ||A - L U - S||_F is zero up to rounding for a consistent L, U, S.
+ * A: n x m row-major (lda >= m), the ORIGINAL matrix; L: n x k column-major
+ * (ldl >= n); U: k x m row-major (ldu >= m); S: n x m row-major (lds >= m)
+ * or NULL. R32 inputs are widened to FP64 before the products; every sum is
+ * FP64 and its order is fixed, so repeated calls give the same bits. Nothing
+ * is modified. Real dtypes (R32, R64) only. Blocks until out is filled. */
+typedef struct {
+    double a_fro2;          /* ||A||_F^2                                       */
+    double err_fro2;        /* ||A - L U||_F^2                                 */
+    double schur_gap_fro2;  /* ||A - L U - S||_F^2 (0 when S is NULL)          */
+} rplu_verify_out;
+rplu_status rplu_verify(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, int64_t k,
+                        const void* A, int64_t lda, const void* L, int64_t ldl,
+                        const void* U, int64_t ldu, const void* S, int64_t lds,
+                        rplu_verify_out* out, void* hip_stream);
+
 /* ------------------------------------------------------------- profiling */
 
 /* Device time per kernel class, measured with HIP events recorded on the

@@ -5,9 +5,10 @@ C ABI of include/rplu.h; all computation runs in the library's HIP kernels.
 Importing fails if the library has not been built (there is no CPU path).
 """
 from ._binding import (  # noqa: F401
-    RPLU_C64, RPLU_C128, RPLU_FLAG_COLMASS, RPLU_FLAG_GRAPH, RPLU_FLAG_NO_GRAPH, RPLU_R32,
-    RPLU_ORDER_AREA, RPLU_ORDER_CUBE, RPLU_ORDER_GIVEN, RPLU_R64, RPLU_STOP_EXHAUSTED, RPLU_STOP_RANK, RPLU_STOP_TOL, RPLU_STOP_TOL_UNREACHED,
-    RPLU_TRACE_WORDS, BatchPlan, Context, Result, RPLUError, default_context, lib, rplu_cauchy,
-    rplu_batched, rplu_batched_tune, rplu_create, rplu_dense, rplu_profile_begin,
-    rplu_profile_end,
+    RPLU_C64, RPLU_C128, RPLU_FLAG_COLMASS, RPLU_FLAG_GRAPH, RPLU_FLAG_NO_GRAPH,
+    RPLU_ORDER_AREA, RPLU_ORDER_CUBE, RPLU_ORDER_GIVEN, RPLU_R32, RPLU_R64,
+    RPLU_STOP_EXHAUSTED, RPLU_STOP_RANK, RPLU_STOP_TOL, RPLU_STOP_TOL_UNREACHED,
+    RPLU_TRACE_WORDS, BatchPlan, Context, Result, RPLUError, default_context, lib,
+    rplu_batched, rplu_batched_tune, rplu_cauchy, rplu_create, rplu_dense,
+    rplu_profile_begin, rplu_profile_end, rplu_verify,
 )

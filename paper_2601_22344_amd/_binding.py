@@ -64,6 +64,10 @@ class rplu_batch_cfg(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class rplu_verify_out(C.Structure):
+    _fields_ = [("a_fro2", C.c_double), ("err_fro2", C.c_double), ("schur_gap_fro2", C.c_double)]
+
+
 class rplu_server_cfg(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32),
                 ("queue_capacity", C.c_int32)]
@@ -95,6 +99,8 @@ lib.rplu_batched_ex.argtypes = [_P, _I64, C.POINTER(rplu_job), C.POINTER(rplu_in
                                 C.POINTER(rplu_batch_cfg), _P]
 lib.rplu_batched_tune.argtypes = [_P, _I64, C.POINTER(rplu_job), C.POINTER(rplu_batch_cfg),
                                   C.POINTER(C.c_double), _P]
+lib.rplu_verify.argtypes = [_P, C.c_int, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _I64,
+                            C.POINTER(rplu_verify_out), _P]
 lib.rplu_server_create.argtypes = [_P, C.POINTER(rplu_server_cfg), C.POINTER(_P)]
 lib.rplu_server_submit.argtypes = [_P, C.POINTER(rplu_job), C.POINTER(C.c_uint64)]
 lib.rplu_server_poll.argtypes = [_P, C.c_uint64, C.POINTER(rplu_info)]
@@ -106,7 +112,7 @@ lib.rplu_status_str.argtypes = [C.c_int32]
 lib.rplu_status_str.restype = C.c_char_p
 lib.rplu_last_error.restype = C.c_char_p
 for _fn in ("rplu_create", "rplu_destroy", "rplu_dense", "rplu_cauchy", "rplu_batched",
-            "rplu_batched_ex", "rplu_batched_tune",
+            "rplu_batched_ex", "rplu_batched_tune", "rplu_verify",
             "rplu_server_create", "rplu_server_submit", "rplu_server_poll",
             "rplu_server_stats", "rplu_server_destroy", "rplu_profile_begin", "rplu_profile_end"):
     getattr(lib, _fn).restype = C.c_int32
@@ -378,3 +384,32 @@ def rplu_batched_tune(As, k=0, tol=0.0, seed=0, streams=None, store_L: bool = Tr
                                  _cur_stream(dev)), "rplu_batched_tune")
     return ({"rows_per_pass": best.rows_per_pass, "wg_per_cu": best.wg_per_cu,
              "order": best.order}, float(ms.value))
+
+
+def rplu_verify(A: torch.Tensor, L: Optional[torch.Tensor], U: Optional[torch.Tensor],
+                S: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> dict:
+    """FP64 norms of a factorisation: ||A||^2, ||A - L U||^2 and (when S is
+    given) ||A - L U - S||^2. A, S: n x m row-major; L: n x k (any view whose
+    columns are contiguous, e.g. Result.L); U: k x m row-major. float32 or
+    float64, one dtype."""
+    if A.dtype not in (torch.float32, torch.float64) or A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A: 2-D float32/float64 CUDA tensor with unit column stride")
+    n, m = A.shape
+    k = 0 if L is None else L.shape[1]
+    dev = A.device
+    ctx = ctx or default_context(dev.index or 0)
+    ldl = 0
+    if k:
+        if L.shape[0] != n or L.stride(0) != 1 or U.shape != (k, m) or U.stride(1) != 1:
+            raise ValueError("L: n x k with contiguous columns; U: k x m row-major")
+        if L.dtype != A.dtype or U.dtype != A.dtype:
+            raise ValueError("A, L, U must share one dtype")
+        ldl = L.stride(1) if k > 1 else n
+    if S is not None and (S.shape != (n, m) or S.stride(1) != 1 or S.dtype != A.dtype):
+        raise ValueError("S: n x m row-major, dtype of A")
+    out = rplu_verify_out()
+    _check(lib.rplu_verify(ctx.handle, _DTYPES[A.dtype], n, m, k, _ptr(A), A.stride(0),
+                           _ptr(L) if k else None, ldl, _ptr(U) if k else None,
+                           U.stride(0) if k else 0, _ptr(S), S.stride(0) if S is not None else 0,
+                           C.byref(out), _cur_stream(dev)), "rplu_verify")
+    return {"a_fro2": out.a_fro2, "err_fro2": out.err_fro2, "schur_gap_fro2": out.schur_gap_fro2}

@@ -275,6 +275,57 @@ rplu_status rplu_create(int device, rplu_ctx* out) {
     return RPLU_OK;
 }
 
+rplu_status rplu_verify(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, int64_t k,
+                        const void* A, int64_t lda, const void* L, int64_t ldl, const void* U,
+                        int64_t ldu, const void* S, int64_t lds, rplu_verify_out* out,
+                        void* hip_stream) {
+    if (ctx == nullptr || out == nullptr) return fail(RPLU_E_ARG, "rplu_verify: ctx and out are required");
+    if (dtype != RPLU_R32 && dtype != RPLU_R64)
+        return fail(RPLU_E_UNSUPPORTED, "rplu_verify: real dtypes (R32, R64) only");
+    if (n < 1 || m < 1 || k < 0 || n > INT32_MAX || m > INT32_MAX || k > INT32_MAX)
+        return fail(RPLU_E_ARG, "rplu_verify: shape out of range");
+    if (A == nullptr || lda < m) return fail(RPLU_E_ARG, "rplu_verify: A NULL or lda < m");
+    if (k > 0 && (L == nullptr || U == nullptr || ldl < n || ldu < m))
+        return fail(RPLU_E_ARG, "rplu_verify: L (ldl >= n) and U (ldu >= m) are required when k > 0");
+    if (S != nullptr && lds < m) return fail(RPLU_E_ARG, "rplu_verify: lds < m");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Carver cv;
+    const size_t o_p = cv.take((size_t)verify_tiles(n, m) * 3 * sizeof(double));
+    const size_t o_o = cv.take(3 * sizeof(double));
+    rplu_status rc = ws_reserve(ctx, cv.off, s);
+    if (rc) return rc;
+    char* ws = (char*)ctx->ws;
+    VerifyArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.dtype = dtype;
+    a.n = n;
+    a.m = m;
+    a.k = k;
+    a.A = A;
+    a.lda = lda;
+    a.L = L;
+    a.ldl = ldl;
+    a.U = U;
+    a.ldu = ldu;
+    a.S = S;
+    a.lds = lds;
+    a.partial = (double*)(ws + o_p);
+    a.out = (double*)(ws + o_o);
+    launch_verify(a, s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "verify launch");
+    double h[3];
+    e = hipMemcpyAsync(h, a.out, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "rplu_verify read-back");
+    out->a_fro2 = h[0];
+    out->err_fro2 = h[1];
+    out->schur_gap_fro2 = S ? h[2] : 0.0;
+    return RPLU_OK;
+}
+
 rplu_status rplu_profile_begin(rplu_ctx ctx) {
     if (ctx == nullptr) return fail(RPLU_E_ARG, "rplu_profile_begin: ctx is NULL");
     ctx->prof.clear();

@@ -141,6 +141,24 @@ struct BatchLaunch {
 };
 
 void launch_batched(const BatchLaunch& a, hipStream_t s);
+
+// Factorisation check (verify.hip): ||A||^2, ||A - L U||^2, ||A - L U - S||^2.
+struct VerifyArgs {
+    int dtype;           // RPLU_R32 or RPLU_R64
+    int64_t n, m, k;
+    const void* A;
+    int64_t lda;
+    const void* L;       // n x k column-major (ldl)
+    int64_t ldl;
+    const void* U;       // k x m row-major (ldu)
+    int64_t ldu;
+    const void* S;       // n x m row-major (lds), or null
+    int64_t lds;
+    double* partial;     // verify_tiles(n, m) * 3
+    double* out;         // 3
+};
+void launch_verify(const VerifyArgs& a, hipStream_t s);
+int64_t verify_tiles(int64_t n, int64_t m);
 size_t batched_lds_bytes(int dtype, int maxn);
 int batched_max_resident(int dtype, int rows, int maxn);
 
