@@ -247,37 +247,70 @@ rplu_status rplu_batched_tune(rplu_ctx ctx, int64_t count, const rplu_job* jobs,
 
 /* ------------------------------------------------------------- server */
 
+/* Continuous-batching server for arriving dense and Cauchy-like jobs.
+ *
+ * Admission: submitted jobs wait in FIFO order; the head is admitted while a
+ * block of its device footprint fits in the server's slot pool (one device
+ * allocation of hbm_budget_bytes, sub-allocated first-fit) and fewer than
+ * max_slots jobs are resident. Admission copies the job's overwritten inputs
+ * (dense A, Cauchy G and B) into its slot, so the Schur state stays on the
+ * device in server memory and the caller's inputs are never modified.
+ * Execution: `workers` host threads, each with its own context and device
+ * stream, take admitted work as it becomes ready: every admitted dense job
+ * with n, m <= batch_max_dim (R32/R64) that is ready when a worker frees up
+ * goes into ONE rplu_batched launch; other jobs (larger dense, Cauchy-like)
+ * run alone (rplu_dense / rplu_cauchy, plain launches). Work of different
+ * workers overlaps on the device. A job's results are those it gets alone:
+ * the batched kernel matches rplu_dense bitwise, and slots keep each input's
+ * row pitch and 16-byte alignment offset.
+ * Footprint of a job: dense n * lda * size + 16; Cauchy (n p + p m) * 16 + 16
+ * bytes (rounded up to 256). */
 typedef struct {
-    size_t hbm_budget_bytes;   /* admit jobs while their device footprint fits */
-    int32_t max_slots;         /* most jobs resident on the device at once     */
+    size_t hbm_budget_bytes;   /* slot pool size                               */
+    int32_t max_slots;         /* most jobs admitted at once (<= 0: no limit)  */
     int32_t queue_capacity;    /* most jobs waiting; beyond -> RPLU_E_BUSY     */
+    int32_t workers;           /* worker threads/streams (<= 0: 3)             */
+    int32_t batch_max_dim;     /* dense jobs with n, m <= this are batched
+                                  (<= 0: 2048; at most 8192)                   */
+    uint32_t flags;            /* RPLU_SERVER_SIMULATE                         */
+    int32_t reserved;
 } rplu_server_cfg;
+
+/* Host-only mode for testing the queueing logic without a device: the pool is
+ * host memory, no HIP call is made, inputs are not read, and a job "runs" for
+ * footprint / 1e10 seconds and completes with rank 0, RPLU_STOP_RANK. */
+#define RPLU_SERVER_SIMULATE 1u
 
 typedef struct {
     int64_t submitted, completed, rejected, queued, active;
     double p50_ms, p99_ms;             /* submit -> completion latency       */
     double p50_dense_ms, p99_dense_ms;
     double p50_cauchy_ms, p99_cauchy_ms;
-    double busy_s;                     /* wall time with >= 1 active job     */
-    size_t hbm_in_use;
+    double busy_s;                     /* wall time with >= 1 admitted job   */
+    size_t hbm_in_use;                 /* bytes of the pool held by slots    */
+    int64_t batches;                   /* batched launches run               */
+    int64_t batched_jobs;              /* jobs run inside those launches     */
 } rplu_server_stats_t;
 
 typedef struct rplu_server_s* rplu_server;
 
-/* A server owns a worker thread and its own device stream(s). Jobs are copied
- * into server-owned device slot memory at admission, so a job's input buffers
- * may be reused as soon as poll returns something other than RPLU_PENDING for
- * the admission (see rplu_server_poll); outputs are written at completion. */
+/* ctx names the device (its workspace is not used; each worker makes its
+ * own context); it may be NULL with RPLU_SERVER_SIMULATE. */
 rplu_status rplu_server_create(rplu_ctx ctx, const rplu_server_cfg* cfg,
                                rplu_server* out);
-/* Non-blocking. Copies the descriptor; returns a ticket. */
+/* Non-blocking, thread-safe. Copies the descriptor and returns a ticket;
+ * RPLU_E_BUSY when queue_capacity jobs are waiting, RPLU_E_ARG for a job that
+ * can never be admitted (footprint above the pool) or is malformed. The job's
+ * input buffers must stay valid, and its outputs untouched, until poll
+ * returns something other than RPLU_PENDING. */
 rplu_status rplu_server_submit(rplu_server srv, const rplu_job* job,
                                uint64_t* ticket);
 /* RPLU_PENDING until the job finished; then its status (RPLU_OK or an error)
- * and info. Thread-safe. */
+ * and info, once: the ticket is then forgotten (a later poll: RPLU_E_ARG).
+ * Thread-safe. */
 rplu_status rplu_server_poll(rplu_server srv, uint64_t ticket, rplu_info* info);
 rplu_status rplu_server_stats(rplu_server srv, rplu_server_stats_t* out);
-/* Drains every submitted job, stops the worker and frees slot memory. */
+/* Drains every submitted job, stops the workers and frees slot memory. */
 rplu_status rplu_server_destroy(rplu_server srv);
 
 /* -------------------------------------------------------- verification */

@@ -8,7 +8,8 @@ from ._binding import (  # noqa: F401
     RPLU_C64, RPLU_C128, RPLU_FLAG_COLMASS, RPLU_FLAG_GRAPH, RPLU_FLAG_NO_GRAPH,
     RPLU_ORDER_AREA, RPLU_ORDER_CUBE, RPLU_ORDER_GIVEN, RPLU_R32, RPLU_R64,
     RPLU_STOP_EXHAUSTED, RPLU_STOP_RANK, RPLU_STOP_TOL, RPLU_STOP_TOL_UNREACHED,
-    RPLU_TRACE_WORDS, BatchPlan, Context, Result, RPLUError, default_context, lib,
+    RPLU_SERVER_SIMULATE, RPLU_TRACE_WORDS, BatchPlan, Context, Result, RPLUError, Server,
+    default_context, lib,
     rplu_batched, rplu_batched_tune, rplu_cauchy, rplu_create, rplu_dense,
     rplu_profile_begin, rplu_profile_end, rplu_verify,
 )

@@ -33,6 +33,7 @@ RPLU_FLAG_COLMASS, RPLU_FLAG_GRAPH, RPLU_FLAG_NO_GRAPH = 1, 2, 4
 RPLU_TRACE_WORDS = 12
 RPLU_JOB_DENSE, RPLU_JOB_CAUCHY = 1, 2
 RPLU_ORDER_AREA, RPLU_ORDER_CUBE, RPLU_ORDER_GIVEN = 1, 2, 3
+RPLU_SERVER_SIMULATE = 1
 
 _DTYPES = {torch.float32: RPLU_R32, torch.float64: RPLU_R64,
            torch.complex64: RPLU_C64, torch.complex128: RPLU_C128}
@@ -70,7 +71,8 @@ class rplu_verify_out(C.Structure):
 
 class rplu_server_cfg(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32),
-                ("queue_capacity", C.c_int32)]
+                ("queue_capacity", C.c_int32), ("workers", C.c_int32),
+                ("batch_max_dim", C.c_int32), ("flags", C.c_uint32), ("reserved", C.c_int32)]
 
 
 class rplu_profile(C.Structure):
@@ -83,7 +85,7 @@ class rplu_server_stats_t(C.Structure):
                 ("p99_ms", C.c_double), ("p50_dense_ms", C.c_double),
                 ("p99_dense_ms", C.c_double), ("p50_cauchy_ms", C.c_double),
                 ("p99_cauchy_ms", C.c_double), ("busy_s", C.c_double),
-                ("hbm_in_use", C.c_size_t)]
+                ("hbm_in_use", C.c_size_t), ("batches", C.c_int64), ("batched_jobs", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -413,3 +415,97 @@ def rplu_verify(A: torch.Tensor, L: Optional[torch.Tensor], U: Optional[torch.Te
                            U.stride(0) if k else 0, _ptr(S), S.stride(0) if S is not None else 0,
                            C.byref(out), _cur_stream(dev)), "rplu_verify")
     return {"a_fro2": out.a_fro2, "err_fro2": out.err_fro2, "schur_gap_fro2": out.schur_gap_fro2}
+
+
+class Server:
+    """Continuous-batching server (rplu_server_*). submit_* allocate the
+    job's outputs and return a ticket; poll returns None while the job is
+    pending, else its Result (raising RPLUError if it failed)."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 0, queue_capacity: int = 0,
+                 workers: int = 0, batch_max_dim: int = 0, simulate: bool = False,
+                 ctx: Optional[Context] = None, device: int = 0):
+        self.ctx = None if simulate else (ctx or default_context(device))
+        cfg = rplu_server_cfg(int(budget_bytes), int(max_slots), int(queue_capacity), int(workers),
+                              int(batch_max_dim), RPLU_SERVER_SIMULATE if simulate else 0, 0)
+        h = C.c_void_p()
+        _check(lib.rplu_server_create(self.ctx.handle if self.ctx else None, C.byref(cfg),
+                                      C.byref(h)), "rplu_server_create")
+        self.handle = h
+        self._pending = {}
+
+    def _submit(self, job, keep):
+        t = C.c_uint64()
+        _check(lib.rplu_server_submit(self.handle, C.byref(job), C.byref(t)), "rplu_server_submit")
+        self._pending[t.value] = keep
+        return t.value
+
+    def submit_dense(self, A: torch.Tensor, k: int = 0, tol: float = 0.0, seed: int = 0,
+                     stream: int = 0, store_L: bool = True, store_U: bool = True) -> int:
+        """A is read (never modified); it must stay valid until poll returns."""
+        if A.dim() != 2 or A.stride(1) != 1 or A.dtype not in _DTYPES:
+            raise ValueError("A: 2-D CUDA tensor with unit column stride")
+        n, m = A.shape
+        kmax = min(n, m) if k <= 0 else min(k, n, m)
+        piv = torch.empty((kmax, 2), dtype=torch.int32, device=A.device)
+        Lt = torch.empty((kmax, n), dtype=A.dtype, device=A.device) if store_L else None
+        U = torch.empty((kmax, m), dtype=A.dtype, device=A.device) if store_U else None
+        j = rplu_job()
+        j.kind, j.dtype, j.n, j.m, j.A, j.lda = RPLU_JOB_DENSE, _DTYPES[A.dtype], n, m, A.data_ptr(), A.stride(0)
+        j.piv = piv.data_ptr()
+        j.L, j.ldl = (Lt.data_ptr(), n) if Lt is not None else (None, 0)
+        j.U, j.ldu = (U.data_ptr(), m) if U is not None else (None, 0)
+        j.max_rank, j.rel_tol = int(k), float(tol)
+        j.seed, j.stream = int(seed) & (2**64 - 1), int(stream) & (2**64 - 1)
+        return self._submit(j, (A, piv, Lt, U))
+
+    def submit_cauchy(self, x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
+                      stream: int = 0, store_L: bool = True, store_U: bool = True) -> int:
+        """x, y, G, B are read (never modified); they must stay valid until poll returns."""
+        n, m, p = x.shape[0], y.shape[0], G.shape[1]
+        for t_ in (x, y, G, B):
+            if t_.dtype != torch.complex128 or not t_.is_contiguous():
+                raise ValueError("x, y, G, B: contiguous complex128 CUDA tensors")
+        kmax = min(n, m) if k <= 0 else min(k, n, m)
+        dev = x.device
+        piv = torch.empty((kmax, 2), dtype=torch.int32, device=dev)
+        Lt = torch.empty((kmax, n), dtype=torch.complex128, device=dev) if store_L else None
+        U = torch.empty((kmax, m), dtype=torch.complex128, device=dev) if store_U else None
+        j = rplu_job()
+        j.kind, j.dtype, j.n, j.m, j.p = RPLU_JOB_CAUCHY, RPLU_C128, n, m, p
+        j.x, j.y, j.G, j.B = x.data_ptr(), y.data_ptr(), G.data_ptr(), B.data_ptr()
+        j.piv = piv.data_ptr()
+        j.L, j.ldl = (Lt.data_ptr(), n) if Lt is not None else (None, 0)
+        j.U, j.ldu = (U.data_ptr(), m) if U is not None else (None, 0)
+        j.max_rank, j.rel_tol = int(k), float(tol)
+        j.seed, j.stream = int(seed) & (2**64 - 1), int(stream) & (2**64 - 1)
+        return self._submit(j, (x, y, G, B, piv, Lt, U))
+
+    def poll(self, ticket: int):
+        info = rplu_info()
+        st = lib.rplu_server_poll(self.handle, int(ticket), C.byref(info))
+        if st == RPLU_PENDING:
+            return None
+        keep = self._pending.pop(ticket, None)
+        if st < 0:
+            raise RPLUError(st, "rplu_server_poll")
+        r = int(info.rank)
+        piv, Lt, U = keep[-3], keep[-2], keep[-1]
+        return Result(piv[:r], Lt[:r].T if Lt is not None else None, U[:r] if U is not None else None,
+                      r, int(info.stop), float(info.a_fro2), float(info.res_fro2), status=int(st))
+
+    def stats(self) -> dict:
+        s = rplu_server_stats_t()
+        _check(lib.rplu_server_stats(self.handle, C.byref(s)), "rplu_server_stats")
+        return {f: getattr(s, f) for f, _ in rplu_server_stats_t._fields_}
+
+    def close(self):
+        if self.handle:
+            lib.rplu_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

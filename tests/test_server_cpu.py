@@ -1,0 +1,163 @@
+"""Queueing logic of the continuous-batching server, on the host only.
+
+RPLU_SERVER_SIMULATE runs the real admission, FIFO, slot pool, batching
+and statistics code with a stand-in executor (no device; a job "runs" for
+footprint / 1e10 s), so these tests need no GPU. Inputs are never read in
+this mode, so host tensors stand in for device buffers.
+"""
+import time
+
+import pytest
+import torch
+
+import paper_2601_22344_amd as rplu
+
+MB = 1 << 20
+
+
+def _dense(n, m=None, dtype=torch.float32):
+    return torch.zeros((n, m or n), dtype=dtype)
+
+
+def _footprint(n, m, es=4):
+    return ((n * m * es + 16) + 255) // 256 * 256
+
+
+def _wait_all(S, tickets, timeout=30.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t not in out:
+                r = S.poll(t)
+                if r is not None:
+                    out[t] = r
+        assert time.time() - t0 < timeout, "server did not finish"
+        time.sleep(0.001)
+    return out
+
+
+def test_all_jobs_complete_and_stats():
+    S = rplu.Server(budget_bytes=64 * MB, workers=2, simulate=True)
+    ts = [S.submit_dense(_dense(256 + 16 * q)) for q in range(20)]
+    res = _wait_all(S, ts)
+    assert all(r.status == 0 and r.rank == 0 for r in res.values())
+    st = S.stats()
+    assert st["submitted"] == 20 and st["completed"] == 20 and st["rejected"] == 0
+    assert st["queued"] == 0 and st["active"] == 0 and st["hbm_in_use"] == 0
+    assert 0.0 <= st["p50_ms"] <= st["p99_ms"]
+    assert st["p99_cauchy_ms"] == 0.0                 # no Cauchy jobs
+    assert st["batched_jobs"] == 20 and 1 <= st["batches"] <= 20
+    S.close()
+
+
+def test_poll_once_then_forgotten():
+    S = rplu.Server(budget_bytes=8 * MB, simulate=True)
+    t = S.submit_dense(_dense(64))
+    _wait_all(S, [t])
+    with pytest.raises(rplu.RPLUError):
+        S.poll(t)
+    with pytest.raises(rplu.RPLUError):
+        S.poll(12345)
+    S.close()
+
+
+def test_admission_by_footprint_is_fifo_and_bounded():
+    """Jobs of 40 MB in a 100 MB pool: at most two resident at once and the
+    pool never over-commits."""
+    n = 3240                                    # 3240^2 * 4 B ~ 40 MB
+    fp = _footprint(n, n)
+    S = rplu.Server(budget_bytes=100 * MB, workers=3, batch_max_dim=1024, simulate=True)
+    ts = [S.submit_dense(_dense(n)) for _ in range(8)]
+    peak_active, peak_bytes = 0, 0
+    done = {}
+    t0 = time.time()
+    while len(done) < len(ts):
+        st = S.stats()
+        peak_active = max(peak_active, st["active"])
+        peak_bytes = max(peak_bytes, st["hbm_in_use"])
+        assert st["hbm_in_use"] <= 100 * MB
+        for t in ts:
+            if t not in done:
+                r = S.poll(t)
+                if r is not None:
+                    done[t] = time.time()
+        assert time.time() - t0 < 30
+    assert peak_active <= 2 and peak_bytes <= 2 * fp
+    assert S.stats()["batches"] == 0            # all above batch_max_dim: run alone
+    S.close()
+
+
+def test_max_slots_limits_residency():
+    S = rplu.Server(budget_bytes=1 << 30, max_slots=3, workers=4, batch_max_dim=64, simulate=True)
+    ts = [S.submit_dense(_dense(2000)) for _ in range(10)]
+    t0 = time.time()
+    pending = set(ts)
+    while pending:
+        assert S.stats()["active"] <= 3
+        for t in list(pending):
+            if S.poll(t) is not None:
+                pending.discard(t)
+        assert time.time() - t0 < 30
+    S.close()
+
+
+def test_queue_capacity_rejects_with_busy():
+    # one huge job occupies the pool; the queue then fills
+    S = rplu.Server(budget_bytes=1100 * MB, queue_capacity=2, workers=1, simulate=True)
+    A = _dense(16000)                            # 1 GB: ~0.1 s of simulated work
+    big = S.submit_dense(A, k=1)
+    q1 = S.submit_dense(A, k=1)
+    q2 = S.submit_dense(A, k=1)
+    with pytest.raises(rplu.RPLUError) as e:
+        S.submit_dense(A, k=1)
+    assert e.value.status == -5                  # RPLU_E_BUSY
+    assert S.stats()["rejected"] == 1
+    _wait_all(S, [big, q1, q2])
+    S.close()
+
+
+def test_job_larger_than_pool_is_refused():
+    S = rplu.Server(budget_bytes=1 * MB, simulate=True)
+    with pytest.raises(rplu.RPLUError) as e:
+        S.submit_dense(_dense(1024))             # 4 MB
+    assert e.value.status == -1
+    S.close()
+
+
+def test_small_jobs_ready_together_share_a_batch():
+    """While one worker is busy with a large job, small jobs pile up and the
+    next free worker runs them as one batch."""
+    S = rplu.Server(budget_bytes=2 << 30, workers=1, batch_max_dim=512, simulate=True)
+    big = S.submit_dense(_dense(16000), k=1)     # runs alone, ~0.1 s
+    time.sleep(0.02)
+    small = [S.submit_dense(_dense(128 + q)) for q in range(16)]
+    _wait_all(S, [big] + small)
+    st = S.stats()
+    assert st["batched_jobs"] == 16 and st["batches"] == 1
+    S.close()
+
+
+def test_destroy_drains():
+    """close() returns only after every submitted job ran: six 36 MB jobs on
+    two workers need at least 3 x 3.6 ms of simulated work."""
+    S = rplu.Server(budget_bytes=256 * MB, workers=2, simulate=True)
+    A = _dense(3000)
+    t0 = time.time()
+    for _ in range(6):
+        S.submit_dense(A, k=1)
+    S.close()
+    assert time.time() - t0 >= 0.9 * 3 * _footprint(3000, 3000) / 1e10
+
+
+def test_cauchy_jobs_counted_per_class():
+    S = rplu.Server(budget_bytes=64 * MB, workers=2, simulate=True)
+    x = torch.zeros(5000, dtype=torch.complex128)
+    y = torch.zeros(4000, dtype=torch.complex128)
+    G = torch.zeros((5000, 2), dtype=torch.complex128)
+    B = torch.zeros((2, 4000), dtype=torch.complex128)
+    ts = [S.submit_cauchy(x, y, G, B, k=5) for _ in range(3)] + [S.submit_dense(_dense(300))]
+    _wait_all(S, ts)
+    st = S.stats()
+    assert st["p50_cauchy_ms"] > 0.0 and st["p50_dense_ms"] > 0.0 and st["completed"] == 4
+    S.close()
