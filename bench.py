@@ -15,6 +15,12 @@ step. Workloads:
   batched4096  4096 dense FP32 instances, n, m ~ U{64..1024}, sigma_i = r^i with
              r ~ U[0.5, 0.95], tol 1e-6, in one persistent autotuned launch;
              also times plain one-at-a-time FP64 rplu_dense on the same inputs
+  serve      Poisson arrivals at 200 jobs/s (--serve-seconds of arrivals) into
+             the continuous-batching server: 70% dense FP32 (n ~ U{256..8192},
+             sigma_i = 0.9^i, from a device pool of 64), 30% Cauchy-like
+             (n ~ U{1e4..1e5}, x in the unit disk, y in the annulus 2..3,
+             p = 1, from a pool of 32), tol 1e-6; reports completed jobs/s and
+             p50/p99 latency (a "step" is the whole arrival window)
 
 Prints one JSON line. The hot kernel's average launch duration is measured
 with HIP events on the library's stream over the timed region; the CPU
@@ -278,10 +284,17 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cauchy20k", choices=["cauchy20k", "dense32k", "dense512", "batched4096"])
+    ap.add_argument("--workload", default="cauchy20k", choices=["cauchy20k", "dense32k", "dense512", "batched4096", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true",
-                    help="batched4096: skip the one-at-a-time FP64 GPU baseline")
+                    help="batched4096/serve: skip the one-at-a-time FP64 GPU baseline")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="serve: length of the arrival window")
+    ap.add_argument("--serve-budget-gb", type=int, default=64,
+                    help="serve: slot pool of the server")
+    ap.add_argument("--serve-workers", type=int, default=4, help="serve: worker streams")
+    ap.add_argument("--serve-batch-dim", type=int, default=2048,
+                    help="serve: dense jobs up to this size are batched")
     ap.add_argument("--no-graph", action="store_true",
                     help="plain kernel launches instead of the default hipGraph replay")
     args = ap.parse_args()
@@ -298,6 +311,8 @@ def main() -> int:
         wl = _setup_cauchy20k(torch, rplu)
     elif args.workload == "batched4096":
         return _main_batched(args, torch, rplu)
+    elif args.workload == "serve":
+        return _main_serve(args, torch, rplu)
     else:
         wl = _setup_dense(torch, rplu, args.workload)
     ctx = rplu.default_context(0)
@@ -417,6 +432,123 @@ def _main_batched(args, torch, rplu) -> int:
             "how": "rplu_dense FP64, plain launches, one instance after another, tol 1e-6"}
         out["speedup_vs_fp64_one_at_a_time"] = value / (count / el64)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline("batched4096")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _dense_live(n, m, k, es):
+    return n * m * es + sum(2 * (n - t) * (m - t) * es for t in range(k))
+
+
+def _cauchy_flop(n, m, k):
+    return CAUCHY_FLOP_PER_PAIR * sum((n - t) * (m - t) for t in range(k + 1))
+
+
+def _main_serve(args, torch, rplu) -> int:
+    import workloads as W
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)   # noqa: E731
+    arrivals = W.serving_arrivals(rate=200.0, duration=args.serve_seconds, seed=5)
+    t0 = time.perf_counter()
+    dense_ns, dense_pool = W.serving_dense_pool()
+    cauchy_pool = W.serving_cauchy_pool()
+    torch.cuda.synchronize()
+    log(f"{len(arrivals)} arrivals; pools generated in {time.perf_counter() - t0:.1f} s")
+    K_DENSE, K_CAUCHY, TOL = 512, 64, 1e-6
+    # single-precision dense runs can sit at their rounding floor above the
+    # tolerance: the stall rule ends them instead of running to K_DENSE
+    FLAGS = rplu.RPLU_FLAG_STALL_STOP
+
+    def job_of(q, a):
+        if a.kind == "dense":
+            return ("dense", dense_pool[q % len(dense_pool)])
+        return ("cauchy", cauchy_pool[q % len(cauchy_pool)])
+
+    S = rplu.Server(budget_bytes=args.serve_budget_gb << 30, workers=args.serve_workers,
+                    batch_max_dim=args.serve_batch_dim)
+    # warm-up (kernel loading) outside the window
+    wt = {S.submit_dense(dense_pool[0], k=8, tol=TOL), S.submit_cauchy(*cauchy_pool[0], k=2, tol=TOL)}
+    while wt:
+        wt = {t for t in wt if S.poll(t) is None}
+        time.sleep(0.001)
+    done = []
+    pending = {}
+    start = time.perf_counter()
+    q, last_log = 0, 0.0
+    while q < len(arrivals) or pending:
+        now = time.perf_counter() - start
+        while q < len(arrivals) and arrivals[q].t <= now:
+            a = arrivals[q]
+            kind, inp = job_of(q, a)
+            if kind == "dense":
+                t = S.submit_dense(inp, k=K_DENSE, tol=TOL, seed=0, stream=a.stream, flags=FLAGS)
+                pending[t] = ("dense", inp.shape[0], inp.shape[1])
+            else:
+                t = S.submit_cauchy(*inp, k=K_CAUCHY, tol=TOL, seed=0, stream=a.stream, flags=FLAGS)
+                pending[t] = ("cauchy", inp[0].shape[0], inp[1].shape[0])
+            q += 1
+        for t in list(pending):
+            r = S.poll(t)
+            if r is not None:
+                kind, n, m = pending.pop(t)
+                done.append((kind, n, m, r.rank, r.stop, math.sqrt(r.res_fro2 / r.a_fro2)))
+        if now - last_log > 5.0:
+            st = S.stats()
+            log(f"t={now:.1f}s submitted {q} completed {len(done)} queued {st['queued']} "
+                f"active {st['active']}")
+            last_log = now
+        time.sleep(0.0005)
+    window = time.perf_counter() - start
+    st = S.stats()
+    S.close()
+    nd = sum(1 for d in done if d[0] == "dense")
+    live = sum(_dense_live(n, m, k, 4) for kind, n, m, k, _, _ in done if kind == "dense")
+    flop = sum(_cauchy_flop(n, m, k) for kind, n, m, k, _, _ in done if kind == "cauchy")
+    stops = {}
+    for d in done:
+        stops[f"{d[0]}:{d[4]}"] = stops.get(f"{d[0]}:{d[4]}", 0) + 1
+    out = {
+        "metric": METRIC, "value": len(done) / window, "unit": "approximations/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": window * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+c128", "data": "synthetic",
+        "config": {"workload": "serving: Poisson 200/s, 70% dense fp32 n~U{256..8192} "
+                               "sigma_i=0.9^i, 30% Cauchy-like n~U{1e4..1e5} p=1, tol 1e-6",
+                   "arrival_seconds": args.serve_seconds, "jobs": len(arrivals),
+                   "server": {"budget_GiB": args.serve_budget_gb, "workers": args.serve_workers,
+                              "batch_max_dim": args.serve_batch_dim},
+                   "k_cap": {"dense": K_DENSE, "cauchy": K_CAUCHY}},
+        "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"],
+                       "p50_dense": st["p50_dense_ms"], "p99_dense": st["p99_dense_ms"],
+                       "p50_cauchy": st["p50_cauchy_ms"], "p99_cauchy": st["p99_cauchy_ms"]},
+        "completed": {"dense": nd, "cauchy": len(done) - nd},
+        "window_s": window, "busy_s": st["busy_s"], "rejected": st["rejected"],
+        "batches": st["batches"], "batched_jobs": st["batched_jobs"],
+        "dense_GB_per_s_live": live / window / 1e9,
+        "cauchy_TFLOP_per_s": flop / window / 1e12,
+        "stops": stops,
+        "rel_residual_max": max(d[5] for d in done) if done else None,
+        "roofline": None,
+        "step_note": "one step = the whole window from the first arrival to the last "
+                     "completion; value = completed jobs / window",
+    }
+    if not args.no_fp64_baseline:
+        # the first 100 jobs one at a time: dense in FP64, Cauchy as served, no server
+        t1 = time.perf_counter()
+        cnt = 0
+        for q2, a in enumerate(arrivals[:100]):
+            kind, inp = job_of(q2, a)
+            if kind == "dense":
+                rplu.rplu_dense(inp.double(), k=K_DENSE, tol=TOL, seed=0, stream=a.stream,
+                                flags=rplu.RPLU_FLAG_NO_GRAPH | FLAGS)
+            else:
+                x, y, G, B = inp
+                rplu.rplu_cauchy(x, y, G.clone(), B.clone(), k=K_CAUCHY, tol=TOL, seed=0,
+                                 stream=a.stream, flags=rplu.RPLU_FLAG_NO_GRAPH | FLAGS)
+            cnt += 1
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        out["fp64_one_at_a_time"] = {"value": cnt / el, "unit": "approximations/s", "jobs": cnt,
+                                     "how": "the first 100 jobs, one after another, dense in FP64"}
+    out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
     return 0
 

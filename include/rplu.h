@@ -40,6 +40,7 @@
  *     zero mass is never drawn.
  *   - Stop test, before each draw, with T = ||S^(t)||_F^2 and T0 = ||A||_F^2:
  *     T == 0 -> EXHAUSTED; rel_tol > 0 and T <= rel_tol^2 T0 -> TOL;
+ *     optional stall rule -> STALL (RPLU_FLAG_STALL_STOP);
  *     t == kmax -> RANK (TOL_UNREACHED if rel_tol > 0), where
  *     kmax = min(n, m) if max_rank == 0, else min(max_rank, n, m).
  *   - Calls that take a hip_stream (a hipStream_t; NULL = default stream)
@@ -87,15 +88,29 @@ enum {
     RPLU_STOP_RANK = 1,
     RPLU_STOP_TOL = 2,
     RPLU_STOP_EXHAUSTED = 3,
-    RPLU_STOP_TOL_UNREACHED = 4
+    RPLU_STOP_TOL_UNREACHED = 4,
+    RPLU_STOP_STALL = 5        /* RPLU_FLAG_STALL_STOP: T stopped falling      */
 };
 
 enum {
     RPLU_FLAG_COLMASS = 1u << 0,  /* also reduce column masses in each sweep  */
     RPLU_FLAG_GRAPH = 1u << 1,    /* replay the step loop as a hipGraph (the
                                      default; accepted for clarity)            */
-    RPLU_FLAG_NO_GRAPH = 1u << 2  /* plain kernel launches, no hipGraph        */
+    RPLU_FLAG_NO_GRAPH = 1u << 2, /* plain kernel launches, no hipGraph        */
+    RPLU_FLAG_STALL_STOP = 1u << 3 /* stall rule (below), for tolerance runs
+                                     whose target may lie under the rounding
+                                     floor of single precision                */
 };
+
+/* Stall rule (a library extension, not from the paper): with
+ * RPLU_FLAG_STALL_STOP the run keeps the best total T_best and the step
+ * t_best where T last fell below (63/64) T_best (at the start T_best = T0,
+ * t_best = 0), and stops with RPLU_STOP_STALL at step t once
+ * t - t_best >= RPLU_STALL_WINDOW. A transient rise of T (one step can
+ * increase the residual) does not end the run; a residual at the rounding
+ * floor of the working precision does. Tested after the tolerance and before
+ * the rank limit. */
+#define RPLU_STALL_WINDOW 64
 
 /* Per-step trace words (opts.trace, RPLU_TRACE_WORDS doubles per step t):
  *  0 T        total mass ||S^(t)||_F^2 (last row prefix)
@@ -181,7 +196,7 @@ typedef struct {
     void* A;                /* dense input, overwritten by S^(rank)            */
     int64_t lda;
     int32_t p;              /* Cauchy displacement rank                        */
-    int32_t reserved;
+    uint32_t flags;         /* RPLU_FLAG_STALL_STOP honoured; others ignored   */
     const void* x;          /* Cauchy nodes and generators                     */
     const void* y;
     void* G;

@@ -6,7 +6,8 @@ never imports it, and the two share no code.
 """
 from .philox import philox4x64_10, step_uniforms, word_to_unit  # noqa: F401
 from .rplu import (  # noqa: F401
-    STOP_EXHAUSTED, STOP_RANK, STOP_TOL, STOP_TOL_UNREACHED, Draw,
+    STALL_RATIO, STALL_WINDOW, STOP_EXHAUSTED, STOP_RANK, STOP_STALL, STOP_TOL,
+    STOP_TOL_UNREACHED, Draw,
     NonFiniteInput, RPLUResult, ZeroPivot, cauchy_col, cauchy_entries,
     cauchy_generator_update, cauchy_row, cauchy_row_masses, first_exceeding,
     inverse_cdf, rplu_cauchy, rplu_dense, schur_closed_form, schur_update,

@@ -49,6 +49,17 @@ STOP_RANK = 1
 STOP_TOL = 2
 STOP_EXHAUSTED = 3
 STOP_TOL_UNREACHED = 4
+STOP_STALL = 5
+
+# Optional stall rule (a library extension, not from the paper): the run
+# keeps the best total T_best and the step t_best at which T last fell below
+# STALL_RATIO * T_best (T_best = T_0, t_best = 0 at the start); it stops at
+# step t when t - t_best reaches STALL_WINDOW. This ends tolerance runs whose
+# target lies under the rounding floor of the working precision, where T
+# stops falling, while a transient rise of T (a step can increase the
+# residual) does not end the run.
+STALL_WINDOW = 64
+STALL_RATIO = 63.0 / 64.0
 
 
 class NonFiniteInput(ValueError):
@@ -124,11 +135,20 @@ class RPLUResult:
     masses: list = field(default_factory=list)   # rowmass per step if asked
 
 
-def _stop_reason(t: int, T: float, T0: float, kmax: int, tol: float) -> int:
+def _stop_reason(t: int, T: float, T0: float, kmax: int, tol: float, stall_ref=None) -> int:
+    """Stop test before the draw of step t. stall_ref: None (no stall rule)
+    or a two-element list [T_best, t_best], updated here."""
     if T == 0.0:
         return STOP_EXHAUSTED
     if tol > 0.0 and T <= (tol * tol) * T0:
         return STOP_TOL
+    if stall_ref is not None:
+        if t == 0:
+            stall_ref[0], stall_ref[1] = T, 0
+        elif T < STALL_RATIO * stall_ref[0]:
+            stall_ref[0], stall_ref[1] = T, t
+        if t - stall_ref[1] >= STALL_WINDOW:
+            return STOP_STALL
     if t == kmax:
         return STOP_TOL_UNREACHED if tol > 0.0 else STOP_RANK
     return 0
@@ -168,7 +188,7 @@ def schur_update(S: np.ndarray, i: int, j: int):
 
 def rplu_dense(A: np.ndarray, k: int = 0, tol: float = 0.0, seed: int = 0,
                stream: int = 0, forced: Optional[Sequence] = None,
-               keep_masses: bool = False) -> RPLUResult:
+               keep_masses: bool = False, stall: bool = False) -> RPLUResult:
     """Alg. 1 with two-stage exact sampling (Sec. 4.1).
 
     forced: optional sequence of (i, j) pivots to use instead of the draws
@@ -184,6 +204,7 @@ def rplu_dense(A: np.ndarray, k: int = 0, tol: float = 0.0, seed: int = 0,
     piv = np.full((kmax, 2), -1, dtype=np.int64)
     trace, masses = [], []
     T0 = None
+    stall_ref = [0.0, 0] if stall else None
     t = 0
     while True:
         rowmass = np.sum(squared_magnitude(S), axis=1)
@@ -192,7 +213,7 @@ def rplu_dense(A: np.ndarray, k: int = 0, tol: float = 0.0, seed: int = 0,
             raise NonFiniteInput("non-finite entry in the input")
         if t == 0:
             T0 = T
-        stop = _stop_reason(t, T, T0, kmax, tol)
+        stop = _stop_reason(t, T, T0, kmax, tol, stall_ref)
         if stop:
             break
         if keep_masses:
@@ -276,7 +297,8 @@ def cauchy_generator_update(x, y, G, B, i: int, j: int):
 
 def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
                 stream: int = 0, forced: Optional[Sequence] = None,
-                keep_masses: bool = False, mass_steps: Optional[set] = None) -> RPLUResult:
+                keep_masses: bool = False, mass_steps: Optional[set] = None,
+                stall: bool = False) -> RPLUResult:
     """Alg. 3 with exact row masses (no rejection), generators in complex128.
 
     mass_steps: if given, row masses (and hence the draw check) are computed
@@ -296,6 +318,9 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
     trace, masses = [], []
     T0 = None
     T = float("nan")
+    stall_ref = [0.0, 0] if stall else None
+    if stall and mass_steps is not None:
+        raise ValueError("the stall rule needs the total at every step")
     t = 0
     while True:
         need_mass = mass_steps is None or t in mass_steps or t == 0
@@ -306,7 +331,7 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
                 raise NonFiniteInput("non-finite generator or node data")
             if t == 0:
                 T0 = T
-            stop = _stop_reason(t, T, T0, kmax, tol)
+            stop = _stop_reason(t, T, T0, kmax, tol, stall_ref)
         else:
             stop = STOP_RANK if t == kmax else 0
         if stop:

@@ -29,7 +29,9 @@ RPLU_E_ARG, RPLU_E_NOMEM, RPLU_E_HIP, RPLU_E_NONFINITE = -1, -2, -3, -4
 RPLU_E_BUSY, RPLU_E_UNSUPPORTED, RPLU_E_ZERO_PIVOT = -5, -6, -7
 RPLU_R32, RPLU_R64, RPLU_C64, RPLU_C128 = 1, 2, 3, 4
 RPLU_STOP_RANK, RPLU_STOP_TOL, RPLU_STOP_EXHAUSTED, RPLU_STOP_TOL_UNREACHED = 1, 2, 3, 4
-RPLU_FLAG_COLMASS, RPLU_FLAG_GRAPH, RPLU_FLAG_NO_GRAPH = 1, 2, 4
+RPLU_STOP_STALL = 5
+RPLU_FLAG_COLMASS, RPLU_FLAG_GRAPH, RPLU_FLAG_NO_GRAPH, RPLU_FLAG_STALL_STOP = 1, 2, 4, 8
+RPLU_STALL_WINDOW = 64
 RPLU_TRACE_WORDS = 12
 RPLU_JOB_DENSE, RPLU_JOB_CAUCHY = 1, 2
 RPLU_ORDER_AREA, RPLU_ORDER_CUBE, RPLU_ORDER_GIVEN = 1, 2, 3
@@ -53,7 +55,7 @@ class rplu_info(C.Structure):
 
 class rplu_job(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("n", C.c_int64), ("m", C.c_int64),
-                ("A", C.c_void_p), ("lda", C.c_int64), ("p", C.c_int32), ("reserved", C.c_int32),
+                ("A", C.c_void_p), ("lda", C.c_int64), ("p", C.c_int32), ("flags", C.c_uint32),
                 ("x", C.c_void_p), ("y", C.c_void_p), ("G", C.c_void_p), ("B", C.c_void_p),
                 ("piv", C.c_void_p), ("L", C.c_void_p), ("ldl", C.c_int64), ("U", C.c_void_p),
                 ("ldu", C.c_int64), ("max_rank", C.c_int64), ("rel_tol", C.c_double),
@@ -289,7 +291,7 @@ def _per_job(v, count, name):
     return [v] * count
 
 
-def _batch_jobs(As, k, tol, seed, streams, store_L, store_U, kind_check=True):
+def _batch_jobs(As, k, tol, seed, streams, store_L, store_U, flags=0):
     count = len(As)
     ks, tols, seeds = _per_job(k, count, "k"), _per_job(tol, count, "tol"), _per_job(seed, count, "seed")
     streams = list(range(count)) if streams is None else _per_job(streams, count, "streams")
@@ -313,6 +315,7 @@ def _batch_jobs(As, k, tol, seed, streams, store_L, store_U, kind_check=True):
         j.U, j.ldu = (U.data_ptr(), m) if U is not None else (None, 0)
         j.max_rank, j.rel_tol = kk, float(tols[b])
         j.seed, j.stream = int(seeds[b]) & (2**64 - 1), int(streams[b]) & (2**64 - 1)
+        j.flags = int(flags)
         outs.append((piv, Lt, U))
     return jobs, outs
 
@@ -322,11 +325,11 @@ class BatchPlan:
     table, for repeated launches (the matrices are overwritten by each run)."""
 
     def __init__(self, As, k=0, tol=0.0, seed=0, streams=None, store_L: bool = True,
-                 store_U: bool = True, ctx: Optional[Context] = None):
+                 store_U: bool = True, ctx: Optional[Context] = None, flags: int = 0):
         self.count = len(As)
         self.device = As[0].device if self.count else torch.device("cuda", 0)
         self.ctx = ctx or default_context(self.device.index or 0)
-        self.jobs, self.outs = _batch_jobs(As, k, tol, seed, streams, store_L, store_U)
+        self.jobs, self.outs = _batch_jobs(As, k, tol, seed, streams, store_L, store_U, flags)
         self.infos = (rplu_info * max(self.count, 1))()
         self._keep = list(As)
 
@@ -360,7 +363,7 @@ class BatchPlan:
 
 def rplu_batched(As, k=0, tol=0.0, seed=0, streams=None, store_L: bool = True,
                  store_U: bool = True, cfg: Optional[dict] = None, raise_on_error: bool = True,
-                 ctx: Optional[Context] = None) -> list:
+                 ctx: Optional[Context] = None, flags: int = 0) -> list:
     """Dense RPLU of every matrix in As (float32 or float64 CUDA tensors, one
     dtype; each overwritten by its final Schur complement) in one persistent
     launch. k, tol, seed may be scalars or per-job lists; streams defaults to
@@ -368,7 +371,7 @@ def rplu_batched(As, k=0, tol=0.0, seed=0, streams=None, store_L: bool = True,
     = tuned). Returns one Result per job."""
     if len(As) == 0:
         return []
-    plan = BatchPlan(As, k, tol, seed, streams, store_L, store_U, ctx)
+    plan = BatchPlan(As, k, tol, seed, streams, store_L, store_U, ctx, flags)
     plan.run(cfg, raise_on_error)
     return plan.results()
 
@@ -441,7 +444,8 @@ class Server:
         return t.value
 
     def submit_dense(self, A: torch.Tensor, k: int = 0, tol: float = 0.0, seed: int = 0,
-                     stream: int = 0, store_L: bool = True, store_U: bool = True) -> int:
+                     stream: int = 0, store_L: bool = True, store_U: bool = True,
+                     flags: int = 0) -> int:
         """A is read (never modified); it must stay valid until poll returns."""
         if A.dim() != 2 or A.stride(1) != 1 or A.dtype not in _DTYPES:
             raise ValueError("A: 2-D CUDA tensor with unit column stride")
@@ -457,10 +461,12 @@ class Server:
         j.U, j.ldu = (U.data_ptr(), m) if U is not None else (None, 0)
         j.max_rank, j.rel_tol = int(k), float(tol)
         j.seed, j.stream = int(seed) & (2**64 - 1), int(stream) & (2**64 - 1)
+        j.flags = int(flags)
         return self._submit(j, (A, piv, Lt, U))
 
     def submit_cauchy(self, x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
-                      stream: int = 0, store_L: bool = True, store_U: bool = True) -> int:
+                      stream: int = 0, store_L: bool = True, store_U: bool = True,
+                      flags: int = 0) -> int:
         """x, y, G, B are read (never modified); they must stay valid until poll returns."""
         n, m, p = x.shape[0], y.shape[0], G.shape[1]
         for t_ in (x, y, G, B):
@@ -479,6 +485,7 @@ class Server:
         j.U, j.ldu = (U.data_ptr(), m) if U is not None else (None, 0)
         j.max_rank, j.rel_tol = int(k), float(tol)
         j.seed, j.stream = int(seed) & (2**64 - 1), int(stream) & (2**64 - 1)
+        j.flags = int(flags)
         return self._submit(j, (x, y, G, B, piv, Lt, U))
 
     def poll(self, ticket: int):

@@ -455,6 +455,7 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, voi
     sa.stream = opts->stream;
     sa.kmax = kmax;
     sa.tol2 = a.tol2;
+    sa.stall = (opts->flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
     sa.forced = opts->forced;
     sa.trace = opts->trace;
     sa.rowmass_out = opts->rowmass_out;
@@ -569,6 +570,7 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     sa.stream = opts->stream;
     sa.kmax = kmax;
     sa.tol2 = a.tol2;
+    sa.stall = (opts->flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
     sa.forced = opts->forced;
     sa.trace = opts->trace;
     sa.rowmass_out = opts->rowmass_out;

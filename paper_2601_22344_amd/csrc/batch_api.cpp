@@ -61,6 +61,7 @@ rplu_status prepare(int64_t count, const rplu_job* jobs, Prepared& P, const char
         q.vec = ((uintptr_t)j.A % 16 == 0) && ((j.lda * es) % 16 == 0) &&
                 (j.U == nullptr || (((uintptr_t)j.U % 16 == 0) && ((j.ldu * es) % 16 == 0)));
         q.tol2 = j.rel_tol * j.rel_tol;
+        q.stall = (j.flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
         q.seed = j.seed;
         q.stream = j.stream;
         P.maxn = std::max(P.maxn, q.n);

@@ -242,8 +242,8 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
     int nalive = n;
     bt_sweep<T, R, V, true>(S, lda, m, -1, -1, s_l, nullptr, s_rm, s_alive, nalive);
     __syncthreads();
-    double T0 = 0.0, Tc = 0.0;
-    int t = 0, stop = 0, err = 0, prev_i = -1;
+    double T0 = 0.0, Tc = 0.0, Tbest = 0.0;
+    int t = 0, stop = 0, err = 0, prev_i = -1, tbest = 0;
     for (;; ++t) {
         if (prev_i >= 0) {
             // the previous pivot row leaves the live list (the barriers of
@@ -258,10 +258,12 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
         }
         auto rmass = [&](int e) { return s_rm[e]; };
         Tc = bt_levels(n, sh.ctr, rmass, sh);
-        if (t == 0) T0 = Tc;
+        if (t == 0) { T0 = Tc; Tbest = Tc; tbest = 0; }
+        else if (Tc < RPLU_STALL_RATIO * Tbest) { Tbest = Tc; tbest = t; }
         if (!isfinite(Tc)) err = RPLU_E_NONFINITE;
         else if (Tc == 0.0) stop = RPLU_STOP_EXHAUSTED;
         else if (jb.tol2 > 0.0 && Tc <= jb.tol2 * T0) stop = RPLU_STOP_TOL;
+        else if (jb.stall && t - tbest >= RPLU_STALL_WINDOW) stop = RPLU_STOP_STALL;
         else if (t >= jb.kmax) stop = jb.tol2 > 0.0 ? RPLU_STOP_TOL_UNREACHED : RPLU_STOP_RANK;
         if (err || stop) break;
         const Philox4 rnd = philox4x64_10((uint64_t)t, jb.stream, 0, 0, jb.seed, 0);

@@ -183,6 +183,8 @@ __device__ inline double wave_incl_scan(double v, int lane) {
 
 // --------------------------------------------------------------- state
 
+constexpr double RPLU_STALL_RATIO = 63.0 / 64.0;   // see RPLU_FLAG_STALL_STOP
+
 // Per-run device state. The row sampler of step t reads t, runs the stop
 // test, and records cur = t and the row i; the column sampler records j, the
 // pivot and its reciprocal and sets t = t + 1; the other kernels of the step
@@ -196,6 +198,9 @@ struct StepState {
     int32_t i, j;       // current pivot
     int32_t pad;
     double T0, T;       // ||A||_F^2 and the latest total
+    double T_best;      // stall rule: best total so far and the step it was
+    int32_t t_best;     // reached (an improvement is a fall below 63/64 of it)
+    int32_t pad2;
     double a_re, a_im;  // pivot entry
     double inv_re, inv_im;  // 1/a in FP64
     double row_tgt, row_lo, row_hi;   // row draw: target u1*T and its bin edges

@@ -59,6 +59,7 @@ struct SampleArgs {
     uint64_t seed, stream;
     int64_t kmax;
     double tol2;
+    int stall;           // RPLU_FLAG_STALL_STOP
     const int32_t* forced;
     double* trace;
     double* rowmass_out;
@@ -116,6 +117,8 @@ struct BatchJob {
     int64_t lda, ldl, ldu;
     int32_t n, m, kmax;
     int32_t vec;         // 16-byte packs aligned for A and U (as rplu_dense decides)
+    int32_t stall;       // RPLU_FLAG_STALL_STOP
+    int32_t pad;
     double tol2;
     uint64_t seed, stream;
 };

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void k_ct_vec(const double* __restrict__ v, in
 __global__ __launch_bounds__(CDF_THREADS) void k_sample_row(
     const double* __restrict__ rowmass, const double* __restrict__ ct, int n,
     StepState* __restrict__ st, uint64_t seed, uint64_t stream, int kmax, double tol2,
-    const int32_t* __restrict__ forced, double* __restrict__ rowmass_out) {
+    int stall, const int32_t* __restrict__ forced, double* __restrict__ rowmass_out) {
     __shared__ CdfShared sh;
     __shared__ int s_flag;
     if (st->done) return;
@@ -38,9 +38,14 @@ __global__ __launch_bounds__(CDF_THREADS) void k_sample_row(
     if (threadIdx.x == 0) {
         int stop = 0, err = 0;
         const double T0 = (t == 0) ? T : st->T0;
+        if (stall) {
+            if (t == 0) { st->T_best = T; st->t_best = 0; }
+            else if (T < RPLU_STALL_RATIO * st->T_best) { st->T_best = T; st->t_best = t; }
+        }
         if (!isfinite(T)) err = RPLU_E_NONFINITE;
         else if (T == 0.0) stop = RPLU_STOP_EXHAUSTED;
         else if (tol2 > 0.0 && T <= tol2 * T0) stop = RPLU_STOP_TOL;
+        else if (stall && t - st->t_best >= RPLU_STALL_WINDOW) stop = RPLU_STOP_STALL;
         else if (t >= kmax) stop = tol2 > 0.0 ? RPLU_STOP_TOL_UNREACHED : RPLU_STOP_RANK;
         st->T = T;
         if (t == 0) st->T0 = T;
@@ -150,7 +155,7 @@ void launch_ct_vec(const double* v, int64_t len, double* ct, StepState* st, hipS
 
 void launch_sample_row(const SampleArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_sample_row, dim3(1), dim3(CDF_THREADS), 0, s, a.rowmass, a.ct_row,
-                       (int)a.n, a.st, a.seed, a.stream, (int)a.kmax, a.tol2, a.forced,
+                       (int)a.n, a.st, a.seed, a.stream, (int)a.kmax, a.tol2, a.stall, a.forced,
                        a.rowmass_out);
 }
 

@@ -184,7 +184,8 @@ void run_single(rplu_server_s* S, Worker& W, SJob* j) {
     o.rel_tol = d.rel_tol;
     o.seed = d.seed;
     o.stream = d.stream;
-    o.flags = RPLU_FLAG_NO_GRAPH;          // every job has new buffers: nothing to reuse
+    // every job has new buffers: no graph to reuse
+    o.flags = RPLU_FLAG_NO_GRAPH | (d.flags & RPLU_FLAG_STALL_STOP);
     hipStream_t s = W.stream;
     if (j->cls == CLS_DENSE) {
         const size_t es = dtype_size(d.dtype), pitch = (size_t)d.lda * es;

@@ -322,6 +322,38 @@ def pin_stop_rules():
     assert res.rank == 3 and res.stop == O.STOP_EXHAUSTED
 
 
+def stall_cases():
+    """Diagonal inputs whose totals are exact in FP32 and FP64: entries are
+    powers of two and a pivot on the diagonal removes exactly its own mass.
+    Each case: (diagonal squared, forced pivot order, k, expected stop,
+    expected rank)."""
+    eps = 2.0 ** -40
+    # one unit of mass that is never pivoted; pivots on tiny entries leave T
+    # flat: no improvement after t = 0, stall at t = 64
+    flat = ([1.0] + [eps] * 71, list(range(1, 72)), 70, O.STOP_STALL, 64)
+    # the first pivot removes 4 of 5 (an improvement at t = 1), then flat:
+    # stall at t = 65
+    late = ([4.0, 1.0] + [eps] * 70, [0] + list(range(2, 72)), 70, O.STOP_STALL, 65)
+    # unit masses: T_t = 72 - t keeps improving by more than 1/64 every
+    # few steps: no stall, the rank limit ends the run
+    unit = ([1.0] * 72, list(range(72)), 70, O.STOP_RANK, 70)
+    return [flat, late, unit]
+
+
+def pin_stall_rule():
+    """Stall rule on diagonal inputs with forced pivots (totals exact, see
+    stall_cases): the stop step pins the window length, the >= comparison and
+    the refresh of the best total."""
+    for d2, order, k, stop, rank in stall_cases():
+        D = np.diag(np.sqrt(np.array(d2)))
+        forced = [(q, q) for q in order[:k]]
+        r = O.rplu_dense(D, k=k, seed=1, forced=forced, stall=True)
+        assert (r.stop, r.rank) == (stop, rank), (r.stop, r.rank, stop, rank)
+        r = O.rplu_dense(D, k=k, seed=1, forced=forced, stall=False)
+        assert (r.stop, r.rank) == (O.STOP_RANK, k)
+    return True
+
+
 def pin_nonfinite():
     A = W.random_dense(4, 4, seed=1)
     A[2, 1] = np.nan
@@ -401,6 +433,7 @@ def pin_loewner_entries():
 
 
 ALL_PINS = [
+    pin_stall_rule,
     pin_philox_numpy, pin_inverse_cdf_bruteforce, pin_chi2_first_pivot,
     pin_chi2_second_pivot, pin_one_step_expectation, pin_unitary_dft,
     pin_doubling_enumeration, pin_closed_form_schur, pin_exact_recovery,

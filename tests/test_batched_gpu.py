@@ -212,3 +212,24 @@ def test_batched_full_size_sampled(rplu_lib):
         r1 = rplu_lib.rplu_dense(A, k=0, tol=1e-6, seed=0, stream=b, store_L=False)
         assert torch.equal(r1.piv, res[b].piv) and torch.equal(A, mats[b]), b
         assert torch.equal(r1.U, res[b].U) and r1.res_fro2 == res[b].res_fro2, b
+
+
+def test_batched_stall_rule(rplu_lib):
+    """The stall rule in the batched kernel stops where rplu_dense does. On
+    an identity of size N every step removes one unit of mass, so an
+    improvement by 1/64 of the best total takes N/64 steps: N = 4096 stalls
+    at t = 64 (4032 is not below 63/64 of 4096), N = 4095 improves just in
+    time in every window and reaches the rank limit."""
+    F = rplu_lib.RPLU_FLAG_STALL_STOP
+    mats = [torch.eye(4096, device=DEV), torch.eye(4095, device=DEV)]
+    try:
+        res = rplu_lib.rplu_batched([m.clone() for m in mats], k=150, seed=1, flags=F)
+    except rplu_lib.RPLUError as e:
+        assert e.status == -6          # workgroups get less LDS than 4096 rows need
+        pytest.skip("4096 rows exceed this device's LDS per workgroup")
+    assert [(r.stop, r.rank) for r in res] == [(rplu_lib.RPLU_STOP_STALL, 64),
+                                                (rplu_lib.RPLU_STOP_RANK, 150)]
+    for b, m in enumerate(mats):
+        a = rplu_lib.rplu_dense(m.clone(), k=150, seed=1, stream=b, flags=F)
+        assert (a.stop, a.rank) == (res[b].stop, res[b].rank)
+        assert torch.equal(a.piv, res[b].piv)

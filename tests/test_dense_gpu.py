@@ -210,3 +210,20 @@ def test_chi2_first_pivot_gpu(rplu_lib):
     p = (A * A).ravel() / np.sum(A * A)
     stat = np.sum((counts - N * p) ** 2 / (N * p))
     assert stats.chi2.sf(stat, 35) > 1e-3
+
+
+@pytest.mark.parametrize("dt", ["r64", "r32"])
+def test_stall_rule(rplu_lib, dt):
+    """Stall rule against the oracle on the pinned diagonal cases (totals
+    exact in both precisions), with the pivot order forced."""
+    import pins
+    rplu = rplu_lib
+    for d2, order, k, stop, rank in pins.stall_cases():
+        D = np.diag(np.sqrt(np.array(d2)))
+        forced = [(q, q) for q in order[:k]]
+        A = torch.from_numpy(D).to(TORCH[dt]).to(DEV)
+        r = rplu.rplu_dense(A, k=k, seed=1, flags=rplu.RPLU_FLAG_STALL_STOP,
+                            forced=torch.tensor(forced, dtype=torch.int32))
+        o = O.rplu_dense(D, k=k, seed=1, forced=forced, stall=True)
+        assert (r.stop, r.rank) == (o.stop, o.rank) == (stop, rank)
+        assert r.res_fro2 == o.res_fro2

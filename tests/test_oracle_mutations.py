@@ -114,11 +114,50 @@ def _philox_no_bump(counter, key):
     return c0, c1, c2, c3
 
 
-def _stop_tol_linear(t, T, T0, kmax, tol):
+def _stop_tol_linear(t, T, T0, kmax, tol, stall_ref=None):
     if T == 0.0:
         return O.STOP_EXHAUSTED
     if tol > 0.0 and T <= tol * T0:     # tol instead of tol^2
         return O.STOP_TOL
+    if stall_ref is not None:
+        if t == 0:
+            stall_ref[0], stall_ref[1] = T, 0
+        elif T < O.STALL_RATIO * stall_ref[0]:
+            stall_ref[0], stall_ref[1] = T, t
+        if t - stall_ref[1] >= O.STALL_WINDOW:
+            return O.STOP_STALL
+    if t == kmax:
+        return O.STOP_TOL_UNREACHED if tol > 0.0 else O.STOP_RANK
+    return 0
+
+
+def _stop_stall_late(t, T, T0, kmax, tol, stall_ref=None):
+    if T == 0.0:
+        return O.STOP_EXHAUSTED
+    if tol > 0.0 and T <= (tol * tol) * T0:
+        return O.STOP_TOL
+    if stall_ref is not None:
+        if t == 0:
+            stall_ref[0], stall_ref[1] = T, 0
+        elif T < O.STALL_RATIO * stall_ref[0]:
+            stall_ref[0], stall_ref[1] = T, t
+        if t - stall_ref[1] > O.STALL_WINDOW:              # > instead of >=
+            return O.STOP_STALL
+    if t == kmax:
+        return O.STOP_TOL_UNREACHED if tol > 0.0 else O.STOP_RANK
+    return 0
+
+
+def _stop_stall_no_update(t, T, T0, kmax, tol, stall_ref=None):
+    if T == 0.0:
+        return O.STOP_EXHAUSTED
+    if tol > 0.0 and T <= (tol * tol) * T0:
+        return O.STOP_TOL
+    if stall_ref is not None:
+        if t == 0:
+            stall_ref[0], stall_ref[1] = T, 0                # best never refreshed
+        if t - stall_ref[1] >= O.STALL_WINDOW:
+            return O.STOP_STALL
     if t == kmax:
         return O.STOP_TOL_UNREACHED if tol > 0.0 else O.STOP_RANK
     return 0
@@ -167,6 +206,8 @@ MUTATIONS = [
     ("gen_conj_pivot", "cauchy_generator_update", _gen_swap, [pins.pin_cauchy_vs_dense]),
     ("col_denominator", "cauchy_col", _col_sign, [pins.pin_cauchy_vs_dense, pins.pin_loewner_entries]),
     ("stop_tol_linear", "_stop_reason", _stop_tol_linear, [pins.pin_stop_rules]),
+    ("stall_late", "_stop_reason", _stop_stall_late, [pins.pin_stall_rule]),
+    ("stall_no_update", "_stop_reason", _stop_stall_no_update, [pins.pin_stall_rule]),
     ("col_stage_transposed", "rplu_dense", _rplu_dense_colstage_from_column, [pins.pin_chi2_first_pivot, pins.pin_mass_bookkeeping]),
 ]
 

@@ -342,3 +342,55 @@ def serving_arrivals(rate: float = 200.0, duration: float = 60.0, seed: int = 5,
             out.append(Arrival(t, "cauchy", n, k))
         k += 1
     return out
+
+
+def serving_dense_pool(count: int = 64, n_range=(256, 8192), decay: float = 0.9, seed: int = 5,
+                       rank_cut: int = 320, device="cuda:0", dtype=None):
+    """The dense inputs of the serving workload: `count` square matrices with
+    n ~ U{n_range} (numpy default_rng(seed + 1)), A = U diag(decay^i) V^T with
+    U, V the orthonormal Q factors of device Gaussians. Singular values past
+    rank_cut (decay^320 ~ 2e-15 for 0.9) are below single precision relative
+    to sigma_1 and are left out. Returns (list of n, list of tensors)."""
+    import torch
+    dtype = dtype or torch.float32
+    rng = np.random.default_rng(seed + 1)
+    ns = [int(v) for v in rng.integers(n_range[0], n_range[1] + 1, size=count)]
+    shapes, seeds = [], []
+    for q, n in enumerate(ns):
+        r = min(n, rank_cut)
+        shapes += [(n, r), (n, r)]
+        seeds += [(seed << 32) + 2 * q + 1_000_000, (seed << 32) + 2 * q + 1_000_001]
+    Q = _stiefel_batched_device(shapes, seeds, device)
+    out = []
+    for q, n in enumerate(ns):
+        r = min(n, rank_cut)
+        sig = decay ** torch.arange(1, r + 1, device=device, dtype=torch.float64)
+        A = (Q[2 * q] * sig[None, :]) @ Q[2 * q + 1].T.contiguous()
+        out.append(A.to(dtype).contiguous())
+        Q[2 * q] = Q[2 * q + 1] = None
+    return ns, out
+
+
+def serving_cauchy_pool(count: int = 32, n_range=(10_000, 100_000), seed: int = 5,
+                        device="cuda:0"):
+    """The Cauchy-like inputs of the serving workload: square n ~ U{n_range}
+    (numpy default_rng(seed + 2)); x uniform in the unit disk, y uniform in
+    the annulus 2 <= |y| <= 3, p = 1 with g, b ~ CN(0, 1) (a scaled Cauchy
+    matrix), drawn on the device from torch's generator. Returns a list of
+    (x, y, G, B) complex128 tensors."""
+    import torch
+    rng = np.random.default_rng(seed + 2)
+    ns = [int(v) for v in rng.integers(n_range[0], n_range[1] + 1, size=count)]
+    g = torch.Generator(device=device)
+    out = []
+    f64 = torch.float64
+    for q, n in enumerate(ns):
+        g.manual_seed((seed << 32) + 2_000_000 + q)
+        u = torch.rand(4, n, generator=g, device=device, dtype=f64)
+        x = torch.sqrt(u[0]) * torch.exp(2j * math.pi * u[1])
+        y = torch.sqrt(4.0 + 5.0 * u[2]) * torch.exp(2j * math.pi * u[3])
+        z = torch.randn(4, n, generator=g, device=device, dtype=f64) / math.sqrt(2.0)
+        G = (z[0] + 1j * z[1]).reshape(n, 1).contiguous()
+        B = (z[2] + 1j * z[3]).reshape(1, n).contiguous()
+        out.append((x.contiguous(), y.contiguous(), G, B))
+    return out
