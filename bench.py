@@ -43,7 +43,10 @@ sys.path.insert(0, ROOT)
 METRIC = "RPLU rank-k approximations/sec and GB/s at rel err ≤1e-6; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_PEAK_TF = 78.6     # MI355X FP64 vector, TFLOP/s
-CAUCHY_FLOP_PER_PAIR = 7       # complex difference 2, |d|^2 3, divide 1, accumulate 1 (p = 1)
+# Algorithmic FLOP per (row, column) pair of the Cauchy-like mass pass, p = 1:
+# complex difference 2, |d|^2 3, multiply-accumulate 2, the p x p Hermitian
+# form 4 p^2, and the reciprocal of |d|^2 counted as one.
+CAUCHY_FLOP_PER_PAIR = 7 + 4 * 1 * 1 + 1
 KERNEL_SOURCES = ["common.hpp", "cdf.hpp", "dense.hip", "cauchy.hip", "batched.hip"]
 
 
@@ -55,13 +58,18 @@ def _source_sha() -> str:
     return h.hexdigest()[:16]
 
 
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
+HOT_KERNEL = {"cauchy20k": "k_cauchy_mass", "dense32k": "k_dense_sweep",
+              "dense512": "k_dense_sweep", "batched4096": "k_batched"}
+CALIBRATION_BYTES = 1 << 30
+
+
 def _traffic(workload: str, launches: int):
     """Counter-measured HBM bytes per launch of the hot kernel, from the
     committed rocprofv3 --pmc summary, if it was taken on the current kernel
     sources; otherwise None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
-        with open(path) as fh:
+        with open(TRAFFIC_PATH) as fh:
             tab = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -69,6 +77,77 @@ def _traffic(workload: str, launches: int):
     if not e or e.get("source_sha") != _source_sha():
         return None
     return e.get("bytes_per_launch")
+
+
+def _calibrate_copy() -> int:
+    """A plain device copy of CALIBRATION_BYTES (read and written once), run
+    under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    src = torch.ones(CALIBRATION_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": CALIBRATION_BYTES, "copies": 3}), flush=True)
+    return 0
+
+
+def _pmc_rows(d: str):
+    """(kernel name, counter name, value) rows of every counter_collection
+    CSV that rocprofv3 wrote under directory d."""
+    import csv
+    rows = []
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith("counter_collection.csv"):
+                with open(os.path.join(root, f)) as fh:
+                    for r in csv.DictReader(fh):
+                        rows.append((r.get("Kernel_Name", ""), r.get("Counter_Name", ""),
+                                     float(r.get("Counter_Value", "nan"))))
+    return rows
+
+
+def _pmc_median(rows, counter: str, pattern: str):
+    """Median over the hot kernel's dispatches (the batched workload's
+    autotuner also launches it on single-job warm-ups)."""
+    vals = sorted(v for k, c, v in rows if c == counter and pattern in k)
+    return (vals[len(vals) // 2], len(vals)) if vals else (None, 0)
+
+
+def _ingest_pmc(workload: str, dirs, command: str) -> int:
+    """Scales the hot kernel's FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+    by the ratio the same counters read for the calibration copy, and records
+    bytes per launch in profiles/traffic.json (keyed by workload and by the
+    sha of the kernel sources)."""
+    fetch_dir, write_dir, cal_fetch_dir, cal_write_dir = dirs
+    pat = HOT_KERNEL[workload]
+    f_kib, nf = _pmc_median(_pmc_rows(fetch_dir), "FETCH_SIZE", pat)
+    w_kib, nw = _pmc_median(_pmc_rows(write_dir), "WRITE_SIZE", pat)
+    # the largest dispatch of the calibration run is the 1 GiB copy
+    cf = sorted(v for k, c, v in _pmc_rows(cal_fetch_dir) if c == "FETCH_SIZE")
+    cw = sorted(v for k, c, v in _pmc_rows(cal_write_dir) if c == "WRITE_SIZE")
+    if f_kib is None or w_kib is None or not cf or not cw:
+        print(json.dumps({"error": "counters not found", "fetch": nf, "write": nw}))
+        return 1
+    kib = CALIBRATION_BYTES / 1024.0
+    fac_f, fac_w = cf[-1] / kib, cw[-1] / kib
+    fetch_b, write_b = f_kib * 1024.0 / fac_f, w_kib * 1024.0 / fac_w
+    try:
+        with open(TRAFFIC_PATH) as fh:
+            tab = json.load(fh)
+    except (OSError, ValueError):
+        tab = {}
+    tab[workload] = {"kernel": pat, "bytes_per_launch": fetch_b + write_b,
+                     "fetch_bytes": fetch_b, "write_bytes": write_b,
+                     "fetch_kib_raw": f_kib, "write_kib_raw": w_kib,
+                     "dispatches": [nf, nw], "copy_factor_fetch": fac_f,
+                     "copy_factor_write": fac_w, "source_sha": _source_sha(),
+                     "command": command}
+    with open(TRAFFIC_PATH, "w") as fh:
+        json.dump(tab, fh, indent=1, sort_keys=True)
+    print(json.dumps(tab[workload]))
+    return 0
 
 
 # ------------------------------------------------------------------ workloads
@@ -297,7 +376,17 @@ def main() -> int:
                     help="serve: dense jobs up to this size are batched")
     ap.add_argument("--no-graph", action="store_true",
                     help="plain kernel launches instead of the default hipGraph replay")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (for rocprofv3 --pmc scaling)")
+    ap.add_argument("--ingest-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR",
+                                                      "CAL_WRITE_DIR"),
+                    help="write profiles/traffic.json for --workload from rocprofv3 --pmc output")
+    ap.add_argument("--pmc-command", default="", help="with --ingest-pmc: the command profiled")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        return _ingest_pmc(args.workload, args.ingest_pmc, args.pmc_command)
+    if args.calibrate_copy:
+        return _calibrate_copy()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the method runs on a single device here)", file=sys.stderr)
