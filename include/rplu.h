@@ -97,9 +97,16 @@ enum {
     RPLU_FLAG_GRAPH = 1u << 1,    /* replay the step loop as a hipGraph (the
                                      default; accepted for clarity)            */
     RPLU_FLAG_NO_GRAPH = 1u << 2, /* plain kernel launches, no hipGraph        */
-    RPLU_FLAG_STALL_STOP = 1u << 3 /* stall rule (below), for tolerance runs
+    RPLU_FLAG_STALL_STOP = 1u << 3, /* stall rule (below), for tolerance runs
                                      whose target may lie under the rounding
                                      floor of single precision                */
+    RPLU_FLAG_SPLIT_SAMPLER = 1u << 4 /* dense: draw each pivot with the two
+                                     wide kernels used for n or m > 12288
+                                     (row draw; pivot row and column draw)
+                                     also when n, m <= 12288, where one
+                                     fused workgroup kernel is the default;
+                                     every output is the same bit for bit.
+                                     The Cauchy-like path has one form.      */
 };
 
 /* Stall rule (a library extension, not from the paper): with
@@ -356,8 +363,10 @@ rplu_status rplu_verify(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
  * rplu_profile_end. While profiling is on, runs use plain launches (events
  * time individual kernels; a replayed graph cannot be timed per kernel).
  * Class 0: the hot kernel (dense sweep / Cauchy all-pairs mass / the batched
- * persistent kernel, queue reset included), 1: the
- * samplers, 2: updates and reductions, 3: initial mass pass. */
+ * persistent kernel, queue reset included), 1: the pivot draws (with the
+ * kernels that produce their chunk totals: the Cauchy-like row-mass
+ * reduction and pivot-row regeneration), 2: the Cauchy-like generator update
+ * and the dense column-mass reduction, 3: initial mass pass. */
 #define RPLU_PROFILE_CLASSES 4
 typedef struct {
     int64_t launches[RPLU_PROFILE_CLASSES];

@@ -221,6 +221,14 @@ static rplu_status run_loop(rplu_ctx_s* ctx, StepState* st, int64_t steps_total,
     return RPLU_OK;
 }
 
+// Dense path: the fused one-workgroup pivot draw (one launch per step
+// instead of two) unless a side exceeds its limit or the caller asks for
+// the wide form.
+static int use_fused_pivot(int64_t n, int64_t m, uint32_t flags) {
+    return (n <= PIVOT_FUSED_MAX && m <= PIVOT_FUSED_MAX && !(flags & RPLU_FLAG_SPLIT_SAMPLER))
+               ? 1 : 0;
+}
+
 static int64_t kmax_of(int64_t n, int64_t m, int64_t k) {
     const int64_t mn = std::min(n, m);
     return k <= 0 ? mn : std::min(k, mn);
@@ -459,15 +467,18 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, voi
     sa.forced = opts->forced;
     sa.trace = opts->trace;
     sa.rowmass_out = opts->rowmass_out;
+    sa.fused = use_fused_pivot(n, m, opts->flags);
 
     const bool graph = !(opts->flags & RPLU_FLAG_NO_GRAPH);
     const uint64_t key = fnv1a(&sa, sizeof sa, fnv1a(&a, sizeof a, 0x64656e7365ull));
     rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
         timed(ctx, 1, q, [&] {
-            launch_ct_vec(a.rowmass, n, sa.ct_row, a.st, q);
-            launch_sample_row(sa, q);
-            launch_dense_rowchunks(a, q);
-            launch_sample_col(sa, q);
+            if (sa.fused) {
+                launch_dense_pivot(a, sa, q);
+            } else {
+                launch_rows_draw(sa, q);
+                launch_dense_pivrow_draw(a, sa, q);
+            }
         });
         timed(ctx, 0, q, [&] { launch_dense_sweep(a, /*init=*/false, q); });
         if (colmass && a.colmass_out)
@@ -578,12 +589,9 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     const uint64_t key = fnv1a(&sa, sizeof sa, fnv1a(&a, sizeof a, 0x636175636879ull));
     rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
         timed(ctx, 0, q, [&] { launch_cauchy_mass(a, q); });
-        timed(ctx, 2, q, [&] { launch_cauchy_reduce(a, q); });
         timed(ctx, 1, q, [&] {
-            launch_ct_vec(a.rowmass, n, sa.ct_row, a.st, q);
-            launch_sample_row(sa, q);
-            launch_cauchy_rowgen(a, q);
-            launch_sample_col(sa, q);
+            launch_cauchy_reduce_draw(a, sa, q);
+            launch_cauchy_rowgen_draw(a, sa, q);
         });
         timed(ctx, 2, q, [&] { launch_cauchy_update(a, q); });
     });

@@ -11,13 +11,14 @@
 //                    LDS and every lane reads them as broadcasts; eight
 //                    columns share one reciprocal. Columns are
 //                    split over `splits` workgroup columns; the partial sums
-//                    are added in split order by k_cauchy_reduce
+//                    are added in split order by k_cauchy_reduce_draw
 //                    (deterministic).
-//   k_cauchy_reduce  row masses from the split partials (fixed order)
-//   k_cauchy_rowgen  after the row draw: regenerate the pivot row
+//   k_cauchy_reduce_draw  row masses from the split partials (fixed order)
+//                    and their chunk totals; the last workgroup runs the
+//                    stop test and draws the row (pivot.hpp)
+//   k_cauchy_rowgen_draw  regenerates the pivot row
 //                    r = (G_i,: B) ./ (x_i - y) into U(t,:) with the chunk
-//                    totals of |r|^2 for the column draw (the draws are in
-//                    sample.hip)
+//                    totals of |r|^2; the last workgroup draws the column
 //   k_cauchy_update  column c = (G B_:,j) ./ (x - y_j), L(:,t) = c / a with
 //                    L(i,t) = 1; G <- G - (1/a) c G_i,: and
 //                    B <- B - (1/a) B_:,j r (eqs. generator_update_g/_b),
@@ -25,6 +26,7 @@
 #include "common.hpp"
 #include "cdf.hpp"
 #include "launch.hpp"
+#include "pivot.hpp"
 
 namespace rplu {
 
@@ -197,38 +199,55 @@ __device__ inline cf64 gen_dot(const cf64* g, const cf64* __restrict__ B, int m,
     return s;
 }
 
-// rowmass[e] = sum over splits s, in order, of partial[s][e].
-__global__ __launch_bounds__(256) void k_cauchy_reduce(
-    const double* __restrict__ partial, int splits, int n, const StepState* __restrict__ st,
-    double* __restrict__ rowmass) {
-    if (st->done) return;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
+// Wide: rowmass[e] = sum over splits s, in order, of partial[s][e], one
+// row per thread, with the chunk totals; the last workgroup runs the stop
+// test and draws the pivot row (pivot.hpp).
+__global__ __launch_bounds__(CDF_THREADS) void k_cauchy_reduce_draw(
+    const double* __restrict__ partial, int splits, double* __restrict__ rowmass, PivotArgs pa,
+    double* __restrict__ ct) {
+    __shared__ WideShared sh;
+    if (pa.st->done) return;
+    const int n = pa.n;
+    const int e = blockIdx.x * WIDE_ELEMS + threadIdx.x;
     double v = 0.0;
-#pragma unroll 8
-    for (int s = 0; s < splits; ++s) v += partial[(int64_t)s * n + e];
-    rowmass[e] = v;
+    if (e < n) {
+#pragma unroll 16
+        for (int s = 0; s < splits; ++s) v += partial[(int64_t)s * n + e];
+        rowmass[e] = v;
+    }
+    wide_chunk_totals(sh, v, n, ct);
+    if (!wide_arrive_last(sh, &pa.st->arrive)) return;
+    int t;
+    pivot_row_draw_ct(sh.cdf, &sh.flag, pa, ct, t);
 }
 
 // Wide: regenerates the pivot row r = (G_i,: B) ./ (x_i - y) into U(t,:)
-// (Alg. 3, row of A^(k)) and writes the chunk totals of |r|^2.
+// (Alg. 3, row of A^(k)), one column per thread, with the chunk totals of
+// |r|^2; the last workgroup draws the column and commits the pivot, copying
+// G_i,: and B_:,j for the generator update.
 template <int P>
-__global__ __launch_bounds__(256) void k_cauchy_rowgen(
+__global__ __launch_bounds__(CDF_THREADS) void k_cauchy_rowgen_draw(
     const cf64* __restrict__ x, const cf64* __restrict__ y, const cf64* __restrict__ G,
-    const cf64* __restrict__ B, int m, const StepState* __restrict__ st, cf64* __restrict__ U,
-    int64_t ldu, double* __restrict__ ct) {
-    if (st->done) return;
-    const int i = st->i;
-    cf64 gi[P];
+    const cf64* __restrict__ B, cf64* __restrict__ U, int64_t ldu, PivotArgs pa,
+    double* __restrict__ ct) {
+    __shared__ WideShared sh;
+    if (pa.st->done) return;
+    const int m = pa.m;
+    const int t = pa.st->cur, i = pa.st->i;
+    cf64* Ut = U + (int64_t)t * ldu;
+    const int c = blockIdx.x * WIDE_ELEMS + threadIdx.x;
+    double v = 0.0;
+    if (c < m) {
+        cf64 gi[P];
 #pragma unroll
-    for (int l = 0; l < P; ++l) gi[l] = G[(int64_t)i * P + l];
-    const cf64 xi = x[i];
-    cf64* Ut = U + (int64_t)st->cur * ldu;
-    cdf_chunk_totals_wave(m, ct, [&](int c) {
-        const cf64 r = cdiv_fast(gen_dot<P>(gi, B, m, c), csub(xi, y[c]));
+        for (int l = 0; l < P; ++l) gi[l] = G[(int64_t)i * P + l];
+        const cf64 r = cdiv_fast(gen_dot<P>(gi, B, m, c), csub(x[i], y[c]));
         Ut[c] = r;
-        return Sc<cf64>::mag2(r);
-    });
+        v = Sc<cf64>::mag2(r);
+    }
+    wide_chunk_totals(sh, v, m, ct);
+    if (!wide_arrive_last(sh, &pa.st->arrive)) return;
+    pivot_col_draw_ct<cf64, P>(sh.cdf, pa, t, Ut, ct, G, B);
 }
 
 template <int P>
@@ -287,17 +306,16 @@ static void mass_p(const CauchyArgs& a, hipStream_t s) {
                        cps, a.st, a.partial);
 }
 
-template <int P>
-static void rowgen_p(const CauchyArgs& a, hipStream_t s) {
-    const int waves = cdf_chunks((int)a.m);
-    hipLaunchKernelGGL(k_cauchy_rowgen<P>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
-                       (const cf64*)a.x, (const cf64*)a.y, (const cf64*)a.G, (const cf64*)a.B,
-                       (int)a.m, a.st, (cf64*)a.U, a.ldu, a.ct_col);
+void launch_cauchy_reduce_draw(const CauchyArgs& a, const SampleArgs& sa, hipStream_t s) {
+    hipLaunchKernelGGL(k_cauchy_reduce_draw, dim3(wide_blocks(a.n)), dim3(CDF_THREADS), 0, s,
+                       a.partial, a.splits, a.rowmass, pivot_args(sa), sa.ct_row);
 }
 
-void launch_cauchy_reduce(const CauchyArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_cauchy_reduce, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s,
-                       a.partial, a.splits, (int)a.n, a.st, a.rowmass);
+template <int P>
+static void rowgen_draw_p(const CauchyArgs& a, const SampleArgs& sa, hipStream_t s) {
+    hipLaunchKernelGGL(k_cauchy_rowgen_draw<P>, dim3(wide_blocks(a.m)), dim3(CDF_THREADS), 0, s,
+                       (const cf64*)a.x, (const cf64*)a.y, (const cf64*)a.G, (const cf64*)a.B,
+                       (cf64*)a.U, a.ldu, pivot_args(sa), a.ct_col);
 }
 
 template <int P>
@@ -317,7 +335,15 @@ static void update_p(const CauchyArgs& a, hipStream_t s) {
     }
 
 void launch_cauchy_mass(const CauchyArgs& a, hipStream_t s) { RPLU_DISPATCH_P(mass_p) }
-void launch_cauchy_rowgen(const CauchyArgs& a, hipStream_t s) { RPLU_DISPATCH_P(rowgen_p) }
 void launch_cauchy_update(const CauchyArgs& a, hipStream_t s) { RPLU_DISPATCH_P(update_p) }
+
+void launch_cauchy_rowgen_draw(const CauchyArgs& a, const SampleArgs& sa, hipStream_t s) {
+    switch (a.p) {
+        case 1: rowgen_draw_p<1>(a, sa, s); break;
+        case 2: rowgen_draw_p<2>(a, sa, s); break;
+        case 3: rowgen_draw_p<3>(a, sa, s); break;
+        case 4: rowgen_draw_p<4>(a, sa, s); break;
+    }
+}
 
 }  // namespace rplu

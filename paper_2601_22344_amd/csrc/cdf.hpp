@@ -54,12 +54,11 @@ struct CdfChunk {
     double ex, lt, ct;
 };
 
-template <class MassFn>
-__device__ inline void cdf_chunk(CdfChunk& c, int chunk, int len, int lane, MassFn& mass) {
+// The chunk structure from the lane's E masses x (elements s0 .. s0 + E - 1,
+// s0 = chunk * CDF_CHUNK + lane * E; entries at or past len are ignored).
+__device__ inline void cdf_chunk_vals(CdfChunk& c, const double (&x)[CDF_E], int chunk, int len,
+                                      int lane) {
     const int s0 = chunk * CDF_CHUNK + lane * CDF_E;
-    double x[CDF_E];
-#pragma unroll
-    for (int u = 0; u < CDF_E; ++u) x[u] = mass(min(s0 + u, len - 1));
     double l = 0.0;
 #pragma unroll
     for (int u = 0; u < CDF_E; ++u) {
@@ -73,6 +72,15 @@ __device__ inline void cdf_chunk(CdfChunk& c, int chunk, int len, int lane, Mass
     c.lt = l;
     const int L = min(RPLU_WAVE - 1, (len - 1 - chunk * CDF_CHUNK) / CDF_E);
     c.ct = __shfl(ex + l, L, RPLU_WAVE);
+}
+
+template <class MassFn>
+__device__ inline void cdf_chunk(CdfChunk& c, int chunk, int len, int lane, MassFn& mass) {
+    const int s0 = chunk * CDF_CHUNK + lane * CDF_E;
+    double x[CDF_E];
+#pragma unroll
+    for (int u = 0; u < CDF_E; ++u) x[u] = mass(min(s0 + u, len - 1));
+    cdf_chunk_vals(c, x, chunk, len, lane);
 }
 
 struct CdfPick {

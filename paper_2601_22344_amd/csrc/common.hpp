@@ -185,10 +185,11 @@ __device__ inline double wave_incl_scan(double v, int lane) {
 
 constexpr double RPLU_STALL_RATIO = 63.0 / 64.0;   // see RPLU_FLAG_STALL_STOP
 
-// Per-run device state. The row sampler of step t reads t, runs the stop
-// test, and records cur = t and the row i; the column sampler records j, the
-// pivot and its reciprocal and sets t = t + 1; the other kernels of the step
-// read cur, i, j. Only the two single-workgroup samplers write the state.
+// Per-run device state. The row draw of step t reads t, runs the stop test,
+// and records cur = t and the row i; the column draw records j, the pivot
+// and its reciprocal and sets t = t + 1; the other kernels of the step read
+// cur, i, j. Only the workgroup running a draw writes the state (besides the
+// arrival counter of the wide draw kernels).
 struct StepState {
     int32_t t;          // pivots taken so far
     int32_t cur;        // step the current sweep/update applies
@@ -206,6 +207,9 @@ struct StepState {
     double row_tgt, row_lo, row_hi;   // row draw: target u1*T and its bin edges
     double gi[8];       // Cauchy: copy of G_i,: (p <= 4 complex)
     double bj[8];       // Cauchy: copy of B_:,j
+    uint32_t arrive;    // workgroups of the running wide draw kernel that
+                        // are done (0 between launches)
+    uint32_t pad3;
 };
 
 }  // namespace rplu

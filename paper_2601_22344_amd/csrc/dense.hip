@@ -1,9 +1,12 @@
 // Dense RPLU kernels (Alg. 1 with two-stage exact sampling, Sec. 4.1).
 //
 //   k_dense_sweep   (INIT) row masses ||A_i,:||^2 (and column partials) of A
-//   k_dense_rowchunks  pivot row i copied into U(t,:), chunk totals of
-//                   |S_i,e|^2 for the column draw (the draws themselves are
-//                   in sample.hip)
+//   k_dense_pivot   small matrices: the whole pivot draw of a step in one
+//                   workgroup (row draw, pivot row i copied into U(t,:),
+//                   column draw; pivot.hpp)
+//   k_rows_draw, k_dense_pivrow_draw  larger ones: the row draw (sample.hip),
+//                   then the pivot row copied by a wide kernel whose last
+//                   workgroup draws the column
 //   k_dense_sweep   S <- S - L(:,t) U(t,:) with row i and column j set to
 //                   exactly 0, L(:,t) formed on the way, and the row masses
 //                   of the NEW Schur complement reduced in the same pass
@@ -21,6 +24,7 @@
 #include "common.hpp"
 #include "cdf.hpp"
 #include "launch.hpp"
+#include "pivot.hpp"
 
 namespace rplu {
 
@@ -215,21 +219,44 @@ __global__ void k_colmass_reduce(const double* __restrict__ colpart, int nb, int
 
 // ----------------------------------------------------------- pivot row
 
-// Wide: copies row i of S into U(t,:) and writes the chunk totals of
-// |S_i,e|^2 for the column draw (one wave per chunk).
+// Wide: copies row i of S into U(t,:) (one element per thread, coalesced)
+// with the chunk totals of |S_i,e|^2; the last workgroup draws the column
+// and commits the pivot (pivot.hpp).
 template <class T>
-__global__ __launch_bounds__(256) void k_dense_rowchunks(const T* __restrict__ S, int64_t lda, int m,
-                                                         const StepState* __restrict__ st,
-                                                         T* __restrict__ U, int64_t ldu,
-                                                         double* __restrict__ ct) {
-    if (st->done) return;
-    const T* Si = S + (int64_t)st->i * lda;
-    T* Ut = U + (int64_t)st->cur * ldu;
-    cdf_chunk_totals_wave(m, ct, [&](int e) {
-        const T v = Si[e];
-        Ut[e] = v;
-        return Sc<T>::mag2(v);
-    });
+__global__ __launch_bounds__(CDF_THREADS) void k_dense_pivrow_draw(
+    const T* __restrict__ S, int64_t lda, T* __restrict__ U, int64_t ldu, PivotArgs pa,
+    double* __restrict__ ct) {
+    __shared__ WideShared sh;
+    if (pa.st->done) return;
+    const int t = pa.st->cur;
+    const T* Si = S + (int64_t)pa.st->i * lda;
+    T* Ut = U + (int64_t)t * ldu;
+    const int e = blockIdx.x * WIDE_ELEMS + threadIdx.x;
+    double v = 0.0;
+    if (e < pa.m) {
+        const T x = Si[e];
+        Ut[e] = x;
+        v = Sc<T>::mag2(x);
+    }
+    wide_chunk_totals(sh, v, pa.m, ct);
+    if (!wide_arrive_last(sh, &pa.st->arrive)) return;
+    pivot_col_draw_ct<T, 0>(sh.cdf, pa, t, Ut, ct, nullptr, nullptr);
+}
+
+// One workgroup: the whole pivot draw of a step (pivot.hpp), the pivot row
+// copied from S into U(t,:); the same results as k_rows_draw followed by
+// k_dense_pivrow_draw, in one launch.
+template <class T>
+__global__ __launch_bounds__(CDF_THREADS) void k_dense_pivot(const T* __restrict__ S, int64_t lda,
+                                                             T* __restrict__ U, int64_t ldu,
+                                                             PivotArgs pa) {
+    __shared__ PivotShared sh;
+    int t = 0;
+    const int i = pivot_draw_row(sh, pa, t);
+    if (i < 0) return;
+    const T* Si = S + (int64_t)i * lda;
+    pivot_draw_col<T, 0>(sh, pa, t, U + (int64_t)t * ldu, nullptr, nullptr,
+                         [&](int e) { return Si[e]; }, [](const T& v) { return v; });
 }
 
 // ---------------------------------------------------------------- launchers
@@ -281,18 +308,32 @@ void launch_colmass_reduce(const DenseArgs& a, bool after_step, hipStream_t s) {
 }
 
 template <class T>
-static void rowchunks_t(const DenseArgs& a, hipStream_t s) {
-    const int waves = cdf_chunks((int)a.m);
-    hipLaunchKernelGGL(k_dense_rowchunks<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
-                       (const T*)a.S, a.lda, (int)a.m, a.st, (T*)a.U, a.ldu, a.ct_col);
+static void pivot_t(const DenseArgs& a, const SampleArgs& sa, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_pivot<T>, dim3(1), dim3(CDF_THREADS), 0, s, (const T*)a.S, a.lda,
+                       (T*)a.U, a.ldu, pivot_args(sa));
 }
 
-void launch_dense_rowchunks(const DenseArgs& a, hipStream_t s) {
+void launch_dense_pivot(const DenseArgs& a, const SampleArgs& sa, hipStream_t s) {
     switch (a.dtype) {
-        case RPLU_R32: rowchunks_t<float>(a, s); break;
-        case RPLU_R64: rowchunks_t<double>(a, s); break;
-        case RPLU_C64: rowchunks_t<cf32>(a, s); break;
-        case RPLU_C128: rowchunks_t<cf64>(a, s); break;
+        case RPLU_R32: pivot_t<float>(a, sa, s); break;
+        case RPLU_R64: pivot_t<double>(a, sa, s); break;
+        case RPLU_C64: pivot_t<cf32>(a, sa, s); break;
+        case RPLU_C128: pivot_t<cf64>(a, sa, s); break;
+    }
+}
+
+template <class T>
+static void pivrow_draw_t(const DenseArgs& a, const SampleArgs& sa, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_pivrow_draw<T>, dim3(wide_blocks(a.m)), dim3(CDF_THREADS), 0, s,
+                       (const T*)a.S, a.lda, (T*)a.U, a.ldu, pivot_args(sa), a.ct_col);
+}
+
+void launch_dense_pivrow_draw(const DenseArgs& a, const SampleArgs& sa, hipStream_t s) {
+    switch (a.dtype) {
+        case RPLU_R32: pivrow_draw_t<float>(a, sa, s); break;
+        case RPLU_R64: pivrow_draw_t<double>(a, sa, s); break;
+        case RPLU_C64: pivrow_draw_t<cf32>(a, sa, s); break;
+        case RPLU_C128: pivrow_draw_t<cf64>(a, sa, s); break;
     }
 }
 

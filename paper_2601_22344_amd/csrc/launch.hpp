@@ -42,6 +42,13 @@ struct DenseArgs {
     double tol2;
 };
 
+// n and m limit of the fused one-workgroup pivot draw of the dense path
+// (pivot.hpp); above it the draws run as wide kernels. Measured on MI355X:
+// per step the fused draw takes 15.7 us against 18.8 at 512^2 and 20.3
+// against 22.3 at 8192^2, the wide one 24.4 against 25.3 at 16384^2 and
+// 25.2 against 31.9 at 32768^2.
+constexpr int PIVOT_FUSED_MAX = 12288;
+
 // Pivot sampling (sample.hip), shared by both forms.
 struct SampleArgs {
     int dtype;           // element type of U
@@ -63,16 +70,17 @@ struct SampleArgs {
     const int32_t* forced;
     double* trace;
     double* rowmass_out;
+    int fused;           // dense: one fused pivot kernel per step (n, m <= PIVOT_FUSED_MAX)
+    int pad;
 };
 
 void launch_state_init(StepState* st, hipStream_t s);
-void launch_ct_vec(const double* v, int64_t len, double* ct, StepState* st, hipStream_t s);
-void launch_sample_row(const SampleArgs& a, hipStream_t s);
-void launch_sample_col(const SampleArgs& a, hipStream_t s);
+void launch_rows_draw(const SampleArgs& a, hipStream_t s);
 
 void launch_dense_sweep(const DenseArgs& a, bool init, hipStream_t s);
-void launch_dense_rowchunks(const DenseArgs& a, hipStream_t s);
+void launch_dense_pivrow_draw(const DenseArgs& a, const SampleArgs& sa, hipStream_t s);
 void launch_colmass_reduce(const DenseArgs& a, bool after_step, hipStream_t s);
+void launch_dense_pivot(const DenseArgs& a, const SampleArgs& sa, hipStream_t s);
 int dense_row_block(bool colmass);
 
 struct CauchyArgs {
@@ -101,8 +109,8 @@ struct CauchyArgs {
 };
 
 void launch_cauchy_mass(const CauchyArgs& a, hipStream_t s);
-void launch_cauchy_reduce(const CauchyArgs& a, hipStream_t s);
-void launch_cauchy_rowgen(const CauchyArgs& a, hipStream_t s);
+void launch_cauchy_reduce_draw(const CauchyArgs& a, const SampleArgs& sa, hipStream_t s);
+void launch_cauchy_rowgen_draw(const CauchyArgs& a, const SampleArgs& sa, hipStream_t s);
 void launch_cauchy_update(const CauchyArgs& a, hipStream_t s);
 int cauchy_rows_per_block();
 

@@ -88,6 +88,17 @@ def test_dense_small_shapes(rplu_lib, dt, n, m):
     _run_and_check(rplu_lib, Ad, Ah, dt, k, seed=seed % 97, stream=n)
 
 
+@pytest.mark.parametrize("dt", ["r64", "r32"])
+@pytest.mark.parametrize("n,m", [(12289, 24), (24, 12289), (16385, 40), (40, 70001)])
+def test_dense_wide_draw_form(rplu_lib, dt, n, m):
+    """Past 12288 rows or columns the draws run as wide kernels finishing in
+    their last workgroup (one form only): parity with the oracle, also across
+    a 16384-element group of chunks."""
+    seed = n + m
+    Ad, Ah = _input(n, m, dt, seed)
+    _run_and_check(rplu_lib, Ad, Ah, dt, 20, seed=3, stream=1)
+
+
 @pytest.mark.parametrize("dt", ["r64", "r32", "c128"])
 def test_dense_unaligned_rows(rplu_lib, dt):
     """Row stride not a multiple of 16 bytes: the scalar (unvectorised) sweep."""

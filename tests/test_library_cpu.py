@@ -34,3 +34,36 @@ def test_status_strings_without_gpu():
     lib.rplu_status_str.restype = ctypes.c_char_p
     assert lib.rplu_status_str(0) == b"RPLU_OK"
     assert lib.rplu_status_str(-7) == b"RPLU_E_ZERO_PIVOT"
+
+
+def _header_constants():
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for body in re.findall(r"enum\s*\w*\s*\{(.*?)\}", src, flags=re.S):
+        nxt = 0
+        for item in body.split(","):
+            item = item.strip()
+            if not item:
+                continue
+            if "=" in item:
+                name, expr = (s.strip() for s in item.split("=", 1))
+                nxt = eval(re.sub(r"(\d+)u\b", r"\1", expr), {})   # integer literals and <<
+            else:
+                name = item
+            out[name] = nxt
+            nxt += 1
+    for name, val in re.findall(r"#define\s+(RPLU_[A-Z0-9_]+)\s+(\d+)\s*$", src, flags=re.M):
+        out[name] = int(val)
+    return out
+
+
+def test_binding_constants_match_header():
+    import paper_2601_22344_amd._binding as B
+    consts = _header_constants()
+    assert "RPLU_FLAG_SPLIT_SAMPLER" in consts and "RPLU_STOP_STALL" in consts
+    checked = 0
+    for name, val in consts.items():
+        if hasattr(B, name):
+            assert getattr(B, name) == val, name
+            checked += 1
+    assert checked >= 20
