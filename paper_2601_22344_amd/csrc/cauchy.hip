@@ -207,6 +207,9 @@ __global__ __launch_bounds__(CDF_THREADS) void k_cauchy_reduce_draw(
     double* __restrict__ ct) {
     __shared__ WideShared sh;
     if (pa.st->done) return;
+    const int t = pa.st->t;
+    const StopInputs in = stop_inputs(pa.st);
+    wide_keep_words(sh, step_words(pa, t));
     const int n = pa.n;
     const int e = blockIdx.x * WIDE_ELEMS + threadIdx.x;
     double v = 0.0;
@@ -217,8 +220,7 @@ __global__ __launch_bounds__(CDF_THREADS) void k_cauchy_reduce_draw(
     }
     wide_chunk_totals(sh, v, n, ct);
     if (!wide_arrive_last(sh, &pa.st->arrive)) return;
-    int t;
-    pivot_row_draw_ct(sh.cdf, &sh.flag, pa, ct, t);
+    pivot_row_draw_ct(sh.cdf, &sh.flag, pa, ct, t, wide_words(sh), in, RowMassGlobal{rowmass});
 }
 
 // Wide: regenerates the pivot row r = (G_i,: B) ./ (x_i - y) into U(t,:)
@@ -234,6 +236,7 @@ __global__ __launch_bounds__(CDF_THREADS) void k_cauchy_rowgen_draw(
     if (pa.st->done) return;
     const int m = pa.m;
     const int t = pa.st->cur, i = pa.st->i;
+    wide_keep_words(sh, step_words(pa, t));
     cf64* Ut = U + (int64_t)t * ldu;
     const int c = blockIdx.x * WIDE_ELEMS + threadIdx.x;
     double v = 0.0;
@@ -247,7 +250,7 @@ __global__ __launch_bounds__(CDF_THREADS) void k_cauchy_rowgen_draw(
     }
     wide_chunk_totals(sh, v, m, ct);
     if (!wide_arrive_last(sh, &pa.st->arrive)) return;
-    pivot_col_draw_ct<cf64, P>(sh.cdf, pa, t, Ut, ct, G, B);
+    pivot_col_draw_ct<cf64, P>(sh.cdf, pa, t, Ut, ct, G, B, wide_words(sh), ColMassGlobal<cf64>{Ut});
 }
 
 template <int P>

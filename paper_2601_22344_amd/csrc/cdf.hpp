@@ -191,17 +191,25 @@ __device__ CdfPick cdf_draw(CdfShared& sh, const double* __restrict__ ct, int K,
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) g = min(g, __shfl_xor(g, off, RPLU_WAVE));
         g = min(g, G - 1);                         // T > target: always found
-        // chunk inside the group: sequential chain, same order as cdf_levels
+        // chunk inside the group: the first k whose upper end goff + io_{k+1}
+        // exceeds the target (the last chunk of the group if none), with the
+        // chain io_{k0} = 0, io_{k+1} = io_k + ct_k added left to right as in
+        // cdf_levels. Lane q forms io_{k0+q} itself (the same additions in
+        // the same order), so every chunk is tested at once.
         const double goff = sh.goff[g];
         const int k0 = g * CDF_GROUP, k1 = min(K, k0 + CDF_GROUP);
         const double myct = ct[min(k0 + lane, K - 1)];   // lane q holds ct[k0 + q]
         double io = 0.0;
-        int k = k0;
-        for (; k < k1 - 1; ++k) {
-            const double nio = io + __shfl(myct, k - k0, RPLU_WAVE);
-            if (goff + nio > target) break;
-            io = nio;
+#pragma unroll
+        for (int q = 0; q < CDF_GROUP - 1; ++q) {
+            const double c = uniform_lane(myct, q);
+            if (q < lane) io = io + c;
         }
+        const bool hit = lane < k1 - 1 - k0 && goff + (io + myct) > target;
+        const unsigned long long hb = __ballot(hit);
+        const int kl = hb ? __ffsll(hb) - 1 : k1 - 1 - k0;
+        const int k = k0 + kl;
+        io = uniform_lane(io, kl);
         const double before = (k == k0) ? goff : goff + io;
         const CdfPick p = cdf_chunk_select(k, len, lane, mass, goff, io, before, target);
         if (lane == 0) { sh.ibcast[0] = p.idx; sh.bcast[0] = p.lo; sh.bcast[1] = p.hi; }

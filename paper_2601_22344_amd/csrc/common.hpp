@@ -171,6 +171,14 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// The value v of lane q (q the same in every lane), for every lane.
+__device__ inline double uniform_lane(double v, int q) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, q);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), q);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Inclusive scan across the 64 lanes of a wave (Hillis-Steele).
 __device__ inline double wave_incl_scan(double v, int lane) {
 #pragma unroll

@@ -229,6 +229,7 @@ __global__ __launch_bounds__(CDF_THREADS) void k_dense_pivrow_draw(
     __shared__ WideShared sh;
     if (pa.st->done) return;
     const int t = pa.st->cur;
+    wide_keep_words(sh, step_words(pa, t));
     const T* Si = S + (int64_t)pa.st->i * lda;
     T* Ut = U + (int64_t)t * ldu;
     const int e = blockIdx.x * WIDE_ELEMS + threadIdx.x;
@@ -240,7 +241,8 @@ __global__ __launch_bounds__(CDF_THREADS) void k_dense_pivrow_draw(
     }
     wide_chunk_totals(sh, v, pa.m, ct);
     if (!wide_arrive_last(sh, &pa.st->arrive)) return;
-    pivot_col_draw_ct<T, 0>(sh.cdf, pa, t, Ut, ct, nullptr, nullptr);
+    pivot_col_draw_ct<T, 0>(sh.cdf, pa, t, Ut, ct, nullptr, nullptr, wide_words(sh),
+                            ColMassGlobal<T>{Ut});
 }
 
 // One workgroup: the whole pivot draw of a step (pivot.hpp), the pivot row
@@ -251,11 +253,14 @@ __global__ __launch_bounds__(CDF_THREADS) void k_dense_pivot(const T* __restrict
                                                              T* __restrict__ U, int64_t ldu,
                                                              PivotArgs pa) {
     __shared__ PivotShared sh;
-    int t = 0;
-    const int i = pivot_draw_row(sh, pa, t);
+    if (pa.st->done) return;
+    const int t = pa.st->t;
+    const StopInputs in = stop_inputs(pa.st);
+    const Philox4 rnd = step_words(pa, t);
+    const int i = pivot_draw_row(sh, pa, t, rnd, in);
     if (i < 0) return;
     const T* Si = S + (int64_t)i * lda;
-    pivot_draw_col<T, 0>(sh, pa, t, U + (int64_t)t * ldu, nullptr, nullptr,
+    pivot_draw_col<T, 0>(sh, pa, t, U + (int64_t)t * ldu, nullptr, nullptr, rnd,
                          [&](int e) { return Si[e]; }, [](const T& v) { return v; });
 }
 

@@ -45,20 +45,40 @@ struct PivotArgs {
     double* rowmass_out;
 };
 
+// What the stop test reads from the state besides t, loaded at the start of
+// a draw kernel (only earlier kernels write it), and the step's two Philox
+// words: neither depends on the masses, so both are ready before the draw.
+struct StopInputs {
+    double T0, T_best;
+    int t_best;
+};
+
+__device__ inline StopInputs stop_inputs(const StepState* st) {
+    return {st->T0, st->T_best, st->t_best};
+}
+
+__device__ inline Philox4 step_words(const PivotArgs& a, int t) {
+    return philox4x64_10((uint64_t)t, a.stream, 0, 0, a.seed, 0);
+}
+
 // Thread 0: stop test at the start of step t on the total T. Returns 1 when
 // the run ends here (done, stop or error recorded in the state).
 __device__ inline int pivot_stop_test(StepState* st, int t, double T, int kmax, double tol2,
-                                      int stall) {
+                                      int stall, const StopInputs& in) {
     int stop = 0, err = 0;
-    const double T0 = (t == 0) ? T : st->T0;
+    const double T0 = (t == 0) ? T : in.T0;
+    double T_best = in.T_best;
+    int t_best = in.t_best;
     if (stall) {
-        if (t == 0) { st->T_best = T; st->t_best = 0; }
-        else if (T < RPLU_STALL_RATIO * st->T_best) { st->T_best = T; st->t_best = t; }
+        if (t == 0) { T_best = T; t_best = 0; }
+        else if (T < RPLU_STALL_RATIO * T_best) { T_best = T; t_best = t; }
+        st->T_best = T_best;
+        st->t_best = t_best;
     }
     if (!isfinite(T)) err = RPLU_E_NONFINITE;
     else if (T == 0.0) stop = RPLU_STOP_EXHAUSTED;
     else if (tol2 > 0.0 && T <= tol2 * T0) stop = RPLU_STOP_TOL;
-    else if (stall && t - st->t_best >= RPLU_STALL_WINDOW) stop = RPLU_STOP_STALL;
+    else if (stall && t - t_best >= RPLU_STALL_WINDOW) stop = RPLU_STOP_STALL;
     else if (t >= kmax) stop = tol2 > 0.0 ? RPLU_STOP_TOL_UNREACHED : RPLU_STOP_RANK;
     st->T = T;
     if (t == 0) st->T0 = T;
@@ -115,25 +135,31 @@ __device__ inline void pivot_commit_col(StepState* st, int t, int j, int m, cons
 
 // ------------------------------------------------ draws from chunk totals
 
-// Whole workgroup (CDF_THREADS): stop test and row draw of step t = st->t
-// from the chunk totals ct of the row masses (global memory or LDS). Returns
-// the row i in every thread (recorded in the state with cur = t), or -1 when
-// the run ends here.
+// Whole workgroup (CDF_THREADS): stop test and row draw of step t (= st->t)
+// from the chunk totals ct of the row masses (global memory or LDS); rnd
+// holds the step's Philox words; mass(e) gives the row masses for the walk
+// of the drawn chunk (by default from a.rowmass). Returns the row i in every
+// thread (recorded in the state with cur = t), or -1 when the run ends here.
+struct RowMassGlobal {
+    const double* rowmass;
+    __device__ double operator()(int e) const { return rowmass[e]; }
+};
+
+template <class MassFn>
 __device__ inline int pivot_row_draw_ct(CdfShared& sh, int* flag, const PivotArgs& a,
-                                        const double* ct, int& t) {
+                                        const double* ct, int t, const Philox4& rnd,
+                                        const StopInputs& in, MassFn mass) {
     StepState* st = a.st;
-    t = st->t;
     const int K = cdf_chunks(a.n);
     const double T = cdf_levels(sh, ct, K);
-    if (threadIdx.x == 0) *flag = pivot_stop_test(st, t, T, a.kmax, a.tol2, a.stall);
+    if (threadIdx.x == 0) *flag = pivot_stop_test(st, t, T, a.kmax, a.tol2, a.stall, in);
     __syncthreads();
     if (*flag) return -1;
     if (a.rowmass_out != nullptr)
         for (int e = threadIdx.x; e < a.n; e += CDF_THREADS)
             a.rowmass_out[(int64_t)t * a.n + e] = a.rowmass[e];
-    const Philox4 rnd = philox4x64_10((uint64_t)t, a.stream, 0, 0, a.seed, 0);
     const double tgt = unit_from_word(rnd.w[0]) * T;
-    const CdfPick p = cdf_draw(sh, ct, K, a.n, [&](int e) { return a.rowmass[e]; }, tgt);
+    const CdfPick p = cdf_draw(sh, ct, K, a.n, mass, tgt);
     const int i = a.forced ? a.forced[2 * t] : p.idx;
     if (i < 0 || i >= a.n) {
         if (threadIdx.x == 0) { st->error = RPLU_E_ARG; st->done = 1; }
@@ -150,17 +176,24 @@ __device__ inline int pivot_row_draw_ct(CdfShared& sh, int* flag, const PivotArg
 }
 
 // Whole workgroup: column draw of step t in the pivot row Ut = U(t,:) from
-// the chunk totals ct of |U(t,e)|^2, and the pivot commit.
-template <class T, int P>
+// the chunk totals ct of |U(t,e)|^2 (mass(e) gives |U(t,e)|^2 for the walk of
+// the drawn chunk), and the pivot commit.
+template <class T>
+struct ColMassGlobal {
+    const T* Ut;
+    __device__ double operator()(int e) const { return Sc<T>::mag2(Ut[e]); }
+};
+
+template <class T, int P, class MassFn>
 __device__ inline void pivot_col_draw_ct(CdfShared& sh, const PivotArgs& a, int t, const T* Ut,
-                                         const double* ct, const cf64* G, const cf64* B) {
+                                         const double* ct, const cf64* G, const cf64* B,
+                                         const Philox4& rnd, MassFn mass) {
     const int K = cdf_chunks(a.m);
     const double Ti = cdf_levels(sh, ct, K);
-    const Philox4 rnd = philox4x64_10((uint64_t)t, a.stream, 0, 0, a.seed, 0);
     const double tgt = unit_from_word(rnd.w[1]) * Ti;
     CdfPick p{0, 0.0, 0.0};
     if (Ti > 0.0 && isfinite(Ti))
-        p = cdf_draw(sh, ct, K, a.m, [&](int e) { return Sc<T>::mag2(Ut[e]); }, tgt);
+        p = cdf_draw(sh, ct, K, a.m, mass, tgt);
     if (threadIdx.x == 0) {
         const int j = a.forced ? a.forced[2 * t + 1] : p.idx;
         pivot_commit_col<T, P>(a.st, t, j, a.m, Ut, Ti, tgt, p, a.piv, a.trace, G, B);
@@ -172,8 +205,21 @@ __device__ inline void pivot_col_draw_ct(CdfShared& sh, const PivotArgs& a, int 
 struct WideShared {
     CdfShared cdf;
     double stage[WIDE_ELEMS + WIDE_ELEMS / CDF_E];   // element q at q + q / CDF_E
+    uint64_t words[2];
     int flag;
 };
+
+// Stores the step's Philox words in LDS before the workgroup's first barrier,
+// so that they are formed while the masses load (left where they are used,
+// the compiler would form them after the arrival, on the draw's path); the
+// draw takes them back with wide_words.
+__device__ inline void wide_keep_words(WideShared& sh, const Philox4& rnd) {
+    if (threadIdx.x == 0) { sh.words[0] = rnd.w[0]; sh.words[1] = rnd.w[1]; }
+}
+
+__device__ inline Philox4 wide_words(const WideShared& sh) {
+    return {{sh.words[0], sh.words[1], 0, 0}};
+}
 
 // Whole workgroup: thread q holds the mass of element blockIdx.x *
 // WIDE_ELEMS + q (anything past len is ignored); writes the totals of the
@@ -231,6 +277,7 @@ struct PivotShared {
     double ctr[PIVOT_MAX_CHUNKS];   // chunk totals of the row masses
     double ctc[PIVOT_MAX_CHUNKS];   // chunk totals of |U(t,e)|^2
     double stage[PIVOT_WAVES][PIVOT_STAGE];
+    uint64_t words[2];              // the step's Philox words (as in WideShared)
     int flag;
 };
 
@@ -280,14 +327,16 @@ __device__ inline void pivot_chunk_totals(PivotShared& sh, double* ct, int len, 
     __syncthreads();
 }
 
-// Whole workgroup: stop test and row draw of step t = st->t (returned in
-// t), the chunk totals formed here. Returns the row i in every thread, or -1
-// when the run ends here (or had ended).
-__device__ inline int pivot_draw_row(PivotShared& sh, const PivotArgs& a, int& t) {
-    if (a.st->done) return -1;
+// Whole workgroup: stop test and row draw of step t (= st->t, not done),
+// the chunk totals formed here. Returns the row i in every thread, or -1
+// when the run ends here.
+__device__ inline int pivot_draw_row(PivotShared& sh, const PivotArgs& a, int t,
+                                     const Philox4& rnd, const StopInputs& in) {
+    if (threadIdx.x == 0) { sh.words[0] = rnd.w[0]; sh.words[1] = rnd.w[1]; }
     pivot_chunk_totals(sh, sh.ctr, a.n, [&](int e) { return a.rowmass[e]; },
                        [](double v, int) { return v; });
-    return pivot_row_draw_ct(sh.cdf, &sh.flag, a, sh.ctr, t);
+    const Philox4 w{{sh.words[0], sh.words[1], 0, 0}};
+    return pivot_row_draw_ct(sh.cdf, &sh.flag, a, sh.ctr, t, w, in, RowMassGlobal{a.rowmass});
 }
 
 // Whole workgroup, after pivot_draw_row returned i >= 0 for step t: writes
@@ -296,13 +345,15 @@ __device__ inline int pivot_draw_row(PivotShared& sh, const PivotArgs& a, int& t
 // re-reads U(t,:) after the barrier that ends the row pass.
 template <class T, int P, class LoadFn, class ValueFn>
 __device__ inline void pivot_draw_col(PivotShared& sh, const PivotArgs& a, int t, T* Ut,
-                                      const cf64* G, const cf64* B, LoadFn load, ValueFn value) {
+                                      const cf64* G, const cf64* B, const Philox4& rnd,
+                                      LoadFn load, ValueFn value) {
     pivot_chunk_totals(sh, sh.ctc, a.m, load, [&](const decltype(load(0))& ld, int e) {
         const T v = value(ld);
         Ut[e] = v;
         return Sc<T>::mag2(v);
     });
-    pivot_col_draw_ct<T, P>(sh.cdf, a, t, Ut, sh.ctc, G, B);
+    const Philox4 w{{sh.words[0], sh.words[1], 0, 0}};
+    pivot_col_draw_ct<T, P>(sh.cdf, a, t, Ut, sh.ctc, G, B, w, ColMassGlobal<T>{Ut});
 }
 
 // Host: the pivot kernels' arguments from a sampler descriptor.

@@ -20,11 +20,13 @@ namespace rplu {
 __global__ __launch_bounds__(CDF_THREADS) void k_rows_draw(PivotArgs pa, double* __restrict__ ct) {
     __shared__ WideShared sh;
     if (pa.st->done) return;
+    const int t = pa.st->t;
+    const StopInputs in = stop_inputs(pa.st);
+    wide_keep_words(sh, step_words(pa, t));
     const int e = blockIdx.x * WIDE_ELEMS + threadIdx.x;
     wide_chunk_totals(sh, e < pa.n ? pa.rowmass[e] : 0.0, pa.n, ct);
     if (!wide_arrive_last(sh, &pa.st->arrive)) return;
-    int t;
-    pivot_row_draw_ct(sh.cdf, &sh.flag, pa, ct, t);
+    pivot_row_draw_ct(sh.cdf, &sh.flag, pa, ct, t, wide_words(sh), in, RowMassGlobal{pa.rowmass});
 }
 
 __global__ void k_state_init(StepState* st) {
