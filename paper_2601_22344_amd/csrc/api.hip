@@ -535,12 +535,16 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     const size_t o_ctr = cv.take((size_t)cdf_chunks((int)n) * 8);
     const size_t o_ctc = cv.take((size_t)cdf_chunks((int)m) * 8);
     const size_t o_u = (U == nullptr) ? cv.take((size_t)m * 16) : 0;
+    const size_t o_mc = cv.take(cauchy_mass_col_bytes(p, m));
+    const size_t o_mf = cv.take(cauchy_mass_frame_bytes(p));
     rplu_status rc = ws_reserve(ctx, cv.off, s);
     if (rc) return rc;
     char* ws = (char*)ctx->ws;
     a.n = n;
     a.m = m;
     a.p = p;
+    a.mcol = (p == 1) ? (void*)(ws + o_mc) : nullptr;
+    a.mframe = (p == 1) ? (void*)(ws + o_mf) : nullptr;
     a.x = x;
     a.y = y;
     a.G = G;
@@ -562,6 +566,7 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     a.tol2 = opts->rel_tol * opts->rel_tol;
 
     launch_state_init(a.st, s);
+    launch_cauchy_frame(a, s);
     SampleArgs sa;
     std::memset(&sa, 0, sizeof sa);
     sa.dtype = RPLU_C128;

@@ -2,14 +2,15 @@
 //
 // S is never stored: s_ij = (G_i,: B_:,j) / (x_i - y_j) (eq. cauchy-like).
 //
-//   k_cauchy_mass    row masses sum_j |s_ij|^2 (Sec. 5.1, row-norm formula),
-//                    all pairs, exact. Compute bound on FP64 vector ALUs:
-//                    per pair a complex difference, |d|^2, the p-term product
-//                    G_i,: B_:,j, its |.|^2 and one reciprocal. Each thread
-//                    keeps RT target rows (x_i, G_i,:) in registers; the
-//                    workgroup stages tiles of source columns (y_j, B_:,j) in
-//                    LDS and every lane reads them as broadcasts; eight
-//                    columns share one reciprocal. Columns are
+//   k_cauchy_mass1, k_cauchy_mass  row masses sum_j |s_ij|^2 (Sec. 5.1,
+//                    row-norm formula), all pairs, exact. Compute bound on
+//                    FP64 vector ALUs: per pair |x_i - y_j|^2, the p-term
+//                    product G_i,: B_:,j, its |.|^2 and one reciprocal. Each
+//                    thread keeps 2 target rows (x_i, G_i,:) in registers;
+//                    source columns come as uniform loads (p = 1, with a
+//                    centred short form of |x - y|^2 where it is accurate)
+//                    or LDS broadcasts (p > 1); eight columns share one
+//                    reciprocal. Columns are
 //                    split over `splits` workgroup columns; the partial sums
 //                    are added in split order by k_cauchy_reduce_draw
 //                    (deterministic).
@@ -19,6 +20,8 @@
 //   k_cauchy_rowgen_draw  regenerates the pivot row
 //                    r = (G_i,: B) ./ (x_i - y) into U(t,:) with the chunk
 //                    totals of |r|^2; the last workgroup draws the column
+//   k_cauchy_frame   once per run (p = 1): the box of y, its centre and the
+//                    per-column data of k_cauchy_mass1
 //   k_cauchy_update  column c = (G B_:,j) ./ (x - y_j), L(:,t) = c / a with
 //                    L(i,t) = 1; G <- G - (1/a) c G_i,: and
 //                    B <- B - (1/a) B_:,j r (eqs. generator_update_g/_b),
@@ -33,7 +36,8 @@ namespace rplu {
 constexpr int CM_THREADS = 512;
 constexpr int CM_RT = 2;                       // target rows per thread
 constexpr int CM_ROWS = CM_THREADS * CM_RT;    // target rows per workgroup
-constexpr int CM_TILE = 256;                   // source columns per LDS tile
+constexpr int CM_TILE = 256;                   // columns per tile (LDS staging for p > 1;
+                                               // the unit of the exactness check)
 constexpr int CM_GRP = 8;                      // columns sharing one reciprocal
 
 // 1/d for d > 0 to about 2^-48 relative: the hardware estimate (~24 bits)
@@ -58,8 +62,9 @@ __device__ inline double gb_mag2(const cf64* g, const cf64 (*sb)[CM_TILE], int e
     return fma(sr, sr, si * si);
 }
 
-// Row masses sum_j |G_i,: B_:,j|^2 / |x_i - y_j|^2 (for p = 1 the factor
-// |g_i|^2 is taken out of the sum and w_j = |b_j|^2 is staged per column).
+// Row masses sum_j w_ij / d_ij with d_ij = |x_i - y_j|^2 and w_ij =
+// |G_i,: B_:,j|^2 (for p = 1, |g_i|^2 |b_j|^2: the factor |g_i|^2 is taken
+// out of the sum).
 //
 // Eight columns share one reciprocal: sum_u w_u / d_u = N / D with
 // D = prod_u d_u and N = sum_u w_u prod_{v != u} d_v, formed as a pairwise
@@ -70,15 +75,30 @@ __device__ inline double gb_mag2(const cf64* g, const cf64 (*sb)[CM_TILE], int e
 // (extreme magnitudes, or x_i == y_j); only then is that thread's tile sum
 // for the row recomputed term by term, so the result is the plain sum for
 // every input.
+__device__ inline void mass_group(const double (&d)[CM_GRP], const double (&w)[CM_GRP], bool& ok,
+                                  double& acc) {
+    const double d01 = d[0] * d[1], d23 = d[2] * d[3];
+    const double d45 = d[4] * d[5], d67 = d[6] * d[7];
+    const double D03 = d01 * d23, D47 = d45 * d67;
+    const double D = D03 * D47;
+    const double N03 = fma(fma(w[0], d[1], w[1] * d[0]), d23, fma(w[2], d[3], w[3] * d[2]) * d01);
+    const double N47 = fma(fma(w[4], d[5], w[5] * d[4]), d67, fma(w[6], d[7], w[7] * d[6]) * d45);
+    const double N = fma(N03, D47, N47 * D03);
+    ok = ok & (D >= 0x1p-1000) & (D <= 0x1p+1000) & (fabs(N) <= 0x1p+1000);
+    acc = fma(N, rcp_1nr(D), acc);
+}
+
+// ------------------------------------------------------------- p >= 2
+
+// Each thread keeps CM_RT target rows (x_i, G_i,:) in registers; the
+// workgroup stages tiles of source columns (y_j, B_:,j) in LDS and every
+// lane reads them as broadcasts.
 template <int P>
 __device__ inline void mass_tile_exact(double& acc_t, double xr, double xi, const cf64* sy,
-                                       const double* sw, const cf64* g, const cf64 (*sb)[CM_TILE],
-                                       int nt) {
+                                       const cf64* g, const cf64 (*sb)[CM_TILE], int nt) {
     double s = 0.0;
     for (int e = 0; e < nt; ++e) {
-        double w;
-        if constexpr (P == 1) w = sw[e];
-        else w = gb_mag2<P>(g, sb, e);
+        const double w = gb_mag2<P>(g, sb, e);
         const double a = xr - sy[e].re, b = xi - sy[e].im;
         s = fma(w, rcp_refined(fma(a, a, b * b)), s);
     }
@@ -90,16 +110,16 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass(
     const cf64* __restrict__ x, const cf64* __restrict__ y, const cf64* __restrict__ G,
     const cf64* __restrict__ B, int n, int m, int cols_per_split,
     const StepState* __restrict__ st, double* __restrict__ partial) {
+    static_assert(P >= 2, "p = 1 has its own kernel");
     if (st->done) return;
     __shared__ cf64 sy[CM_TILE];
-    __shared__ double sw[P == 1 ? CM_TILE : 1];                 // |b_j|^2 (p = 1)
-    __shared__ cf64 sb[P == 1 ? 1 : P][CM_TILE];                // b_lj (p > 1)
+    __shared__ cf64 sb[P][CM_TILE];
     const int tid = threadIdx.x;
     const int split = blockIdx.y;
     const int c_beg = split * cols_per_split;
     const int c_end = min(m, c_beg + cols_per_split);
 
-    double xr[CM_RT], xi[CM_RT], acc[CM_RT], gscale[CM_RT];
+    double xr[CM_RT], xi[CM_RT], acc[CM_RT];
     cf64 g[CM_RT][P];
 #pragma unroll
     for (int q = 0; q < CM_RT; ++q) {
@@ -109,13 +129,8 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass(
         xr[q] = xv.re;
         xi[q] = xv.im;
         acc[q] = 0.0;
-        double gg = 0.0;
 #pragma unroll
-        for (int l = 0; l < P; ++l) {
-            g[q][l] = ok ? G[(int64_t)r * P + l] : cf64{0.0, 0.0};
-            gg += g[q][l].re * g[q][l].re + g[q][l].im * g[q][l].im;
-        }
-        gscale[q] = gg;
+        for (int l = 0; l < P; ++l) g[q][l] = ok ? G[(int64_t)r * P + l] : cf64{0.0, 0.0};
     }
 
     for (int c0 = c_beg; c0 < c_end; c0 += CM_TILE) {
@@ -123,13 +138,8 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass(
         __syncthreads();
         for (int e = tid; e < nt; e += CM_THREADS) {
             sy[e] = y[c0 + e];
-            if constexpr (P == 1) {
-                const cf64 b = B[c0 + e];
-                sw[e] = b.re * b.re + b.im * b.im;
-            } else {
 #pragma unroll
-                for (int l = 0; l < P; ++l) sb[l][e] = B[(int64_t)l * m + c0 + e];
-            }
+            for (int l = 0; l < P; ++l) sb[l][e] = B[(int64_t)l * m + c0 + e];
         }
         __syncthreads();
         double acc_t[CM_RT];
@@ -148,30 +158,17 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass(
                 for (int u = 0; u < CM_GRP; ++u) {
                     const double a = xr[q] - yy[u].re, b = xi[q] - yy[u].im;
                     d[u] = fma(a, a, b * b);
-                    if constexpr (P == 1) w[u] = sw[e + u];
-                    else w[u] = gb_mag2<P>(g[q], sb, e + u);
+                    w[u] = gb_mag2<P>(g[q], sb, e + u);
                 }
-                const double d01 = d[0] * d[1], d23 = d[2] * d[3];
-                const double d45 = d[4] * d[5], d67 = d[6] * d[7];
-                const double D03 = d01 * d23, D47 = d45 * d67;
-                const double D = D03 * D47;
-                const double N03 = fma(fma(w[0], d[1], w[1] * d[0]), d23,
-                                       fma(w[2], d[3], w[3] * d[2]) * d01);
-                const double N47 = fma(fma(w[4], d[5], w[5] * d[4]), d67,
-                                       fma(w[6], d[7], w[7] * d[6]) * d45);
-                const double N = fma(N03, D47, N47 * D03);
-                ok[q] = ok[q] & (D >= 0x1p-1000) & (D <= 0x1p+1000) & (fabs(N) <= 0x1p+1000);
-                acc_t[q] = fma(N, rcp_1nr(D), acc_t[q]);
+                mass_group(d, w, ok[q], acc_t[q]);
             }
         }
 #pragma unroll
         for (int q = 0; q < CM_RT; ++q) {
             if (__builtin_expect(!ok[q], 0))      // rare: recompute this tile term by term
-                mass_tile_exact<P>(acc_t[q], xr[q], xi[q], sy, sw, g[q], sb, ng);
+                mass_tile_exact<P>(acc_t[q], xr[q], xi[q], sy, g[q], sb, ng);
             for (int e = ng; e < nt; ++e) {       // ragged tail of the tile
-                double w;
-                if constexpr (P == 1) w = sw[e];
-                else w = gb_mag2<P>(g[q], sb, e);
+                const double w = gb_mag2<P>(g[q], sb, e);
                 const double a = xr[q] - sy[e].re, b = xi[q] - sy[e].im;
                 acc_t[q] = fma(w, rcp_refined(fma(a, a, b * b)), acc_t[q]);
             }
@@ -181,7 +178,198 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass(
 #pragma unroll
     for (int q = 0; q < CM_RT; ++q) {
         const int r = blockIdx.x * CM_ROWS + q * CM_THREADS + tid;
-        if (r < n) partial[(int64_t)split * n + r] = (P == 1) ? gscale[q] * acc[q] : acc[q];
+        if (r < n) partial[(int64_t)split * n + r] = acc[q];
+    }
+}
+
+// --------------------------------------------------------------- p = 1
+
+// For p = 1 the source column j is three numbers besides w_j = |b_j|^2, the
+// same for every lane: the kernel reads them straight from memory with
+// uniform (scalar) loads into scalar registers, which FP64 instructions take
+// as operands, so no LDS staging or broadcast reads remain and the vector
+// ALUs do only the pair arithmetic. With c the centre of the bounding box of
+// y, |x - y|^2 = |x - c|^2 + |y - c|^2 - 2 Re((x - c) conj(y - c)); with
+// -2(x - c) and |x - c|^2 per row in registers and y - c, |y - c|^2 per
+// column precomputed (MassCol), a pair costs an add and two FMAs instead of
+// two subtractions, a multiply and an FMA. The rounding error of that form is
+// a few units of 2^-53 of |x - c|^2 + |y - c|^2 rather than of |x - y|^2, so
+// a wave takes it only when, for each of its rows x, the distance from x to
+// the bounding box of y proves |x - c|^2 + max_j |y_j - c|^2 <= 64 min_j
+// |x - y_j|^2: the relative error of each |x - y|^2 then stays under 400
+// units of 2^-53 (4.4e-14, the draws being compared at 1e-12). Other waves,
+// and the exact recomputation of a flagged tile, use the plain form from y
+// itself.
+struct MassCol {
+    double yr, yi;      // y_j - c
+    double sy;          // |y_j - c|^2
+    double w;           // |b_j|^2, rewritten by the generator update
+};
+
+struct MassFrame {
+    double cr, ci;                  // c: centre of the bounding box of y
+    double yr0, yr1, yi0, yi1;      // the box
+    double R2;                      // max_j |y_j - c|^2
+    double pad;
+};
+
+constexpr double CM_SHORT_RATIO = 0x1p-6;
+
+__device__ inline double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, RPLU_WAVE));
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, RPLU_WAVE));
+    return v;
+}
+
+// One workgroup, once per run: the box of y, its centre, R2 and MassCol.
+__global__ __launch_bounds__(1024) void k_cauchy_frame(const cf64* __restrict__ y,
+                                                       const cf64* __restrict__ B, int m,
+                                                       MassFrame* __restrict__ fr,
+                                                       MassCol* __restrict__ col) {
+    __shared__ double red[5][16];
+    __shared__ double cen[2];
+    const int tid = threadIdx.x, lane = tid % RPLU_WAVE, w = tid / RPLU_WAVE;
+    double r0 = INFINITY, r1 = -INFINITY, i0 = INFINITY, i1 = -INFINITY;
+    for (int j = tid; j < m; j += 1024) {
+        const cf64 v = y[j];
+        r0 = fmin(r0, v.re); r1 = fmax(r1, v.re);
+        i0 = fmin(i0, v.im); i1 = fmax(i1, v.im);
+    }
+    r0 = wave_min(r0); r1 = wave_max(r1); i0 = wave_min(i0); i1 = wave_max(i1);
+    if (lane == 0) { red[0][w] = r0; red[1][w] = r1; red[2][w] = i0; red[3][w] = i1; }
+    __syncthreads();
+    if (tid == 0) {
+        for (int q = 1; q < 16; ++q) {
+            r0 = fmin(r0, red[0][q]); r1 = fmax(r1, red[1][q]);
+            i0 = fmin(i0, red[2][q]); i1 = fmax(i1, red[3][q]);
+        }
+        cen[0] = 0.5 * (r0 + r1);
+        cen[1] = 0.5 * (i0 + i1);
+        fr->cr = cen[0]; fr->ci = cen[1];
+        fr->yr0 = r0; fr->yr1 = r1; fr->yi0 = i0; fr->yi1 = i1;
+        fr->pad = 0.0;
+    }
+    __syncthreads();
+    const double cr = cen[0], ci = cen[1];
+    double smax = 0.0;
+    for (int j = tid; j < m; j += 1024) {
+        const cf64 v = y[j], b = B[j];
+        const double yr = v.re - cr, yi = v.im - ci;
+        const double sy = fma(yr, yr, yi * yi);
+        col[j] = MassCol{yr, yi, sy, b.re * b.re + b.im * b.im};
+        smax = fmax(smax, sy);
+    }
+    smax = wave_max(smax);
+    if (lane == 0) red[4][w] = smax;
+    __syncthreads();
+    if (tid == 0) {
+        for (int q = 1; q < 16; ++q) smax = fmax(smax, red[4][q]);
+        fr->R2 = smax;
+    }
+}
+
+__global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass1(
+    const cf64* __restrict__ x, const cf64* __restrict__ y, const cf64* __restrict__ G,
+    const MassCol* __restrict__ col, const MassFrame* __restrict__ frame, int n, int m,
+    int cols_per_split, const StepState* __restrict__ st, double* __restrict__ partial) {
+    if (st->done) return;
+    const int tid = threadIdx.x;
+    const int split = blockIdx.y;
+    const int c_beg = split * cols_per_split;
+    const int c_end = min(m, c_beg + cols_per_split);
+    const double cr = frame->cr, ci = frame->ci;
+
+    double xr[CM_RT], xi[CM_RT], a2[CM_RT], b2[CM_RT], sx[CM_RT], gscale[CM_RT], acc[CM_RT];
+    bool safe = true;     // the short form is accurate for this lane's rows
+#pragma unroll
+    for (int q = 0; q < CM_RT; ++q) {
+        const int r = blockIdx.x * CM_ROWS + q * CM_THREADS + tid;
+        const bool valid = r < n;
+        const cf64 xv = valid ? x[r] : cf64{0.0, 0.0};
+        const cf64 g = valid ? G[r] : cf64{0.0, 0.0};
+        xr[q] = xv.re;
+        xi[q] = xv.im;
+        const double ar = xv.re - cr, ai = xv.im - ci;
+        a2[q] = -2.0 * ar;
+        b2[q] = -2.0 * ai;
+        sx[q] = fma(ar, ar, ai * ai);
+        gscale[q] = g.re * g.re + g.im * g.im;
+        acc[q] = 0.0;
+        // min_j |x - y_j|^2 >= the squared distance from x to the box of y,
+        // and max_j (|x - c|^2 + |y_j - c|^2) <= |x - c|^2 + R2
+        const double dx = fmax(0.0, fmax(frame->yr0 - xv.re, xv.re - frame->yr1));
+        const double dy = fmax(0.0, fmax(frame->yi0 - xv.im, xv.im - frame->yi1));
+        if (valid) safe = safe & (fma(dx, dx, dy * dy) >= CM_SHORT_RATIO * (sx[q] + frame->R2));
+    }
+    const int shortf = __all(safe) ? 1 : 0;     // the same in every lane of the wave
+
+    for (int c0 = c_beg; c0 < c_end; c0 += CM_TILE) {
+        const int nt = min(CM_TILE, c_end - c0);
+        const int ng = nt / CM_GRP * CM_GRP;
+        double acc_t[CM_RT];
+        bool ok[CM_RT];
+#pragma unroll
+        for (int q = 0; q < CM_RT; ++q) { acc_t[q] = 0.0; ok[q] = true; }
+        if (shortf) {
+            for (int e = c0; e < c0 + ng; e += CM_GRP) {
+                MassCol cc[CM_GRP];
+                double w[CM_GRP];
+#pragma unroll
+                for (int u = 0; u < CM_GRP; ++u) { cc[u] = col[e + u]; w[u] = cc[u].w; }
+#pragma unroll
+                for (int q = 0; q < CM_RT; ++q) {
+                    double d[CM_GRP];
+#pragma unroll
+                    for (int u = 0; u < CM_GRP; ++u)
+                        d[u] = fma(a2[q], cc[u].yr, fma(b2[q], cc[u].yi, sx[q] + cc[u].sy));
+                    mass_group(d, w, ok[q], acc_t[q]);
+                }
+            }
+        } else {
+            for (int e = c0; e < c0 + ng; e += CM_GRP) {
+                cf64 yy[CM_GRP];
+                double w[CM_GRP];
+#pragma unroll
+                for (int u = 0; u < CM_GRP; ++u) { yy[u] = y[e + u]; w[u] = col[e + u].w; }
+#pragma unroll
+                for (int q = 0; q < CM_RT; ++q) {
+                    double d[CM_GRP];
+#pragma unroll
+                    for (int u = 0; u < CM_GRP; ++u) {
+                        const double a = xr[q] - yy[u].re, b = xi[q] - yy[u].im;
+                        d[u] = fma(a, a, b * b);
+                    }
+                    mass_group(d, w, ok[q], acc_t[q]);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < CM_RT; ++q) {
+            if (__builtin_expect(!ok[q], 0)) {    // rare: recompute this tile term by term
+                double s = 0.0;
+                for (int e = c0; e < c0 + ng; ++e) {
+                    const double a = xr[q] - y[e].re, b = xi[q] - y[e].im;
+                    s = fma(col[e].w, rcp_refined(fma(a, a, b * b)), s);
+                }
+                acc_t[q] = s;
+            }
+            for (int e = c0 + ng; e < c0 + nt; ++e) {   // ragged tail of the tile
+                const double a = xr[q] - y[e].re, b = xi[q] - y[e].im;
+                acc_t[q] = fma(col[e].w, rcp_refined(fma(a, a, b * b)), acc_t[q]);
+            }
+            acc[q] += acc_t[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CM_RT; ++q) {
+        const int r = blockIdx.x * CM_ROWS + q * CM_THREADS + tid;
+        if (r < n) partial[(int64_t)split * n + r] = gscale[q] * acc[q];
     }
 }
 
@@ -253,11 +441,13 @@ __global__ __launch_bounds__(CDF_THREADS) void k_cauchy_rowgen_draw(
     pivot_col_draw_ct<cf64, P>(sh.cdf, pa, t, Ut, ct, G, B, wide_words(sh), ColMassGlobal<cf64>{Ut});
 }
 
+// For p = 1 it also rewrites w_j = |b_j|^2 of the mass kernel's column data.
 template <int P>
 __global__ __launch_bounds__(256) void k_cauchy_update(
     const cf64* __restrict__ x, const cf64* __restrict__ y, cf64* __restrict__ G,
     cf64* __restrict__ B, int n, int m, const StepState* __restrict__ st,
-    const cf64* __restrict__ U, int64_t ldu, cf64* __restrict__ L, int64_t ldl) {
+    const cf64* __restrict__ U, int64_t ldu, cf64* __restrict__ L, int64_t ldl,
+    MassCol* __restrict__ col) {
     if (st->done) return;
     const int pi = st->i, pj = st->j, t = st->cur;
     const cf64 inv{st->inv_re, st->inv_im};
@@ -291,7 +481,9 @@ __global__ __launch_bounds__(256) void k_cauchy_update(
         for (int l = 0; l < P; ++l) {
             const cf64 bjl{st->bj[2 * l], st->bj[2 * l + 1]};
             const cf64 b = B[(int64_t)l * m + c];
-            B[(int64_t)l * m + c] = (c == pj) ? cf64{0.0, 0.0} : csub(b, wmul(bjl, f));
+            const cf64 nb = (c == pj) ? cf64{0.0, 0.0} : csub(b, wmul(bjl, f));
+            B[(int64_t)l * m + c] = nb;
+            if constexpr (P == 1) col[c].w = nb.re * nb.re + nb.im * nb.im;
         }
     }
 }
@@ -304,9 +496,23 @@ template <int P>
 static void mass_p(const CauchyArgs& a, hipStream_t s) {
     const int cps = a.cols_per_split;
     dim3 grid((unsigned)((a.n + CM_ROWS - 1) / CM_ROWS), (unsigned)a.splits);
-    hipLaunchKernelGGL(k_cauchy_mass<P>, grid, dim3(CM_THREADS), 0, s, (const cf64*)a.x,
-                       (const cf64*)a.y, (const cf64*)a.G, (const cf64*)a.B, (int)a.n, (int)a.m,
-                       cps, a.st, a.partial);
+    if constexpr (P == 1)
+        hipLaunchKernelGGL(k_cauchy_mass1, grid, dim3(CM_THREADS), 0, s, (const cf64*)a.x,
+                           (const cf64*)a.y, (const cf64*)a.G, (const MassCol*)a.mcol,
+                           (const MassFrame*)a.mframe, (int)a.n, (int)a.m, cps, a.st, a.partial);
+    else
+        hipLaunchKernelGGL(k_cauchy_mass<P>, grid, dim3(CM_THREADS), 0, s, (const cf64*)a.x,
+                           (const cf64*)a.y, (const cf64*)a.G, (const cf64*)a.B, (int)a.n,
+                           (int)a.m, cps, a.st, a.partial);
+}
+
+size_t cauchy_mass_col_bytes(int p, int64_t m) { return p == 1 ? (size_t)m * sizeof(MassCol) : 0; }
+size_t cauchy_mass_frame_bytes(int p) { return p == 1 ? sizeof(MassFrame) : 0; }
+
+void launch_cauchy_frame(const CauchyArgs& a, hipStream_t s) {
+    if (a.p != 1) return;
+    hipLaunchKernelGGL(k_cauchy_frame, dim3(1), dim3(1024), 0, s, (const cf64*)a.y,
+                       (const cf64*)a.B, (int)a.m, (MassFrame*)a.mframe, (MassCol*)a.mcol);
 }
 
 void launch_cauchy_reduce_draw(const CauchyArgs& a, const SampleArgs& sa, hipStream_t s) {
@@ -326,7 +532,8 @@ static void update_p(const CauchyArgs& a, hipStream_t s) {
     const int64_t work = a.n > a.m ? a.n : a.m;
     hipLaunchKernelGGL(k_cauchy_update<P>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s,
                        (const cf64*)a.x, (const cf64*)a.y, (cf64*)a.G, (cf64*)a.B, (int)a.n,
-                       (int)a.m, a.st, (const cf64*)a.U, a.ldu, (cf64*)a.L, a.ldl);
+                       (int)a.m, a.st, (const cf64*)a.U, a.ldu, (cf64*)a.L, a.ldl,
+                       (MassCol*)a.mcol);
 }
 
 #define RPLU_DISPATCH_P(fn)                         \

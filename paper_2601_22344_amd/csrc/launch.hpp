@@ -97,6 +97,8 @@ struct CauchyArgs {
     int32_t* piv;
     StepState* st;
     double* partial;     // splits * n
+    void* mcol;          // p = 1: per-column data of the mass kernel (m entries)
+    void* mframe;        // p = 1: the bounding box of y and its centre
     int splits;
     int cols_per_split;  // columns of y per workgroup column of the mass kernel
     double* rowmass;     // n (reduced masses)
@@ -108,7 +110,10 @@ struct CauchyArgs {
     double tol2;
 };
 
+void launch_cauchy_frame(const CauchyArgs& a, hipStream_t s);
 void launch_cauchy_mass(const CauchyArgs& a, hipStream_t s);
+size_t cauchy_mass_col_bytes(int p, int64_t m);
+size_t cauchy_mass_frame_bytes(int p);
 void launch_cauchy_reduce_draw(const CauchyArgs& a, const SampleArgs& sa, hipStream_t s);
 void launch_cauchy_rowgen_draw(const CauchyArgs& a, const SampleArgs& sa, hipStream_t s);
 void launch_cauchy_update(const CauchyArgs& a, hipStream_t s);

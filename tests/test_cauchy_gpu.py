@@ -63,6 +63,40 @@ def test_cauchy_small(rplu_lib, p, n, m):
     _check_small(rplu_lib, x, y, G, B, k, seed=p, stream=m)
 
 
+@pytest.mark.parametrize("n,m", [(300, 257), (2049, 1500), (3000, 4100)])
+def test_cauchy_p1_separated_discs(rplu_lib, n, m):
+    """x in the unit disc, y in the unit disc around 4: every wave of the p = 1
+    mass kernel proves the centred short form of |x - y|^2 accurate and uses
+    it; parity with the oracle as for the other inputs."""
+    rng = np.random.default_rng(n + m)
+    x = np.sqrt(rng.random(n)) * np.exp(2j * np.pi * rng.random(n))
+    y = 4.0 + np.sqrt(rng.random(m)) * np.exp(2j * np.pi * rng.random(m))
+    G = (rng.standard_normal((n, 1)) + 1j * rng.standard_normal((n, 1))) / math.sqrt(2)
+    B = (rng.standard_normal((1, m)) + 1j * rng.standard_normal((1, m))) / math.sqrt(2)
+    _check_small(rplu_lib, x, y, G, B, 25, seed=3, stream=1)
+
+
+def test_cauchy_p1_spirals_small(rplu_lib):
+    """The spirals-vs-cluster geometry of the benchmark at 3000 x 2000 (every
+    wave takes the short form)."""
+    x, y, G, B = W.config2_cauchy_spirals(3000, 2000)
+    _check_small(rplu_lib, x, y, G, B, 30, seed=0)
+
+
+def test_cauchy_p1_mixed_waves(rplu_lib):
+    """x on a line from -10 to 3.9 (rows in order), y in the unit disc around
+    5: the waves holding the rows nearest the disc cannot prove the short form
+    accurate and take the plain one, the others the short one; both agree
+    with the oracle."""
+    rng = np.random.default_rng(11)
+    n, m = 3000, 2000
+    x = np.linspace(-10.0, 3.9, n) + 0.3j * rng.standard_normal(n)
+    y = 5.0 + np.sqrt(rng.random(m)) * np.exp(2j * np.pi * rng.random(m))
+    G = np.ones((n, 1), dtype=np.complex128)
+    B = (rng.standard_normal((1, m)) + 1j * rng.standard_normal((1, m))) / math.sqrt(2)
+    _check_small(rplu_lib, x, y, G, B, 30, seed=4)
+
+
 def test_cauchy_loewner_p2(rplu_lib):
     rng = np.random.default_rng(4)
     x = rng.uniform(-1, 1, 400).astype(np.complex128)
