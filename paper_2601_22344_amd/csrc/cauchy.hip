@@ -14,8 +14,8 @@
 //                    split over `splits` workgroup columns; the partial sums
 //                    are added in split order by k_cauchy_reduce_draw
 //                    (deterministic).
-//   k_cauchy_reduce_draw  row masses from the split partials (fixed order)
-//                    and their chunk totals; the last workgroup runs the
+//   k_cauchy_reduce_draw  row masses from the split partials (fixed order,
+//                    two halves of the splits per row) and their chunk totals; the last workgroup runs the
 //                    stop test and draws the row (pivot.hpp)
 //   k_cauchy_rowgen_draw  regenerates the pivot row
 //                    r = (G_i,: B) ./ (x_i - y) into U(t,:) with the chunk
@@ -387,9 +387,11 @@ __device__ inline cf64 gen_dot(const cf64* g, const cf64* __restrict__ B, int m,
     return s;
 }
 
-// Wide: rowmass[e] = sum over splits s, in order, of partial[s][e], one
-// row per thread, with the chunk totals; the last workgroup runs the stop
-// test and draws the pivot row (pivot.hpp).
+// Wide: rowmass[e] = sum over splits s of partial[s][e] for one chunk of
+// rows per workgroup, two threads per row: each adds one half of the splits
+// in order and the row's mass is (first half) + (second half); with the
+// chunk totals. The last workgroup runs the stop test and draws the pivot
+// row (pivot.hpp).
 __global__ __launch_bounds__(CDF_THREADS) void k_cauchy_reduce_draw(
     const double* __restrict__ partial, int splits, double* __restrict__ rowmass, PivotArgs pa,
     double* __restrict__ ct) {
@@ -399,14 +401,22 @@ __global__ __launch_bounds__(CDF_THREADS) void k_cauchy_reduce_draw(
     const StopInputs in = stop_inputs(pa.st);
     wide_keep_words(sh, step_words(pa, t));
     const int n = pa.n;
-    const int e = blockIdx.x * WIDE_ELEMS + threadIdx.x;
+    const int q = threadIdx.x % CDF_CHUNK, h = threadIdx.x / CDF_CHUNK;
+    const int e = blockIdx.x * CDF_CHUNK + q;
+    const int mid = (splits + 1) / 2;
     double v = 0.0;
     if (e < n) {
+        const int s0 = h ? mid : 0, s1 = h ? splits : mid;
 #pragma unroll 16
-        for (int s = 0; s < splits; ++s) v += partial[(int64_t)s * n + e];
-        rowmass[e] = v;
+        for (int s = s0; s < s1; ++s) v += partial[(int64_t)s * n + e];
     }
-    wide_chunk_totals(sh, v, n, ct);
+    if (h == 1) sh.pair[q] = v;
+    __syncthreads();
+    if (h == 0) {
+        v = v + sh.pair[q];
+        if (e < n) rowmass[e] = v;
+    }
+    wide_chunk_totals<CDF_CHUNK>(sh, v, n, ct);
     if (!wide_arrive_last(sh, &pa.st->arrive)) return;
     pivot_row_draw_ct(sh.cdf, &sh.flag, pa, ct, t, wide_words(sh), in, RowMassGlobal{rowmass});
 }
@@ -516,7 +526,7 @@ void launch_cauchy_frame(const CauchyArgs& a, hipStream_t s) {
 }
 
 void launch_cauchy_reduce_draw(const CauchyArgs& a, const SampleArgs& sa, hipStream_t s) {
-    hipLaunchKernelGGL(k_cauchy_reduce_draw, dim3(wide_blocks(a.n)), dim3(CDF_THREADS), 0, s,
+    hipLaunchKernelGGL(k_cauchy_reduce_draw, dim3((unsigned)cdf_chunks((int)a.n)), dim3(CDF_THREADS), 0, s,
                        a.partial, a.splits, a.rowmass, pivot_args(sa), sa.ct_row);
 }
 

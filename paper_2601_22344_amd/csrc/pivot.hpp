@@ -205,6 +205,7 @@ __device__ inline void pivot_col_draw_ct(CdfShared& sh, const PivotArgs& a, int 
 struct WideShared {
     CdfShared cdf;
     double stage[WIDE_ELEMS + WIDE_ELEMS / CDF_E];   // element q at q + q / CDF_E
+    double pair[CDF_CHUNK];                          // partial sums handed between threads
     uint64_t words[2];
     int flag;
 };
@@ -221,17 +222,21 @@ __device__ inline Philox4 wide_words(const WideShared& sh) {
     return {{sh.words[0], sh.words[1], 0, 0}};
 }
 
-// Whole workgroup: thread q holds the mass of element blockIdx.x *
-// WIDE_ELEMS + q (anything past len is ignored); writes the totals of the
-// workgroup's chunks to ct. The staging pads one slot per CDF_E elements so
-// that a lane's consecutive reads do not all hit its neighbours' banks.
+// Whole workgroup: thread q < ELEMS holds the mass of element blockIdx.x *
+// ELEMS + q (anything past len is ignored); writes the totals of the
+// workgroup's ELEMS / CDF_CHUNK chunks to ct. The staging pads one slot per
+// CDF_E elements so that a lane's consecutive reads do not all hit its
+// neighbours' banks.
+template <int ELEMS = WIDE_ELEMS>
 __device__ inline void wide_chunk_totals(WideShared& sh, double mass, int len, double* ct) {
+    static_assert(ELEMS % CDF_CHUNK == 0 && ELEMS <= WIDE_ELEMS, "whole chunks per workgroup");
+    constexpr int CHUNKS = ELEMS / CDF_CHUNK;
     const int q = threadIdx.x;
-    sh.stage[q + q / CDF_E] = mass;
+    if (q < ELEMS) sh.stage[q + q / CDF_E] = mass;
     __syncthreads();
     const int w = q / RPLU_WAVE, lane = q % RPLU_WAVE;
-    const int chunk = blockIdx.x * WIDE_CHUNKS + w;
-    if (w < WIDE_CHUNKS && chunk < cdf_chunks(len)) {
+    const int chunk = blockIdx.x * CHUNKS + w;
+    if (w < CHUNKS && chunk < cdf_chunks(len)) {
         const int s0 = w * CDF_CHUNK + lane * CDF_E;      // first of the lane's elements
         double x[CDF_E];
 #pragma unroll
