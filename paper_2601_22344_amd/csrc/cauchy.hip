@@ -317,6 +317,7 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass1(
 #pragma unroll
         for (int q = 0; q < CM_RT; ++q) { acc_t[q] = 0.0; ok[q] = true; }
         if (shortf) {
+#pragma unroll 2
             for (int e = c0; e < c0 + ng; e += CM_GRP) {
                 MassCol cc[CM_GRP];
                 double w[CM_GRP];
