@@ -97,6 +97,23 @@ def test_cauchy_p1_mixed_waves(rplu_lib):
     _check_small(rplu_lib, x, y, G, B, 30, seed=4)
 
 
+@pytest.mark.parametrize("bad", ["nan", "inf"])
+def test_cauchy_p1_nonfinite_node(rplu_lib, bad):
+    """A non-finite y_j in a geometry where the other waves take the short
+    form: the run reports RPLU_E_NONFINITE instead of drawing."""
+    rng = np.random.default_rng(5)
+    n, m = 1500, 1200
+    x = np.sqrt(rng.random(n)) * np.exp(2j * np.pi * rng.random(n))
+    y = 4.0 + np.sqrt(rng.random(m)) * np.exp(2j * np.pi * rng.random(m))
+    y[700] = complex(float(bad), 0.0)
+    G = np.ones((n, 1), dtype=np.complex128)
+    B = np.ones((1, m), dtype=np.complex128)
+    xd, yd, Gd, Bd = _dev(x, y, G, B)
+    with pytest.raises(rplu_lib.RPLUError) as e:
+        rplu_lib.rplu_cauchy(xd, yd, Gd, Bd, k=3)
+    assert e.value.status == -4
+
+
 def test_cauchy_loewner_p2(rplu_lib):
     rng = np.random.default_rng(4)
     x = rng.uniform(-1, 1, 400).astype(np.complex128)
