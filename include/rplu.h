@@ -147,7 +147,7 @@ typedef struct {
     double* rowmass_out;    /* device, kmax*n doubles: the row masses each draw
                                used (dense: per row; Cauchy: per row), or NULL  */
     double* colmass_out;    /* device, kmax*m doubles: column masses of S^(t),
-                               needs RPLU_FLAG_COLMASS (dense only), or NULL     */
+                               needs RPLU_FLAG_COLMASS, or NULL                  */
 } rplu_opts;
 
 typedef struct {
@@ -184,7 +184,10 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m,
  * row-major, B: p x m row-major, 1 <= p <= 4. G and B are OVERWRITTEN with the
  * generators of S^(rank) (eqs. generator_update_g/_b). L, U, piv as for
  * rplu_dense; U(t,:) is the regenerated pivot row, L(:,t) the pivot column
- * divided by the pivot. No n x m array is ever stored. */
+ * divided by the pivot. No n x m array is ever stored. With
+ * RPLU_FLAG_COLMASS and opts.colmass_out, row t of colmass_out receives the
+ * exact column masses sum_i |s_ij|^2 of S^(t) (the same all-pairs pass with
+ * rows and columns exchanged, which doubles the mass work of a step). */
 rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m,
                         int32_t p, const void* x, const void* y, void* G, void* B,
                         const rplu_opts* opts, int32_t* piv, void* L, int64_t ldl,

@@ -239,8 +239,8 @@ def rplu_dense(A: torch.Tensor, k: int = 0, tol: float = 0.0, seed: int = 0, str
 def rplu_cauchy(x: torch.Tensor, y: torch.Tensor, G: torch.Tensor, B: torch.Tensor, k: int = 0,
                 tol: float = 0.0, seed: int = 0, stream: int = 0, flags: int = 0,
                 forced: Optional[torch.Tensor] = None, want_trace: bool = False,
-                want_rowmass: bool = False, store_L: bool = True, store_U: bool = True,
-                ctx: Optional[Context] = None) -> Result:
+                want_rowmass: bool = False, want_colmass: bool = False, store_L: bool = True,
+                store_U: bool = True, ctx: Optional[Context] = None) -> Result:
     """Cauchy-like RPLU from nodes x (n), y (m) and generators G (n x p),
     B (p x m), complex128 CUDA tensors; G and B are overwritten by the
     generators of the final Schur complement."""
@@ -258,9 +258,12 @@ def rplu_cauchy(x: torch.Tensor, y: torch.Tensor, G: torch.Tensor, B: torch.Tens
     U = torch.empty((kmax, m), dtype=torch.complex128, device=dev) if store_U else None
     trace = torch.empty((kmax, RPLU_TRACE_WORDS), dtype=torch.float64, device=dev) if want_trace else None
     rmo = torch.empty((kmax, n), dtype=torch.float64, device=dev) if want_rowmass else None
+    cmo = torch.empty((kmax, m), dtype=torch.float64, device=dev) if want_colmass else None
+    if want_colmass:
+        flags |= RPLU_FLAG_COLMASS
     if forced is not None:
         forced = forced.to(device=dev, dtype=torch.int32).contiguous()
-    opts = _opts(k, tol, seed, stream, flags, forced, trace, rmo, None)
+    opts = _opts(k, tol, seed, stream, flags, forced, trace, rmo, cmo)
     info = rplu_info()
     st = lib.rplu_cauchy(ctx.handle, RPLU_C128, n, m, p, _ptr(x), _ptr(y), _ptr(G), _ptr(B),
                          C.byref(opts), _ptr(piv), _ptr(Lt), n, _ptr(U), m, C.byref(info),
@@ -269,7 +272,8 @@ def rplu_cauchy(x: torch.Tensor, y: torch.Tensor, G: torch.Tensor, B: torch.Tens
     r = int(info.rank)
     return Result(piv[:r], Lt[:r].T if Lt is not None else None, U[:r] if U is not None else None,
                   r, int(info.stop), float(info.a_fro2), float(info.res_fro2),
-                  trace[:r] if trace is not None else None, rmo[:r] if rmo is not None else None)
+                  trace[:r] if trace is not None else None, rmo[:r] if rmo is not None else None,
+                  cmo[:r] if cmo is not None else None)
 
 
 def rplu_profile_begin(ctx: Context) -> None:

@@ -221,6 +221,20 @@ static rplu_status run_loop(rplu_ctx_s* ctx, StepState* st, int64_t steps_total,
     return RPLU_OK;
 }
 
+// Work split of an all-pairs mass pass with `rows` targets and `cols`
+// sources: enough workgroups to fill every CU a few times over, columns per
+// split a multiple of the 8-column reciprocal group.
+static void cauchy_mass_layout(rplu_ctx_s* ctx, int64_t rows, int64_t cols, int64_t* splits_out,
+                               int64_t* cps_out) {
+    const int64_t nbr = (rows + cauchy_rows_per_block() - 1) / cauchy_rows_per_block();
+    int64_t splits = (4 * (int64_t)ctx->cu_count + nbr - 1) / nbr;
+    splits = std::max<int64_t>(1, std::min<int64_t>(splits, std::max<int64_t>(1, cols / 256)));
+    int64_t cps = (cols + splits - 1) / splits;
+    cps = (cps + 7) / 8 * 8;
+    *splits_out = (cols + cps - 1) / cps;
+    *cps_out = cps;
+}
+
 // Dense path: the fused one-workgroup pivot draw (one launch per step
 // instead of two) unless a side exceeds its limit or the caller asks for
 // the wide form.
@@ -507,8 +521,9 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     if (U != nullptr && ldu < m) return fail(RPLU_E_ARG, "rplu_cauchy: ldu < m");
     if (opts->rel_tol < 0 || !(opts->rel_tol == opts->rel_tol))
         return fail(RPLU_E_ARG, "rplu_cauchy: rel_tol must be >= 0");
-    if (opts->colmass_out != nullptr || (opts->flags & RPLU_FLAG_COLMASS))
-        return fail(RPLU_E_UNSUPPORTED, "rplu_cauchy: column masses are not provided");
+    if (opts->colmass_out != nullptr && !(opts->flags & RPLU_FLAG_COLMASS))
+        return fail(RPLU_E_ARG, "rplu_cauchy: colmass_out needs RPLU_FLAG_COLMASS");
+    const bool colmass = opts->colmass_out != nullptr;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
@@ -518,16 +533,14 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
         return fail(RPLU_E_UNSUPPORTED, "rplu_cauchy: n and m must be <= %d", RPLU_MAX_DIM);
     CauchyArgs a;
     std::memset(&a, 0, sizeof a);        // padding too: the struct keys the graph cache
-    const int64_t nbr = (n + cauchy_rows_per_block() - 1) / cauchy_rows_per_block();
-    // enough workgroups to fill every CU a few times over
-    int64_t splits = (4 * (int64_t)ctx->cu_count + nbr - 1) / nbr;
-    splits = std::max<int64_t>(1, std::min<int64_t>(splits, std::max<int64_t>(1, m / 256)));
-    // columns per split: a multiple of the 8-column reciprocal group
-    int64_t cps = (m + splits - 1) / splits;
-    cps = (cps + 7) / 8 * 8;
-    splits = (m + cps - 1) / cps;
+    int64_t splits, cps;
+    cauchy_mass_layout(ctx, n, m, &splits, &cps);
     a.splits = (int)splits;
     a.cols_per_split = (int)cps;
+    // optional column masses: the same all-pairs pass with rows and columns
+    // exchanged (targets y_j with B_:,j, sources x_i with G_i,:)
+    int64_t splits_c = 0, cps_c = 0;
+    if (colmass) cauchy_mass_layout(ctx, m, n, &splits_c, &cps_c);
     Carver cv;
     const size_t o_st = cv.take(sizeof(StepState));
     const size_t o_rm = cv.take((size_t)n * 8);
@@ -537,6 +550,9 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     const size_t o_u = (U == nullptr) ? cv.take((size_t)m * 16) : 0;
     const size_t o_mc = cv.take(cauchy_mass_col_bytes(p, m));
     const size_t o_mf = cv.take(cauchy_mass_frame_bytes(p));
+    const size_t o_pc = colmass ? cv.take((size_t)m * splits_c * 8) : 0;
+    const size_t o_gt = (colmass && p > 1) ? cv.take((size_t)n * p * 16) : 0;
+    const size_t o_bt = (colmass && p > 1) ? cv.take((size_t)m * p * 16) : 0;
     rplu_status rc = ws_reserve(ctx, cv.off, s);
     if (rc) return rc;
     char* ws = (char*)ctx->ws;
@@ -565,6 +581,23 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     a.kmax = kmax;
     a.tol2 = opts->rel_tol * opts->rel_tol;
 
+    CauchyArgs ac;                       // the column pass
+    std::memset(&ac, 0, sizeof ac);
+    if (colmass) {
+        ac.n = m;
+        ac.m = n;
+        ac.p = p;
+        ac.x = y;
+        ac.y = x;
+        // for p = 1, B (1 x m) read as m x 1 is B^T and G (n x 1) read as 1 x n is G^T
+        ac.G = (p > 1) ? (void*)(ws + o_bt) : B;     // B^T, m x p
+        ac.B = (p > 1) ? (void*)(ws + o_gt) : G;     // G^T, p x n
+        ac.st = a.st;
+        ac.partial = (double*)(ws + o_pc);
+        ac.splits = (int)splits_c;
+        ac.cols_per_split = (int)cps_c;
+    }
+
     launch_state_init(a.st, s);
     launch_cauchy_frame(a, s);
     SampleArgs sa;
@@ -591,9 +624,16 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     sa.trace = opts->trace;
     sa.rowmass_out = opts->rowmass_out;
     const bool graph = !(opts->flags & RPLU_FLAG_NO_GRAPH);
-    const uint64_t key = fnv1a(&sa, sizeof sa, fnv1a(&a, sizeof a, 0x636175636879ull));
+    const uint64_t key = fnv1a(&ac, sizeof ac, fnv1a(&sa, sizeof sa,
+                                                    fnv1a(&a, sizeof a, 0x636175636879ull)));
     rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
         timed(ctx, 0, q, [&] { launch_cauchy_mass(a, q); });
+        if (colmass)
+            timed(ctx, 2, q, [&] {
+                if (p > 1) launch_cauchy_transpose(a, ac.B, ac.G, q);
+                launch_cauchy_mass(ac, q);
+                launch_colmass_sum(ac.partial, ac.splits, m, a.st, opts->colmass_out, m, kmax, q);
+            });
         timed(ctx, 1, q, [&] {
             launch_cauchy_reduce_draw(a, sa, q);
             launch_cauchy_rowgen_draw(a, sa, q);

@@ -20,6 +20,8 @@
 //   k_cauchy_rowgen_draw  regenerates the pivot row
 //                    r = (G_i,: B) ./ (x_i - y) into U(t,:) with the chunk
 //                    totals of |r|^2; the last workgroup draws the column
+//   k_cauchy_transpose  optional column masses (the same all-pairs sums with
+//                    rows and columns exchanged, in k_cauchy_mass): G^T, B^T
 //   k_cauchy_frame   once per run (p = 1): the box of y, its centre and the
 //                    per-column data of k_cauchy_mass1
 //   k_cauchy_update  column c = (G B_:,j) ./ (x - y_j), L(:,t) = c / a with
@@ -88,11 +90,13 @@ __device__ inline void mass_group(const double (&d)[CM_GRP], const double (&w)[C
     acc = fma(N, rcp_1nr(D), acc);
 }
 
-// ------------------------------------------------------------- p >= 2
+// ------------------------------------------------------- LDS-staged form
 
 // Each thread keeps CM_RT target rows (x_i, G_i,:) in registers; the
 // workgroup stages tiles of source columns (y_j, B_:,j) in LDS and every
-// lane reads them as broadcasts.
+// lane reads them as broadcasts. The row masses for p >= 2, and the column
+// masses for every p (the same sums with the roles of (x, G) and (y, B^T)
+// exchanged).
 template <int P>
 __device__ inline void mass_tile_exact(double& acc_t, double xr, double xi, const cf64* sy,
                                        const cf64* g, const cf64 (*sb)[CM_TILE], int nt) {
@@ -110,7 +114,6 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass(
     const cf64* __restrict__ x, const cf64* __restrict__ y, const cf64* __restrict__ G,
     const cf64* __restrict__ B, int n, int m, int cols_per_split,
     const StepState* __restrict__ st, double* __restrict__ partial) {
-    static_assert(P >= 2, "p = 1 has its own kernel");
     if (st->done) return;
     __shared__ cf64 sy[CM_TILE];
     __shared__ cf64 sb[P][CM_TILE];
@@ -499,6 +502,24 @@ __global__ __launch_bounds__(256) void k_cauchy_update(
     }
 }
 
+// Column-mass pass, p > 1: G^T (p x n) and B^T (m x p), row-major.
+__global__ __launch_bounds__(256) void k_cauchy_transpose(const cf64* __restrict__ G,
+                                                          const cf64* __restrict__ B, int n,
+                                                          int m, int p, const StepState* st,
+                                                          cf64* __restrict__ Gt,
+                                                          cf64* __restrict__ Bt) {
+    if (st->done) return;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < (int64_t)n * p) {
+        const int64_t i = idx / p, l = idx % p;
+        Gt[l * n + i] = G[idx];
+    }
+    if (idx < (int64_t)m * p) {
+        const int64_t j = idx / p, l = idx % p;
+        Bt[idx] = B[l * m + j];
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 
 int cauchy_rows_per_block() { return CM_ROWS; }
@@ -507,7 +528,7 @@ template <int P>
 static void mass_p(const CauchyArgs& a, hipStream_t s) {
     const int cps = a.cols_per_split;
     dim3 grid((unsigned)((a.n + CM_ROWS - 1) / CM_ROWS), (unsigned)a.splits);
-    if constexpr (P == 1)
+    if (P == 1 && a.mcol != nullptr)
         hipLaunchKernelGGL(k_cauchy_mass1, grid, dim3(CM_THREADS), 0, s, (const cf64*)a.x,
                            (const cf64*)a.y, (const cf64*)a.G, (const MassCol*)a.mcol,
                            (const MassFrame*)a.mframe, (int)a.n, (int)a.m, cps, a.st, a.partial);
@@ -519,6 +540,13 @@ static void mass_p(const CauchyArgs& a, hipStream_t s) {
 
 size_t cauchy_mass_col_bytes(int p, int64_t m) { return p == 1 ? (size_t)m * sizeof(MassCol) : 0; }
 size_t cauchy_mass_frame_bytes(int p) { return p == 1 ? sizeof(MassFrame) : 0; }
+
+void launch_cauchy_transpose(const CauchyArgs& a, void* Gt, void* Bt, hipStream_t s) {
+    const int64_t work = (a.n > a.m ? a.n : a.m) * a.p;
+    hipLaunchKernelGGL(k_cauchy_transpose, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s,
+                       (const cf64*)a.G, (const cf64*)a.B, (int)a.n, (int)a.m, a.p, a.st,
+                       (cf64*)Gt, (cf64*)Bt);
+}
 
 void launch_cauchy_frame(const CauchyArgs& a, hipStream_t s) {
     if (a.p != 1) return;

@@ -304,6 +304,12 @@ void launch_dense_sweep(const DenseArgs& a, bool init, hipStream_t s) {
 
 int dense_row_block(bool colmass) { return colmass ? DENSE_ROWS_COLMASS : DENSE_ROWS; }
 
+void launch_colmass_sum(const double* part, int nb, int64_t m, StepState* st, double* out,
+                        int64_t ld_out, int64_t rows_cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_colmass_reduce, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, part,
+                       nb, (int)m, st, 1, out, ld_out, (int)rows_cap);
+}
+
 void launch_colmass_reduce(const DenseArgs& a, bool after_step, hipStream_t s) {
     const int nb = (int)((a.n + DENSE_ROWS_COLMASS - 1) / DENSE_ROWS_COLMASS);
     const int threads = 256;

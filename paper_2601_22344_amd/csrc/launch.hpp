@@ -80,6 +80,10 @@ void launch_rows_draw(const SampleArgs& a, hipStream_t s);
 void launch_dense_sweep(const DenseArgs& a, bool init, hipStream_t s);
 void launch_dense_pivrow_draw(const DenseArgs& a, const SampleArgs& sa, hipStream_t s);
 void launch_colmass_reduce(const DenseArgs& a, bool after_step, hipStream_t s);
+// Row st->t of out (ld_out per row, rows below rows_cap) = sum over b in
+// order of part[b][0..m); skipped once the run is done.
+void launch_colmass_sum(const double* part, int nb, int64_t m, StepState* st, double* out,
+                        int64_t ld_out, int64_t rows_cap, hipStream_t s);
 void launch_dense_pivot(const DenseArgs& a, const SampleArgs& sa, hipStream_t s);
 int dense_row_block(bool colmass);
 
@@ -111,6 +115,7 @@ struct CauchyArgs {
 };
 
 void launch_cauchy_frame(const CauchyArgs& a, hipStream_t s);
+void launch_cauchy_transpose(const CauchyArgs& a, void* Gt, void* Bt, hipStream_t s);
 void launch_cauchy_mass(const CauchyArgs& a, hipStream_t s);
 size_t cauchy_mass_col_bytes(int p, int64_t m);
 size_t cauchy_mass_frame_bytes(int p);

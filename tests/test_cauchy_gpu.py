@@ -114,6 +114,35 @@ def test_cauchy_p1_nonfinite_node(rplu_lib, bad):
     assert e.value.status == -4
 
 
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("n,m", [(300, 257), (1500, 2049)])
+def test_cauchy_column_masses(rplu_lib, p, n, m):
+    """Optional column masses of the Cauchy-like form: at t = 0 the column
+    sums of |A_ij|^2 of the regenerated matrix, at every step the same total
+    as the row masses, and equal to the dense path's column masses under the
+    same pivots."""
+    x, y, G, B = W.cauchy_like_random(n, m, p, seed=n + m + p)
+    A = O.cauchy_entries(x, y, G, B)
+    xd, yd, Gd, Bd = _dev(x, y, G, B)
+    k = 20
+    rc = rplu_lib.rplu_cauchy(xd, yd, Gd, Bd, k=k, seed=1, want_rowmass=True, want_colmass=True)
+    cm = rc.colmass.cpu().numpy()
+    rm = rc.rowmass.cpu().numpy()
+    assert cm.shape == (k, m)
+    ref0 = np.sum(np.abs(A) ** 2, axis=0)
+    assert np.allclose(cm[0], ref0, rtol=1e-12, atol=1e-14 * ref0.sum())
+    for t in range(k):
+        assert abs(cm[t].sum() - rm[t].sum()) <= 1e-12 * rm[t].sum(), t
+    rd = rplu_lib.rplu_dense(torch.from_numpy(A).to(DEV), k=k, seed=1, forced=rc.piv.flatten(),
+                             want_colmass=True)
+    cd = rd.colmass.cpu().numpy()
+    # the two forms round differently on the scale of the input, so the
+    # absolute allowance is sqrt(T_t T_0) * 1e-12 per step (as for row masses)
+    for t in range(k):
+        allow = 1e-12 * math.sqrt(cd[t].sum() * cd[0].sum())
+        assert np.allclose(cm[t], cd[t], rtol=1e-10, atol=allow), t
+
+
 def test_cauchy_loewner_p2(rplu_lib):
     rng = np.random.default_rng(4)
     x = rng.uniform(-1, 1, 400).astype(np.complex128)
