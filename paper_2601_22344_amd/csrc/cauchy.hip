@@ -10,13 +10,13 @@
 //                    source columns come as uniform loads (p = 1, with a
 //                    centred short form of |x - y|^2 where it is accurate)
 //                    or LDS broadcasts (p > 1); eight columns share one
-//                    reciprocal. Columns are
-//                    split over `splits` workgroup columns; the partial sums
-//                    are added in split order by k_cauchy_reduce_draw
-//                    (deterministic).
-//   k_cauchy_reduce_draw  row masses from the split partials (fixed order,
-//                    two halves of the splits per row) and their chunk totals; the last workgroup runs the
-//                    stop test and draws the row (pivot.hpp)
+//                    reciprocal. Columns are split over `splits` workgroup
+//                    columns; the partial sums are added in a fixed order by
+//                    k_cauchy_reduce_draw (deterministic).
+//   k_cauchy_reduce_draw  row masses from the split partials (two halves of
+//                    the splits per row, each in order) and their chunk
+//                    totals; the last workgroup runs the stop test and draws
+//                    the row (pivot.hpp)
 //   k_cauchy_rowgen_draw  regenerates the pivot row
 //                    r = (G_i,: B) ./ (x_i - y) into U(t,:) with the chunk
 //                    totals of |r|^2; the last workgroup draws the column
