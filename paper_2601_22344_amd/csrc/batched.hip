@@ -34,6 +34,45 @@ static_assert(BT_MAXK <= CDF_GROUP, "one CDF group: the chain is a single sequen
 
 template <class T, int V>
 struct alignas(V == 1 ? alignof(T) : 16) BPack { T v[V]; };
+
+// Instance buffers come from the job table, so the compiler cannot tell that
+// they are global memory: through plain pointers it emits flat accesses,
+// which also count against the LDS counter, and every LDS wait of the sweep
+// then waits for the row loads and stores in flight as well. Pointers into
+// instance memory carry the global address space instead.
+template <class T> using gmem = __attribute__((address_space(1))) T;
+
+// A whole pack from / to instance memory as one 16-byte access: a native
+// vector value (the pack's own copy operations take generic references, and
+// element-wise copies let the compiler split the store).
+template <class T, int V> struct PackVec { typedef T type __attribute__((ext_vector_type(V))); };
+template <class T> struct PackVec<T, 1> { typedef T type; };
+
+template <class T, int V>
+__device__ __forceinline__ BPack<T, V> ld_pack(const gmem<T>* p) {
+    using VT = typename PackVec<T, V>::type;
+    const VT w = *reinterpret_cast<const gmem<VT>*>(p);
+    BPack<T, V> x;
+    if constexpr (V == 1) x.v[0] = w;
+    else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) x.v[v] = w[v];
+    }
+    return x;
+}
+
+template <class T, int V>
+__device__ __forceinline__ void st_pack(gmem<T>* p, const BPack<T, V>& x) {
+    using VT = typename PackVec<T, V>::type;
+    VT w;
+    if constexpr (V == 1) w = x.v[0];
+    else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) w[v] = x.v[v];
+    }
+    *reinterpret_cast<gmem<VT>*>(p) = w;
+}
+
 static_assert(sizeof(BPack<float, 1>) == 4 && sizeof(BPack<double, 2>) == 16, "pack size");
 
 struct BtShared {
@@ -70,8 +109,8 @@ __device__ __forceinline__ double uniform_d(double v) {
 // wave sums and the same ordered total; a virtual wave that holds no column
 // would add an exact 0 and is skipped.
 template <class T, int R, int V, bool INIT>
-__device__ __forceinline__ void bt_sweep(T* __restrict__ S, int64_t lda, int m, int pi, int pj,
-                                         const T* __restrict__ s_l, const T* __restrict__ Ut,
+__device__ __forceinline__ void bt_sweep(gmem<T>* __restrict__ S, int64_t lda, int m, int pi, int pj,
+                                         const T* __restrict__ s_l, const gmem<T>* __restrict__ Ut,
                                          double* __restrict__ s_rm,
                                          const uint16_t* __restrict__ rows, int nalive) {
     const int lane = threadIdx.x % RPLU_WAVE, wv = threadIdx.x / RPLU_WAVE;
@@ -92,7 +131,7 @@ __device__ __forceinline__ void bt_sweep(T* __restrict__ S, int64_t lda, int m, 
         for (int q = 0; q < R; ++q) tot[q] = 0.0;
         double rp[R];
 
-        T* rowp[R];
+        gmem<T>* rowp[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) rowp[q] = S + (int64_t)ri[q] * lda;
 
@@ -103,7 +142,7 @@ __device__ __forceinline__ void bt_sweep(T* __restrict__ S, int64_t lda, int m, 
             constexpr bool ALLR = decltype(allrows_tag)::value;
             BPack<T, V> u;
             if constexpr (!INIT) {
-                if constexpr (FULL) u = *reinterpret_cast<const BPack<T, V>*>(Ut + c);
+                if constexpr (FULL) u = ld_pack<T, V>(Ut + c);
                 else {
 #pragma unroll
                     for (int v = 0; v < V; ++v) u.v[v] = (c + v < m) ? Ut[c + v] : Sc<T>::zero();
@@ -113,8 +152,8 @@ __device__ __forceinline__ void bt_sweep(T* __restrict__ S, int64_t lda, int m, 
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 if (ALLR || q < nr) {
-                    const T* p = rowp[q] + c;
-                    if constexpr (FULL) s[q] = *reinterpret_cast<const BPack<T, V>*>(p);
+                    const gmem<T>* p = rowp[q] + c;
+                    if constexpr (FULL) s[q] = ld_pack<T, V>(p);
                     else {
 #pragma unroll
                         for (int v = 0; v < V; ++v) s[q].v[v] = (c + v < m) ? p[v] : Sc<T>::zero();
@@ -136,8 +175,8 @@ __device__ __forceinline__ void bt_sweep(T* __restrict__ S, int64_t lda, int m, 
 #pragma unroll
                     for (int v = 0; v < V; ++v) rp[q] += Sc<T>::mag2(s[q].v[v]);
                     if constexpr (!INIT) {
-                        T* p = rowp[q] + c;
-                        if constexpr (FULL) *reinterpret_cast<BPack<T, V>*>(p) = s[q];
+                        gmem<T>* p = rowp[q] + c;
+                        if constexpr (FULL) st_pack<T, V>(p, s[q]);
                         else {
 #pragma unroll
                             for (int v = 0; v < V; ++v) if (c + v < m) p[v] = s[q].v[v];
@@ -173,6 +212,136 @@ __device__ __forceinline__ void bt_sweep(T* __restrict__ S, int64_t lda, int m, 
             for (int q = 0; q < R; ++q)
                 if (q < nr) s_rm[ri[q]] = tot[q];
         }
+    }
+}
+
+// The pack of V elements at p when `rem` = m - c elements remain in the row:
+// a 16-byte load when the pack is whole, element loads with zeros past m at
+// the row's end, zeros (and no load) past it.
+template <class T, int V>
+__device__ __forceinline__ BPack<T, V> bt_load(const gmem<T>* p, int rem) {
+    BPack<T, V> x;
+    if (rem >= V) x = ld_pack<T, V>(p);
+    else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) x.v[v] = (v < rem) ? p[v] : Sc<T>::zero();
+    }
+    return x;
+}
+
+template <class T, int V>
+__device__ __forceinline__ void bt_store(gmem<T>* p, int rem, const BPack<T, V>& x) {
+    if (rem >= V) st_pack<T, V>(p, x);
+    else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) if (v < rem) p[v] = x.v[v];
+    }
+}
+
+constexpr int BT_NV = 4;   // virtual waves a row may span in the block pass
+
+// The value of lane 0 (every lane holds the same), in scalar registers.
+__device__ __forceinline__ float uniform_v(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform_v(double v) { return uniform_d(v); }
+
+// The pass of bt_sweep for rows of NVW <= BT_NV virtual waves (m <= NVW x 64 V
+// columns), where each lane holds at most one pack per virtual wave. A wave
+// takes blocks of RB rows and loads a whole block (RB rows by NVW packs)
+// before any arithmetic, so one memory round trip serves the block instead of
+// one per virtual wave. Each row keeps the per-lane sums (0 + |x_0|^2 + ... in
+// pack order, exactly 0 for a lane with no column), the wave sums and their
+// sum in virtual-wave order of bt_sweep, so S and the masses are the same
+// bits; lane q holds the running total of row q (the wave sums are the same
+// in every lane).
+template <class T, int RB, int NVW, int V, bool INIT>
+__device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t lda, int m, int pi, int pj,
+                                               const T* __restrict__ s_l, const gmem<T>* __restrict__ Ut,
+                                               double* __restrict__ s_rm,
+                                               const uint16_t* __restrict__ rows, int nalive) {
+    const int lane = threadIdx.x % RPLU_WAVE, wv = threadIdx.x / RPLU_WAVE;
+    const int nblk = (nalive + RB - 1) / RB;
+    int rem[NVW];                         // columns of the row from this lane's pack on
+#pragma unroll
+    for (int k = 0; k < NVW; ++k) rem[k] = m - (k * RPLU_WAVE + lane) * V;
+#pragma unroll 1
+    for (int blk = wv; blk < nblk; blk += BT_WAVES) {
+        const int b0 = blk * RB;
+        const int nr = min(RB, nalive - b0);
+        int ri[RB];
+        T lq[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            ri[q] = uniform_i(rows[b0 + min(q, nr - 1)]);
+            lq[q] = INIT ? Sc<T>::zero() : uniform_v(s_l[ri[q]]);
+        }
+        BPack<T, V> u[NVW];
+#pragma unroll
+        for (int k = 0; k < NVW; ++k) {
+            if constexpr (!INIT) u[k] = bt_load<T, V>(Ut + (m - rem[k]), rem[k]);
+        }
+        BPack<T, V> x[RB][NVW];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            if (q < nr) {
+                const gmem<T>* rp = S + (int64_t)ri[q] * lda;
+#pragma unroll
+                for (int k = 0; k < NVW; ++k) x[q][k] = bt_load<T, V>(rp + (m - rem[k]), rem[k]);
+            }
+        }
+        double tot = 0.0;
+#pragma unroll
+        for (int k = 0; k < NVW; ++k) {
+            const int c = m - rem[k];
+            const int pv = pj - c;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                double part = 0.0;
+                if (q < nr) {
+                    if constexpr (!INIT) {
+                        const bool zr = ri[q] == pi;
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            const T y = Sc<T>::fms(x[q][k].v[v], lq[q], u[k].v[v]);
+                            x[q][k].v[v] = ((v == pv) | zr) ? Sc<T>::zero() : y;
+                        }
+                    }
+                    double acc = 0.0;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc += Sc<T>::mag2(x[q][k].v[v]);
+                    part = rem[k] > 0 ? acc : 0.0;
+                    if constexpr (!INIT) {
+                        if (rem[k] > 0) bt_store<T, V>(S + (int64_t)ri[q] * lda + c, rem[k], x[q][k]);
+                    }
+                }
+                const double w = wave_sum(part);
+                if (lane == q) tot = (k == 0) ? w : tot + w;
+            }
+        }
+        if (lane < nr) s_rm[rows[b0 + lane]] = tot;
+    }
+}
+
+// Packs a wave holds at once in the block pass for the row knob R (more than
+// 8 spill registers at 1024 threads).
+template <int R> constexpr int bt_packs() { return R == 1 ? 4 : 8; }
+
+// One pass of the sweep: the block pass when every row spans at most BT_NV
+// virtual waves, with RB = packs / (virtual waves) rows per block; else
+// bt_sweep with R rows in flight.
+template <class T, int R, int V, bool INIT>
+__device__ __forceinline__ void bt_pass(gmem<T>* __restrict__ S, int64_t lda, int m, int pi, int pj,
+                                        const T* __restrict__ s_l, const gmem<T>* __restrict__ Ut,
+                                        double* __restrict__ s_rm, const uint16_t* __restrict__ rows,
+                                        int nalive) {
+    constexpr int P = bt_packs<R>();
+    switch ((m + RPLU_WAVE * V - 1) / (RPLU_WAVE * V)) {
+        case 1: bt_sweep_block<T, P, 1, V, INIT>(S, lda, m, pi, pj, s_l, Ut, s_rm, rows, nalive); break;
+        case 2: bt_sweep_block<T, P / 2, 2, V, INIT>(S, lda, m, pi, pj, s_l, Ut, s_rm, rows, nalive); break;
+        case 3: bt_sweep_block<T, P / 3, 3, V, INIT>(S, lda, m, pi, pj, s_l, Ut, s_rm, rows, nalive); break;
+        case 4: bt_sweep_block<T, P / 4, 4, V, INIT>(S, lda, m, pi, pj, s_l, Ut, s_rm, rows, nalive); break;
+        default: bt_sweep<T, R, V, INIT>(S, lda, m, pi, pj, s_l, Ut, s_rm, rows, nalive); break;
     }
 }
 
@@ -228,11 +397,11 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
                        double* __restrict__ s_rm, T* __restrict__ s_l, uint16_t* __restrict__ s_alive,
                        uint16_t* __restrict__ s_pos, BtShared& sh) {
     using W = typename Sc<T>::W;
-    T* __restrict__ S = (T*)jb.A;
-    T* __restrict__ L = (T*)jb.L;
+    gmem<T>* __restrict__ S = (gmem<T>*)jb.A;
+    gmem<T>* __restrict__ L = (gmem<T>*)jb.L;
     const int n = jb.n, m = jb.m;
     const int64_t lda = jb.lda;
-    T* Ubase = jb.U ? (T*)jb.U : uscr;
+    gmem<T>* Ubase = (gmem<T>*)(jb.U ? (T*)jb.U : uscr);
     const int64_t ldu = jb.U ? jb.ldu : 0;
     for (int r = threadIdx.x; r < n; r += BT_THREADS) {
         s_alive[r] = (uint16_t)r;
@@ -240,7 +409,7 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
     }
     __syncthreads();
     int nalive = n;
-    bt_sweep<T, R, V, true>(S, lda, m, -1, -1, s_l, nullptr, s_rm, s_alive, nalive);
+    bt_pass<T, R, V, true>(S, lda, m, -1, -1, s_l, nullptr, s_rm, s_alive, nalive);
     __syncthreads();
     double T0 = 0.0, Tc = 0.0, Tbest = 0.0;
     int t = 0, stop = 0, err = 0, prev_i = -1, tbest = 0;
@@ -270,8 +439,8 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
         const CdfPick pr = bt_draw(n, sh.ctr, rmass, unit_from_word(rnd.w[0]) * Tc, sh);
         const int i = pr.idx;
         if (i < 0 || i >= n) { err = RPLU_E_ARG; break; }
-        const T* Si = S + (int64_t)i * lda;
-        T* Ut = Ubase + (int64_t)t * ldu;
+        const gmem<T>* Si = S + (int64_t)i * lda;
+        gmem<T>* Ut = Ubase + (int64_t)t * ldu;
         auto rcopy = [&](int e) { const T v = Si[e]; Ut[e] = v; return Sc<T>::mag2(v); };
         const double Ti = bt_levels(m, sh.ctc, rcopy, sh);
         auto smass = [&](int e) { return Sc<T>::mag2(Si[e]); };
@@ -283,7 +452,11 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
         const double a2 = Sc<T>::mag2(a);
         if (!(a2 > 0.0)) { err = isfinite(a2) ? RPLU_E_ZERO_PIVOT : RPLU_E_NONFINITE; break; }
         const W inv = winv(Sc<T>::widen(a));
-        if (threadIdx.x == 0 && jb.piv != nullptr) { jb.piv[2 * t] = i; jb.piv[2 * t + 1] = j; }
+        if (threadIdx.x == 0 && jb.piv != nullptr) {
+            gmem<int32_t>* piv = (gmem<int32_t>*)jb.piv;
+            piv[2 * t] = i;
+            piv[2 * t + 1] = j;
+        }
         // scaled pivot column: L(:,t) and the multipliers of the sweep
         for (int r = threadIdx.x; r < n; r += BT_THREADS) {
             const T l = (r == i) ? Sc<T>::one()
@@ -292,7 +465,7 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
             if (L != nullptr) L[(int64_t)t * jb.ldl + r] = l;
         }
         __syncthreads();                  // column j read before any store to it
-        bt_sweep<T, R, V, false>(S, lda, m, i, j, s_l, Ut, s_rm, s_alive, nalive);
+        bt_pass<T, R, V, false>(S, lda, m, i, j, s_l, Ut, s_rm, s_alive, nalive);
         __syncthreads();                  // new masses and S visible to every wave
         prev_i = i;
     }
@@ -306,7 +479,11 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
 }
 
 // Persistent kernel. Every workgroup leaves once the queue index passes
-// `count`, so the grid drains after the last instance.
+// `count`, so the grid drains after the last instance. Keep a barrier between
+// any thread-0-only work at the end of an iteration and the thread-0 queue
+// fetch at the top: with the two adjacent, the compiler can give the loop a
+// second back edge that bypasses the fetch for the other lanes, and since a
+// barrier counts whole waves those lanes then re-run a stale job index.
 template <class T, int R>
 __global__ __launch_bounds__(BT_THREADS) void k_batched(const BatchJob* __restrict__ jobs,
                                                          const int32_t* __restrict__ order,

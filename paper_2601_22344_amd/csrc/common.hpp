@@ -165,9 +165,50 @@ __device__ inline double unit_from_word(uint64_t w) {
 
 // ------------------------------------------------------------ reductions
 
+// Cross-lane moves of a double as two 32-bit halves, all 64 lanes active.
+// dpp_d: the value of the lane that the DPP control CTRL selects (within a
+// row of 16 lanes). swap_sum32 / swap_sum16: v + v(lane ^ 32) / v + v(lane ^
+// 16), from the gfx950 lane swaps (the first result holds the lower half-wave
+// or the even rows in both places, the second the upper half or the odd rows,
+// so each lane adds its own value and its partner's).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)b, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double swap_sum32(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)b, (uint32_t)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | lo[0]) +
+           __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | lo[1]);
+}
+
+__device__ __forceinline__ double swap_sum16(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)b, (uint32_t)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | lo[0]) +
+           __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | lo[1]);
+}
+
+// Sum over the 64 lanes, the same in every lane: the butterfly
+// v <- v + v(lane ^ d) for d = 32, 16, 8, 4, 2, 1, without LDS. Within a row
+// of 16 lanes a rotation by 8 is lane ^ 8; after the steps d' > d a lane's
+// value depends only on lane mod 2d, where a rotation by d and lane ^ d pick
+// equal values. Every step adds the butterfly's two operands (addition
+// commutes), so each lane gets the butterfly's bits. Call with every lane of
+// the wave active.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, RPLU_WAVE);
+    v = swap_sum32(v);
+    v = swap_sum16(v);
+    v = v + dpp_d<0x128>(v);     // row_ror:8
+    v = v + dpp_d<0x124>(v);     // row_ror:4
+    v = v + dpp_d<0x122>(v);     // row_ror:2
+    v = v + dpp_d<0x121>(v);     // row_ror:1
     return v;
 }
 
