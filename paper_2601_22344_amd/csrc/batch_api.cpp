@@ -125,8 +125,6 @@ rplu_status check_cfg(const rplu_batch_cfg& c) {
     return RPLU_OK;
 }
 
-constexpr size_t BT_STATIC_LDS = 2048;   // bound on the kernel's static LDS
-
 // One launch over P.jobs with configuration c; optionally the device time
 // (events around the launch) and the per-job results.
 rplu_status run_batch(rplu_ctx_s* ctx, const Prepared& P, const rplu_batch_cfg& c, hipStream_t s,

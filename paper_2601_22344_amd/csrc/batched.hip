@@ -216,19 +216,8 @@ __device__ __forceinline__ void bt_sweep(gmem<T>* __restrict__ S, int64_t lda, i
 }
 
 // The pack of V elements at p when `rem` = m - c elements remain in the row:
-// a 16-byte load when the pack is whole, element loads with zeros past m at
-// the row's end, zeros (and no load) past it.
-template <class T, int V>
-__device__ __forceinline__ BPack<T, V> bt_load(const gmem<T>* p, int rem) {
-    BPack<T, V> x;
-    if (rem >= V) x = ld_pack<T, V>(p);
-    else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) x.v[v] = (v < rem) ? p[v] : Sc<T>::zero();
-    }
-    return x;
-}
-
+// a 16-byte store when the pack is whole, element stores up to m at the row's
+// end, nothing past it.
 template <class T, int V>
 __device__ __forceinline__ void bt_store(gmem<T>* p, int rem, const BPack<T, V>& x) {
     if (rem >= V) st_pack<T, V>(p, x);
@@ -236,6 +225,33 @@ __device__ __forceinline__ void bt_store(gmem<T>* p, int rem, const BPack<T, V>&
 #pragma unroll
         for (int v = 0; v < V; ++v) if (v < rem) p[v] = x.v[v];
     }
+}
+
+// Branch-free pieces of the block pass. A branch between loads into the same
+// registers (a whole-pack load on one side, element loads or zeros on the
+// other) makes the compiler wait for every load in flight before it, which
+// serialises a block's loads. So every lane loads a whole pack inside the row
+// (its own when its pack is whole, else the row's first: rows of at least V
+// columns), the one partial pack of a row (m mod V columns from cp = m - m mod
+// V on) comes from V element loads at clamped addresses into registers of its
+// own, and bt_pick selects what the lane's pack holds: the whole pack, the
+// partial pack's first rem columns then zeros, or zeros.
+template <class T, int V>
+__device__ __forceinline__ BPack<T, V> bt_tail(const gmem<T>* row, int cp, int mt) {
+    BPack<T, V> x;
+#pragma unroll
+    for (int v = 0; v < V; ++v) x.v[v] = row[cp + min(v, mt - 1)];
+    return x;
+}
+
+template <class T, int V>
+__device__ __forceinline__ BPack<T, V> bt_pick(const BPack<T, V>& whole, const BPack<T, V>& tail,
+                                               int rem) {
+    BPack<T, V> x;
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        x.v[v] = rem >= V ? whole.v[v] : (v < rem ? tail.v[v] : Sc<T>::zero());
+    return x;
 }
 
 constexpr int BT_NV = 4;   // virtual waves a row may span in the block pass
@@ -246,25 +262,31 @@ __device__ __forceinline__ float uniform_v(float v) {
 }
 __device__ __forceinline__ double uniform_v(double v) { return uniform_d(v); }
 
-// The pass of bt_sweep for rows of NVW <= BT_NV virtual waves (m <= NVW x 64 V
-// columns), where each lane holds at most one pack per virtual wave. A wave
+// The pass of bt_sweep for rows of NVW <= BT_NV virtual waves (V <= m <= NVW x
+// 64 V columns), where each lane holds at most one pack per virtual wave. A wave
 // takes blocks of RB rows and loads a whole block (RB rows by NVW packs)
 // before any arithmetic, so one memory round trip serves the block instead of
-// one per virtual wave. Each row keeps the per-lane sums (0 + |x_0|^2 + ... in
+// one per virtual wave; the pivot row's packs come from its LDS copy s_u
+// (zero past m). Each row keeps the per-lane sums (0 + |x_0|^2 + ... in
 // pack order, exactly 0 for a lane with no column), the wave sums and their
 // sum in virtual-wave order of bt_sweep, so S and the masses are the same
 // bits; lane q holds the running total of row q (the wave sums are the same
 // in every lane).
 template <class T, int RB, int NVW, int V, bool INIT>
 __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t lda, int m, int pi, int pj,
-                                               const T* __restrict__ s_l, const gmem<T>* __restrict__ Ut,
+                                               const T* __restrict__ s_l, const T* __restrict__ s_u,
                                                double* __restrict__ s_rm,
                                                const uint16_t* __restrict__ rows, int nalive) {
     const int lane = threadIdx.x % RPLU_WAVE, wv = threadIdx.x / RPLU_WAVE;
     const int nblk = (nalive + RB - 1) / RB;
     int rem[NVW];                         // columns of the row from this lane's pack on
+    int cl[NVW];                          // a whole pack inside the row to load
 #pragma unroll
-    for (int k = 0; k < NVW; ++k) rem[k] = m - (k * RPLU_WAVE + lane) * V;
+    for (int k = 0; k < NVW; ++k) {
+        rem[k] = m - (k * RPLU_WAVE + lane) * V;
+        cl[k] = rem[k] >= V ? m - rem[k] : 0;
+    }
+    const int mt = m % V, cp = m - mt;
 #pragma unroll 1
     for (int blk = wv; blk < nblk; blk += BT_WAVES) {
         const int b0 = blk * RB;
@@ -276,43 +298,48 @@ __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t 
             ri[q] = uniform_i(rows[b0 + min(q, nr - 1)]);
             lq[q] = INIT ? Sc<T>::zero() : uniform_v(s_l[ri[q]]);
         }
-        BPack<T, V> u[NVW];
+        BPack<T, V> x[RB][NVW], xt[RB];
 #pragma unroll
-        for (int k = 0; k < NVW; ++k) {
-            if constexpr (!INIT) u[k] = bt_load<T, V>(Ut + (m - rem[k]), rem[k]);
+        for (int v = 0; v < V; ++v) {
+#pragma unroll
+            for (int q = 0; q < RB; ++q) xt[q].v[v] = Sc<T>::zero();
         }
-        BPack<T, V> x[RB][NVW];
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
-            if (q < nr) {
-                const gmem<T>* rp = S + (int64_t)ri[q] * lda;
+            const gmem<T>* rp = S + (int64_t)ri[q] * lda;
 #pragma unroll
-                for (int k = 0; k < NVW; ++k) x[q][k] = bt_load<T, V>(rp + (m - rem[k]), rem[k]);
-            }
+            for (int k = 0; k < NVW; ++k) x[q][k] = ld_pack<T, V>(rp + cl[k]);
+        }
+        if (mt != 0) {
+#pragma unroll
+            for (int q = 0; q < RB; ++q) xt[q] = bt_tail<T, V>(S + (int64_t)ri[q] * lda, cp, mt);
         }
         double tot = 0.0;
 #pragma unroll
         for (int k = 0; k < NVW; ++k) {
             const int c = m - rem[k];
             const int pv = pj - c;
+            BPack<T, V> uk;
+            if constexpr (!INIT) uk = *reinterpret_cast<const BPack<T, V>*>(s_u + c);
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
                 double part = 0.0;
                 if (q < nr) {
+                    BPack<T, V> xk = bt_pick<T, V>(x[q][k], xt[q], rem[k]);
                     if constexpr (!INIT) {
                         const bool zr = ri[q] == pi;
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
-                            const T y = Sc<T>::fms(x[q][k].v[v], lq[q], u[k].v[v]);
-                            x[q][k].v[v] = ((v == pv) | zr) ? Sc<T>::zero() : y;
+                            const T y = Sc<T>::fms(xk.v[v], lq[q], uk.v[v]);
+                            xk.v[v] = ((v == pv) | zr) ? Sc<T>::zero() : y;
                         }
                     }
                     double acc = 0.0;
 #pragma unroll
-                    for (int v = 0; v < V; ++v) acc += Sc<T>::mag2(x[q][k].v[v]);
+                    for (int v = 0; v < V; ++v) acc += Sc<T>::mag2(xk.v[v]);
                     part = rem[k] > 0 ? acc : 0.0;
                     if constexpr (!INIT) {
-                        if (rem[k] > 0) bt_store<T, V>(S + (int64_t)ri[q] * lda + c, rem[k], x[q][k]);
+                        if (rem[k] > 0) bt_store<T, V>(S + (int64_t)ri[q] * lda + c, rem[k], xk);
                     }
                 }
                 const double w = wave_sum(part);
@@ -327,20 +354,22 @@ __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t 
 // 8 spill registers at 1024 threads).
 template <int R> constexpr int bt_packs() { return R == 1 ? 4 : 8; }
 
-// One pass of the sweep: the block pass when every row spans at most BT_NV
-// virtual waves, with RB = packs / (virtual waves) rows per block; else
-// bt_sweep with R rows in flight.
+// One pass of the sweep: the block pass when rows have V to BT_NV x 64 V
+// columns, with RB = packs / (virtual waves) rows per block; else bt_sweep
+// with R rows in flight.
 template <class T, int R, int V, bool INIT>
 __device__ __forceinline__ void bt_pass(gmem<T>* __restrict__ S, int64_t lda, int m, int pi, int pj,
                                         const T* __restrict__ s_l, const gmem<T>* __restrict__ Ut,
+                                        const T* __restrict__ s_u,
                                         double* __restrict__ s_rm, const uint16_t* __restrict__ rows,
                                         int nalive) {
     constexpr int P = bt_packs<R>();
-    switch ((m + RPLU_WAVE * V - 1) / (RPLU_WAVE * V)) {
-        case 1: bt_sweep_block<T, P, 1, V, INIT>(S, lda, m, pi, pj, s_l, Ut, s_rm, rows, nalive); break;
-        case 2: bt_sweep_block<T, P / 2, 2, V, INIT>(S, lda, m, pi, pj, s_l, Ut, s_rm, rows, nalive); break;
-        case 3: bt_sweep_block<T, P / 3, 3, V, INIT>(S, lda, m, pi, pj, s_l, Ut, s_rm, rows, nalive); break;
-        case 4: bt_sweep_block<T, P / 4, 4, V, INIT>(S, lda, m, pi, pj, s_l, Ut, s_rm, rows, nalive); break;
+    static_assert(BT_NV == 4, "one case per virtual-wave count");
+    switch (m < V ? 0 : (m + RPLU_WAVE * V - 1) / (RPLU_WAVE * V)) {
+        case 1: bt_sweep_block<T, P, 1, V, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive); break;
+        case 2: bt_sweep_block<T, P / 2, 2, V, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive); break;
+        case 3: bt_sweep_block<T, P / 3, 3, V, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive); break;
+        case 4: bt_sweep_block<T, P / 4, 4, V, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive); break;
         default: bt_sweep<T, R, V, INIT>(S, lda, m, pi, pj, s_l, Ut, s_rm, rows, nalive); break;
     }
 }
@@ -392,10 +421,13 @@ __device__ __forceinline__ CdfPick bt_draw(int len, const double* ct, MassFn& ma
     return r;
 }
 
+// s_u: the pivot row in LDS for rows that take the block pass (V <= m <=
+// BT_NV x 64 V), zero past m, so the column draw, the pivot entry and the
+// sweep's multiplier packs read LDS instead of the row in memory.
 template <class T, int R, int V>
 __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr, BatchInfo* __restrict__ info,
                        double* __restrict__ s_rm, T* __restrict__ s_l, uint16_t* __restrict__ s_alive,
-                       uint16_t* __restrict__ s_pos, BtShared& sh) {
+                       uint16_t* __restrict__ s_pos, T* __restrict__ s_u, BtShared& sh) {
     using W = typename Sc<T>::W;
     gmem<T>* __restrict__ S = (gmem<T>*)jb.A;
     gmem<T>* __restrict__ L = (gmem<T>*)jb.L;
@@ -403,13 +435,16 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
     const int64_t lda = jb.lda;
     gmem<T>* Ubase = (gmem<T>*)(jb.U ? (T*)jb.U : uscr);
     const int64_t ldu = jb.U ? jb.ldu : 0;
+    constexpr int SU = BT_NV * RPLU_WAVE * V;
+    const bool lds_row = m >= V && m <= SU;
     for (int r = threadIdx.x; r < n; r += BT_THREADS) {
         s_alive[r] = (uint16_t)r;
         s_pos[r] = (uint16_t)r;
     }
+    for (int e = m + threadIdx.x; e < SU; e += BT_THREADS) s_u[e] = Sc<T>::zero();
     __syncthreads();
     int nalive = n;
-    bt_pass<T, R, V, true>(S, lda, m, -1, -1, s_l, nullptr, s_rm, s_alive, nalive);
+    bt_pass<T, R, V, true>(S, lda, m, -1, -1, s_l, nullptr, s_u, s_rm, s_alive, nalive);
     __syncthreads();
     double T0 = 0.0, Tc = 0.0, Tbest = 0.0;
     int t = 0, stop = 0, err = 0, prev_i = -1, tbest = 0;
@@ -441,14 +476,19 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
         if (i < 0 || i >= n) { err = RPLU_E_ARG; break; }
         const gmem<T>* Si = S + (int64_t)i * lda;
         gmem<T>* Ut = Ubase + (int64_t)t * ldu;
-        auto rcopy = [&](int e) { const T v = Si[e]; Ut[e] = v; return Sc<T>::mag2(v); };
+        auto rcopy = [&](int e) {
+            const T v = Si[e];
+            Ut[e] = v;
+            if (lds_row) s_u[e] = v;
+            return Sc<T>::mag2(v);
+        };
         const double Ti = bt_levels(m, sh.ctc, rcopy, sh);
-        auto smass = [&](int e) { return Sc<T>::mag2(Si[e]); };
+        auto smass = [&](int e) { return Sc<T>::mag2(lds_row ? s_u[e] : Si[e]); };
         CdfPick pc{0, 0.0, 0.0};
         if (Ti > 0.0 && isfinite(Ti)) pc = bt_draw(m, sh.ctc, smass, unit_from_word(rnd.w[1]) * Ti, sh);
         const int j = pc.idx;
         if (j < 0 || j >= m) { err = RPLU_E_ARG; break; }
-        const T a = Si[j];
+        const T a = lds_row ? s_u[j] : Si[j];
         const double a2 = Sc<T>::mag2(a);
         if (!(a2 > 0.0)) { err = isfinite(a2) ? RPLU_E_ZERO_PIVOT : RPLU_E_NONFINITE; break; }
         const W inv = winv(Sc<T>::widen(a));
@@ -465,7 +505,7 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
             if (L != nullptr) L[(int64_t)t * jb.ldl + r] = l;
         }
         __syncthreads();                  // column j read before any store to it
-        bt_pass<T, R, V, false>(S, lda, m, i, j, s_l, Ut, s_rm, s_alive, nalive);
+        bt_pass<T, R, V, false>(S, lda, m, i, j, s_l, Ut, s_u, s_rm, s_alive, nalive);
         __syncthreads();                  // new masses and S visible to every wave
         prev_i = i;
     }
@@ -498,6 +538,8 @@ __global__ __launch_bounds__(BT_THREADS) void k_batched(const BatchJob* __restri
     uint16_t* s_pos = s_alive + maxn;
     T* myscr = uscratch + (int64_t)blockIdx.x * uscr_ld;
     constexpr int VV = 16 / (int)sizeof(T);
+    __shared__ __align__(16) T s_u[BT_NV * RPLU_WAVE * VV];
+    static_assert(sizeof(BtShared) + sizeof(s_u) <= BT_STATIC_LDS, "static LDS bound of the host check");
     for (;;) {
         if (threadIdx.x == 0) sh.job = atomicAdd(queue, 1);
         __syncthreads();
@@ -506,8 +548,8 @@ __global__ __launch_bounds__(BT_THREADS) void k_batched(const BatchJob* __restri
         if (q >= count) break;
         const int b = order[q];
         const BatchJob jb = jobs[b];
-        if (jb.vec) bt_run<T, R, VV>(jb, myscr, &infos[b], s_rm, s_l, s_alive, s_pos, sh);
-        else bt_run<T, R, 1>(jb, myscr, &infos[b], s_rm, s_l, s_alive, s_pos, sh);
+        if (jb.vec) bt_run<T, R, VV>(jb, myscr, &infos[b], s_rm, s_l, s_alive, s_pos, s_u, sh);
+        else bt_run<T, R, 1>(jb, myscr, &infos[b], s_rm, s_l, s_alive, s_pos, s_u, sh);
         __syncthreads();
     }
 }

@@ -181,6 +181,7 @@ struct VerifyArgs {
 void launch_verify(const VerifyArgs& a, hipStream_t s);
 int64_t verify_tiles(int64_t n, int64_t m);
 size_t batched_lds_bytes(int dtype, int maxn);
+constexpr size_t BT_STATIC_LDS = 8192;   // bound on k_batched's static LDS (checked there)
 int batched_max_resident(int dtype, int rows, int maxn);
 
 }  // namespace rplu
