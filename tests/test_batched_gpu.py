@@ -26,18 +26,22 @@ DEV = "cuda:0"
 def _instances(dtype, seed=11):
     """Shapes that cover tiny, ragged (m % 4 != 0), one- to eight-wave rows,
     multi-pass rows, unaligned rows (lda * size % 16 != 0) and misaligned
-    starts, plus rank-deficient inputs (exhausted before k)."""
+    starts, plus rank-deficient inputs (exhausted before k). The block pass
+    (rows of one pack to four virtual waves: 4..1024 FP32 columns, 2..512
+    FP64, 1..256 unaligned) is taken at and just past each of its limits:
+    m = 2, 3, 4, 256, 512, 768, 769, 1024, 1025 and, unaligned, 256 and 257."""
     rng = np.random.default_rng(seed)
     shapes = [(1, 1), (1, 7), (7, 1), (3, 5), (64, 64), (100, 37), (37, 100), (130, 257),
               (257, 130), (513, 20), (20, 513), (997, 1000), (64, 1024), (1024, 64), (40, 3001),
-              (33, 2100), (200, 555)]
+              (33, 2100), (200, 555), (9, 4), (6, 2), (11, 3), (25, 256), (30, 512),
+              (12, 768), (12, 769), (40, 1025)]
     mats, meta = [], []
     for q, (n, m) in enumerate(shapes):
         A = torch.from_numpy(rng.standard_normal((n, m))).to(dtype)
         mats.append(A.to(DEV))
         meta.append(("plain", n, m))
     # unaligned row pitch: lda = m + 1
-    for (n, m) in [(50, 71), (129, 64)]:
+    for (n, m) in [(50, 71), (129, 64), (30, 256), (30, 257)]:
         buf = torch.zeros((n, m + 1), dtype=dtype)
         buf[:, :m] = torch.from_numpy(rng.standard_normal((n, m))).to(dtype)
         mats.append(buf.to(DEV)[:, :m])
