@@ -5,7 +5,8 @@
 // and runs an instance's whole step loop (Alg. 1 with two-stage sampling,
 // Sec. 4.1) with workgroup barriers only. Row masses, the scaled pivot
 // column and the list of rows not yet pivoted live in LDS; the pivot row goes
-// to U(t,:) (or a per-workgroup row).
+// to U(t,:) (or a per-workgroup row) and, for rows of up to four virtual
+// waves, to LDS as well.
 //
 // Every reduction uses the thread-to-element mapping and order of the
 // single-instance path (the sweep's 512-thread x 16-byte-pack layout, its wave
@@ -13,8 +14,9 @@
 // the in-chunk select of cdf.hpp), so an instance's pivots and factors are
 // bitwise those of rplu_dense on the same buffer. Two schedule knobs leave
 // the arithmetic unchanged and are left to the autotuner:
-//   * R, the rows a wave sweeps at once (each row keeps its own partial
-//     sums, so R changes only how many rows are in flight);
+//   * R: the rows a wave sweeps at once in the general pass (each row keeps
+//     its own partial sums, so R changes only how many rows are in flight)
+//     and the packs a wave loads at once in the block pass (bt_packs);
 //   * the number of resident workgroups per CU.
 #include <type_traits>
 
