@@ -35,6 +35,10 @@ Readings where the paper is silent (each also listed in the design notes):
   tol > 0 and T <= tol^2 * T0 -> TOL; t == kmax -> RANK (or TOL_UNREACHED
   when tol > 0). kmax = min(n, m) when k == 0, else min(k, n, m).
 * Random numbers come from oracle.philox.step_uniforms(seed, stream, t).
+* C2PLU (complete 2-norm pivoting, Sec. 2.3.3), the greedy counterpart:
+  i = a row of largest mass ||S_i,:||^2, then j = a column of largest
+  |S_ij| in that row; ties go to the smallest index. Same update and stop
+  test; no random numbers.
 """
 from __future__ import annotations
 
@@ -97,6 +101,14 @@ class Draw:
     target: float       # u * T
     lo: float           # lower edge of the used index's bin (0 for idx 0)
     hi: float           # upper edge of the used index's bin
+
+
+def largest(weights: np.ndarray, forced: Optional[int] = None) -> Draw:
+    """C2PLU's choice (Sec. 2.3.3): the first index of the largest weight."""
+    w = np.asarray(weights, dtype=np.float64)
+    drawn = int(np.argmax(w))
+    used = drawn if forced is None else int(forced)
+    return Draw(drawn, used, float(np.sum(w)), float("nan"), float("nan"), float("nan"))
 
 
 def inverse_cdf(weights: np.ndarray, u: float, forced: Optional[int] = None) -> Draw:
@@ -188,12 +200,14 @@ def schur_update(S: np.ndarray, i: int, j: int):
 
 def rplu_dense(A: np.ndarray, k: int = 0, tol: float = 0.0, seed: int = 0,
                stream: int = 0, forced: Optional[Sequence] = None,
-               keep_masses: bool = False, stall: bool = False) -> RPLUResult:
+               keep_masses: bool = False, stall: bool = False,
+               greedy: bool = False) -> RPLUResult:
     """Alg. 1 with two-stage exact sampling (Sec. 4.1).
 
     forced: optional sequence of (i, j) pivots to use instead of the draws
     (the draws are still made and recorded, so a caller can check where a
     draw landed relative to the forced pivot's CDF bin).
+    greedy: C2PLU (Sec. 2.3.3) instead of the random draws.
     """
     S = np.array(A, dtype=np.complex128 if np.iscomplexobj(A) else np.float64,
                  copy=True)
@@ -220,9 +234,10 @@ def rplu_dense(A: np.ndarray, k: int = 0, tol: float = 0.0, seed: int = 0,
             masses.append(rowmass)
         u1, u2 = step_uniforms(seed, stream, t)
         fi, fj = _forced_at(forced, t)
-        rd = inverse_cdf(rowmass, u1, fi)
+        rd = largest(rowmass, fi) if greedy else inverse_cdf(rowmass, u1, fi)
         i = rd.used
-        cd = inverse_cdf(squared_magnitude(S[i, :]), u2, fj)
+        w_row = squared_magnitude(S[i, :])
+        cd = largest(w_row, fj) if greedy else inverse_cdf(w_row, u2, fj)
         j = cd.used
         l, u, a = schur_update(S, i, j)
         L[:, t] = l
@@ -298,8 +313,11 @@ def cauchy_generator_update(x, y, G, B, i: int, j: int):
 def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
                 stream: int = 0, forced: Optional[Sequence] = None,
                 keep_masses: bool = False, mass_steps: Optional[set] = None,
-                stall: bool = False) -> RPLUResult:
+                stall: bool = False, greedy: bool = False) -> RPLUResult:
     """Alg. 3 with exact row masses (no rejection), generators in complex128.
+
+    greedy: C2PLU (Sec. 2.3.3) instead of the random draws (needs the masses
+    at every step).
 
     mass_steps: if given, row masses (and hence the draw check) are computed
     only at these steps; elsewhere the run must be forced. This keeps
@@ -319,6 +337,8 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
     T0 = None
     T = float("nan")
     stall_ref = [0.0, 0] if stall else None
+    if greedy and mass_steps is not None:
+        raise ValueError("C2PLU needs the row masses at every step")
     if stall and mass_steps is not None:
         raise ValueError("the stall rule needs the total at every step")
     t = 0
@@ -343,12 +363,12 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
         if need_mass:
             if keep_masses:
                 masses.append(rowmass)
-            rd = inverse_cdf(rowmass, u1, fi)
+            rd = largest(rowmass, fi) if greedy else inverse_cdf(rowmass, u1, fi)
         else:
             rd = Draw(-1, fi, float("nan"), float("nan"), float("nan"), float("nan"))
         i = rd.used
         r = cauchy_row(x, y, G, B, i)
-        cd = inverse_cdf(squared_magnitude(r), u2, fj)
+        cd = largest(squared_magnitude(r), fj) if greedy else inverse_cdf(squared_magnitude(r), u2, fj)
         j = cd.used
         c, r, a = cauchy_generator_update(x, y, G, B, i, j)
         l = c / a

@@ -432,6 +432,44 @@ def pin_loewner_entries():
     assert np.allclose(rm, np.sum(np.abs(ref) ** 2, axis=1), rtol=1e-12)
 
 
+def pin_c2plu():
+    """C2PLU (Sec. 2.3.3): on diag(d) with distinct |d_i| the pivots are the
+    diagonal in decreasing |d_i| and S ends exactly 0; on a rank-one u v^T
+    the first pivot is (argmax |u_i|, argmax |v_j|) and one step leaves S ~ 0;
+    equal masses go to the smallest index; the first row is a row of largest
+    2-norm (numpy.linalg.norm) and the first column the largest |A_ij| in it;
+    the Schur relations hold as for RPLU; the Cauchy-like form makes the same
+    choices as the dense form on its entries."""
+    d = np.array([3.0, -5.0, 1.0, 4.0])
+    r = O.rplu_dense(np.diag(d), greedy=True)
+    assert [tuple(int(v) for v in p_) for p_ in r.piv] == [(1, 1), (3, 3), (0, 0), (2, 2)]
+    assert r.stop == O.STOP_EXHAUSTED and np.all(r.S == 0.0)
+    u = np.array([1.0, -3.0, 2.0])
+    v = np.array([0.5, 4.0, -1.0, 2.0])
+    r = O.rplu_dense(np.outer(u, v), k=1, greedy=True)
+    assert tuple(int(x) for x in r.piv[0]) == (1, 1)
+    assert np.abs(r.S).max() <= 1e-15 * np.abs(np.outer(u, v)).max()
+    r = O.rplu_dense(np.array([[1.0, 1.0], [1.0, -1.0]]), k=1, greedy=True)
+    assert tuple(int(x) for x in r.piv[0]) == (0, 0)
+    rng = np.random.default_rng(31)
+    for trial in range(8):
+        n, m = int(rng.integers(3, 12)), int(rng.integers(3, 12))
+        A = W.random_dense(n, m, seed=300 + trial, complex_=bool(trial % 2))
+        k = int(rng.integers(1, min(n, m) + 1))
+        res = O.rplu_dense(A, k=k, greedy=True)
+        i0 = int(np.argmax(np.linalg.norm(A, axis=1)))
+        assert int(res.piv[0, 0]) == i0
+        assert int(res.piv[0, 1]) == int(np.argmax(np.abs(A[i0, :])))
+        _check_schur_relations(A, res, 1e-10)
+    for p_, (n, m) in ((1, (30, 24)), (2, (21, 35))):
+        x, y, G, B = W.cauchy_like_random(n, m, p_, seed=40 + p_)
+        A = O.cauchy_entries(x, y, G, B)
+        rc = O.rplu_cauchy(x, y, G, B, k=10, greedy=True)
+        rd = O.rplu_dense(A, k=10, greedy=True)
+        assert np.array_equal(rc.piv, rd.piv), (rc.piv, rd.piv)
+        assert np.allclose(rc.U, rd.U, rtol=0, atol=1e-12 * np.abs(A).max())
+
+
 ALL_PINS = [
     pin_stall_rule,
     pin_philox_numpy, pin_inverse_cdf_bruteforce, pin_chi2_first_pivot,
@@ -439,5 +477,5 @@ ALL_PINS = [
     pin_doubling_enumeration, pin_closed_form_schur, pin_exact_recovery,
     pin_eckart_young_floor, pin_mass_bookkeeping, pin_stop_rules,
     pin_nonfinite, pin_cauchy_vs_dense, pin_cauchy_determinant,
-    pin_loewner_entries,
+    pin_loewner_entries, pin_c2plu,
 ]

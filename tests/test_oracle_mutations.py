@@ -194,6 +194,20 @@ def _rplu_dense_colstage_from_column(A, k=0, tol=0.0, seed=0, stream=0, forced=N
     return O.RPLUResult(L[:, :t], U[:t], piv[:t], t, stop, T0, T, S=S)
 
 
+def _largest_last(weights, forced=None):
+    w = np.asarray(weights, dtype=np.float64)
+    drawn = int(len(w) - 1 - np.argmax(w[::-1]))       # ties to the largest index
+    used = drawn if forced is None else int(forced)
+    return O.Draw(drawn, used, float(np.sum(w)), float("nan"), float("nan"), float("nan"))
+
+
+def _largest_min(weights, forced=None):
+    w = np.asarray(weights, dtype=np.float64)
+    drawn = int(np.argmin(w))                           # smallest instead of largest
+    used = drawn if forced is None else int(forced)
+    return O.Draw(drawn, used, float(np.sum(w)), float("nan"), float("nan"), float("nan"))
+
+
 MUTATIONS = [
     ("schur_sign", "schur_update", _schur_plus, [pins.pin_closed_form_schur, pins.pin_one_step_expectation]),
     ("schur_conj_u", "schur_update", _schur_conj, [pins.pin_one_step_expectation, pins.pin_unitary_dft, pins.pin_closed_form_schur]),
@@ -209,6 +223,8 @@ MUTATIONS = [
     ("stall_late", "_stop_reason", _stop_stall_late, [pins.pin_stall_rule]),
     ("stall_no_update", "_stop_reason", _stop_stall_no_update, [pins.pin_stall_rule]),
     ("col_stage_transposed", "rplu_dense", _rplu_dense_colstage_from_column, [pins.pin_chi2_first_pivot, pins.pin_mass_bookkeeping]),
+    ("c2plu_ties_last", "largest", _largest_last, [pins.pin_c2plu]),
+    ("c2plu_argmin", "largest", _largest_min, [pins.pin_c2plu]),
 ]
 
 
