@@ -365,6 +365,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cauchy20k", choices=["cauchy20k", "dense32k", "dense512", "batched4096", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pivoting", default="rplu", choices=["rplu", "c2plu"],
+                    help="cauchy20k / dense workloads: c2plu = complete 2-norm pivoting "
+                         "(RPLU_FLAG_C2PLU) instead of the random draws; no CPU baseline")
     ap.add_argument("--no-fp64-baseline", action="store_true",
                     help="batched4096/serve: skip the one-at-a-time FP64 GPU baseline")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -396,6 +399,10 @@ def main() -> int:
     import paper_2601_22344_amd as rplu
 
     torch.cuda.set_device(0)
+    if args.pivoting != "rplu" and args.workload in ("batched4096", "serve"):
+        print(f"--pivoting {args.pivoting} applies to the dense and Cauchy workloads only",
+              file=sys.stderr)
+        return 2
     if args.workload == "cauchy20k":
         wl = _setup_cauchy20k(torch, rplu)
     elif args.workload == "batched4096":
@@ -406,6 +413,10 @@ def main() -> int:
         wl = _setup_dense(torch, rplu, args.workload)
     ctx = rplu.default_context(0)
     flags = rplu.RPLU_FLAG_NO_GRAPH if args.no_graph else 0
+    if args.pivoting == "c2plu":
+        flags |= rplu.RPLU_FLAG_C2PLU
+        wl["config"] = dict(wl["config"], pivoting="c2plu")
+        args.no_cpu_baseline = True
     res = None
     # warm-up also builds the step-loop graphs (cached in the context)
     for _ in range(args.warmup):

@@ -100,13 +100,22 @@ enum {
     RPLU_FLAG_STALL_STOP = 1u << 3, /* stall rule (below), for tolerance runs
                                      whose target may lie under the rounding
                                      floor of single precision                */
-    RPLU_FLAG_SPLIT_SAMPLER = 1u << 4 /* dense: draw each pivot with the two
+    RPLU_FLAG_SPLIT_SAMPLER = 1u << 4, /* dense: draw each pivot with the two
                                      wide kernels used for n or m > 12288
                                      (row draw; pivot row and column draw)
                                      also when n, m <= 12288, where one
                                      fused workgroup kernel is the default;
                                      every output is the same bit for bit.
                                      The Cauchy-like path has one form.      */
+    RPLU_FLAG_C2PLU = 1u << 5       /* dense and Cauchy-like: complete 2-norm
+                                     pivoting (Sec. 2.3.3) instead of the
+                                     random draws: i = the first row of
+                                     largest mass, then j = the first column
+                                     of largest |S_ij| in that row (ties go
+                                     to the smallest index); same update and
+                                     stop test, seed and stream unused.
+                                     rplu_batched and rplu_server_submit
+                                     reject it in a job (RPLU_E_ARG).        */
 };
 
 /* Stall rule (a library extension, not from the paper): with
@@ -206,7 +215,8 @@ typedef struct {
     void* A;                /* dense input, overwritten by S^(rank)            */
     int64_t lda;
     int32_t p;              /* Cauchy displacement rank                        */
-    uint32_t flags;         /* RPLU_FLAG_STALL_STOP honoured; others ignored   */
+    uint32_t flags;         /* RPLU_FLAG_STALL_STOP honoured; RPLU_FLAG_C2PLU
+                               rejected (RPLU_E_ARG); others ignored          */
     const void* x;          /* Cauchy nodes and generators                     */
     const void* y;
     void* G;

@@ -32,6 +32,7 @@ RPLU_STOP_RANK, RPLU_STOP_TOL, RPLU_STOP_EXHAUSTED, RPLU_STOP_TOL_UNREACHED = 1,
 RPLU_STOP_STALL = 5
 RPLU_FLAG_COLMASS, RPLU_FLAG_GRAPH, RPLU_FLAG_NO_GRAPH, RPLU_FLAG_STALL_STOP = 1, 2, 4, 8
 RPLU_FLAG_SPLIT_SAMPLER = 16
+RPLU_FLAG_C2PLU = 32
 RPLU_STALL_WINDOW = 64
 RPLU_TRACE_WORDS = 12
 RPLU_JOB_DENSE, RPLU_JOB_CAUCHY = 1, 2

@@ -478,6 +478,7 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, voi
     sa.kmax = kmax;
     sa.tol2 = a.tol2;
     sa.stall = (opts->flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
+    sa.greedy = (opts->flags & RPLU_FLAG_C2PLU) ? 1 : 0;
     sa.forced = opts->forced;
     sa.trace = opts->trace;
     sa.rowmass_out = opts->rowmass_out;
@@ -620,6 +621,7 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     sa.kmax = kmax;
     sa.tol2 = a.tol2;
     sa.stall = (opts->flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
+    sa.greedy = (opts->flags & RPLU_FLAG_C2PLU) ? 1 : 0;
     sa.forced = opts->forced;
     sa.trace = opts->trace;
     sa.rowmass_out = opts->rowmass_out;

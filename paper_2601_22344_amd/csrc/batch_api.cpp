@@ -43,6 +43,8 @@ rplu_status prepare(int64_t count, const rplu_job* jobs, Prepared& P, const char
         if (j.L != nullptr && j.ldl < j.n) return fail(RPLU_E_ARG, "%s: job %lld: ldl < n", who, lb);
         if (j.U != nullptr && j.ldu < j.m) return fail(RPLU_E_ARG, "%s: job %lld: ldu < m", who, lb);
         if (!(j.rel_tol >= 0.0)) return fail(RPLU_E_ARG, "%s: job %lld: rel_tol must be >= 0", who, lb);
+        if (j.flags & RPLU_FLAG_C2PLU)
+            return fail(RPLU_E_ARG, "%s: job %lld: RPLU_FLAG_C2PLU is not available in batches", who, lb);
         const int64_t es = (int64_t)dtype_size(j.dtype);
         const int64_t mn = std::min(j.n, j.m);
         BatchJob& q = P.jobs[(size_t)b];

@@ -147,6 +147,8 @@ struct CdfShared {
     int flag[CDF_THREADS / RPLU_WAVE];
     double bcast[4];
     int ibcast[4];
+    double amax[CDF_THREADS / RPLU_WAVE];   // wg_argmax: per-wave best value
+    int aidx[CDF_THREADS / RPLU_WAVE];      // and its index
 };
 
 // Group totals and offsets from the chunk totals ct[0..K); returns T in every

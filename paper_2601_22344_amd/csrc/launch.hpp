@@ -71,7 +71,7 @@ struct SampleArgs {
     double* trace;
     double* rowmass_out;
     int fused;           // dense: one fused pivot kernel per step (n, m <= PIVOT_FUSED_MAX)
-    int pad;
+    int greedy;          // RPLU_FLAG_C2PLU: the largest masses instead of the draws
 };
 
 void launch_state_init(StepState* st, hipStream_t s);

@@ -43,6 +43,7 @@ struct PivotArgs {
     const int32_t* forced;
     double* trace;
     double* rowmass_out;
+    int greedy;             // C2PLU (Sec. 2.3.3): the largest masses instead of the draws
 };
 
 // What the stop test reads from the state besides t, loaded at the start of
@@ -135,6 +136,38 @@ __device__ inline void pivot_commit_col(StepState* st, int t, int j, int m, cons
 
 // ------------------------------------------------ draws from chunk totals
 
+// Whole workgroup (CDF_THREADS): the first index e < len of the largest
+// mass(e), the choice of C2PLU (complete 2-norm pivoting, Sec. 2.3.3; ties go
+// to the smallest index), in every thread. Masses are finite and >= 0 here
+// (the stop test has seen their finite sum).
+template <class MassFn>
+__device__ inline int wg_argmax(CdfShared& sh, int len, MassFn mass) {
+    const int lane = threadIdx.x % RPLU_WAVE, w = threadIdx.x / RPLU_WAVE;
+    double bv = -1.0;
+    int bi = len;
+    for (int e = threadIdx.x; e < len; e += CDF_THREADS) {
+        const double v = mass(e);
+        if (v > bv) { bv = v; bi = e; }              // ascending e: keeps the first
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, RPLU_WAVE);
+        const int oi = __shfl_xor(bi, off, RPLU_WAVE);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { sh.amax[w] = bv; sh.aidx[w] = bi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = sh.amax[0];
+        int idx = sh.aidx[0];
+        for (int q = 1; q < CDF_THREADS / RPLU_WAVE; ++q)
+            if (sh.amax[q] > v || (sh.amax[q] == v && sh.aidx[q] < idx)) { v = sh.amax[q]; idx = sh.aidx[q]; }
+        sh.ibcast[3] = idx;
+    }
+    __syncthreads();
+    return sh.ibcast[3];
+}
+
 // Whole workgroup (CDF_THREADS): stop test and row draw of step t (= st->t)
 // from the chunk totals ct of the row masses (global memory or LDS); rnd
 // holds the step's Philox words; mass(e) gives the row masses for the walk
@@ -159,7 +192,8 @@ __device__ inline int pivot_row_draw_ct(CdfShared& sh, int* flag, const PivotArg
         for (int e = threadIdx.x; e < a.n; e += CDF_THREADS)
             a.rowmass_out[(int64_t)t * a.n + e] = a.rowmass[e];
     const double tgt = unit_from_word(rnd.w[0]) * T;
-    const CdfPick p = cdf_draw(sh, ct, K, a.n, mass, tgt);
+    const CdfPick p = a.greedy ? CdfPick{wg_argmax(sh, a.n, mass), 0.0, 0.0}
+                               : cdf_draw(sh, ct, K, a.n, mass, tgt);
     const int i = a.forced ? a.forced[2 * t] : p.idx;
     if (i < 0 || i >= a.n) {
         if (threadIdx.x == 0) { st->error = RPLU_E_ARG; st->done = 1; }
@@ -193,7 +227,8 @@ __device__ inline void pivot_col_draw_ct(CdfShared& sh, const PivotArgs& a, int 
     const double tgt = unit_from_word(rnd.w[1]) * Ti;
     CdfPick p{0, 0.0, 0.0};
     if (Ti > 0.0 && isfinite(Ti))
-        p = cdf_draw(sh, ct, K, a.m, mass, tgt);
+        p = a.greedy ? CdfPick{wg_argmax(sh, a.m, mass), 0.0, 0.0}
+                     : cdf_draw(sh, ct, K, a.m, mass, tgt);
     if (threadIdx.x == 0) {
         const int j = a.forced ? a.forced[2 * t + 1] : p.idx;
         pivot_commit_col<T, P>(a.st, t, j, a.m, Ut, Ti, tgt, p, a.piv, a.trace, G, B);
@@ -377,6 +412,7 @@ inline PivotArgs pivot_args(const SampleArgs& sa) {
     p.forced = sa.forced;
     p.trace = sa.trace;
     p.rowmass_out = sa.rowmass_out;
+    p.greedy = sa.greedy;
     return p;
 }
 

@@ -309,6 +309,7 @@ rplu_status check_job(const rplu_server_s* S, const rplu_job& d, size_t* bytes, 
         return fail(RPLU_E_ARG, "rplu_server_submit: unknown job kind %d", d.kind);
     }
     if (!(d.rel_tol >= 0.0)) return fail(RPLU_E_ARG, "rplu_server_submit: rel_tol must be >= 0");
+    if (d.flags & RPLU_FLAG_C2PLU) return fail(RPLU_E_ARG, "rplu_server_submit: RPLU_FLAG_C2PLU is not served");
     if (*bytes > S->pool_cap)
         return fail(RPLU_E_ARG, "rplu_server_submit: footprint %zu exceeds the pool (%zu bytes)",
                     *bytes, S->pool_cap);

@@ -61,6 +61,7 @@ def test_binding_constants_match_header():
     import paper_2601_22344_amd._binding as B
     consts = _header_constants()
     assert "RPLU_FLAG_SPLIT_SAMPLER" in consts and "RPLU_STOP_STALL" in consts
+    assert consts.get("RPLU_FLAG_C2PLU") == 32
     checked = 0
     for name, val in consts.items():
         if hasattr(B, name):
