@@ -145,9 +145,19 @@ __device__ inline int wg_argmax(CdfShared& sh, int len, MassFn mass) {
     const int lane = threadIdx.x % RPLU_WAVE, w = threadIdx.x / RPLU_WAVE;
     double bv = -1.0;
     int bi = len;
-    for (int e = threadIdx.x; e < len; e += CDF_THREADS) {
+    constexpr int UG = 8;                            // loads in flight per thread
+    int e = threadIdx.x;
+    for (; e + (UG - 1) * CDF_THREADS < len; e += UG * CDF_THREADS) {
+        double v[UG];
+#pragma unroll
+        for (int u = 0; u < UG; ++u) v[u] = mass(e + u * CDF_THREADS);
+#pragma unroll
+        for (int u = 0; u < UG; ++u)
+            if (v[u] > bv) { bv = v[u]; bi = e + u * CDF_THREADS; }   // ascending: keeps the first
+    }
+    for (; e < len; e += CDF_THREADS) {
         const double v = mass(e);
-        if (v > bv) { bv = v; bi = e; }              // ascending e: keeps the first
+        if (v > bv) { bv = v; bi = e; }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
