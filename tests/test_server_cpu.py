@@ -161,3 +161,15 @@ def test_cauchy_jobs_counted_per_class():
     st = S.stats()
     assert st["p50_cauchy_ms"] > 0.0 and st["p50_dense_ms"] > 0.0 and st["completed"] == 4
     S.close()
+
+
+def test_c2plu_flag_is_refused():
+    """C2PLU is a single-run option (rplu_dense / rplu_cauchy); a served job
+    carrying RPLU_FLAG_C2PLU is refused at submission with RPLU_E_ARG."""
+    S = rplu.Server(budget_bytes=64 * MB, simulate=True)
+    with pytest.raises(rplu.RPLUError) as e:
+        S.submit_dense(_dense(64), k=4, flags=rplu.RPLU_FLAG_C2PLU)
+    assert e.value.status == -1
+    t = S.submit_dense(_dense(64), k=4)            # the server keeps working
+    assert t in _wait_all(S, [t])
+    S.close()
