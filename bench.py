@@ -394,15 +394,15 @@ def main() -> int:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the method runs on a single device here)", file=sys.stderr)
         return 2
+    if args.pivoting != "rplu" and args.workload in ("batched4096", "serve"):
+        print(f"--pivoting {args.pivoting} applies to the dense and Cauchy workloads only",
+              file=sys.stderr)
+        return 2
 
     import torch
     import paper_2601_22344_amd as rplu
 
     torch.cuda.set_device(0)
-    if args.pivoting != "rplu" and args.workload in ("batched4096", "serve"):
-        print(f"--pivoting {args.pivoting} applies to the dense and Cauchy workloads only",
-              file=sys.stderr)
-        return 2
     if args.workload == "cauchy20k":
         wl = _setup_cauchy20k(torch, rplu)
     elif args.workload == "batched4096":
