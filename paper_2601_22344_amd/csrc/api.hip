@@ -87,14 +87,15 @@ struct Carver {
     }
 };
 
+// Without a context the copy goes straight to the caller's (pageable) stack.
 static rplu_status read_state(rplu_ctx_s* ctx, const StepState* st, hipStream_t s,
                               StepState* out) {
-    hipError_t e = hipMemcpyAsync(ctx->host_state, st, sizeof(StepState),
-                                  hipMemcpyDeviceToHost, s);
+    StepState* dst = ctx ? ctx->host_state : out;
+    hipError_t e = hipMemcpyAsync(dst, st, sizeof(StepState), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(state)");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    std::memcpy(out, ctx->host_state, sizeof(StepState));
+    if (ctx) std::memcpy(out, ctx->host_state, sizeof(StepState));
     return RPLU_OK;
 }
 
@@ -153,18 +154,19 @@ static rplu_status run_loop(rplu_ctx_s* ctx, StepState* st, int64_t steps_total,
                             uint64_t key, hipStream_t s, F&& enqueue_step) {
     if (steps_total <= 0) return RPLU_OK;
     const int64_t CH = steps_total <= 64 ? steps_total : 32;
+    int32_t done_word = 0;             // pageable landing word when there is no context
     auto done_after_sync = [&](bool& done) -> rplu_status {
-        hipError_t e = hipMemcpyAsync(&ctx->host_state->done, &st->done, sizeof(int32_t),
-                                      hipMemcpyDeviceToHost, s);
+        int32_t* dst = ctx ? &ctx->host_state->done : &done_word;
+        hipError_t e = hipMemcpyAsync(dst, &st->done, sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(done)");
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-        done = ctx->host_state->done != 0;
+        done = *dst != 0;
         return RPLU_OK;
     };
 
     rplu_graph_entry* g = nullptr;
-    if (use_graph && !ctx->prof_on && ctx->cap_stream != nullptr) {
+    if (use_graph && ctx != nullptr && !ctx->prof_on && ctx->cap_stream != nullptr) {
         key = fnv1a(&steps_total, sizeof steps_total, key);
         for (rplu_graph_entry& c : ctx->graphs)
             if (c.valid && c.key == key) g = &c;
@@ -246,6 +248,138 @@ static int use_fused_pivot(int64_t n, int64_t m, uint32_t flags) {
 static int64_t kmax_of(int64_t n, int64_t m, int64_t k) {
     const int64_t mn = std::min(n, m);
     return k <= 0 ? mn : std::min(k, mn);
+}
+
+// Workspace of one dense run, carved from a 256-byte aligned base.
+DenseWs dense_ws_layout(int dtype, int64_t n, int64_t m, uint32_t flags, bool need_u) {
+    const size_t es = dtype_size(dtype);
+    const bool colmass = (flags & RPLU_FLAG_COLMASS) != 0;
+    Carver cv;
+    DenseWs w;
+    w.o_st = cv.take(sizeof(StepState));
+    w.o_rm = cv.take((size_t)n * 8);
+    w.o_ctr = cv.take((size_t)cdf_chunks((int)n) * 8);
+    w.o_ctc = cv.take((size_t)cdf_chunks((int)m) * 8);
+    const int64_t nbc = (n + DENSE_ROWS_COLMASS - 1) / DENSE_ROWS_COLMASS;
+    w.o_cp = colmass ? cv.take((size_t)nbc * m * 8) : 0;
+    w.o_u = need_u ? cv.take((size_t)m * es) : 0;
+    w.total = cv.off;
+    return w;
+}
+
+rplu_status dense_check(const char* who, int dtype, int64_t n, int64_t m, const void* A,
+                        int64_t lda, const rplu_opts* opts, const int32_t* piv, const void* L,
+                        int64_t ldl, const void* U, int64_t ldu, const rplu_info* info) {
+    if (opts == nullptr || info == nullptr)
+        return fail(RPLU_E_ARG, "%s: opts and info are required", who);
+    if (dtype_size(dtype) == 0) return fail(RPLU_E_ARG, "%s: unknown dtype %d", who, dtype);
+    if (n < 1 || m < 1 || n > INT32_MAX || m > INT32_MAX)
+        return fail(RPLU_E_ARG, "%s: shape %lld x %lld out of range", who, (long long)n,
+                    (long long)m);
+    if (A == nullptr || lda < m) return fail(RPLU_E_ARG, "%s: A NULL or lda < m", who);
+    if (piv == nullptr) return fail(RPLU_E_ARG, "%s: piv is required", who);
+    if (L != nullptr && ldl < n) return fail(RPLU_E_ARG, "%s: ldl < n", who);
+    if (U != nullptr && ldu < m) return fail(RPLU_E_ARG, "%s: ldu < m", who);
+    if (opts->rel_tol < 0 || !(opts->rel_tol == opts->rel_tol))
+        return fail(RPLU_E_ARG, "%s: rel_tol must be >= 0", who);
+    if (opts->colmass_out != nullptr && !(opts->flags & RPLU_FLAG_COLMASS))
+        return fail(RPLU_E_ARG, "%s: colmass_out needs RPLU_FLAG_COLMASS", who);
+    if (n > RPLU_MAX_DIM || m > RPLU_MAX_DIM)
+        return fail(RPLU_E_UNSUPPORTED, "%s: n and m must be <= %lld", who,
+                    (long long)RPLU_MAX_DIM);
+    return RPLU_OK;
+}
+
+// The dense step loop on a workspace laid out by dense_ws_layout at `ws`.
+// With a context: graph replay (unless RPLU_FLAG_NO_GRAPH), profiling, pinned
+// read-back. Without (ctx == nullptr): plain launches and pageable read-back
+// only, so nothing is allocated.
+rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m, void* A,
+                      int64_t lda, const rplu_opts* opts, int32_t* piv, void* L, int64_t ldl,
+                      void* U, int64_t ldu, rplu_info* info, hipStream_t s) {
+    const size_t es = dtype_size(dtype);
+    const int64_t kmax = kmax_of(n, m, opts->max_rank);
+    const bool colmass = (opts->flags & RPLU_FLAG_COLMASS) != 0;
+    const DenseWs w = dense_ws_layout(dtype, n, m, opts->flags, U == nullptr);
+
+    DenseArgs a;
+    std::memset(&a, 0, sizeof a);        // padding too: the struct keys the graph cache
+    a.dtype = dtype;
+    a.n = n;
+    a.m = m;
+    a.S = A;
+    a.lda = lda;
+    a.U = U ? U : (void*)(ws + w.o_u);
+    a.ldu = U ? ldu : 0;          // a single workspace row, reused every step
+    a.L = L;
+    a.ldl = ldl;
+    a.piv = piv;
+    a.st = (StepState*)(ws + w.o_st);
+    a.rowmass = (double*)(ws + w.o_rm);
+    a.ct_col = (double*)(ws + w.o_ctc);
+    a.colpart = colmass ? (double*)(ws + w.o_cp) : nullptr;
+    a.colmass = colmass;
+    a.vec_ok = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)es) % 16 == 0) &&
+               ((uintptr_t)a.U % 16 == 0) && ((a.ldu * (int64_t)es) % 16 == 0);
+    a.colmass_out = opts->colmass_out;
+    a.rowmass_out = opts->rowmass_out;
+    a.trace = opts->trace;
+    a.forced = opts->forced;
+    a.seed = opts->seed;
+    a.stream = opts->stream;
+    a.kmax = kmax;
+    a.tol2 = opts->rel_tol * opts->rel_tol;
+
+    launch_state_init(a.st, s);
+    timed(ctx, 3, s, [&] { launch_dense_sweep(a, /*init=*/true, s); });
+    if (colmass && a.colmass_out) launch_colmass_reduce(a, false, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "initial mass launch");
+
+    SampleArgs sa;
+    std::memset(&sa, 0, sizeof sa);
+    sa.dtype = dtype;
+    sa.p = 0;
+    sa.n = n;
+    sa.m = m;
+    sa.rowmass = a.rowmass;
+    sa.ct_row = (double*)(ws + w.o_ctr);
+    sa.ct_col = a.ct_col;
+    sa.st = a.st;
+    sa.piv = piv;
+    sa.U = a.U;
+    sa.ldu = a.ldu;
+    sa.seed = opts->seed;
+    sa.stream = opts->stream;
+    sa.kmax = kmax;
+    sa.tol2 = a.tol2;
+    sa.stall = (opts->flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
+    sa.greedy = (opts->flags & RPLU_FLAG_C2PLU) ? 1 : 0;
+    sa.forced = opts->forced;
+    sa.trace = opts->trace;
+    sa.rowmass_out = opts->rowmass_out;
+    sa.fused = use_fused_pivot(n, m, opts->flags);
+
+    const bool graph = ctx != nullptr && !(opts->flags & RPLU_FLAG_NO_GRAPH);
+    const uint64_t key = fnv1a(&sa, sizeof sa, fnv1a(&a, sizeof a, 0x64656e7365ull));
+    rplu_status rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
+        timed(ctx, 1, q, [&] {
+            if (sa.fused) {
+                launch_dense_pivot(a, sa, q);
+            } else {
+                launch_rows_draw(sa, q);
+                launch_dense_pivrow_draw(a, sa, q);
+            }
+        });
+        timed(ctx, 0, q, [&] { launch_dense_sweep(a, /*init=*/false, q); });
+        if (colmass && a.colmass_out)
+            timed(ctx, 2, q, [&] { launch_colmass_reduce(a, true, q); });
+    });
+    if (rc) return rc;
+    StepState hs;
+    rc = read_state(ctx, a.st, s, &hs);
+    if (rc) return rc;
+    return finish(hs, info);
 }
 
 }  // namespace rplu
@@ -391,119 +525,16 @@ rplu_status rplu_destroy(rplu_ctx ctx) {
 rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, void* A,
                        int64_t lda, const rplu_opts* opts, int32_t* piv, void* L, int64_t ldl,
                        void* U, int64_t ldu, rplu_info* info, void* hip_stream) {
-    if (ctx == nullptr || opts == nullptr || info == nullptr)
-        return fail(RPLU_E_ARG, "rplu_dense: ctx, opts and info are required");
-    const size_t es = dtype_size(dtype);
-    if (es == 0) return fail(RPLU_E_ARG, "rplu_dense: unknown dtype %d", (int)dtype);
-    if (n < 1 || m < 1 || n > INT32_MAX || m > INT32_MAX)
-        return fail(RPLU_E_ARG, "rplu_dense: shape %lld x %lld out of range", (long long)n,
-                    (long long)m);
-    if (A == nullptr || lda < m) return fail(RPLU_E_ARG, "rplu_dense: A NULL or lda < m");
-    if (piv == nullptr) return fail(RPLU_E_ARG, "rplu_dense: piv is required");
-    if (L != nullptr && ldl < n) return fail(RPLU_E_ARG, "rplu_dense: ldl < n");
-    if (U != nullptr && ldu < m) return fail(RPLU_E_ARG, "rplu_dense: ldu < m");
-    if (opts->rel_tol < 0 || !(opts->rel_tol == opts->rel_tol))
-        return fail(RPLU_E_ARG, "rplu_dense: rel_tol must be >= 0");
-    if (opts->colmass_out != nullptr && !(opts->flags & RPLU_FLAG_COLMASS))
-        return fail(RPLU_E_ARG, "rplu_dense: colmass_out needs RPLU_FLAG_COLMASS");
+    if (ctx == nullptr) return fail(RPLU_E_ARG, "rplu_dense: ctx is required");
+    rplu_status rc = dense_check("rplu_dense", dtype, n, m, A, lda, opts, piv, L, ldl, U, ldu, info);
+    if (rc) return rc;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
-    const int64_t kmax = kmax_of(n, m, opts->max_rank);
-    const bool colmass = (opts->flags & RPLU_FLAG_COLMASS) != 0;
-
-    if (n > RPLU_MAX_DIM || m > RPLU_MAX_DIM)
-        return fail(RPLU_E_UNSUPPORTED, "rplu_dense: n and m must be <= %d", RPLU_MAX_DIM);
-    Carver cv;
-    const size_t o_st = cv.take(sizeof(StepState));
-    const size_t o_rm = cv.take((size_t)n * 8);
-    const size_t o_ctr = cv.take((size_t)cdf_chunks((int)n) * 8);
-    const size_t o_ctc = cv.take((size_t)cdf_chunks((int)m) * 8);
-    const int nbc = (int)((n + DENSE_ROWS_COLMASS - 1) / DENSE_ROWS_COLMASS);
-    const size_t o_cp = colmass ? cv.take((size_t)nbc * m * 8) : 0;
-    const size_t o_u = (U == nullptr) ? cv.take((size_t)m * es) : 0;
-    rplu_status rc = ws_reserve(ctx, cv.off, s);
+    const DenseWs w = dense_ws_layout(dtype, n, m, opts->flags, U == nullptr);
+    rc = ws_reserve(ctx, w.total, s);
     if (rc) return rc;
-    char* ws = (char*)ctx->ws;
-
-    DenseArgs a;
-    std::memset(&a, 0, sizeof a);        // padding too: the struct keys the graph cache
-    a.dtype = dtype;
-    a.n = n;
-    a.m = m;
-    a.S = A;
-    a.lda = lda;
-    a.U = U ? U : (void*)(ws + o_u);
-    a.ldu = U ? ldu : 0;          // a single workspace row, reused every step
-    a.L = L;
-    a.ldl = ldl;
-    a.piv = piv;
-    a.st = (StepState*)(ws + o_st);
-    a.rowmass = (double*)(ws + o_rm);
-    a.ct_col = (double*)(ws + o_ctc);
-    a.colpart = colmass ? (double*)(ws + o_cp) : nullptr;
-    a.colmass = colmass;
-    a.vec_ok = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)es) % 16 == 0) &&
-               ((uintptr_t)a.U % 16 == 0) && ((a.ldu * (int64_t)es) % 16 == 0);
-    a.colmass_out = opts->colmass_out;
-    a.rowmass_out = opts->rowmass_out;
-    a.trace = opts->trace;
-    a.forced = opts->forced;
-    a.seed = opts->seed;
-    a.stream = opts->stream;
-    a.kmax = kmax;
-    a.tol2 = opts->rel_tol * opts->rel_tol;
-
-    launch_state_init(a.st, s);
-    timed(ctx, 3, s, [&] { launch_dense_sweep(a, /*init=*/true, s); });
-    if (colmass && a.colmass_out) launch_colmass_reduce(a, false, s);
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "initial mass launch");
-
-    SampleArgs sa;
-    std::memset(&sa, 0, sizeof sa);
-    sa.dtype = dtype;
-    sa.p = 0;
-    sa.n = n;
-    sa.m = m;
-    sa.rowmass = a.rowmass;
-    sa.ct_row = (double*)(ws + o_ctr);
-    sa.ct_col = a.ct_col;
-    sa.st = a.st;
-    sa.piv = piv;
-    sa.U = a.U;
-    sa.ldu = a.ldu;
-    sa.seed = opts->seed;
-    sa.stream = opts->stream;
-    sa.kmax = kmax;
-    sa.tol2 = a.tol2;
-    sa.stall = (opts->flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
-    sa.greedy = (opts->flags & RPLU_FLAG_C2PLU) ? 1 : 0;
-    sa.forced = opts->forced;
-    sa.trace = opts->trace;
-    sa.rowmass_out = opts->rowmass_out;
-    sa.fused = use_fused_pivot(n, m, opts->flags);
-
-    const bool graph = !(opts->flags & RPLU_FLAG_NO_GRAPH);
-    const uint64_t key = fnv1a(&sa, sizeof sa, fnv1a(&a, sizeof a, 0x64656e7365ull));
-    rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
-        timed(ctx, 1, q, [&] {
-            if (sa.fused) {
-                launch_dense_pivot(a, sa, q);
-            } else {
-                launch_rows_draw(sa, q);
-                launch_dense_pivrow_draw(a, sa, q);
-            }
-        });
-        timed(ctx, 0, q, [&] { launch_dense_sweep(a, /*init=*/false, q); });
-        if (colmass && a.colmass_out)
-            timed(ctx, 2, q, [&] { launch_colmass_reduce(a, true, q); });
-    });
-    if (rc) return rc;
-    StepState hs;
-    rc = read_state(ctx, a.st, s, &hs);
-    if (rc) return rc;
-    return finish(hs, info);
+    return dense_run(ctx, (char*)ctx->ws, dtype, n, m, A, lda, opts, piv, L, ldl, U, ldu, info, s);
 }
 
 rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, int32_t p,
@@ -575,6 +606,7 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     a.partial = (double*)(ws + o_pa);
     a.rowmass = (double*)(ws + o_rm);
     a.ct_col = (double*)(ws + o_ctc);
+    a.colmass_out = opts->colmass_out;
     a.trace = opts->trace;
     a.forced = opts->forced;
     a.seed = opts->seed;
@@ -634,7 +666,7 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
             timed(ctx, 2, q, [&] {
                 if (p > 1) launch_cauchy_transpose(a, ac.B, ac.G, q);
                 launch_cauchy_mass(ac, q);
-                launch_colmass_sum(ac.partial, ac.splits, m, a.st, opts->colmass_out, m, kmax, q);
+                launch_colmass_sum(ac.partial, ac.splits, m, a.st, a.colmass_out, m, kmax, q);
             });
         timed(ctx, 1, q, [&] {
             launch_cauchy_reduce_draw(a, sa, q);

@@ -107,6 +107,8 @@ struct CauchyArgs {
     int cols_per_split;  // columns of y per workgroup column of the mass kernel
     double* rowmass;     // n (reduced masses)
     double* ct_col;      // chunk totals of the regenerated pivot row
+    double* colmass_out; // column masses per step (RPLU_FLAG_COLMASS), or null;
+                         // part of the graph-cache key like every pointer here
     double* trace;
     const int32_t* forced;
     uint64_t seed, stream;

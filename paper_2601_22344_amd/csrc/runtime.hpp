@@ -71,7 +71,7 @@ void graph_cache_clear(rplu_ctx_s* ctx);
 // remembers them under class `cls`.
 template <class F>
 inline void timed(rplu_ctx_s* ctx, int cls, hipStream_t s, F&& launch) {
-    if (!ctx->prof_on) { launch(); return; }
+    if (ctx == nullptr || !ctx->prof_on) { launch(); return; }
     while (ctx->ev_pool.size() < ctx->ev_used + 2) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) { launch(); return; }
@@ -83,6 +83,19 @@ inline void timed(rplu_ctx_s* ctx, int cls, hipStream_t s, F&& launch) {
     (void)hipEventRecord(b, s);
     ctx->prof.push_back({cls, a, b});
 }
+
+// Dense-run workspace layout and the shared dense step loop (api.hip); the
+// context-free caller (rplu_dense_noalloc) passes ctx == nullptr.
+struct DenseWs {
+    size_t o_st, o_rm, o_ctr, o_ctc, o_cp, o_u, total;
+};
+DenseWs dense_ws_layout(int dtype, int64_t n, int64_t m, uint32_t flags, bool need_u);
+rplu_status dense_check(const char* who, int dtype, int64_t n, int64_t m, const void* A,
+                        int64_t lda, const rplu_opts* opts, const int32_t* piv, const void* L,
+                        int64_t ldl, const void* U, int64_t ldu, const rplu_info* info);
+rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m, void* A,
+                      int64_t lda, const rplu_opts* opts, int32_t* piv, void* L, int64_t ldl,
+                      void* U, int64_t ldu, rplu_info* info, hipStream_t s);
 
 // FNV-1a over raw bytes, for graph cache keys.
 inline uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {

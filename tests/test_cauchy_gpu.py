@@ -223,3 +223,42 @@ def test_cauchy_graph_matches_plain(rplu_lib):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert torch.equal(a, b)
+
+
+def test_cauchy_graph_key_follows_colmass_out(rplu_lib):
+    """Two graph-path calls on the same buffers that differ only in the
+    column-mass output: each call writes its own array, and the first array
+    keeps what the first call wrote (the replayed graph must not write into
+    the earlier caller's buffer)."""
+    import ctypes as C
+    from paper_2601_22344_amd import _binding as Bd
+    n, m, p, k = 300, 257, 1, 12
+    x, y, G, B = W.cauchy_like_random(n, m, p, seed=77)
+    xd, yd = _dev(x, y)
+    Gd, Bd_ = _dev(G, B)
+    G0, B0 = Gd.clone(), Bd_.clone()
+    piv = torch.empty((k, 2), dtype=torch.int32, device=DEV)
+    Lt = torch.empty((k, n), dtype=torch.complex128, device=DEV)
+    U = torch.empty((k, m), dtype=torch.complex128, device=DEV)
+    cm1 = torch.full((k, m), -1.0, dtype=torch.float64, device=DEV)
+    cm2 = torch.full((k, m), -2.0, dtype=torch.float64, device=DEV)
+    ctx = Bd.Context(0)
+
+    def run(cm):
+        Gd.copy_(G0)
+        Bd_.copy_(B0)
+        opts = Bd._opts(k, 0.0, 5, 0, Bd.RPLU_FLAG_COLMASS, None, None, None, cm)
+        info = Bd.rplu_info()
+        st = Bd.lib.rplu_cauchy(ctx.handle, Bd.RPLU_C128, n, m, p, Bd._ptr(xd), Bd._ptr(yd),
+                                Bd._ptr(Gd), Bd._ptr(Bd_), C.byref(opts), Bd._ptr(piv),
+                                Bd._ptr(Lt), n, Bd._ptr(U), m, C.byref(info),
+                                Bd._cur_stream(xd.device))
+        assert st == 0 and info.rank == k
+        torch.cuda.synchronize()
+
+    run(cm1)
+    first = cm1.clone()
+    run(cm2)
+    assert torch.equal(cm1, first), "the second call wrote into the first call's array"
+    assert torch.equal(cm2, first), "the second call's array does not hold its masses"
+    ctx.close()
