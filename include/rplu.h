@@ -202,6 +202,29 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m,
                         const rplu_opts* opts, int32_t* piv, void* L, int64_t ldl,
                         void* U, int64_t ldu, rplu_info* info, void* hip_stream);
 
+/* Allocation-free dense RPLU, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same arguments, results and errors as rplu_dense (bit for bit:
+ * the same kernels in plain launches), without a context. The step state,
+ * row masses and chunk totals live in a fixed device array of
+ * RPLU_NOALLOC_SCRATCH_BYTES that the library defines once per device and
+ * keeps until the process ends; this call and what it calls allocate nothing
+ * (no hipMalloc, hipFree or graph instantiation; the state is read back into
+ * pageable host memory on the caller's stream). Runs on the current device.
+ * A problem whose scratch (rplu_dense_noalloc_bytes) exceeds the array is
+ * rejected with RPLU_E_ARG before anything is enqueued; without U and with
+ * RPLU_FLAG_COLMASS the scratch also holds a U row and the column partials.
+ * RPLU_FLAG_NO_GRAPH is implied. Calls on one device share the array: calls
+ * that overlap in time on one device (other host threads, other streams)
+ * race and must be serialised by the caller. */
+#define RPLU_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+rplu_status rplu_dense_noalloc(rplu_dtype dtype, int64_t n, int64_t m, void* A, int64_t lda,
+                               const rplu_opts* opts, int32_t* piv, void* L, int64_t ldl,
+                               void* U, int64_t ldu, rplu_info* info, void* hip_stream);
+/* Scratch bytes rplu_dense_noalloc needs for this problem (has_U: U is not
+ * NULL); 0 for an invalid dtype or shape. */
+size_t rplu_dense_noalloc_bytes(int dtype, int64_t n, int64_t m, uint32_t flags, int has_U);
+
 /* ------------------------------------------------------------- batched */
 
 enum { RPLU_JOB_DENSE = 1, RPLU_JOB_CAUCHY = 2 };

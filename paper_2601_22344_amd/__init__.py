@@ -11,6 +11,6 @@ from ._binding import (  # noqa: F401
     RPLU_STOP_EXHAUSTED, RPLU_STOP_RANK, RPLU_STOP_TOL, RPLU_STOP_TOL_UNREACHED,
     RPLU_SERVER_SIMULATE, RPLU_TRACE_WORDS, BatchPlan, Context, Result, RPLUError, Server,
     default_context, lib,
-    rplu_batched, rplu_batched_tune, rplu_cauchy, rplu_create, rplu_dense,
+    rplu_batched, rplu_batched_tune, rplu_cauchy, rplu_create, rplu_dense, rplu_dense_noalloc,
     rplu_profile_begin, rplu_profile_end, rplu_verify,
 )

@@ -114,10 +114,15 @@ lib.rplu_server_stats.argtypes = [_P, C.POINTER(rplu_server_stats_t)]
 lib.rplu_server_destroy.argtypes = [_P]
 lib.rplu_profile_begin.argtypes = [_P]
 lib.rplu_profile_end.argtypes = [_P, C.POINTER(rplu_profile)]
+lib.rplu_dense_noalloc.argtypes = [C.c_int, _I64, _I64, _P, _I64, C.POINTER(rplu_opts), _P, _P,
+                                   _I64, _P, _I64, C.POINTER(rplu_info), _P]
+lib.rplu_dense_noalloc_bytes.argtypes = [C.c_int, _I64, _I64, C.c_uint32, C.c_int]
+lib.rplu_dense_noalloc_bytes.restype = C.c_size_t
 lib.rplu_status_str.argtypes = [C.c_int32]
 lib.rplu_status_str.restype = C.c_char_p
 lib.rplu_last_error.restype = C.c_char_p
-for _fn in ("rplu_create", "rplu_destroy", "rplu_dense", "rplu_cauchy", "rplu_batched",
+for _fn in ("rplu_create", "rplu_destroy", "rplu_dense", "rplu_dense_noalloc", "rplu_cauchy",
+            "rplu_batched",
             "rplu_batched_ex", "rplu_batched_tune", "rplu_verify",
             "rplu_server_create", "rplu_server_submit", "rplu_server_poll",
             "rplu_server_stats", "rplu_server_destroy", "rplu_profile_begin", "rplu_profile_end"):
@@ -235,6 +240,34 @@ def rplu_dense(A: torch.Tensor, k: int = 0, tol: float = 0.0, seed: int = 0, str
                   r, int(info.stop), float(info.a_fro2), float(info.res_fro2),
                   trace[:r] if trace is not None else None, rmo[:r] if rmo is not None else None,
                   cmo[:r] if cmo is not None else None)
+
+
+def rplu_dense_noalloc(A: torch.Tensor, piv: torch.Tensor, L: Optional[torch.Tensor] = None,
+                       U: Optional[torch.Tensor] = None, k: int = 0, tol: float = 0.0,
+                       seed: int = 0, stream: int = 0, flags: int = 0) -> Result:
+    """rplu_dense without a context and without device allocation: the caller
+    passes every output (piv: kmax x 2 int32; L: kmax x n, row t = L(:,t);
+    U: kmax x m, both of A's dtype, or None). Runs on A's device, on the
+    current stream; the library's fixed scratch array holds the step state."""
+    if A.dim() != 2 or A.stride(1) != 1 or A.dtype not in _DTYPES or not A.is_cuda:
+        raise ValueError("A must be a 2-D CUDA tensor (float32/64, complex64/128), unit column stride")
+    n, m = A.shape
+    kmax = min(n, m) if k <= 0 else min(k, n, m)
+    if piv.dtype != torch.int32 or piv.numel() < 2 * kmax or not piv.is_contiguous():
+        raise ValueError("piv must be a contiguous int32 tensor of 2*kmax entries")
+    for t_, w in ((L, n), (U, m)):
+        if t_ is not None and (t_.dtype != A.dtype or not t_.is_contiguous() or t_.numel() < kmax * w):
+            raise ValueError("L (kmax x n) and U (kmax x m) must be contiguous, of A's dtype")
+    opts = _opts(k, tol, seed, stream, flags, None, None, None, None)
+    info = rplu_info()
+    with torch.cuda.device(A.device):
+        st = lib.rplu_dense_noalloc(_DTYPES[A.dtype], n, m, _ptr(A), A.stride(0), C.byref(opts),
+                                    _ptr(piv), _ptr(L), n, _ptr(U), m, C.byref(info),
+                                    _cur_stream(A.device))
+    _check(st, "rplu_dense_noalloc")
+    r = int(info.rank)
+    return Result(piv[:r], L[:r].T if L is not None else None, U[:r] if U is not None else None,
+                  r, int(info.stop), float(info.a_fro2), float(info.res_fro2))
 
 
 def rplu_cauchy(x: torch.Tensor, y: torch.Tensor, G: torch.Tensor, B: torch.Tensor, k: int = 0,
