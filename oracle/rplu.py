@@ -261,6 +261,39 @@ def schur_closed_form(A: np.ndarray, I: Sequence[int], J: Sequence[int]) -> np.n
     return A - A[:, J] @ np.linalg.solve(W, A[I, :])
 
 
+def schur_closed_form_masses(get_rows, n: int, I: Sequence[int], J: Sequence[int],
+                             steps: Sequence[int], row_block: int = 1024):
+    """Row masses ||S^(t)_r,:||^2 (all n rows) and the row i_t of S^(t), for
+    each t in `steps`, where S^(t) is the closed-form Schur complement after
+    the first t pivots (I[:t], J[:t]): A - A[:,J_t] A[I_t,J_t]^{-1} A[I_t,:]
+    (as in schur_closed_form), streamed a block of rows at a time so that no
+    n x m FP64 array is held. get_rows(r0, r1) returns rows r0..r1-1 of A in
+    FP64. Returns {t: (masses, pivot_row)}."""
+    I = np.asarray(I, dtype=np.int64)
+    J = np.asarray(J, dtype=np.int64)
+    AI = get_rows_at(get_rows, I)                    # all pivot rows of A
+    X = {}
+    for t in steps:
+        X[t] = np.linalg.solve(AI[:t][:, J[:t]], AI[:t]) if t else None
+    out = {t: [np.empty(n), None] for t in steps}
+    for r0 in range(0, n, row_block):
+        r1 = min(n, r0 + row_block)
+        blk = get_rows(r0, r1)
+        for t in steps:
+            S = blk if t == 0 else blk - blk[:, J[:t]] @ X[t]
+            out[t][0][r0:r1] = np.sum(squared_magnitude(S), axis=1)
+    for t in steps:
+        if t < len(I):
+            row = AI[t:t + 1]
+            out[t][1] = (row if t == 0 else row - row[:, J[:t]] @ X[t])[0]
+    return {t: (v[0], v[1]) for t, v in out.items()}
+
+
+def get_rows_at(get_rows, idx):
+    """Rows idx of A (FP64) through a row-range accessor."""
+    return np.stack([get_rows(int(r), int(r) + 1)[0] for r in idx]) if len(idx) else None
+
+
 # -------------------------------------------------------- Cauchy-like form
 
 def cauchy_entries(x, y, G, B) -> np.ndarray:

@@ -55,3 +55,26 @@ def check_trace_self(trace, piv):
         assert loj <= tj < hij, (t, loj, tj, hij)
         assert 0 <= ti < T and 0 <= tj < Ti
         assert int(tr[t, 10]) == int(piv[t, 0]) and int(tr[t, 11]) == int(piv[t, 1])
+
+
+def check_draws_ref(trace, tau=1e-12):
+    """As check_draws, for the C++ oracle's trace words (oracle/ref.py): per
+    step its own row target u1*T and the edges [lo, hi) of the used (GPU)
+    row's bin in its own prefix sums, and the same for the column. The
+    oracle's own draw equals the GPU index exactly when lo <= target < hi.
+    Returns (#rows exact, #columns exact, #steps)."""
+    tr = np.asarray(trace)
+    ex_r = ex_c = 0
+    for t in range(tr.shape[0]):
+        for stage, (T, tgt, lo, hi) in (("row", tr[t, 0:4]), ("col", tr[t, 4:8])):
+            if not math.isfinite(T):
+                continue
+            if lo <= tgt < hi:
+                ex_r += stage == "row"
+                ex_c += stage == "col"
+                continue
+            win = tau * T
+            assert lo - win <= tgt < hi + win, (
+                f"step {t} {stage}: GPU bin [{lo}, {hi}) in the oracle's prefix sums vs the "
+                f"oracle's target {tgt} (T={T}, window {win})")
+    return ex_r, ex_c, tr.shape[0]

@@ -79,3 +79,61 @@ def test_config3_dense_32768_fp32(rplu_lib):
     assert est <= 1e-5 * fa
     # the residual reported by the run is the FP64 total of the FP32 S
     assert abs(math.sqrt(res.res_fro2) - math.sqrt(v["err_fro2"])) <= 1e-5 * fa
+
+
+SAMPLED_STEPS = [0, 1, 2, 3, 7, 15, 31, 63, 95, 127, 191, 255, 319, 383, 447, 511]
+
+
+@pytest.mark.timeout(900)
+def test_config3_draws_against_closed_form_masses(rplu_lib):
+    """Draw agreement (protocol P2) at 16 sampled steps of the 32768^2 FP32
+    run: the oracle's FP64 row masses of S^(t) from the closed-form Schur
+    complement of the same (FP32-valued) A under the GPU's first t pivots;
+    the oracle's target u1*T lands in the GPU's row bin within delta_t*T,
+    delta_t = sum_i |m_gpu,i - m_orc,i| / T the measured mass discrepancy, and
+    the same for the column draw in the pivot row. Each step's delta and
+    whether the draw matched exactly are printed."""
+    n, k = 32768, 512
+    print("generating the 32768^2 input", flush=True)
+    A0 = W.dense_reflector_matrix_device(n, sigma_power=-2.0, q=256, seed=3, device=DEV,
+                                         dtype=torch.float32)
+    S = A0.clone()
+    res = rplu_lib.rplu_dense(S, k=k, seed=0, want_trace=True, want_rowmass=True)
+    assert res.rank == k
+    piv = res.piv.cpu().numpy().astype(np.int64)
+    rm_gpu = res.rowmass[SAMPLED_STEPS].cpu().numpy()
+    U_gpu = res.U[SAMPLED_STEPS].double().cpu().numpy()
+    tr = res.trace.cpu().numpy()
+    del S, res
+    A_host = A0.cpu().numpy()                      # FP32, 4.3 GB
+    del A0
+    torch.cuda.empty_cache()
+    print("closed-form masses at 16 steps on the host", flush=True)
+    get_rows = lambda a, b: A_host[a:b].astype(np.float64)      # noqa: E731
+    orc = O.schur_closed_form_masses(get_rows, n, piv[:, 0], piv[:, 1], SAMPLED_STEPS,
+                                     row_block=2048)
+    exact = 0
+    for q, t in enumerate(SAMPLED_STEPS):
+        m_orc, row_orc = orc[t]
+        i, j = int(piv[t, 0]), int(piv[t, 1])
+        u1, u2 = step_uniforms(0, 0, t)
+        P = np.cumsum(m_orc)
+        T = P[-1]
+        delta = float(np.sum(np.abs(rm_gpu[q] - m_orc)) / T)
+        lo, hi = (P[i - 1] if i else 0.0), P[i]
+        tgt = u1 * T
+        win = delta * T
+        assert lo - win <= tgt < hi + win, (t, lo, tgt, hi, delta)
+        w_orc = row_orc ** 2
+        Pc = np.cumsum(w_orc)
+        Ti = Pc[-1]
+        delta_c = float(np.sum(np.abs(U_gpu[q] ** 2 - w_orc)) / Ti)
+        loc, hic = (Pc[j - 1] if j else 0.0), Pc[j]
+        tgc = u2 * Ti
+        assert loc - delta_c * Ti <= tgc < hic + delta_c * Ti, (t, loc, tgc, hic, delta_c)
+        ok = lo <= tgt < hi and loc <= tgc < hic
+        exact += ok
+        # the GPU's own T against the oracle's
+        print(f"t={t:3d} delta_row={delta:.2e} delta_col={delta_c:.2e} "
+              f"T_gpu/T_orc-1={tr[t, 0] / T - 1:+.2e} exact={ok}", flush=True)
+    print(f"{exact}/{len(SAMPLED_STEPS)} sampled draws land in the GPU's bins exactly", flush=True)
