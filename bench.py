@@ -24,7 +24,10 @@ step. Workloads:
 
 Prints one JSON line. The hot kernel's average launch duration is measured
 with HIP events on the library's stream over the timed region; the CPU
-baseline times the oracle on a bounded sample of the same workload.
+baseline times the C++ FP64 oracle on a bounded sample of the same workload,
+on all host cores and on one. The default run (cauchy20k) also times
+dense32k and batched4096 in the same process and reports each, with its own
+roofline, under "extra_workloads".
 """
 from __future__ import annotations
 
@@ -44,9 +47,10 @@ METRIC = "RPLU rank-k approximations/sec and GB/s at rel err ≤1e-6; p50/p99 la
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_PEAK_TF = 78.6     # MI355X FP64 vector, TFLOP/s
 # Algorithmic FLOP per (row, column) pair of the Cauchy-like mass pass, p = 1:
-# complex difference 2, |d|^2 3, multiply-accumulate 2, the p x p Hermitian
-# form 4 p^2, and the reciprocal of |d|^2 counted as one.
-CAUCHY_FLOP_PER_PAIR = 7 + 4 * 1 * 1 + 1
+# complex difference 2, |d|^2 3, row and column accumulation 2, the p x p
+# Hermitian form 4 p^2 = 11. The reciprocal of |d|^2 (one per pair) is
+# reported separately and not counted as a FLOP.
+CAUCHY_FLOP_PER_PAIR = 7 + 4 * 1 * 1
 KERNEL_SOURCES = ["common.hpp", "cdf.hpp", "dense.hip", "cauchy.hip", "batched.hip"]
 
 
@@ -167,10 +171,11 @@ def _setup_cauchy20k(torch, rplu):
         B1.copy_(B0)
         return rplu.rplu_cauchy(xd, yd, G1, B1, k=k, seed=0, flags=flags)
 
-    # all-pairs mass launches at steps t = 0..k (the stop test at k included)
-    pairs = sum((n - s) * (m - s) for s in range(k + 1)) / (k + 1)
+    # every all-pairs mass launch (steps t = 0..k, the stop test at k
+    # included) evaluates n * m (row, column) pairs, as the survey counts them
+    pairs = float(n * m)
     return dict(step=step, k=k, n=n, m=m, kind="cauchy", dtype="c128",
-                per_launch=pairs * CAUCHY_FLOP_PER_PAIR,
+                per_launch=pairs * CAUCHY_FLOP_PER_PAIR, pairs_per_launch=pairs,
                 config={"workload": "cauchy n=m=20000 complex128 p=1 k=200 "
                                     "spirals-vs-cluster (generator form, no stored matrix)",
                         "n": n, "m": m, "k": k, "p": 1, "seed": 0})
@@ -285,75 +290,115 @@ _CPU_SAMPLE = r"""
 import sys, time, json
 sys.path.insert(0, {root!r})
 import numpy as np, workloads as W
-from oracle import rplu as O
-wl = {wl!r}
+from oracle import ref as R
+wl, budget = {wl!r}, {budget!r}
+threads = R.threads()
 if wl == "cauchy20k":
     x, y, G, B = W.config2_cauchy_spirals()
+    passes = 20 if threads > 1 else 3
     t0 = time.perf_counter()
-    r = O.rplu_cauchy(x, y, G, B, k=2, seed=0)
+    r = R.rplu_cauchy(x, y, G, B, k=passes - 1, seed=0)
     el = time.perf_counter() - t0
-    print(json.dumps({{"elapsed": el, "passes": 3, "k": 200}}))
+    print(json.dumps({{"elapsed": el, "passes": passes, "k": 200, "threads": threads}}))
 elif wl == "dense512":
     A = W.config1_dense_512()
     t0 = time.perf_counter()
     reps = 0
-    while time.perf_counter() - t0 < 10.0:
-        O.rplu_dense(A, k=50, seed=0)
+    while time.perf_counter() - t0 < budget:
+        R.rplu_dense(A, k=50, seed=0)
         reps += 1
     el = time.perf_counter() - t0
-    print(json.dumps({{"elapsed": el / reps, "passes": 51, "k": 50, "reps": reps}}))
+    print(json.dumps({{"elapsed": el / reps, "k": 50, "reps": reps, "threads": threads}}))
 elif wl == "batched4096":
-    import random
     specs = W.batched_instance_specs()
     order = np.random.default_rng(99).permutation(len(specs))
     spent, done = 0.0, 0
     for b in order:
         A = W.batched_instance(specs[int(b)]).astype(np.float32).astype(np.float64)
         t0 = time.perf_counter()
-        O.rplu_dense(A, k=0, tol=1e-6, seed=0, stream=int(b))
+        R.rplu_dense(A, k=0, tol=1e-6, seed=0, stream=int(b))
         spent += time.perf_counter() - t0
         done += 1
-        if spent > 15.0:
+        if spent > budget:
             break
-    print(json.dumps({{"elapsed": spent, "done": done, "count": len(specs)}}))
+    print(json.dumps({{"elapsed": spent, "done": done, "count": len(specs), "threads": threads}}))
 else:
     n = 8192
     A = W.dense_with_spectrum(n, n, np.arange(1, n + 1, dtype=np.float64) ** -2.0, seed=3).astype(np.float32).astype(np.float64)
+    passes = 4
     t0 = time.perf_counter()
-    O.rplu_dense(A, k=3, seed=0)
+    R.rplu_dense(A, k=passes - 1, seed=0, copy=False)
     el = time.perf_counter() - t0
-    print(json.dumps({{"elapsed": el, "passes": 4, "k": 512, "sub_n": n}}))
+    print(json.dumps({{"elapsed": el, "passes": passes, "k": 512, "sub_n": n, "threads": threads}}))
 """
 
 
-def cpu_baseline(workload: str):
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    code = _CPU_SAMPLE.format(root=ROOT, wl=workload)
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_run(workload: str, threads: int, budget: float):
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads), OPENBLAS_NUM_THREADS="1",
+               MKL_NUM_THREADS="1", OMP_PROC_BIND="false")
+    code = _CPU_SAMPLE.format(root=ROOT, wl=workload, budget=budget)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
-                       timeout=600)
+                       timeout=900)
     if r.returncode != 0:
-        return {"error": r.stderr[-500:]}
+        return None, r.stderr[-500:]
     d = json.loads(r.stdout.strip().splitlines()[-1])
     if workload == "cauchy20k":
-        per_pass = d["elapsed"] / d["passes"]
-        full = per_pass * (d["k"] + 1)
-        sample = ("oracle rplu_cauchy on the full 20000x20000 input, k=2 (3 exact all-pairs "
-                  "mass passes), extrapolated to k=200 (201 passes)")
+        full = d["elapsed"] / d["passes"] * (d["k"] + 1)
+        sample = (f"C++ oracle rplu_cauchy (exact all-pairs masses) on the full 20000x20000 "
+                  f"input, k={d['passes'] - 1}: {d['passes']} all-pairs mass passes timed, "
+                  f"scaled to the 201 passes of k=200")
     elif workload == "batched4096":
-        full = d["elapsed"] / d["done"] * d["count"]
-        sample = (f"oracle rplu_dense (tol 1e-6) on {d['done']} instances drawn at random "
-                  f"(seeded) from the {d['count']}-instance batch recipe, generated on the host; "
-                  f"mean time per instance x {d['count']}; one approximation = the whole batch")
+        sample = (f"C++ oracle rplu_dense (tol 1e-6) on {d['done']} instances drawn at random "
+                  f"(seeded) from the {d['count']}-instance batch recipe; mean time per "
+                  f"instance x {d['count']}; one approximation = one instance")
+        full = d["elapsed"] / d["done"]
     elif workload == "dense512":
         full = d["elapsed"]
-        sample = f"oracle rplu_dense on the full 512x512 input, k=50, {d['reps']} repetitions"
+        sample = f"C++ oracle rplu_dense on the full 512x512 input, k=50, {d['reps']} repetitions"
     else:
-        per_pass = d["elapsed"] / d["passes"]
-        full = per_pass * (32768 / d["sub_n"]) ** 2 * (d["k"] + 1)
-        sample = ("oracle rplu_dense, k=3 on an 8192x8192 matrix of the same spectrum, "
-                  "scaled by (32768/8192)^2 per step and to k=512")
-    return {"value": 1.0 / full, "unit": "approximations/s", "cores": 1, "kind": "oracle",
-            "sample": sample, "seconds_per_approximation": full}
+        full = d["elapsed"] / d["passes"] * (32768 / d["sub_n"]) ** 2 * (d["k"] + 1)
+        sample = (f"C++ oracle rplu_dense, k={d['passes'] - 1} on an 8192x8192 FP64 matrix of "
+                  "the same spectrum, scaled by (32768/8192)^2 per pass and to the 513 passes "
+                  "of k=512")
+    return {"value": 1.0 / full, "seconds_per_approximation": full, "sample": sample,
+            "threads": d["threads"]}, None
+
+
+def cpu_baseline(workload: str):
+    """The C++ FP64 oracle (oracle/rplu_ref.cpp, -O3, OpenMP over rows) timed
+    on the host on a bounded sample: all host cores, and one core."""
+    nproc = os.cpu_count() or 1
+    try:
+        allc, err = _cpu_run(workload, nproc, 15.0)
+        one, err1 = _cpu_run(workload, 1, 8.0)
+    except subprocess.TimeoutExpired as e:
+        return {"error": f"timeout: {e}"}
+    if allc is None:
+        return {"error": err}
+    out = {"value": allc["value"], "unit": "approximations/s", "cores": allc["threads"],
+           "kind": "oracle", "sample": allc["sample"],
+           "seconds_per_approximation": allc["seconds_per_approximation"],
+           "oracle": "C++17 FP64 (oracle/rplu_ref.cpp), g++ -O3 -march=x86-64-v3 "
+                     "-ffp-contract=off -fopenmp",
+           "cpu_model": _cpu_model(), "nproc": nproc}
+    if one is not None:
+        out["one_core"] = {"value": one["value"], "unit": "approximations/s", "cores": 1,
+                           "sample": one["sample"],
+                           "seconds_per_approximation": one["seconds_per_approximation"]}
+    else:
+        out["one_core"] = {"error": err1}
+    return out
 
 
 # ------------------------------------------------------------------------ main
@@ -365,6 +410,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cauchy20k", choices=["cauchy20k", "dense32k", "dense512", "batched4096", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="cauchy20k: skip the dense32k and batched4096 lines the default run "
+                         "adds under extra_workloads")
+    ap.add_argument("--extra-steps", type=int, default=3,
+                    help="timed steps of each extra workload")
     ap.add_argument("--pivoting", default="rplu", choices=["rplu", "c2plu"],
                     help="cauchy20k / dense workloads: c2plu = complete 2-norm pivoting "
                          "(RPLU_FLAG_C2PLU) instead of the random draws; no CPU baseline")
@@ -403,14 +453,39 @@ def main() -> int:
     import paper_2601_22344_amd as rplu
 
     torch.cuda.set_device(0)
-    if args.workload == "cauchy20k":
-        wl = _setup_cauchy20k(torch, rplu)
-    elif args.workload == "batched4096":
-        return _main_batched(args, torch, rplu)
-    elif args.workload == "serve":
+    if args.workload == "serve":
         return _main_serve(args, torch, rplu)
+    if args.workload == "batched4096":
+        out = _run_batched(args, torch, rplu)
     else:
-        wl = _setup_dense(torch, rplu, args.workload)
+        out = _run_workload(args, torch, rplu, args.workload)
+    if args.workload == "cauchy20k" and not args.no_extras and args.pivoting == "rplu":
+        # the dense HBM-bound workload and the batched workload, each timed
+        # in this process under its own key with its own roofline
+        ex = argparse.Namespace(**vars(args))
+        ex.steps, ex.warmup, ex.no_cpu_baseline = args.extra_steps, 1, True
+        torch.cuda.empty_cache()
+        extras = {}
+        for name in ("dense32k", "batched4096"):
+            print(f"[bench] extra workload {name}", file=sys.stderr, flush=True)
+            ex.workload = name
+            r = _run_batched(ex, torch, rplu) if name == "batched4096" else \
+                _run_workload(ex, torch, rplu, name)
+            for key in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data",
+                        "cpu_baseline"):
+                r.pop(key, None)
+            extras[name] = r
+            torch.cuda.empty_cache()
+        out["extra_workloads"] = extras
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _run_workload(args, torch, rplu, workload) -> dict:
+    if workload == "cauchy20k":
+        wl = _setup_cauchy20k(torch, rplu)
+    else:
+        wl = _setup_dense(torch, rplu, workload)
     ctx = rplu.default_context(0)
     flags = rplu.RPLU_FLAG_NO_GRAPH if args.no_graph else 0
     if args.pivoting == "c2plu":
@@ -443,13 +518,18 @@ def main() -> int:
     achieved = wl["per_launch"] / (hot_ms * 1e-3) if hot_launches else float("nan")
     if wl["kind"] == "cauchy":
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK_TF,
-                "unit": "TFLOP/s", "frac": achieved / 1e12 / FP64_VECTOR_PEAK_TF}
+                "unit": "TFLOP/s", "frac": achieved / 1e12 / FP64_VECTOR_PEAK_TF,
+                "flop_per_pair": CAUCHY_FLOP_PER_PAIR,
+                "pairs_per_launch": wl["pairs_per_launch"],
+                "pairs_per_s": wl["pairs_per_launch"] / (hot_ms * 1e-3) if hot_launches else None,
+                "count": "n*m pairs per launch x 11 FLOP; the reciprocal per pair is not "
+                         "counted"}
         kernel = "k_cauchy_mass<1>"
     else:
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / 1e9 / HBM_PEAK_GBS}
         kernel = "k_dense_sweep"
-    roof["traffic"] = _traffic(args.workload, hot_launches)
+    roof["traffic"] = _traffic(workload, hot_launches)
     roof["kernel"] = kernel
     roof["avg_launch_us"] = hot_ms * 1e3
     roof["launches"] = hot_launches
@@ -468,12 +548,11 @@ def main() -> int:
     if wl["kind"] == "dense":
         out["GB_per_s_live"] = wl["live_total"] / (elapsed / args.steps) / 1e9
         out["verify"] = wl["verify"](res)
-    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.workload)
-    print(json.dumps(out), flush=True)
-    return 0
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(workload)
+    return out
 
 
-def _main_batched(args, torch, rplu) -> int:
+def _run_batched(args, torch, rplu) -> dict:
     wl = _setup_batched(torch, rplu)
     ctx = rplu.default_context(0)
     t0 = time.perf_counter()
@@ -532,8 +611,7 @@ def _main_batched(args, torch, rplu) -> int:
             "how": "rplu_dense FP64, plain launches, one instance after another, tol 1e-6"}
         out["speedup_vs_fp64_one_at_a_time"] = value / (count / el64)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline("batched4096")
-    print(json.dumps(out), flush=True)
-    return 0
+    return out
 
 
 def _dense_live(n, m, k, es):
@@ -541,7 +619,7 @@ def _dense_live(n, m, k, es):
 
 
 def _cauchy_flop(n, m, k):
-    return CAUCHY_FLOP_PER_PAIR * sum((n - t) * (m - t) for t in range(k + 1))
+    return CAUCHY_FLOP_PER_PAIR * n * m * (k + 1)
 
 
 def _main_serve(args, torch, rplu) -> int:
