@@ -89,7 +89,9 @@ enum {
     RPLU_STOP_TOL = 2,
     RPLU_STOP_EXHAUSTED = 3,
     RPLU_STOP_TOL_UNREACHED = 4,
-    RPLU_STOP_STALL = 5        /* RPLU_FLAG_STALL_STOP: T stopped falling      */
+    RPLU_STOP_STALL = 5,       /* RPLU_FLAG_STALL_STOP: T stopped falling      */
+    RPLU_STOP_REFRESH = 6      /* internal: a residual replacement is due
+                                  (RPLU_FLAG_REFRESH); never returned          */
 };
 
 enum {
@@ -107,7 +109,7 @@ enum {
                                      fused workgroup kernel is the default;
                                      every output is the same bit for bit.
                                      The Cauchy-like path has one form.      */
-    RPLU_FLAG_C2PLU = 1u << 5       /* dense and Cauchy-like: complete 2-norm
+    RPLU_FLAG_C2PLU = 1u << 5,      /* dense and Cauchy-like: complete 2-norm
                                      pivoting (Sec. 2.3.3) instead of the
                                      random draws: i = the first row of
                                      largest mass, then j = the first column
@@ -116,7 +118,45 @@ enum {
                                      stop test, seed and stream unused.
                                      rplu_batched and rplu_server_submit
                                      reject it in a job (RPLU_E_ARG).        */
+    RPLU_FLAG_CERTIFY = 1u << 7,    /* server, dense R32/R64 jobs: after the run,
+                                     ||A - L U||_F^2 is formed in FP64 on the
+                                     matrix cores from the original A and
+                                     returned in info.err_fro2 (needs L, U) */
+    RPLU_FLAG_REFRESH = 1u << 6     /* dense R32/R64 (rplu_dense, batches, the
+                                     server): residual replacement. Before
+                                     the draw of step t, when ||S||^2 has
+                                     fallen to RPLU_REFRESH_DROP2 times its
+                                     value at the start or at the previous
+                                     replacement, or when the stall rule
+                                     fires above rel_tol, S is replaced by
+                                     the true residual A - L U of the t steps
+                                     taken, formed in FP64 with the matrix
+                                     cores from the original matrix
+                                     (opts.A_orig / job.A_orig) and rounded to
+                                     the element type (every entry: earlier
+                                     pivot rows and columns keep the errors
+                                     the stored factors leave there and may
+                                     be drawn again); the run goes on from
+                                     step t (same Philox stream, stall window
+                                     restarted), at most RPLU_MAX_REFRESH
+                                     times. The rounding errors of earlier
+                                     steps then no longer stay in S, so a
+                                     single-precision sweep draws its pivots
+                                     from a residual accurate to its own
+                                     precision at every level and reaches
+                                     tolerances near its rounding floor. A
+                                     tolerance stop on a swept S is taken
+                                     again on the replaced residual (whose
+                                     total is the true error of the stored
+                                     factors), so res_fro2 at a TOL stop is
+                                     ||A - L U||_F^2 up to the rounding of
+                                     the residual. Needs L and U.            */
 };
+
+/* Residual replacements per run under RPLU_FLAG_REFRESH, and the fall of
+ * ||S||_F^2 between two of them that triggers one. */
+#define RPLU_MAX_REFRESH 8
+#define RPLU_REFRESH_DROP2 1e-4
 
 /* Stall rule (a library extension, not from the paper): with
  * RPLU_FLAG_STALL_STOP the run keeps the best total T_best and the step
@@ -157,6 +197,10 @@ typedef struct {
                                used (dense: per row; Cauchy: per row), or NULL  */
     double* colmass_out;    /* device, kmax*m doubles: column masses of S^(t),
                                needs RPLU_FLAG_COLMASS, or NULL                  */
+    const void* A_orig;     /* device: the unmodified input (RPLU_FLAG_REFRESH),
+                               n x m row-major with lda_orig >= m, not
+                               overlapping A; otherwise ignored                 */
+    int64_t lda_orig;
 } rplu_opts;
 
 typedef struct {
@@ -166,6 +210,11 @@ typedef struct {
                                code (per instance for rplu_batched)            */
     double a_fro2;          /* ||A||_F^2 as reduced on the device               */
     double res_fro2;        /* ||S^(rank)||_F^2 at the final stop test          */
+    double err_fro2;        /* server jobs with RPLU_FLAG_CERTIFY: ||A - L U||_F^2
+                               in FP64 from the original A (rplu_verify's
+                               contraction); -1 otherwise                      */
+    int32_t refreshes;      /* residual replacements made (RPLU_FLAG_REFRESH)   */
+    int32_t first_refresh;  /* step of the first one, or -1                    */
 } rplu_info;
 
 typedef struct rplu_ctx_s* rplu_ctx;
@@ -238,8 +287,9 @@ typedef struct {
     void* A;                /* dense input, overwritten by S^(rank)            */
     int64_t lda;
     int32_t p;              /* Cauchy displacement rank                        */
-    uint32_t flags;         /* RPLU_FLAG_STALL_STOP honoured; RPLU_FLAG_C2PLU
-                               rejected (RPLU_E_ARG); others ignored          */
+    uint32_t flags;         /* RPLU_FLAG_STALL_STOP and RPLU_FLAG_REFRESH
+                               honoured; RPLU_FLAG_C2PLU rejected
+                               (RPLU_E_ARG); others ignored                   */
     const void* x;          /* Cauchy nodes and generators                     */
     const void* y;
     void* G;
@@ -253,6 +303,14 @@ typedef struct {
     double rel_tol;
     uint64_t seed;
     uint64_t stream;
+    const void* A_orig;     /* dense, RPLU_FLAG_REFRESH: the unmodified input
+                               (lda_orig >= m); the server uses A itself      */
+    int64_t lda_orig;
+    void* ready_event;      /* server: a hipEvent_t recorded (on the
+                               submitter's stream) after the job's inputs are
+                               written; the admission copy waits for it. NULL:
+                               the inputs are ready at submit. It must stay
+                               valid until poll stops returning RPLU_PENDING. */
 } rplu_job;
 
 /* Batched launch configuration. None of these fields changes the arithmetic:
@@ -307,36 +365,49 @@ rplu_status rplu_batched_tune(rplu_ctx ctx, int64_t count, const rplu_job* jobs,
 
 /* Continuous-batching server for arriving dense and Cauchy-like jobs.
  *
- * Admission: submitted jobs wait in FIFO order; the head is admitted while a
- * block of its device footprint fits in the server's slot pool (one device
- * allocation of hbm_budget_bytes, sub-allocated first-fit) and fewer than
- * max_slots jobs are resident. Admission copies the job's overwritten inputs
- * (dense A, Cauchy G and B) into its slot, so the Schur state stays on the
- * device in server memory and the caller's inputs are never modified.
- * Execution: `workers` host threads, each with its own context and device
- * stream, take admitted work as it becomes ready: every admitted dense job
- * with n, m <= batch_max_dim (R32/R64) that is ready when a worker frees up
- * goes into ONE rplu_batched launch; other jobs (larger dense, Cauchy-like)
- * run alone (rplu_dense / rplu_cauchy, plain launches). Work of different
- * workers overlaps on the device. A job's results are those it gets alone:
- * the batched kernel matches rplu_dense bitwise, and slots keep each input's
- * row pitch and 16-byte alignment offset.
- * Footprint of a job: dense n * lda * size + 16; Cauchy (n p + p m) * 16 + 16
- * bytes (rounded up to 256). */
+ * Admission: submitted jobs wait in FIFO order; the head is admitted while
+ * its footprint fits in the server's slot pool (one device allocation of
+ * hbm_budget_bytes, sub-allocated first-fit) and fewer than max_slots jobs
+ * are running. A job's footprint is everything it touches on the device
+ * besides its read-only inputs: a work block (the copy of the input the run
+ * overwrites: dense A, Cauchy G and B; the run's workspace: step state,
+ * masses, chunk totals, Cauchy split partials; the certification partials)
+ * and, when the server owns the outputs (job.piv == NULL), an output block
+ * (piv, L, U of kmax steps), allocated at admission. The work block returns
+ * to the pool when the job finishes, the output block at
+ * rplu_server_release. The caller's inputs are never modified.
+ * Execution, overlapping on the device:
+ *   - step-level batching: every admitted dense R32/R64 job with n, m <=
+ *     batch_max_dim joins the resident set of the tick thread; each tick is
+ *     one launch of the batched kernel over all resident jobs, advancing
+ *     each by up to tick_steps steps (a job pauses at a step boundary and
+ *     resumes in the next tick), so an arriving job starts at the next step
+ *     boundary and a finished one leaves at once;
+ *   - `workers` threads, each with its own stream, run larger dense jobs
+ *     and Cauchy-like jobs alone (rplu_dense / rplu_cauchy steps, plain
+ *     launches).
+ * A job's results are those it gets alone (rplu_dense / rplu_cauchy, bit for
+ * bit): the batched kernel reproduces rplu_dense, pauses change no bit, slots
+ * keep each input's row pitch and 16-byte offset, and RPLU_FLAG_REFRESH acts
+ * at the same step in both. Honoured job flags: RPLU_FLAG_STALL_STOP,
+ * RPLU_FLAG_REFRESH (dense R32/R64: the caller's A is the original),
+ * RPLU_FLAG_CERTIFY (dense R32/R64). */
 typedef struct {
     size_t hbm_budget_bytes;   /* slot pool size                               */
-    int32_t max_slots;         /* most jobs admitted at once (<= 0: no limit)  */
+    int32_t max_slots;         /* most jobs running at once (<= 0: no limit)   */
     int32_t queue_capacity;    /* most jobs waiting; beyond -> RPLU_E_BUSY     */
     int32_t workers;           /* worker threads/streams (<= 0: 3)             */
-    int32_t batch_max_dim;     /* dense jobs with n, m <= this are batched
-                                  (<= 0: 2048; at most 8192)                   */
+    int32_t batch_max_dim;     /* dense R32/R64 jobs with n, m <= this go to
+                                  the step ticks (<= 0: 2048; at most 8192)    */
     uint32_t flags;            /* RPLU_SERVER_SIMULATE                         */
-    int32_t reserved;
+    int32_t tick_steps;        /* steps per tick (<= 0: 32)                    */
 } rplu_server_cfg;
 
 /* Host-only mode for testing the queueing logic without a device: the pool is
- * host memory, no HIP call is made, inputs are not read, and a job "runs" for
- * footprint / 1e10 seconds and completes with rank 0, RPLU_STOP_RANK. */
+ * host memory, no HIP call is made, inputs are not read. A worker job "runs"
+ * for footprint / 1e10 seconds; a tick advances every resident job by
+ * tick_steps steps and takes the sum of footprint * steps / kmax / 1e10
+ * seconds. Jobs complete with rank kmax and RPLU_STOP_RANK. */
 #define RPLU_SERVER_SIMULATE 1u
 
 typedef struct {
@@ -345,30 +416,44 @@ typedef struct {
     double p50_dense_ms, p99_dense_ms;
     double p50_cauchy_ms, p99_cauchy_ms;
     double busy_s;                     /* wall time with >= 1 admitted job   */
-    size_t hbm_in_use;                 /* bytes of the pool held by slots    */
-    int64_t batches;                   /* batched launches run               */
-    int64_t batched_jobs;              /* jobs run inside those launches     */
+    size_t hbm_in_use;                 /* bytes of the pool held by blocks   */
+    size_t hbm_peak;                   /* largest hbm_in_use so far          */
+    int64_t ticks;                     /* batched step ticks launched        */
+    int64_t tick_jobs;                 /* jobs completed through the ticks   */
+    int64_t refreshes;                 /* residual replacements (ticks)      */
 } rplu_server_stats_t;
 
 typedef struct rplu_server_s* rplu_server;
 
-/* ctx names the device (its workspace is not used; each worker makes its
- * own context); it may be NULL with RPLU_SERVER_SIMULATE. */
+/* ctx names the device (its workspace is not used; the tick thread and each
+ * worker make their own context); it may be NULL with RPLU_SERVER_SIMULATE. */
 rplu_status rplu_server_create(rplu_ctx ctx, const rplu_server_cfg* cfg,
                                rplu_server* out);
 /* Non-blocking, thread-safe. Copies the descriptor and returns a ticket;
  * RPLU_E_BUSY when queue_capacity jobs are waiting, RPLU_E_ARG for a job that
- * can never be admitted (footprint above the pool) or is malformed. The job's
- * input buffers must stay valid, and its outputs untouched, until poll
- * returns something other than RPLU_PENDING. */
+ * can never be admitted (footprint above the pool) or is malformed.
+ * Outputs: job.piv/L/U given (caller-owned, written by the run), or all three
+ * NULL (server-owned, in the job's output block: rplu_server_outputs). The
+ * job's input buffers must stay valid and unmodified until poll returns
+ * something other than RPLU_PENDING; if they are written on a stream, record
+ * job.ready_event after the writes (the admission copy waits for it). */
 rplu_status rplu_server_submit(rplu_server srv, const rplu_job* job,
                                uint64_t* ticket);
 /* RPLU_PENDING until the job finished; then its status (RPLU_OK or an error)
- * and info, once: the ticket is then forgotten (a later poll: RPLU_E_ARG).
- * Thread-safe. */
+ * and info. A ticket with caller-owned outputs (or a failed job) is then
+ * forgotten (a later poll: RPLU_E_ARG); one with server-owned outputs stays
+ * until rplu_server_release. Thread-safe. */
 rplu_status rplu_server_poll(rplu_server srv, uint64_t ticket, rplu_info* info);
+/* Device pointers of a finished job's server-owned outputs: piv (2 kmax
+ * int32), L (n x kmax column-major, *ldl = n), U (kmax x m row-major,
+ * *ldu = m); valid until rplu_server_release. RPLU_PENDING while running. */
+rplu_status rplu_server_outputs(rplu_server srv, uint64_t ticket, int32_t** piv, void** L,
+                                int64_t* ldl, void** U, int64_t* ldu);
+/* Returns a finished job's output block to the pool and forgets the ticket. */
+rplu_status rplu_server_release(rplu_server srv, uint64_t ticket);
 rplu_status rplu_server_stats(rplu_server srv, rplu_server_stats_t* out);
-/* Drains every submitted job, stops the workers and frees slot memory. */
+/* Drains every submitted job, stops the threads and frees the pool (outputs
+ * not yet released go with it). */
 rplu_status rplu_server_destroy(rplu_server srv);
 
 /* -------------------------------------------------------- verification */

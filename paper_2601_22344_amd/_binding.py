@@ -22,6 +22,17 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python paper_2601_22344_amd/build.py` "
         "(the RPLU path has no CPU fallback)")
 lib = C.CDLL(LIB_PATH)
+# the HIP runtime the library links, for copies out of server-owned memory
+_hip = C.CDLL("libamdhip64.so.7", mode=C.RTLD_GLOBAL)
+_hip.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+_hip.hipMemcpyAsync.restype = C.c_int
+_hip.hipStreamSynchronize.argtypes = [C.c_void_p]
+_hip.hipStreamSynchronize.restype = C.c_int
+
+
+def _hip_check(e: int) -> None:
+    if e != 0:
+        raise RuntimeError(f"HIP error {e}")
 
 # ------------------------------------------------------------------ constants
 RPLU_OK, RPLU_PENDING = 0, 1
@@ -33,6 +44,11 @@ RPLU_STOP_STALL = 5
 RPLU_FLAG_COLMASS, RPLU_FLAG_GRAPH, RPLU_FLAG_NO_GRAPH, RPLU_FLAG_STALL_STOP = 1, 2, 4, 8
 RPLU_FLAG_SPLIT_SAMPLER = 16
 RPLU_FLAG_C2PLU = 32
+RPLU_FLAG_REFRESH = 64
+RPLU_FLAG_CERTIFY = 128
+RPLU_MAX_REFRESH = 8
+RPLU_REFRESH_DROP2 = 1e-4
+RPLU_STOP_REFRESH = 6
 RPLU_STALL_WINDOW = 64
 RPLU_TRACE_WORDS = 12
 RPLU_JOB_DENSE, RPLU_JOB_CAUCHY = 1, 2
@@ -47,12 +63,13 @@ class rplu_opts(C.Structure):
     _fields_ = [("max_rank", C.c_int64), ("rel_tol", C.c_double), ("seed", C.c_uint64),
                 ("stream", C.c_uint64), ("flags", C.c_uint32), ("reserved", C.c_uint32),
                 ("forced", C.c_void_p), ("trace", C.c_void_p), ("rowmass_out", C.c_void_p),
-                ("colmass_out", C.c_void_p)]
+                ("colmass_out", C.c_void_p), ("A_orig", C.c_void_p), ("lda_orig", C.c_int64)]
 
 
 class rplu_info(C.Structure):
     _fields_ = [("rank", C.c_int64), ("stop", C.c_int32), ("status", C.c_int32),
-                ("a_fro2", C.c_double), ("res_fro2", C.c_double)]
+                ("a_fro2", C.c_double), ("res_fro2", C.c_double), ("err_fro2", C.c_double),
+                ("refreshes", C.c_int32), ("first_refresh", C.c_int32)]
 
 
 class rplu_job(C.Structure):
@@ -61,7 +78,8 @@ class rplu_job(C.Structure):
                 ("x", C.c_void_p), ("y", C.c_void_p), ("G", C.c_void_p), ("B", C.c_void_p),
                 ("piv", C.c_void_p), ("L", C.c_void_p), ("ldl", C.c_int64), ("U", C.c_void_p),
                 ("ldu", C.c_int64), ("max_rank", C.c_int64), ("rel_tol", C.c_double),
-                ("seed", C.c_uint64), ("stream", C.c_uint64)]
+                ("seed", C.c_uint64), ("stream", C.c_uint64), ("A_orig", C.c_void_p),
+                ("lda_orig", C.c_int64), ("ready_event", C.c_void_p)]
 
 
 class rplu_batch_cfg(C.Structure):
@@ -76,7 +94,7 @@ class rplu_verify_out(C.Structure):
 class rplu_server_cfg(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32),
                 ("queue_capacity", C.c_int32), ("workers", C.c_int32),
-                ("batch_max_dim", C.c_int32), ("flags", C.c_uint32), ("reserved", C.c_int32)]
+                ("batch_max_dim", C.c_int32), ("flags", C.c_uint32), ("tick_steps", C.c_int32)]
 
 
 class rplu_profile(C.Structure):
@@ -89,7 +107,8 @@ class rplu_server_stats_t(C.Structure):
                 ("p99_ms", C.c_double), ("p50_dense_ms", C.c_double),
                 ("p99_dense_ms", C.c_double), ("p50_cauchy_ms", C.c_double),
                 ("p99_cauchy_ms", C.c_double), ("busy_s", C.c_double),
-                ("hbm_in_use", C.c_size_t), ("batches", C.c_int64), ("batched_jobs", C.c_int64)]
+                ("hbm_in_use", C.c_size_t), ("hbm_peak", C.c_size_t), ("ticks", C.c_int64),
+                ("tick_jobs", C.c_int64), ("refreshes", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -111,6 +130,9 @@ lib.rplu_server_create.argtypes = [_P, C.POINTER(rplu_server_cfg), C.POINTER(_P)
 lib.rplu_server_submit.argtypes = [_P, C.POINTER(rplu_job), C.POINTER(C.c_uint64)]
 lib.rplu_server_poll.argtypes = [_P, C.c_uint64, C.POINTER(rplu_info)]
 lib.rplu_server_stats.argtypes = [_P, C.POINTER(rplu_server_stats_t)]
+lib.rplu_server_outputs.argtypes = [_P, C.c_uint64, C.POINTER(_P), C.POINTER(_P),
+                                    C.POINTER(_I64), C.POINTER(_P), C.POINTER(_I64)]
+lib.rplu_server_release.argtypes = [_P, C.c_uint64]
 lib.rplu_server_destroy.argtypes = [_P]
 lib.rplu_profile_begin.argtypes = [_P]
 lib.rplu_profile_end.argtypes = [_P, C.POINTER(rplu_profile)]
@@ -125,7 +147,8 @@ for _fn in ("rplu_create", "rplu_destroy", "rplu_dense", "rplu_dense_noalloc", "
             "rplu_batched",
             "rplu_batched_ex", "rplu_batched_tune", "rplu_verify",
             "rplu_server_create", "rplu_server_submit", "rplu_server_poll",
-            "rplu_server_stats", "rplu_server_destroy", "rplu_profile_begin", "rplu_profile_end"):
+            "rplu_server_stats", "rplu_server_destroy", "rplu_server_outputs",
+            "rplu_server_release", "rplu_profile_begin", "rplu_profile_end"):
     getattr(lib, _fn).restype = C.c_int32
 
 
@@ -198,20 +221,31 @@ class Result:
     rowmass: Optional[torch.Tensor] = None    # rank x n float64
     colmass: Optional[torch.Tensor] = None    # rank x m float64
     status: int = 0                           # RPLU_OK or the job's RPLU_E_* code
+    refreshes: int = 0                        # residual replacements (RPLU_FLAG_REFRESH)
+    first_refresh: int = -1                   # step of the first one, or -1
+    err_fro2: float = -1.0                    # certified ||A - L U||^2 (server), or -1
 
 
-def _opts(k, tol, seed, stream, flags, forced, trace, rowmass_out, colmass_out):
+def _opts(k, tol, seed, stream, flags, forced, trace, rowmass_out, colmass_out, A_orig=None):
     return rplu_opts(int(k), float(tol), int(seed) & (2**64 - 1), int(stream) & (2**64 - 1),
                      int(flags), 0, _ptr(forced), _ptr(trace), _ptr(rowmass_out),
-                     _ptr(colmass_out))
+                     _ptr(colmass_out), _ptr(A_orig),
+                     A_orig.stride(0) if A_orig is not None else 0)
 
 
 def rplu_dense(A: torch.Tensor, k: int = 0, tol: float = 0.0, seed: int = 0, stream: int = 0,
                flags: int = 0, forced: Optional[torch.Tensor] = None, want_trace: bool = False,
                want_rowmass: bool = False, want_colmass: bool = False, store_L: bool = True,
-               store_U: bool = True, ctx: Optional[Context] = None) -> Result:
+               store_U: bool = True, ctx: Optional[Context] = None,
+               A_orig: Optional[torch.Tensor] = None) -> Result:
     """Dense RPLU of A (n x m CUDA tensor, row stride >= m, overwritten by the
-    final Schur complement). Returns device factors sliced to the rank."""
+    final Schur complement). Returns device factors sliced to the rank.
+    A_orig: the unmodified input, for RPLU_FLAG_REFRESH (set by default when
+    given)."""
+    if A_orig is not None:
+        if A_orig.shape != A.shape or A_orig.dtype != A.dtype or A_orig.stride(1) != 1:
+            raise ValueError("A_orig must have A's shape and dtype, unit column stride")
+        flags |= RPLU_FLAG_REFRESH
     if A.dim() != 2 or A.stride(1) != 1 or A.dtype not in _DTYPES or not A.is_cuda:
         raise ValueError("A must be a 2-D CUDA tensor (float32/64, complex64/128), unit column stride")
     n, m = A.shape
@@ -230,7 +264,7 @@ def rplu_dense(A: torch.Tensor, k: int = 0, tol: float = 0.0, seed: int = 0, str
         forced = forced.to(device=dev, dtype=torch.int32).contiguous()
         if forced.numel() < 2 * kmax:
             raise ValueError("forced needs 2*kmax entries")
-    opts = _opts(k, tol, seed, stream, flags, forced, trace, rmo, cmo)
+    opts = _opts(k, tol, seed, stream, flags, forced, trace, rmo, cmo, A_orig)
     info = rplu_info()
     st = lib.rplu_dense(ctx.handle, _DTYPES[A.dtype], n, m, _ptr(A), A.stride(0), C.byref(opts),
                         _ptr(piv), _ptr(Lt), n, _ptr(U), m, C.byref(info), _cur_stream(dev))
@@ -239,7 +273,8 @@ def rplu_dense(A: torch.Tensor, k: int = 0, tol: float = 0.0, seed: int = 0, str
     return Result(piv[:r], Lt[:r].T if Lt is not None else None, U[:r] if U is not None else None,
                   r, int(info.stop), float(info.a_fro2), float(info.res_fro2),
                   trace[:r] if trace is not None else None, rmo[:r] if rmo is not None else None,
-                  cmo[:r] if cmo is not None else None)
+                  cmo[:r] if cmo is not None else None, refreshes=int(info.refreshes),
+                  first_refresh=int(info.first_refresh))
 
 
 def rplu_dense_noalloc(A: torch.Tensor, piv: torch.Tensor, L: Optional[torch.Tensor] = None,
@@ -307,7 +342,8 @@ def rplu_cauchy(x: torch.Tensor, y: torch.Tensor, G: torch.Tensor, B: torch.Tens
     return Result(piv[:r], Lt[:r].T if Lt is not None else None, U[:r] if U is not None else None,
                   r, int(info.stop), float(info.a_fro2), float(info.res_fro2),
                   trace[:r] if trace is not None else None, rmo[:r] if rmo is not None else None,
-                  cmo[:r] if cmo is not None else None)
+                  cmo[:r] if cmo is not None else None, refreshes=int(info.refreshes),
+                  first_refresh=int(info.first_refresh))
 
 
 def rplu_profile_begin(ctx: Context) -> None:
@@ -330,7 +366,7 @@ def _per_job(v, count, name):
     return [v] * count
 
 
-def _batch_jobs(As, k, tol, seed, streams, store_L, store_U, flags=0):
+def _batch_jobs(As, k, tol, seed, streams, store_L, store_U, flags=0, A_origs=None):
     count = len(As)
     ks, tols, seeds = _per_job(k, count, "k"), _per_job(tol, count, "tol"), _per_job(seed, count, "seed")
     streams = list(range(count)) if streams is None else _per_job(streams, count, "streams")
@@ -355,6 +391,12 @@ def _batch_jobs(As, k, tol, seed, streams, store_L, store_U, flags=0):
         j.max_rank, j.rel_tol = kk, float(tols[b])
         j.seed, j.stream = int(seeds[b]) & (2**64 - 1), int(streams[b]) & (2**64 - 1)
         j.flags = int(flags)
+        if A_origs is not None:
+            Ao = A_origs[b]
+            if Ao.shape != A.shape or Ao.dtype != A.dtype or Ao.stride(1) != 1:
+                raise ValueError("A_origs[b] must have A's shape and dtype, unit column stride")
+            j.A_orig, j.lda_orig = Ao.data_ptr(), Ao.stride(0)
+            j.flags |= RPLU_FLAG_REFRESH
         outs.append((piv, Lt, U))
     return jobs, outs
 
@@ -364,13 +406,15 @@ class BatchPlan:
     table, for repeated launches (the matrices are overwritten by each run)."""
 
     def __init__(self, As, k=0, tol=0.0, seed=0, streams=None, store_L: bool = True,
-                 store_U: bool = True, ctx: Optional[Context] = None, flags: int = 0):
+                 store_U: bool = True, ctx: Optional[Context] = None, flags: int = 0,
+                 A_origs=None):
         self.count = len(As)
         self.device = As[0].device if self.count else torch.device("cuda", 0)
         self.ctx = ctx or default_context(self.device.index or 0)
-        self.jobs, self.outs = _batch_jobs(As, k, tol, seed, streams, store_L, store_U, flags)
+        self.jobs, self.outs = _batch_jobs(As, k, tol, seed, streams, store_L, store_U, flags,
+                                           A_origs)
         self.infos = (rplu_info * max(self.count, 1))()
-        self._keep = list(As)
+        self._keep = list(As) + list(A_origs or [])
 
     def run(self, cfg: Optional[dict] = None, raise_on_error: bool = True) -> int:
         if self.count == 0:
@@ -396,7 +440,8 @@ class BatchPlan:
             r = int(inf.rank)
             res.append(Result(piv[:r], Lt[:r].T if Lt is not None else None,
                               U[:r] if U is not None else None, r, int(inf.stop),
-                              float(inf.a_fro2), float(inf.res_fro2), status=int(inf.status)))
+                              float(inf.a_fro2), float(inf.res_fro2), status=int(inf.status),
+                              refreshes=int(inf.refreshes), first_refresh=int(inf.first_refresh)))
         return res
 
 
@@ -460,85 +505,108 @@ def rplu_verify(A: torch.Tensor, L: Optional[torch.Tensor], U: Optional[torch.Te
 
 
 class Server:
-    """Continuous-batching server (rplu_server_*). submit_* allocate the
-    job's outputs and return a ticket; poll returns None while the job is
-    pending, else its Result (raising RPLUError if it failed)."""
+    """Continuous-batching server (rplu_server_*). submit_* return a ticket;
+    the server owns each job's outputs (allocated in its pool at admission).
+    poll returns None while the job is pending, else its Result (raising
+    RPLUError if it failed): the outputs are copied into new tensors and the
+    job's output block is released."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 0, queue_capacity: int = 0,
                  workers: int = 0, batch_max_dim: int = 0, simulate: bool = False,
-                 ctx: Optional[Context] = None, device: int = 0):
+                 ctx: Optional[Context] = None, device: int = 0, tick_steps: int = 0):
         self.ctx = None if simulate else (ctx or default_context(device))
+        self.simulate = simulate
         cfg = rplu_server_cfg(int(budget_bytes), int(max_slots), int(queue_capacity), int(workers),
-                              int(batch_max_dim), RPLU_SERVER_SIMULATE if simulate else 0, 0)
+                              int(batch_max_dim), RPLU_SERVER_SIMULATE if simulate else 0,
+                              int(tick_steps))
         h = C.c_void_p()
         _check(lib.rplu_server_create(self.ctx.handle if self.ctx else None, C.byref(cfg),
                                       C.byref(h)), "rplu_server_create")
         self.handle = h
         self._pending = {}
 
-    def _submit(self, job, keep):
+    def _submit(self, job, keep, dtype, n, m):
+        ev = None
+        if not self.simulate:
+            # the admission copy waits for the inputs' writes on this stream
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream(keep[0].device))
+            job.ready_event = ev.cuda_event
         t = C.c_uint64()
         _check(lib.rplu_server_submit(self.handle, C.byref(job), C.byref(t)), "rplu_server_submit")
-        self._pending[t.value] = keep
+        self._pending[t.value] = (keep, ev, dtype, n, m)
         return t.value
 
     def submit_dense(self, A: torch.Tensor, k: int = 0, tol: float = 0.0, seed: int = 0,
-                     stream: int = 0, store_L: bool = True, store_U: bool = True,
-                     flags: int = 0) -> int:
-        """A is read (never modified); it must stay valid until poll returns."""
+                     stream: int = 0, flags: int = 0) -> int:
+        """A is read (never modified); it must stay valid until poll returns.
+        flags: RPLU_FLAG_STALL_STOP, RPLU_FLAG_REFRESH, RPLU_FLAG_CERTIFY."""
         if A.dim() != 2 or A.stride(1) != 1 or A.dtype not in _DTYPES:
-            raise ValueError("A: 2-D CUDA tensor with unit column stride")
+            raise ValueError("A: 2-D tensor with unit column stride")
         n, m = A.shape
-        kmax = min(n, m) if k <= 0 else min(k, n, m)
-        piv = torch.empty((kmax, 2), dtype=torch.int32, device=A.device)
-        Lt = torch.empty((kmax, n), dtype=A.dtype, device=A.device) if store_L else None
-        U = torch.empty((kmax, m), dtype=A.dtype, device=A.device) if store_U else None
         j = rplu_job()
         j.kind, j.dtype, j.n, j.m, j.A, j.lda = RPLU_JOB_DENSE, _DTYPES[A.dtype], n, m, A.data_ptr(), A.stride(0)
-        j.piv = piv.data_ptr()
-        j.L, j.ldl = (Lt.data_ptr(), n) if Lt is not None else (None, 0)
-        j.U, j.ldu = (U.data_ptr(), m) if U is not None else (None, 0)
+        j.piv, j.L, j.U = None, None, None
         j.max_rank, j.rel_tol = int(k), float(tol)
         j.seed, j.stream = int(seed) & (2**64 - 1), int(stream) & (2**64 - 1)
         j.flags = int(flags)
-        return self._submit(j, (A, piv, Lt, U))
+        return self._submit(j, (A,), A.dtype, n, m)
 
     def submit_cauchy(self, x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
-                      stream: int = 0, store_L: bool = True, store_U: bool = True,
-                      flags: int = 0) -> int:
+                      stream: int = 0, flags: int = 0) -> int:
         """x, y, G, B are read (never modified); they must stay valid until poll returns."""
         n, m, p = x.shape[0], y.shape[0], G.shape[1]
         for t_ in (x, y, G, B):
             if t_.dtype != torch.complex128 or not t_.is_contiguous():
-                raise ValueError("x, y, G, B: contiguous complex128 CUDA tensors")
-        kmax = min(n, m) if k <= 0 else min(k, n, m)
-        dev = x.device
-        piv = torch.empty((kmax, 2), dtype=torch.int32, device=dev)
-        Lt = torch.empty((kmax, n), dtype=torch.complex128, device=dev) if store_L else None
-        U = torch.empty((kmax, m), dtype=torch.complex128, device=dev) if store_U else None
+                raise ValueError("x, y, G, B: contiguous complex128 tensors")
         j = rplu_job()
         j.kind, j.dtype, j.n, j.m, j.p = RPLU_JOB_CAUCHY, RPLU_C128, n, m, p
         j.x, j.y, j.G, j.B = x.data_ptr(), y.data_ptr(), G.data_ptr(), B.data_ptr()
-        j.piv = piv.data_ptr()
-        j.L, j.ldl = (Lt.data_ptr(), n) if Lt is not None else (None, 0)
-        j.U, j.ldu = (U.data_ptr(), m) if U is not None else (None, 0)
+        j.piv, j.L, j.U = None, None, None
         j.max_rank, j.rel_tol = int(k), float(tol)
         j.seed, j.stream = int(seed) & (2**64 - 1), int(stream) & (2**64 - 1)
         j.flags = int(flags)
-        return self._submit(j, (x, y, G, B, piv, Lt, U))
+        return self._submit(j, (x, y, G, B), torch.complex128, n, m)
 
-    def poll(self, ticket: int):
+    def poll(self, ticket: int, fetch: bool = True):
+        """None while pending; else the Result. fetch=False returns the info
+        only (no factors) and releases the job's outputs at once."""
         info = rplu_info()
         st = lib.rplu_server_poll(self.handle, int(ticket), C.byref(info))
         if st == RPLU_PENDING:
             return None
-        keep = self._pending.pop(ticket, None)
+        keep, ev, dtype, n, m = self._pending.pop(ticket, (None, None, None, 0, 0))
         if st < 0:
             raise RPLUError(st, "rplu_server_poll")
         r = int(info.rank)
-        piv, Lt, U = keep[-3], keep[-2], keep[-1]
-        return Result(piv[:r], Lt[:r].T if Lt is not None else None, U[:r] if U is not None else None,
-                      r, int(info.stop), float(info.a_fro2), float(info.res_fro2), status=int(st))
+        res = Result(None, None, None, r, int(info.stop), float(info.a_fro2),
+                     float(info.res_fro2), status=int(st))
+        res.err_fro2 = float(info.err_fro2)
+        res.refreshes = int(info.refreshes)
+        res.first_refresh = int(info.first_refresh)
+        if self.simulate or not fetch:
+            _check(lib.rplu_server_release(self.handle, int(ticket)), "rplu_server_release")
+            return res
+        piv_p, L_p, U_p = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        ldl, ldu = C.c_int64(), C.c_int64()
+        _check(lib.rplu_server_outputs(self.handle, int(ticket), C.byref(piv_p), C.byref(L_p),
+                                       C.byref(ldl), C.byref(U_p), C.byref(ldu)),
+               "rplu_server_outputs")
+        dev = keep[0].device
+        es = torch.empty((), dtype=dtype).element_size()
+        piv = torch.empty((r, 2), dtype=torch.int32, device=dev)
+        Lt = torch.empty((r, n), dtype=dtype, device=dev)
+        U = torch.empty((r, m), dtype=dtype, device=dev)
+        cur = torch.cuda.current_stream(dev).cuda_stream
+        if r:
+            for dst, src, nbytes in ((piv, piv_p, r * 2 * 4), (Lt, L_p, r * n * es),
+                                     (U, U_p, r * m * es)):
+                _hip_check(_hip.hipMemcpyAsync(C.c_void_p(dst.data_ptr()), src,
+                                               C.c_size_t(nbytes), 3, C.c_void_p(cur)))
+            _hip_check(_hip.hipStreamSynchronize(C.c_void_p(cur)))
+        _check(lib.rplu_server_release(self.handle, int(ticket)), "rplu_server_release")
+        res.piv, res.L, res.U = piv, Lt.T, U
+        return res
 
     def stats(self) -> dict:
         s = rplu_server_stats_t()

@@ -99,12 +99,16 @@ static rplu_status read_state(rplu_ctx_s* ctx, const StepState* st, hipStream_t 
     return RPLU_OK;
 }
 
-static rplu_status finish(const StepState& hs, rplu_info* info) {
+static rplu_status finish(const StepState& hs, rplu_info* info, int refreshes = 0,
+                          int first_refresh = -1) {
     info->rank = hs.t;
     info->stop = hs.stop;
     info->status = hs.error;
     info->a_fro2 = hs.T0;
     info->res_fro2 = hs.T;
+    info->err_fro2 = -1.0;
+    info->refreshes = refreshes;
+    info->first_refresh = first_refresh;
     switch (hs.error) {
         case 0: return RPLU_OK;
         case RPLU_E_NONFINITE: return fail(RPLU_E_NONFINITE, "non-finite mass or pivot at step %d", hs.t);
@@ -226,10 +230,10 @@ static rplu_status run_loop(rplu_ctx_s* ctx, StepState* st, int64_t steps_total,
 // Work split of an all-pairs mass pass with `rows` targets and `cols`
 // sources: enough workgroups to fill every CU a few times over, columns per
 // split a multiple of the 8-column reciprocal group.
-static void cauchy_mass_layout(rplu_ctx_s* ctx, int64_t rows, int64_t cols, int64_t* splits_out,
+static void cauchy_mass_layout(int cu_count, int64_t rows, int64_t cols, int64_t* splits_out,
                                int64_t* cps_out) {
     const int64_t nbr = (rows + cauchy_rows_per_block() - 1) / cauchy_rows_per_block();
-    int64_t splits = (4 * (int64_t)ctx->cu_count + nbr - 1) / nbr;
+    int64_t splits = (4 * (int64_t)cu_count + nbr - 1) / nbr;
     splits = std::max<int64_t>(1, std::min<int64_t>(splits, std::max<int64_t>(1, cols / 256)));
     int64_t cps = (cols + splits - 1) / splits;
     cps = (cps + 7) / 8 * 8;
@@ -287,6 +291,15 @@ rplu_status dense_check(const char* who, int dtype, int64_t n, int64_t m, const 
     if (n > RPLU_MAX_DIM || m > RPLU_MAX_DIM)
         return fail(RPLU_E_UNSUPPORTED, "%s: n and m must be <= %lld", who,
                     (long long)RPLU_MAX_DIM);
+    if (opts->flags & RPLU_FLAG_REFRESH) {
+        if (dtype != RPLU_R32 && dtype != RPLU_R64)
+            return fail(RPLU_E_UNSUPPORTED, "%s: RPLU_FLAG_REFRESH needs R32 or R64", who);
+        if (opts->flags & RPLU_FLAG_COLMASS)
+            return fail(RPLU_E_UNSUPPORTED, "%s: RPLU_FLAG_REFRESH with RPLU_FLAG_COLMASS", who);
+        if (opts->A_orig == nullptr || opts->lda_orig < m || L == nullptr || U == nullptr)
+            return fail(RPLU_E_ARG, "%s: RPLU_FLAG_REFRESH needs A_orig (lda_orig >= m), L and U",
+                        who);
+    }
     return RPLU_OK;
 }
 
@@ -330,7 +343,8 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
     a.kmax = kmax;
     a.tol2 = opts->rel_tol * opts->rel_tol;
 
-    launch_state_init(a.st, s);
+    const bool refresh = (opts->flags & RPLU_FLAG_REFRESH) != 0;
+    launch_state_init(a.st, s, refresh ? 1 : 0);
     timed(ctx, 3, s, [&] { launch_dense_sweep(a, /*init=*/true, s); });
     if (colmass && a.colmass_out) launch_colmass_reduce(a, false, s);
     hipError_t e = hipGetLastError();
@@ -362,7 +376,7 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
 
     const bool graph = ctx != nullptr && !(opts->flags & RPLU_FLAG_NO_GRAPH);
     const uint64_t key = fnv1a(&sa, sizeof sa, fnv1a(&a, sizeof a, 0x64656e7365ull));
-    rplu_status rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
+    auto step = [&](hipStream_t q) {
         timed(ctx, 1, q, [&] {
             if (sa.fused) {
                 launch_dense_pivot(a, sa, q);
@@ -374,6 +388,201 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
         timed(ctx, 0, q, [&] { launch_dense_sweep(a, /*init=*/false, q); });
         if (colmass && a.colmass_out)
             timed(ctx, 2, q, [&] { launch_colmass_reduce(a, true, q); });
+    };
+    rplu_status rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, step);
+    if (rc) return rc;
+    StepState hs;
+    rc = read_state(ctx, a.st, s, &hs);
+    if (rc) return rc;
+    // RPLU_FLAG_REFRESH: when a replacement is due (the device stopped with
+    // RPLU_STOP_REFRESH) or the stall rule fired above the tolerance, the run
+    // goes on from the true residual A_orig - L U (formed in FP64)
+    // A tolerance stop reached on a swept (not replaced) S is checked the same
+    // way: the replaced residual's total is the true error of the factors, so
+    // the run stops at once when that is within the tolerance, else goes on.
+    int r = 0, first = -1, t_last = -1;
+    for (; refresh && r < RPLU_MAX_REFRESH && hs.error == 0 && hs.t < kmax &&
+           (hs.stop == RPLU_STOP_REFRESH || hs.stop == RPLU_STOP_STALL ||
+            (hs.stop == RPLU_STOP_TOL && hs.t > t_last));
+         ++r) {
+        if (r == 0) first = hs.t;
+        t_last = hs.t;
+        RefreshArgs ra;
+        std::memset(&ra, 0, sizeof ra);
+        ra.dtype = dtype;
+        ra.n = n;
+        ra.m = m;
+        ra.t = hs.t;
+        ra.A = opts->A_orig;
+        ra.lda = opts->lda_orig;
+        ra.L = L;
+        ra.ldl = ldl;
+        ra.U = U;
+        ra.ldu = ldu;
+        ra.S = A;
+        ra.lds = lda;
+        ra.piv = piv;
+        launch_refresh(ra, s);
+        timed(ctx, 3, s, [&] { launch_dense_sweep(a, /*init=*/true, s); });
+        launch_state_resume(a.st, r + 1 < RPLU_MAX_REFRESH ? 1 : 0, s);
+        hipError_t e2 = hipGetLastError();
+        if (e2 != hipSuccess) return hip_fail(e2, "residual replacement launch");
+        rc = run_loop(ctx, a.st, kmax + 1 - hs.t, graph, key, s, step);
+        if (rc) return rc;
+        rc = read_state(ctx, a.st, s, &hs);
+        if (rc) return rc;
+    }
+    return finish(hs, info, r, first);
+}
+
+
+// Cauchy-like run: argument checks, workspace layout and the step loop on a
+// given workspace (the server places it in a job's slot).
+rplu_status cauchy_check(const char* who, int dtype, int64_t n, int64_t m, int p, const void* x,
+                         const void* y, const void* G, const void* B, const rplu_opts* opts,
+                         const int32_t* piv, const void* L, int64_t ldl, const void* U,
+                         int64_t ldu, const rplu_info* info) {
+    if (opts == nullptr || info == nullptr)
+        return fail(RPLU_E_ARG, "%s: opts and info are required", who);
+    if (dtype != RPLU_C128) return fail(RPLU_E_UNSUPPORTED, "%s: only RPLU_C128", who);
+    if (n < 1 || m < 1 || n > INT32_MAX || m > INT32_MAX)
+        return fail(RPLU_E_ARG, "%s: shape out of range", who);
+    if (p < 1 || p > 4) return fail(RPLU_E_UNSUPPORTED, "%s: p must be in [1, 4]", who);
+    if (!x || !y || !G || !B || !piv)
+        return fail(RPLU_E_ARG, "%s: x, y, G, B and piv are required", who);
+    if (L != nullptr && ldl < n) return fail(RPLU_E_ARG, "%s: ldl < n", who);
+    if (U != nullptr && ldu < m) return fail(RPLU_E_ARG, "%s: ldu < m", who);
+    if (opts->rel_tol < 0 || !(opts->rel_tol == opts->rel_tol))
+        return fail(RPLU_E_ARG, "%s: rel_tol must be >= 0", who);
+    if (opts->colmass_out != nullptr && !(opts->flags & RPLU_FLAG_COLMASS))
+        return fail(RPLU_E_ARG, "%s: colmass_out needs RPLU_FLAG_COLMASS", who);
+    if (opts->flags & RPLU_FLAG_REFRESH)
+        return fail(RPLU_E_UNSUPPORTED, "%s: RPLU_FLAG_REFRESH is for dense runs", who);
+    if (n > RPLU_MAX_DIM || m > RPLU_MAX_DIM)
+        return fail(RPLU_E_UNSUPPORTED, "%s: n and m must be <= %lld", who,
+                    (long long)RPLU_MAX_DIM);
+    return RPLU_OK;
+}
+
+CauchyWs cauchy_ws_layout(int cu_count, int64_t n, int64_t m, int p, uint32_t flags,
+                          bool colmass, bool need_u) {
+    (void)flags;
+    CauchyWs w;
+    cauchy_mass_layout(cu_count, n, m, &w.splits, &w.cps);
+    if (colmass) cauchy_mass_layout(cu_count, m, n, &w.splits_c, &w.cps_c);
+    Carver cv;
+    w.o_st = cv.take(sizeof(StepState));
+    w.o_rm = cv.take((size_t)n * 8);
+    w.o_pa = cv.take((size_t)n * w.splits * 8);
+    w.o_ctr = cv.take((size_t)cdf_chunks((int)n) * 8);
+    w.o_ctc = cv.take((size_t)cdf_chunks((int)m) * 8);
+    w.o_u = need_u ? cv.take((size_t)m * 16) : 0;
+    w.o_mc = cv.take(cauchy_mass_col_bytes(p, m));
+    w.o_mf = cv.take(cauchy_mass_frame_bytes(p));
+    w.o_pc = colmass ? cv.take((size_t)m * w.splits_c * 8) : 0;
+    w.o_gt = (colmass && p > 1) ? cv.take((size_t)n * p * 16) : 0;
+    w.o_bt = (colmass && p > 1) ? cv.take((size_t)m * p * 16) : 0;
+    w.total = cv.off;
+    return w;
+}
+
+rplu_status cauchy_run(rplu_ctx_s* ctx, char* ws, int64_t n, int64_t m, int p, const void* x,
+                       const void* y, void* G, void* B, const rplu_opts* opts, int32_t* piv,
+                       void* L, int64_t ldl, void* U, int64_t ldu, rplu_info* info,
+                       hipStream_t s) {
+    const bool colmass = opts->colmass_out != nullptr;
+    const int64_t kmax = kmax_of(n, m, opts->max_rank);
+    const CauchyWs w = cauchy_ws_layout(ctx->cu_count, n, m, p, opts->flags, colmass, U == nullptr);
+    CauchyArgs a;
+    std::memset(&a, 0, sizeof a);        // padding too: the struct keys the graph cache
+    a.splits = (int)w.splits;
+    a.cols_per_split = (int)w.cps;
+    char* wsb = ws;
+    a.n = n;
+    a.m = m;
+    a.p = p;
+    a.mcol = (p == 1) ? (void*)(wsb + w.o_mc) : nullptr;
+    a.mframe = (p == 1) ? (void*)(wsb + w.o_mf) : nullptr;
+    a.x = x;
+    a.y = y;
+    a.G = G;
+    a.B = B;
+    a.U = U ? U : (void*)(wsb + w.o_u);
+    a.ldu = U ? ldu : 0;
+    a.L = L;
+    a.ldl = ldl;
+    a.piv = piv;
+    a.st = (StepState*)(wsb + w.o_st);
+    a.partial = (double*)(wsb + w.o_pa);
+    a.rowmass = (double*)(wsb + w.o_rm);
+    a.ct_col = (double*)(wsb + w.o_ctc);
+    a.colmass_out = opts->colmass_out;
+    a.trace = opts->trace;
+    a.forced = opts->forced;
+    a.seed = opts->seed;
+    a.stream = opts->stream;
+    a.kmax = kmax;
+    a.tol2 = opts->rel_tol * opts->rel_tol;
+
+    CauchyArgs ac;                       // the column pass
+    std::memset(&ac, 0, sizeof ac);
+    if (colmass) {
+        ac.n = m;
+        ac.m = n;
+        ac.p = p;
+        ac.x = y;
+        ac.y = x;
+        // for p = 1, B (1 x m) read as m x 1 is B^T and G (n x 1) read as 1 x n is G^T
+        ac.G = (p > 1) ? (void*)(wsb + w.o_bt) : B;     // B^T, m x p
+        ac.B = (p > 1) ? (void*)(wsb + w.o_gt) : G;     // G^T, p x n
+        ac.st = a.st;
+        ac.partial = (double*)(wsb + w.o_pc);
+        ac.splits = (int)w.splits_c;
+        ac.cols_per_split = (int)w.cps_c;
+    }
+
+    launch_state_init(a.st, s);
+    launch_cauchy_frame(a, s);
+    SampleArgs sa;
+    std::memset(&sa, 0, sizeof sa);
+    sa.dtype = RPLU_C128;
+    sa.p = p;
+    sa.n = n;
+    sa.m = m;
+    sa.rowmass = a.rowmass;
+    sa.ct_row = (double*)(wsb + w.o_ctr);
+    sa.ct_col = a.ct_col;
+    sa.st = a.st;
+    sa.piv = piv;
+    sa.U = a.U;
+    sa.ldu = a.ldu;
+    sa.G = G;
+    sa.B = B;
+    sa.seed = opts->seed;
+    sa.stream = opts->stream;
+    sa.kmax = kmax;
+    sa.tol2 = a.tol2;
+    sa.stall = (opts->flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
+    sa.greedy = (opts->flags & RPLU_FLAG_C2PLU) ? 1 : 0;
+    sa.forced = opts->forced;
+    sa.trace = opts->trace;
+    sa.rowmass_out = opts->rowmass_out;
+    const bool graph = !(opts->flags & RPLU_FLAG_NO_GRAPH);
+    const uint64_t key = fnv1a(&ac, sizeof ac, fnv1a(&sa, sizeof sa,
+                                                    fnv1a(&a, sizeof a, 0x636175636879ull)));
+    rplu_status rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
+        timed(ctx, 0, q, [&] { launch_cauchy_mass(a, q); });
+        if (colmass)
+            timed(ctx, 2, q, [&] {
+                if (p > 1) launch_cauchy_transpose(a, ac.B, ac.G, q);
+                launch_cauchy_mass(ac, q);
+                launch_colmass_sum(ac.partial, ac.splits, m, a.st, a.colmass_out, m, kmax, q);
+            });
+        timed(ctx, 1, q, [&] {
+            launch_cauchy_reduce_draw(a, sa, q);
+            launch_cauchy_rowgen_draw(a, sa, q);
+        });
+        timed(ctx, 2, q, [&] { launch_cauchy_update(a, q); });
     });
     if (rc) return rc;
     StepState hs;
@@ -381,6 +590,7 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
     if (rc) return rc;
     return finish(hs, info);
 }
+
 
 }  // namespace rplu
 
@@ -541,144 +751,18 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
                         const void* x, const void* y, void* G, void* B, const rplu_opts* opts,
                         int32_t* piv, void* L, int64_t ldl, void* U, int64_t ldu,
                         rplu_info* info, void* hip_stream) {
-    if (ctx == nullptr || opts == nullptr || info == nullptr)
-        return fail(RPLU_E_ARG, "rplu_cauchy: ctx, opts and info are required");
-    if (dtype != RPLU_C128) return fail(RPLU_E_UNSUPPORTED, "rplu_cauchy: only RPLU_C128");
-    if (n < 1 || m < 1 || n > INT32_MAX || m > INT32_MAX)
-        return fail(RPLU_E_ARG, "rplu_cauchy: shape out of range");
-    if (p < 1 || p > 4) return fail(RPLU_E_UNSUPPORTED, "rplu_cauchy: p must be in [1, 4]");
-    if (!x || !y || !G || !B || !piv)
-        return fail(RPLU_E_ARG, "rplu_cauchy: x, y, G, B and piv are required");
-    if (L != nullptr && ldl < n) return fail(RPLU_E_ARG, "rplu_cauchy: ldl < n");
-    if (U != nullptr && ldu < m) return fail(RPLU_E_ARG, "rplu_cauchy: ldu < m");
-    if (opts->rel_tol < 0 || !(opts->rel_tol == opts->rel_tol))
-        return fail(RPLU_E_ARG, "rplu_cauchy: rel_tol must be >= 0");
-    if (opts->colmass_out != nullptr && !(opts->flags & RPLU_FLAG_COLMASS))
-        return fail(RPLU_E_ARG, "rplu_cauchy: colmass_out needs RPLU_FLAG_COLMASS");
-    const bool colmass = opts->colmass_out != nullptr;
+    if (ctx == nullptr) return fail(RPLU_E_ARG, "rplu_cauchy: ctx is required");
+    rplu_status rc = cauchy_check("rplu_cauchy", dtype, n, m, p, x, y, G, B, opts, piv, L, ldl, U,
+                                  ldu, info);
+    if (rc) return rc;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
-    const int64_t kmax = kmax_of(n, m, opts->max_rank);
-
-    if (n > RPLU_MAX_DIM || m > RPLU_MAX_DIM)
-        return fail(RPLU_E_UNSUPPORTED, "rplu_cauchy: n and m must be <= %d", RPLU_MAX_DIM);
-    CauchyArgs a;
-    std::memset(&a, 0, sizeof a);        // padding too: the struct keys the graph cache
-    int64_t splits, cps;
-    cauchy_mass_layout(ctx, n, m, &splits, &cps);
-    a.splits = (int)splits;
-    a.cols_per_split = (int)cps;
-    // optional column masses: the same all-pairs pass with rows and columns
-    // exchanged (targets y_j with B_:,j, sources x_i with G_i,:)
-    int64_t splits_c = 0, cps_c = 0;
-    if (colmass) cauchy_mass_layout(ctx, m, n, &splits_c, &cps_c);
-    Carver cv;
-    const size_t o_st = cv.take(sizeof(StepState));
-    const size_t o_rm = cv.take((size_t)n * 8);
-    const size_t o_pa = cv.take((size_t)n * splits * 8);
-    const size_t o_ctr = cv.take((size_t)cdf_chunks((int)n) * 8);
-    const size_t o_ctc = cv.take((size_t)cdf_chunks((int)m) * 8);
-    const size_t o_u = (U == nullptr) ? cv.take((size_t)m * 16) : 0;
-    const size_t o_mc = cv.take(cauchy_mass_col_bytes(p, m));
-    const size_t o_mf = cv.take(cauchy_mass_frame_bytes(p));
-    const size_t o_pc = colmass ? cv.take((size_t)m * splits_c * 8) : 0;
-    const size_t o_gt = (colmass && p > 1) ? cv.take((size_t)n * p * 16) : 0;
-    const size_t o_bt = (colmass && p > 1) ? cv.take((size_t)m * p * 16) : 0;
-    rplu_status rc = ws_reserve(ctx, cv.off, s);
+    const CauchyWs w = cauchy_ws_layout(ctx->cu_count, n, m, p, opts->flags,
+                                        opts->colmass_out != nullptr, U == nullptr);
+    rc = ws_reserve(ctx, w.total, s);
     if (rc) return rc;
-    char* ws = (char*)ctx->ws;
-    a.n = n;
-    a.m = m;
-    a.p = p;
-    a.mcol = (p == 1) ? (void*)(ws + o_mc) : nullptr;
-    a.mframe = (p == 1) ? (void*)(ws + o_mf) : nullptr;
-    a.x = x;
-    a.y = y;
-    a.G = G;
-    a.B = B;
-    a.U = U ? U : (void*)(ws + o_u);
-    a.ldu = U ? ldu : 0;
-    a.L = L;
-    a.ldl = ldl;
-    a.piv = piv;
-    a.st = (StepState*)(ws + o_st);
-    a.partial = (double*)(ws + o_pa);
-    a.rowmass = (double*)(ws + o_rm);
-    a.ct_col = (double*)(ws + o_ctc);
-    a.colmass_out = opts->colmass_out;
-    a.trace = opts->trace;
-    a.forced = opts->forced;
-    a.seed = opts->seed;
-    a.stream = opts->stream;
-    a.kmax = kmax;
-    a.tol2 = opts->rel_tol * opts->rel_tol;
-
-    CauchyArgs ac;                       // the column pass
-    std::memset(&ac, 0, sizeof ac);
-    if (colmass) {
-        ac.n = m;
-        ac.m = n;
-        ac.p = p;
-        ac.x = y;
-        ac.y = x;
-        // for p = 1, B (1 x m) read as m x 1 is B^T and G (n x 1) read as 1 x n is G^T
-        ac.G = (p > 1) ? (void*)(ws + o_bt) : B;     // B^T, m x p
-        ac.B = (p > 1) ? (void*)(ws + o_gt) : G;     // G^T, p x n
-        ac.st = a.st;
-        ac.partial = (double*)(ws + o_pc);
-        ac.splits = (int)splits_c;
-        ac.cols_per_split = (int)cps_c;
-    }
-
-    launch_state_init(a.st, s);
-    launch_cauchy_frame(a, s);
-    SampleArgs sa;
-    std::memset(&sa, 0, sizeof sa);
-    sa.dtype = RPLU_C128;
-    sa.p = p;
-    sa.n = n;
-    sa.m = m;
-    sa.rowmass = a.rowmass;
-    sa.ct_row = (double*)(ws + o_ctr);
-    sa.ct_col = a.ct_col;
-    sa.st = a.st;
-    sa.piv = piv;
-    sa.U = a.U;
-    sa.ldu = a.ldu;
-    sa.G = G;
-    sa.B = B;
-    sa.seed = opts->seed;
-    sa.stream = opts->stream;
-    sa.kmax = kmax;
-    sa.tol2 = a.tol2;
-    sa.stall = (opts->flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
-    sa.greedy = (opts->flags & RPLU_FLAG_C2PLU) ? 1 : 0;
-    sa.forced = opts->forced;
-    sa.trace = opts->trace;
-    sa.rowmass_out = opts->rowmass_out;
-    const bool graph = !(opts->flags & RPLU_FLAG_NO_GRAPH);
-    const uint64_t key = fnv1a(&ac, sizeof ac, fnv1a(&sa, sizeof sa,
-                                                    fnv1a(&a, sizeof a, 0x636175636879ull)));
-    rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
-        timed(ctx, 0, q, [&] { launch_cauchy_mass(a, q); });
-        if (colmass)
-            timed(ctx, 2, q, [&] {
-                if (p > 1) launch_cauchy_transpose(a, ac.B, ac.G, q);
-                launch_cauchy_mass(ac, q);
-                launch_colmass_sum(ac.partial, ac.splits, m, a.st, a.colmass_out, m, kmax, q);
-            });
-        timed(ctx, 1, q, [&] {
-            launch_cauchy_reduce_draw(a, sa, q);
-            launch_cauchy_rowgen_draw(a, sa, q);
-        });
-        timed(ctx, 2, q, [&] { launch_cauchy_update(a, q); });
-    });
-    if (rc) return rc;
-    StepState hs;
-    rc = read_state(ctx, a.st, s, &hs);
-    if (rc) return rc;
-    return finish(hs, info);
+    return cauchy_run(ctx, (char*)ctx->ws, n, m, p, x, y, G, B, opts, piv, L, ldl, U, ldu, info, s);
 }
 
 }  // extern "C"

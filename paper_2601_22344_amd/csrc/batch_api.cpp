@@ -45,6 +45,10 @@ rplu_status prepare(int64_t count, const rplu_job* jobs, Prepared& P, const char
         if (!(j.rel_tol >= 0.0)) return fail(RPLU_E_ARG, "%s: job %lld: rel_tol must be >= 0", who, lb);
         if (j.flags & RPLU_FLAG_C2PLU)
             return fail(RPLU_E_ARG, "%s: job %lld: RPLU_FLAG_C2PLU is not available in batches", who, lb);
+        if ((j.flags & RPLU_FLAG_REFRESH) &&
+            (j.A_orig == nullptr || j.lda_orig < j.m || j.L == nullptr || j.U == nullptr))
+            return fail(RPLU_E_ARG, "%s: job %lld: RPLU_FLAG_REFRESH needs A_orig (lda_orig >= m), "
+                        "L and U", who, lb);
         const int64_t es = (int64_t)dtype_size(j.dtype);
         const int64_t mn = std::min(j.n, j.m);
         BatchJob& q = P.jobs[(size_t)b];
@@ -64,6 +68,7 @@ rplu_status prepare(int64_t count, const rplu_job* jobs, Prepared& P, const char
                 (j.U == nullptr || (((uintptr_t)j.U % 16 == 0) && ((j.ldu * es) % 16 == 0)));
         q.tol2 = j.rel_tol * j.rel_tol;
         q.stall = (j.flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
+        q.refresh_on = (j.flags & RPLU_FLAG_REFRESH) ? 1 : 0;
         q.seed = j.seed;
         q.stream = j.stream;
         P.maxn = std::max(P.maxn, q.n);
@@ -332,6 +337,29 @@ const rplu_tune_entry* lookup(const rplu_ctx_s* ctx, const Prepared& P) {
 }
 
 }  // namespace
+
+// Internal, for the server's step ticks: the BatchJob of one rplu_job (the
+// checks and decisions of rplu_batched), and one launch over given jobs.
+rplu_status batch_job_of(const rplu_job& j, BatchJob* out) {
+    Prepared P;
+    rplu_status rc = prepare(1, &j, P, "rplu_server");
+    if (rc) return rc;
+    *out = P.jobs[0];
+    return RPLU_OK;
+}
+
+rplu_status batch_launch_jobs(rplu_ctx_s* ctx, int dtype, const std::vector<BatchJob>& jobs,
+                              const rplu_batch_cfg& c, hipStream_t s, std::vector<BatchInfo>* out) {
+    Prepared P;
+    P.dtype = dtype;
+    P.jobs = jobs;
+    for (const BatchJob& q : jobs) {
+        P.maxn = std::max(P.maxn, q.n);
+        P.maxm = std::max(P.maxm, q.m);
+    }
+    return run_batch(ctx, P, c, s, out, nullptr);
+}
+
 }  // namespace rplu
 
 using namespace rplu;
@@ -382,6 +410,67 @@ rplu_status rplu_batched_ex(rplu_ctx ctx, int64_t count, const rplu_job* jobs,
     std::vector<BatchInfo> out;
     rc = run_batch(ctx, P, c, s, &out, nullptr);
     if (rc) return rc;
+    // RPLU_FLAG_REFRESH: jobs the stall rule stopped above their tolerance
+    // go on from the true residual, as in rplu_dense (a resumed launch over
+    // just those jobs, at most RPLU_MAX_REFRESH rounds)
+    std::vector<int32_t> refreshes((size_t)count, 0), first_ref((size_t)count, -1);
+    std::vector<int64_t> last_ref((size_t)count, -1);
+    for (int round = 0; round < RPLU_MAX_REFRESH; ++round) {
+        Prepared R;
+        R.dtype = P.dtype;
+        std::vector<int64_t> idx;
+        for (int64_t b = 0; b < count; ++b) {
+            const BatchInfo& o = out[(size_t)b];
+            const BatchJob& q = P.jobs[(size_t)b];
+            // a tolerance stop on a swept S (steps taken since the start or the
+            // last replacement) is checked on the replaced residual too
+            const bool tol_check = o.stop == RPLU_STOP_TOL && o.rank > last_ref[(size_t)b];
+            if (!(jobs[b].flags & RPLU_FLAG_REFRESH) || o.error != 0 || o.rank >= q.kmax ||
+                (o.stop != RPLU_STOP_STALL && o.stop != RPLU_STOP_REFRESH && !tol_check))
+                continue;
+            last_ref[(size_t)b] = o.rank;
+            RefreshArgs ra;
+            std::memset(&ra, 0, sizeof ra);
+            ra.dtype = P.dtype;
+            ra.n = q.n;
+            ra.m = q.m;
+            ra.t = o.rank;
+            ra.A = jobs[b].A_orig;
+            ra.lda = jobs[b].lda_orig;
+            ra.L = q.L;
+            ra.ldl = q.ldl;
+            ra.U = q.U;
+            ra.ldu = q.ldu;
+            ra.S = q.A;
+            ra.lds = q.lda;
+            ra.piv = q.piv;
+            launch_refresh(ra, s);
+            BatchJob r = q;
+            r.t0 = (int32_t)o.rank;
+            r.t_end = 0;
+            r.T0_in = o.a_fro2;
+            r.Tbest_in = -1.0;
+            r.Tref_in = -1.0;
+            r.refresh_on = refreshes[(size_t)b] + 1 < RPLU_MAX_REFRESH ? 1 : 0;
+            R.jobs.push_back(r);
+            R.maxn = std::max(R.maxn, r.n);
+            R.maxm = std::max(R.maxm, r.m);
+            idx.push_back(b);
+        }
+        if (idx.empty()) break;
+        hipError_t e2 = hipGetLastError();
+        if (e2 != hipSuccess) return hip_fail(e2, "residual replacement launch");
+        std::vector<BatchInfo> o2;
+        rplu_batch_cfg c2 = c;
+        c2.order = RPLU_ORDER_GIVEN;
+        rc = run_batch(ctx, R, c2, s, &o2, nullptr);
+        if (rc) return rc;
+        for (size_t q = 0; q < idx.size(); ++q) {
+            if (refreshes[(size_t)idx[q]] == 0) first_ref[(size_t)idx[q]] = R.jobs[q].t0;
+            out[(size_t)idx[q]] = o2[q];
+            refreshes[(size_t)idx[q]] += 1;
+        }
+    }
     rplu_status first = RPLU_OK;
     int64_t first_b = -1;
     for (int64_t b = 0; b < count; ++b) {
@@ -391,6 +480,9 @@ rplu_status rplu_batched_ex(rplu_ctx ctx, int64_t count, const rplu_job* jobs,
         inf.status = out[b].error;
         inf.a_fro2 = out[b].a_fro2;
         inf.res_fro2 = out[b].res_fro2;
+        inf.err_fro2 = -1.0;
+        inf.refreshes = refreshes[(size_t)b];
+        inf.first_refresh = first_ref[(size_t)b];
         if (out[b].error != 0 && first_b < 0) { first = out[b].error; first_b = b; }
     }
     if (first_b >= 0)

@@ -446,10 +446,16 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
     for (int e = m + threadIdx.x; e < SU; e += BT_THREADS) s_u[e] = Sc<T>::zero();
     __syncthreads();
     int nalive = n;
+    const int t0 = jb.t0;
+    // A resumed run (t0 > 0) starts with every row live: rows pivoted since
+    // the last residual replacement are exactly +0, get mass 0 from this
+    // pass and stay +0 under later updates (multiplier +-0, entries +0), so
+    // sweeping them changes no bit, while rows pivoted before a replacement
+    // hold the residual of the stored factors and must be swept.
     bt_pass<T, R, V, true>(S, lda, m, -1, -1, s_l, nullptr, s_u, s_rm, s_alive, nalive);
     __syncthreads();
-    double T0 = 0.0, Tc = 0.0, Tbest = 0.0;
-    int t = 0, stop = 0, err = 0, prev_i = -1, tbest = 0;
+    double T0 = 0.0, Tc = 0.0, Tbest = 0.0, Tref = 0.0;
+    int t = t0, stop = 0, err = 0, prev_i = -1, tbest = 0;
     for (;; ++t) {
         if (prev_i >= 0) {
             // the previous pivot row leaves the live list (the barriers of
@@ -464,14 +470,27 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
         }
         auto rmass = [&](int e) { return s_rm[e]; };
         Tc = bt_levels(n, sh.ctr, rmass, sh);
-        if (t == 0) { T0 = Tc; Tbest = Tc; tbest = 0; }
+        if (t == 0) { T0 = Tc; Tbest = Tc; tbest = 0; Tref = Tc; }
+        else if (t == t0) {
+            T0 = jb.T0_in;
+            Tref = jb.Tref_in < 0.0 ? Tc : jb.Tref_in;
+            if (jb.Tbest_in < 0.0) { Tbest = Tc; tbest = t; }
+            else {
+                Tbest = jb.Tbest_in;
+                tbest = jb.tbest_in;
+                if (Tc < RPLU_STALL_RATIO * Tbest) { Tbest = Tc; tbest = t; }
+            }
+        }
         else if (Tc < RPLU_STALL_RATIO * Tbest) { Tbest = Tc; tbest = t; }
         if (!isfinite(Tc)) err = RPLU_E_NONFINITE;
         else if (Tc == 0.0) stop = RPLU_STOP_EXHAUSTED;
         else if (jb.tol2 > 0.0 && Tc <= jb.tol2 * T0) stop = RPLU_STOP_TOL;
+        else if (jb.refresh_on && t < jb.kmax && Tc <= RPLU_REFRESH_DROP2 * Tref)
+            stop = RPLU_STOP_REFRESH;
         else if (jb.stall && t - tbest >= RPLU_STALL_WINDOW) stop = RPLU_STOP_STALL;
         else if (t >= jb.kmax) stop = jb.tol2 > 0.0 ? RPLU_STOP_TOL_UNREACHED : RPLU_STOP_RANK;
         if (err || stop) break;
+        if (jb.t_end > t0 && t >= jb.t_end) break;      // paused: resumed by a later launch
         const Philox4 rnd = philox4x64_10((uint64_t)t, jb.stream, 0, 0, jb.seed, 0);
         const CdfPick pr = bt_draw(n, sh.ctr, rmass, unit_from_word(rnd.w[0]) * Tc, sh);
         const int i = pr.idx;
@@ -517,6 +536,9 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
         info->error = err;
         info->a_fro2 = T0;
         info->res_fro2 = Tc;
+        info->T_best = Tbest;
+        info->T_ref = Tref;
+        info->t_best = tbest;
     }
 }
 

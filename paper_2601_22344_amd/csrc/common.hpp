@@ -259,6 +259,10 @@ struct StepState {
     uint32_t arrive;    // workgroups of the running wide draw kernel that
                         // are done (0 between launches)
     uint32_t pad3;
+    double T_ref;       // RPLU_FLAG_REFRESH: the total at the start or at the
+                        // last residual replacement (inf: take the next one)
+    int32_t refresh_on; // replacements left to trigger (0 or 1)
+    int32_t pad4;
 };
 
 }  // namespace rplu

@@ -74,7 +74,8 @@ struct SampleArgs {
     int greedy;          // RPLU_FLAG_C2PLU: the largest masses instead of the draws
 };
 
-void launch_state_init(StepState* st, hipStream_t s);
+void launch_state_init(StepState* st, hipStream_t s, int refresh_on = 0);
+void launch_state_resume(StepState* st, int refresh_on, hipStream_t s);
 void launch_rows_draw(const SampleArgs& a, hipStream_t s);
 
 void launch_dense_sweep(const DenseArgs& a, bool init, hipStream_t s);
@@ -133,20 +134,33 @@ struct BatchJob {
     void* A;             // n x m row-major, lda
     void* L;             // n x kmax col-major (ldl), or null
     void* U;             // kmax x m row-major (ldu), or null: a per-workgroup row
-    int32_t* piv;        // 2 * kmax, or null
+    int32_t* piv;        // 2 * kmax, or null (required when t0 > 0)
     int64_t lda, ldl, ldu;
     int32_t n, m, kmax;
     int32_t vec;         // 16-byte packs aligned for A and U (as rplu_dense decides)
     int32_t stall;       // RPLU_FLAG_STALL_STOP
-    int32_t pad;
+    // Resumption (the server's step ticks): the run starts at step t0 on an A
+    // that already holds S^(t0) (pivots 0..t0-1 in piv), with the original
+    // total T0_in and the stall state (Tbest_in, tbest_in; Tbest_in < 0:
+    // restart the stall window at t0), and pauses (stop 0) when it reaches
+    // step t_end > t0 without another stop. t0 = t_end = 0: a whole run.
+    int32_t t0, t_end;
+    int32_t tbest_in;
+    int32_t refresh_on;  // RPLU_FLAG_REFRESH with replacements left: stop with
+                         // RPLU_STOP_REFRESH when T <= RPLU_REFRESH_DROP2 T_ref
+    double Tbest_in, T0_in;
+    double Tref_in;      // T_ref at t0 (< 0: take the total at t0)
     double tol2;
     uint64_t seed, stream;
 };
 
 struct BatchInfo {
     int64_t rank;
-    int32_t stop, error;
+    int32_t stop, error;    // stop 0 and no error: paused at t_end
     double a_fro2, res_fro2;
+    double T_best;          // stall and replacement state at the last stop test
+    double T_ref;           // (for resumption)
+    int32_t t_best, pad;
 };
 
 struct BatchLaunch {
@@ -181,6 +195,25 @@ struct VerifyArgs {
     double* out;         // 3
 };
 void launch_verify(const VerifyArgs& a, hipStream_t s);
+
+// Residual replacement (verify.hip): S = A - L(:,0:t) U(0:t,:) formed in FP64
+// with the matrix cores and rounded to the element type, every entry (the
+// rows and columns of earlier pivots keep the rounding errors the stored
+// factors leave there, so the total of S is the error of the factors).
+struct RefreshArgs {
+    int dtype;           // RPLU_R32 or RPLU_R64
+    int64_t n, m, t;
+    const void* A;       // the original matrix, lda
+    int64_t lda;
+    const void* L;       // n x >= t column-major (ldl)
+    int64_t ldl;
+    const void* U;       // >= t x m row-major (ldu)
+    int64_t ldu;
+    void* S;             // n x m row-major (lds), overwritten
+    int64_t lds;
+    const int32_t* piv;  // 2 t (unused)
+};
+void launch_refresh(const RefreshArgs& a, hipStream_t s);
 int64_t verify_tiles(int64_t n, int64_t m);
 size_t batched_lds_bytes(int dtype, int maxn);
 constexpr size_t BT_STATIC_LDS = 8192;   // bound on k_batched's static LDS (checked there)

@@ -50,12 +50,12 @@ struct PivotArgs {
 // a draw kernel (only earlier kernels write it), and the step's two Philox
 // words: neither depends on the masses, so both are ready before the draw.
 struct StopInputs {
-    double T0, T_best;
-    int t_best;
+    double T0, T_best, T_ref;
+    int t_best, refresh_on;
 };
 
 __device__ inline StopInputs stop_inputs(const StepState* st) {
-    return {st->T0, st->T_best, st->t_best};
+    return {st->T0, st->T_best, st->T_ref, st->t_best, st->refresh_on};
 }
 
 __device__ inline Philox4 step_words(const PivotArgs& a, int t) {
@@ -76,9 +76,15 @@ __device__ inline int pivot_stop_test(StepState* st, int t, double T, int kmax, 
         st->T_best = T_best;
         st->t_best = t_best;
     }
+    double T_ref = in.T_ref;
+    if (in.refresh_on && (t == 0 || !(T_ref < __builtin_inf()))) {
+        T_ref = T;
+        st->T_ref = T;
+    }
     if (!isfinite(T)) err = RPLU_E_NONFINITE;
     else if (T == 0.0) stop = RPLU_STOP_EXHAUSTED;
     else if (tol2 > 0.0 && T <= tol2 * T0) stop = RPLU_STOP_TOL;
+    else if (in.refresh_on && t < kmax && T <= RPLU_REFRESH_DROP2 * T_ref) stop = RPLU_STOP_REFRESH;
     else if (stall && t - t_best >= RPLU_STALL_WINDOW) stop = RPLU_STOP_STALL;
     else if (t >= kmax) stop = tol2 > 0.0 ? RPLU_STOP_TOL_UNREACHED : RPLU_STOP_RANK;
     st->T = T;

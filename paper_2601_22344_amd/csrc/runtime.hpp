@@ -97,6 +97,27 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
                       int64_t lda, const rplu_opts* opts, int32_t* piv, void* L, int64_t ldl,
                       void* U, int64_t ldu, rplu_info* info, hipStream_t s);
 
+struct CauchyWs {
+    int64_t splits = 0, cps = 0, splits_c = 0, cps_c = 0;
+    size_t o_st, o_rm, o_pa, o_ctr, o_ctc, o_u, o_mc, o_mf, o_pc, o_gt, o_bt, total;
+};
+rplu_status cauchy_check(const char* who, int dtype, int64_t n, int64_t m, int p, const void* x,
+                         const void* y, const void* G, const void* B, const rplu_opts* opts,
+                         const int32_t* piv, const void* L, int64_t ldl, const void* U,
+                         int64_t ldu, const rplu_info* info);
+CauchyWs cauchy_ws_layout(int cu_count, int64_t n, int64_t m, int p, uint32_t flags,
+                          bool colmass, bool need_u);
+rplu_status cauchy_run(rplu_ctx_s* ctx, char* ws, int64_t n, int64_t m, int p, const void* x,
+                       const void* y, void* G, void* B, const rplu_opts* opts, int32_t* piv,
+                       void* L, int64_t ldl, void* U, int64_t ldu, rplu_info* info,
+                       hipStream_t s);
+
+struct BatchJob;
+struct BatchInfo;
+rplu_status batch_job_of(const rplu_job& j, BatchJob* out);
+rplu_status batch_launch_jobs(rplu_ctx_s* ctx, int dtype, const std::vector<BatchJob>& jobs,
+                              const rplu_batch_cfg& c, hipStream_t s, std::vector<BatchInfo>* out);
+
 // FNV-1a over raw bytes, for graph cache keys.
 inline uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
     const unsigned char* c = static_cast<const unsigned char*>(p);

@@ -29,17 +29,38 @@ __global__ __launch_bounds__(CDF_THREADS) void k_rows_draw(PivotArgs pa, double*
     pivot_row_draw_ct(sh.cdf, &sh.flag, pa, ct, t, wide_words(sh), in, RowMassGlobal{pa.rowmass});
 }
 
-__global__ void k_state_init(StepState* st) {
+__global__ void k_state_init(StepState* st, int refresh_on) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         StepState z{};
+        z.refresh_on = refresh_on;
         *st = z;
+    }
+}
+
+// After a residual replacement at step t (RPLU_FLAG_REFRESH): the run goes
+// on from t with the stall window and the replacement reference restarted
+// (inf: the next stop test records its total, at step t); refresh_on = 0
+// once no replacement is left.
+__global__ void k_state_resume(StepState* st, int refresh_on) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->done = 0;
+        st->stop = 0;
+        st->T_best = __builtin_inf();
+        st->t_best = st->t;
+        st->T_ref = __builtin_inf();
+        st->refresh_on = refresh_on;
+        st->arrive = 0;
     }
 }
 
 // ---------------------------------------------------------------- launchers
 
-void launch_state_init(StepState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st);
+void launch_state_resume(StepState* st, int refresh_on, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_resume, dim3(1), dim3(64), 0, s, st, refresh_on);
+}
+
+void launch_state_init(StepState* st, hipStream_t s, int refresh_on) {
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, refresh_on);
 }
 
 void launch_rows_draw(const SampleArgs& a, hipStream_t s) {

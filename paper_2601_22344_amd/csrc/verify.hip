@@ -1,4 +1,5 @@
-// Verification of a rank-k factorisation with FP64 matrix cores.
+// Verification of a rank-k factorisation with FP64 matrix cores, and the
+// residual replacement S := A - L U of a single-precision run.
 //
 // The residual after k steps is A^(k) = A - A_hat^(k) with A_hat^(k) = L U
 // (eqs. residual_update and approximation_update; Alg. 1 builds L(:,t) and
@@ -33,11 +34,15 @@ typedef double vf_d4 __attribute__((ext_vector_type(4)));
 template <class T>
 __device__ inline double vf_load(const T* p) { return (double)*p; }
 
-template <class T, bool WITH_S>
+// MODE 0: norms of A and E; 1: also ||E - S||; 2 (refresh): no norms, E
+// rounded to T is written to S (the residual replacement of a run that has
+// stalled in single precision).
+template <class T, int MODE>
 __global__ __launch_bounds__(VF_THREADS) void k_verify(
     int n, int m, int k, const T* __restrict__ A, int64_t lda, const T* __restrict__ L,
-    int64_t ldl, const T* __restrict__ U, int64_t ldu, const T* __restrict__ S, int64_t lds,
+    int64_t ldl, const T* __restrict__ U, int64_t ldu, const T* S, int64_t lds,
     double* __restrict__ partial) {
+    constexpr bool WITH_S = MODE == 1;
     __shared__ double sL[VF_KC][VF_TILE + VF_PAD];
     __shared__ double sU[VF_KC][VF_TILE + VF_PAD];
     __shared__ double sred[VF_THREADS / RPLU_WAVE][3];
@@ -92,6 +97,10 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(
                 if (row < n && col < m) {
                     const double av = vf_load(A + (int64_t)row * lda + col);
                     const double e = av - acc[i][j][r];
+                    if constexpr (MODE == 2) {
+                        const_cast<T*>(S)[(int64_t)row * lds + col] = (T)e;
+                        continue;
+                    }
                     sa = fma(av, av, sa);
                     se = fma(e, e, se);
                     if constexpr (WITH_S) {
@@ -100,6 +109,7 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(
                     }
                 }
             }
+    if constexpr (MODE == 2) return;
     sa = wave_sum(sa);
     se = wave_sum(se);
     ss = wave_sum(ss);
@@ -141,11 +151,11 @@ template <class T>
 static void verify_t(const VerifyArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((a.m + VF_TILE - 1) / VF_TILE), (unsigned)((a.n + VF_TILE - 1) / VF_TILE));
     if (a.S)
-        hipLaunchKernelGGL((k_verify<T, true>), grid, dim3(VF_THREADS), 0, s, (int)a.n, (int)a.m,
+        hipLaunchKernelGGL((k_verify<T, 1>), grid, dim3(VF_THREADS), 0, s, (int)a.n, (int)a.m,
                            (int)a.k, (const T*)a.A, a.lda, (const T*)a.L, a.ldl, (const T*)a.U,
                            a.ldu, (const T*)a.S, a.lds, a.partial);
     else
-        hipLaunchKernelGGL((k_verify<T, false>), grid, dim3(VF_THREADS), 0, s, (int)a.n, (int)a.m,
+        hipLaunchKernelGGL((k_verify<T, 0>), grid, dim3(VF_THREADS), 0, s, (int)a.n, (int)a.m,
                            (int)a.k, (const T*)a.A, a.lda, (const T*)a.L, a.ldl, (const T*)a.U,
                            a.ldu, (const T*)nullptr, (int64_t)0, a.partial);
     hipLaunchKernelGGL(k_verify_reduce, dim3(1), dim3(256), 0, s, a.partial,
@@ -155,6 +165,19 @@ static void verify_t(const VerifyArgs& a, hipStream_t s) {
 void launch_verify(const VerifyArgs& a, hipStream_t s) {
     if (a.dtype == RPLU_R64) verify_t<double>(a, s);
     else verify_t<float>(a, s);
+}
+
+template <class T>
+static void refresh_t(const RefreshArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)((a.m + VF_TILE - 1) / VF_TILE), (unsigned)((a.n + VF_TILE - 1) / VF_TILE));
+    hipLaunchKernelGGL((k_verify<T, 2>), grid, dim3(VF_THREADS), 0, s, (int)a.n, (int)a.m, (int)a.t,
+                       (const T*)a.A, a.lda, (const T*)a.L, a.ldl, (const T*)a.U, a.ldu,
+                       (const T*)a.S, a.lds, (double*)nullptr);
+}
+
+void launch_refresh(const RefreshArgs& a, hipStream_t s) {
+    if (a.dtype == RPLU_R64) refresh_t<double>(a, s);
+    else refresh_t<float>(a, s);
 }
 
 }  // namespace rplu

@@ -1,9 +1,10 @@
 """Queueing logic of the continuous-batching server, on the host only.
 
-RPLU_SERVER_SIMULATE runs the real admission, FIFO, slot pool, batching
-and statistics code with a stand-in executor (no device; a job "runs" for
-footprint / 1e10 s), so these tests need no GPU. Inputs are never read in
-this mode, so host tensors stand in for device buffers.
+RPLU_SERVER_SIMULATE runs the real admission, FIFO, slot pool, step-tick
+and statistics code with a stand-in executor (no device: a worker job "runs"
+for footprint / 1e10 s, a tick advances every resident small job by
+tick_steps steps for its share of that), so these tests need no GPU. Inputs
+are never read in this mode, so host tensors stand in for device buffers.
 """
 import time
 
@@ -19,8 +20,15 @@ def _dense(n, m=None, dtype=torch.float32):
     return torch.zeros((n, m or n), dtype=dtype)
 
 
-def _footprint(n, m, es=4):
-    return ((n * m * es + 16) + 255) // 256 * 256
+def _rup(v):
+    return (v + 255) // 256 * 256
+
+
+def _footprint(n, m, k=0, es=4):
+    """Work block (the input copy) plus the server-owned outputs (piv, L, U of
+    kmax steps); the dense workspace of a worker job adds a little more."""
+    kmax = min(n, m) if k <= 0 else min(k, n, m)
+    return _rup(n * m * es + 16) + _rup(kmax * 8) + _rup(n * kmax * es) + _rup(kmax * m * es)
 
 
 def _wait_all(S, tickets, timeout=30.0):
@@ -41,13 +49,14 @@ def test_all_jobs_complete_and_stats():
     S = rplu.Server(budget_bytes=64 * MB, workers=2, simulate=True)
     ts = [S.submit_dense(_dense(256 + 16 * q)) for q in range(20)]
     res = _wait_all(S, ts)
-    assert all(r.status == 0 and r.rank == 0 for r in res.values())
+    assert all(res[t].status == 0 and res[t].rank == 256 + 16 * q for q, t in enumerate(ts))
     st = S.stats()
     assert st["submitted"] == 20 and st["completed"] == 20 and st["rejected"] == 0
     assert st["queued"] == 0 and st["active"] == 0 and st["hbm_in_use"] == 0
     assert 0.0 <= st["p50_ms"] <= st["p99_ms"]
     assert st["p99_cauchy_ms"] == 0.0                 # no Cauchy jobs
-    assert st["batched_jobs"] == 20 and 1 <= st["batches"] <= 20
+    # every job goes through the step ticks: 256 steps / 32 per tick at least
+    assert st["tick_jobs"] == 20 and st["ticks"] >= 8
     S.close()
 
 
@@ -63,12 +72,12 @@ def test_poll_once_then_forgotten():
 
 
 def test_admission_by_footprint_is_fifo_and_bounded():
-    """Jobs of 40 MB in a 100 MB pool: at most two resident at once and the
-    pool never over-commits."""
+    """Jobs of about 42 MB (input copy, outputs and workspace) in a 100 MB
+    pool: at most two resident at once and the pool never over-commits."""
     n = 3240                                    # 3240^2 * 4 B ~ 40 MB
-    fp = _footprint(n, n)
+    fp = _footprint(n, n, k=64) + 2 * MB        # + the dense workspace (masses, totals)
     S = rplu.Server(budget_bytes=100 * MB, workers=3, batch_max_dim=1024, simulate=True)
-    ts = [S.submit_dense(_dense(n)) for _ in range(8)]
+    ts = [S.submit_dense(_dense(n), k=64) for _ in range(8)]
     peak_active, peak_bytes = 0, 0
     done = {}
     t0 = time.time()
@@ -84,7 +93,23 @@ def test_admission_by_footprint_is_fifo_and_bounded():
                     done[t] = time.time()
         assert time.time() - t0 < 30
     assert peak_active <= 2 and peak_bytes <= 2 * fp
-    assert S.stats()["batches"] == 0            # all above batch_max_dim: run alone
+    st = S.stats()
+    assert st["ticks"] == 0                     # all above batch_max_dim: run alone
+    assert st["hbm_peak"] <= 100 * MB and st["hbm_peak"] >= fp - 2 * MB
+    S.close()
+
+
+def test_footprint_counts_outputs_and_workspace():
+    """A dense job whose input copy alone fits the pool but whose outputs do
+    not is refused; the outputs are part of the footprint."""
+    n = 1024                                    # input copy 4 MB, L and U 8 MB at k = n
+    S = rplu.Server(budget_bytes=8 * MB, simulate=True)
+    with pytest.raises(rplu.RPLUError) as e:
+        S.submit_dense(_dense(n), k=0)
+    assert e.value.status == -1
+    t = S.submit_dense(_dense(n), k=64)         # 4 MB + 0.5 MB of outputs
+    _wait_all(S, [t])
+    assert S.stats()["hbm_in_use"] == 0         # output block released by poll
     S.close()
 
 
@@ -125,16 +150,23 @@ def test_job_larger_than_pool_is_refused():
     S.close()
 
 
-def test_small_jobs_ready_together_share_a_batch():
-    """While one worker is busy with a large job, small jobs pile up and the
-    next free worker runs them as one batch."""
-    S = rplu.Server(budget_bytes=2 << 30, workers=1, batch_max_dim=512, simulate=True)
-    big = S.submit_dense(_dense(16000), k=1)     # runs alone, ~0.1 s
-    time.sleep(0.02)
-    small = [S.submit_dense(_dense(128 + q)) for q in range(16)]
-    _wait_all(S, [big] + small)
+def test_small_jobs_join_the_ticks_while_a_large_job_runs():
+    """Step-level batching: small jobs do not wait for a large job on the only
+    worker; they are admitted into the resident set and finish in ticks while
+    it still runs, and jobs arriving later join at a tick boundary."""
+    S = rplu.Server(budget_bytes=2 << 30, workers=1, batch_max_dim=512, tick_steps=16,
+                    simulate=True)
+    big = S.submit_dense(_dense(16000), k=1)     # runs alone on the worker, ~0.1 s
+    time.sleep(0.01)
+    first = [S.submit_dense(_dense(128 + q), k=64) for q in range(8)]
+    time.sleep(0.002)
+    later = [S.submit_dense(_dense(200 + q), k=64) for q in range(8)]
+    res = _wait_all(S, first + later)
+    assert all(r.rank == 64 for r in res.values())
+    assert S.poll(big) is None                   # the large job is still running
     st = S.stats()
-    assert st["batched_jobs"] == 16 and st["batches"] == 1
+    assert st["tick_jobs"] == 16 and st["ticks"] >= 4     # 64 steps / 16 per tick
+    _wait_all(S, [big])
     S.close()
 
 
@@ -147,7 +179,7 @@ def test_destroy_drains():
     for _ in range(6):
         S.submit_dense(A, k=1)
     S.close()
-    assert time.time() - t0 >= 0.9 * 3 * _footprint(3000, 3000) / 1e10
+    assert time.time() - t0 >= 0.9 * 3 * _footprint(3000, 3000, k=1) / 1e10
 
 
 def test_cauchy_jobs_counted_per_class():
