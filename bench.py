@@ -63,7 +63,7 @@ def _source_sha() -> str:
 
 
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
-HOT_KERNEL = {"cauchy20k": "k_cauchy_mass", "dense32k": "k_dense_sweep",
+HOT_KERNEL = {"cauchy20k": "k_cauchy_mass", "dense32k": "k_dense_lazy",
               "dense512": "k_dense_sweep", "batched4096": "k_batched"}
 CALIBRATION_BYTES = 1 << 30
 
@@ -98,8 +98,8 @@ def _calibrate_copy() -> int:
 
 
 def _pmc_rows(d: str):
-    """(kernel name, counter name, value) rows of every counter_collection
-    CSV that rocprofv3 wrote under directory d."""
+    """(dispatch id, kernel name, counter name, value) rows of every
+    counter_collection CSV that rocprofv3 wrote under directory d."""
     import csv
     rows = []
     for root, _, files in os.walk(d):
@@ -107,16 +107,15 @@ def _pmc_rows(d: str):
             if f.endswith("counter_collection.csv"):
                 with open(os.path.join(root, f)) as fh:
                     for r in csv.DictReader(fh):
-                        rows.append((r.get("Kernel_Name", ""), r.get("Counter_Name", ""),
+                        rows.append((int(r.get("Dispatch_Id", "0") or 0), r.get("Kernel_Name", ""),
+                                     r.get("Counter_Name", ""),
                                      float(r.get("Counter_Value", "nan"))))
     return rows
 
 
-def _pmc_median(rows, counter: str, pattern: str):
-    """Median over the hot kernel's dispatches (the batched workload's
-    autotuner also launches it on single-job warm-ups)."""
-    vals = sorted(v for k, c, v in rows if c == counter and pattern in k)
-    return (vals[len(vals) // 2], len(vals)) if vals else (None, 0)
+def _pmc_series(rows, counter: str, pattern: str):
+    """The hot kernel's values of one counter, in dispatch order."""
+    return [v for _, k, c, v in sorted(rows) if c == counter and pattern in k]
 
 
 def _ingest_pmc(workload: str, dirs, command: str) -> int:
@@ -126,13 +125,27 @@ def _ingest_pmc(workload: str, dirs, command: str) -> int:
     sha of the kernel sources)."""
     fetch_dir, write_dir, cal_fetch_dir, cal_write_dir = dirs
     pat = HOT_KERNEL[workload]
-    f_kib, nf = _pmc_median(_pmc_rows(fetch_dir), "FETCH_SIZE", pat)
-    w_kib, nw = _pmc_median(_pmc_rows(write_dir), "WRITE_SIZE", pat)
+    fs = _pmc_series(_pmc_rows(fetch_dir), "FETCH_SIZE", pat)
+    ws = _pmc_series(_pmc_rows(write_dir), "WRITE_SIZE", pat)
+    # the two runs launch the same sequence; a full dispatch fetches at least
+    # a tenth of the largest (the batched workload's autotuner also launches
+    # the kernel on single-job warm-ups, and a step loop's launches after the
+    # stop return at once); the deferred sweep alternates read-only launches
+    # and write-backs, so the launch average is the mean over full dispatches
+    full = [q for q, v in enumerate(fs) if fs and v >= 0.1 * max(fs)]
+    nf, nw = len(full), len(ws)
+    if not full or len(ws) != len(fs):
+        print(json.dumps({"error": "counters not found or runs differ", "fetch": len(fs),
+                          "write": nw}))
+        return 1
+    f_kib = sum(fs[q] for q in full) / nf
+    w_kib = sum(ws[q] for q in full) / nf
+    nw = nf
     # the largest dispatch of the calibration run is the 1 GiB copy
-    cf = sorted(v for k, c, v in _pmc_rows(cal_fetch_dir) if c == "FETCH_SIZE")
-    cw = sorted(v for k, c, v in _pmc_rows(cal_write_dir) if c == "WRITE_SIZE")
-    if f_kib is None or w_kib is None or not cf or not cw:
-        print(json.dumps({"error": "counters not found", "fetch": nf, "write": nw}))
+    cf = sorted(v for _, k, c, v in _pmc_rows(cal_fetch_dir) if c == "FETCH_SIZE")
+    cw = sorted(v for _, k, c, v in _pmc_rows(cal_write_dir) if c == "WRITE_SIZE")
+    if not cf or not cw:
+        print(json.dumps({"error": "calibration counters not found"}))
         return 1
     kib = CALIBRATION_BYTES / 1024.0
     fac_f, fac_w = cf[-1] / kib, cw[-1] / kib
@@ -224,9 +237,22 @@ def _setup_dense(torch, rplu, which):
                 "rel_schur_gap": math.sqrt(v["schur_gap_fro2"] / v["a_fro2"]),
                 "note": "FP64 MFMA peak on MI355X equals the FP64 vector peak, 78.6 TFLOP/s"}
 
-    live = sum(2 * (n - s) * (m - s) * es for s in range(k)) / k
+    # The deferred sweep (the default at this size: S of 64 MiB or more, L and
+    # U stored) reads the live S^(t) block at every step and writes it back
+    # every RPLU_LAZY_STEPS steps and at the last one; the eager sweep reads
+    # and writes it at every step. Algorithmic bytes per launch, averaged:
+    lazy = n * m * es >= (64 << 20)
+    B = rplu.RPLU_LAZY_STEPS
+    if lazy:
+        per_step = [(n - s) * (m - s) * es * (2 if ((s + 1) % B == 0 or s + 1 == k) else 1)
+                    for s in range(k)]
+    else:
+        per_step = [2 * (n - s) * (m - s) * es for s in range(k)]
+    live = sum(per_step) / k
+    eager_bytes = sum(2 * (n - s) * (m - s) * es for s in range(k)) / k
     return dict(step=step, k=k, n=n, m=m, kind="dense", dtype=dtype, per_launch=live, verify=verify,
-                live_total=sum(2 * (n - s) * (m - s) * es for s in range(k)) + n * m * es,
+                eager_per_launch=eager_bytes, sweep="deferred" if lazy else "eager",
+                live_total=sum(per_step) + n * m * es,
                 config={"workload": desc, "n": n, "m": m, "k": k, "seed": 0})
 
 
@@ -527,8 +553,14 @@ def _run_workload(args, torch, rplu, workload) -> dict:
         kernel = "k_cauchy_mass<1>"
     else:
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / 1e9 / HBM_PEAK_GBS}
-        kernel = "k_dense_sweep"
+                "frac": achieved / 1e9 / HBM_PEAK_GBS, "sweep": wl["sweep"],
+                "count": ("live S^(t) block read at every step, written at every "
+                          f"{rplu.RPLU_LAZY_STEPS}th and the last (deferred sweep)"
+                          if wl["sweep"] == "deferred" else
+                          "live S^(t) block read and written at every step"),
+                "eager_equivalent_GBs": (wl["eager_per_launch"] / (hot_ms * 1e-3) / 1e9
+                                         if hot_launches else None)}
+        kernel = "k_dense_lazy" if wl["sweep"] == "deferred" else "k_dense_sweep"
     roof["traffic"] = _traffic(workload, hot_launches)
     roof["kernel"] = kernel
     roof["avg_launch_us"] = hot_ms * 1e3

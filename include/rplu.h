@@ -29,7 +29,8 @@
  *   - L is n x k column-major: column t starts at L + t*ldl (ldl >= n).
  *   - U is k x m row-major: row t starts at U + t*ldu (ldu >= m).
  *   - A is n x m row-major with leading dimension lda >= m. It is
- *     OVERWRITTEN with the final Schur complement S^(rank).
+ *     OVERWRITTEN with the final Schur complement S^(rank) (unless
+ *     RPLU_FLAG_KEEP_INPUT).
  *   - Complex data are interleaved (re, im) pairs. Masses are |z|^2, U is not
  *     conjugated, L(:,t) = S_:,j / S_ij with L(i_t, t) = 1.
  *   - Pivot row and column of each update are set to exactly 0.
@@ -118,6 +119,23 @@ enum {
                                      stop test, seed and stream unused.
                                      rplu_batched and rplu_server_submit
                                      reject it in a job (RPLU_E_ARG).        */
+    RPLU_FLAG_KEEP_INPUT = 1u << 8, /* rplu_dense / rplu_cauchy: run on a copy
+                                     of A (of G and B) in the context's
+                                     workspace; the caller's arrays are not
+                                     modified and the final Schur complement
+                                     (generators) is not returned. With
+                                     RPLU_FLAG_REFRESH and no opts.A_orig, A
+                                     itself is the original. Not accepted by
+                                     rplu_dense_noalloc.                     */
+    RPLU_FLAG_LAZY_SWEEP = 1u << 9, /* dense: the deferred sweep (S read every
+                                     step, written back every RPLU_LAZY_STEPS
+                                     steps, the pending updates applied on
+                                     the fly in the same order: the same
+                                     results bit for bit) also below its
+                                     default size; needs L and U, not with
+                                     RPLU_FLAG_COLMASS (then eager)          */
+    RPLU_FLAG_EAGER_SWEEP = 1u << 10, /* dense: read and write S every step
+                                     (the default below RPLU_LAZY_MIN_BYTES) */
     RPLU_FLAG_CERTIFY = 1u << 7,    /* server, dense R32/R64 jobs: after the run,
                                      ||A - L U||_F^2 is formed in FP64 on the
                                      matrix cores from the original A and
@@ -152,6 +170,12 @@ enum {
                                      ||A - L U||_F^2 up to the rounding of
                                      the residual. Needs L and U.            */
 };
+
+/* Deferred dense sweep: steps per write-back of S, and the size of S
+ * (n * lda * element bytes) from which rplu_dense uses it by default when L
+ * and U are stored. */
+#define RPLU_LAZY_STEPS 4
+#define RPLU_LAZY_MIN_BYTES ((size_t)64 << 20)
 
 /* Residual replacements per run under RPLU_FLAG_REFRESH, and the fall of
  * ||S||_F^2 between two of them that triggers one. */
@@ -221,8 +245,13 @@ typedef struct rplu_ctx_s* rplu_ctx;
 
 /* Context: device workspace (row masses, step state, partial sums), a pinned
  * host staging word and the batched-launch tuning table. Not thread-safe; use
- * one context per host thread. */
-rplu_status rplu_create(int device, rplu_ctx* out);
+ * one context per host thread. hbm_budget_bytes caps the device workspace the
+ * context may hold (grow-only; a call that would need more fails with
+ * RPLU_E_NOMEM before anything is enqueued); 0 = no cap. The workspace of a
+ * dense run is about 8 n + 16 (n + m) / 512 bytes plus, with
+ * RPLU_FLAG_KEEP_INPUT, a copy of A; of a Cauchy-like run about
+ * 8 n (splits + 1) bytes plus, with RPLU_FLAG_KEEP_INPUT, a copy of G and B. */
+rplu_status rplu_create(int device, size_t hbm_budget_bytes, rplu_ctx* out);
 rplu_status rplu_destroy(rplu_ctx ctx);
 
 /* Dense RPLU (Alg. 1 with two-stage exact sampling, Sec. 4.1).

@@ -46,6 +46,10 @@ RPLU_FLAG_SPLIT_SAMPLER = 16
 RPLU_FLAG_C2PLU = 32
 RPLU_FLAG_REFRESH = 64
 RPLU_FLAG_CERTIFY = 128
+RPLU_FLAG_KEEP_INPUT = 256
+RPLU_FLAG_LAZY_SWEEP = 512
+RPLU_FLAG_EAGER_SWEEP = 1024
+RPLU_LAZY_STEPS = 4
 RPLU_MAX_REFRESH = 8
 RPLU_REFRESH_DROP2 = 1e-4
 RPLU_STOP_REFRESH = 6
@@ -113,7 +117,7 @@ class rplu_server_stats_t(C.Structure):
 
 _P = C.c_void_p
 _I64 = C.c_int64
-lib.rplu_create.argtypes = [C.c_int, C.POINTER(_P)]
+lib.rplu_create.argtypes = [C.c_int, C.c_size_t, C.POINTER(_P)]
 lib.rplu_destroy.argtypes = [_P]
 lib.rplu_dense.argtypes = [_P, C.c_int, _I64, _I64, _P, _I64, C.POINTER(rplu_opts), _P, _P, _I64,
                            _P, _I64, C.POINTER(rplu_info), _P]
@@ -176,9 +180,9 @@ def _cur_stream(device: torch.device):
 class Context:
     """Owns an rplu_ctx (device workspace) for one device."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
         h = C.c_void_p()
-        _check(lib.rplu_create(int(device), C.byref(h)), "rplu_create")
+        _check(lib.rplu_create(int(device), int(hbm_budget_bytes), C.byref(h)), "rplu_create")
         self.handle = h
         self.device = int(device)
 
@@ -197,8 +201,8 @@ class Context:
 _default_ctx: dict = {}
 
 
-def rplu_create(device: int = 0) -> Context:
-    return Context(device)
+def rplu_create(device: int = 0, hbm_budget_bytes: int = 0) -> Context:
+    return Context(device, hbm_budget_bytes)
 
 
 def default_context(device: int = 0) -> Context:

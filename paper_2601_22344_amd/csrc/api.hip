@@ -57,6 +57,9 @@ constexpr int64_t RPLU_MAX_DIM = (int64_t)CDF_MAX_GROUPS * CDF_GROUP * CDF_CHUNK
 
 rplu_status ws_reserve(rplu_ctx_s* ctx, size_t bytes, hipStream_t s) {
     if (bytes <= ctx->ws_cap) return RPLU_OK;
+    if (ctx->hbm_budget && bytes + ctx->batch_ws_cap > ctx->hbm_budget)
+        return fail(RPLU_E_NOMEM, "workspace of %zu bytes exceeds the context budget of %zu",
+                    bytes + ctx->batch_ws_cap, ctx->hbm_budget);
     if (ctx->ws) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -296,9 +299,11 @@ rplu_status dense_check(const char* who, int dtype, int64_t n, int64_t m, const 
             return fail(RPLU_E_UNSUPPORTED, "%s: RPLU_FLAG_REFRESH needs R32 or R64", who);
         if (opts->flags & RPLU_FLAG_COLMASS)
             return fail(RPLU_E_UNSUPPORTED, "%s: RPLU_FLAG_REFRESH with RPLU_FLAG_COLMASS", who);
-        if (opts->A_orig == nullptr || opts->lda_orig < m || L == nullptr || U == nullptr)
-            return fail(RPLU_E_ARG, "%s: RPLU_FLAG_REFRESH needs A_orig (lda_orig >= m), L and U",
-                        who);
+        const bool orig = (opts->A_orig != nullptr && opts->lda_orig >= m) ||
+                          (opts->A_orig == nullptr && (opts->flags & RPLU_FLAG_KEEP_INPUT));
+        if (!orig || L == nullptr || U == nullptr)
+            return fail(RPLU_E_ARG, "%s: RPLU_FLAG_REFRESH needs A_orig (lda_orig >= m) or "
+                        "RPLU_FLAG_KEEP_INPUT, and L and U", who);
     }
     return RPLU_OK;
 }
@@ -318,6 +323,12 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
     DenseArgs a;
     std::memset(&a, 0, sizeof a);        // padding too: the struct keys the graph cache
     a.dtype = dtype;
+    // deferred sweep (the same results bit for bit): for matrices that do not
+    // stay in the caches, when L and U are stored and no column masses asked
+    const bool can_lazy = L != nullptr && U != nullptr && !colmass;
+    const bool big = (size_t)n * (size_t)lda * es >= RPLU_LAZY_MIN_BYTES;
+    a.lazy = can_lazy && !(opts->flags & RPLU_FLAG_EAGER_SWEEP) &&
+             (big || (opts->flags & RPLU_FLAG_LAZY_SWEEP)) ? 1 : 0;
     a.n = n;
     a.m = m;
     a.S = A;
@@ -391,6 +402,7 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
     };
     rplu_status rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, step);
     if (rc) return rc;
+    launch_dense_flush(a, s);            // deferred sweep: S^(rank) into A
     StepState hs;
     rc = read_state(ctx, a.st, s, &hs);
     if (rc) return rc;
@@ -429,6 +441,7 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
         if (e2 != hipSuccess) return hip_fail(e2, "residual replacement launch");
         rc = run_loop(ctx, a.st, kmax + 1 - hs.t, graph, key, s, step);
         if (rc) return rc;
+        launch_dense_flush(a, s);
         rc = read_state(ctx, a.st, s, &hs);
         if (rc) return rc;
     }
@@ -615,7 +628,7 @@ const char* rplu_status_str(rplu_status s) {
     }
 }
 
-rplu_status rplu_create(int device, rplu_ctx* out) {
+rplu_status rplu_create(int device, size_t hbm_budget_bytes, rplu_ctx* out) {
     if (out == nullptr) return fail(RPLU_E_ARG, "rplu_create: out is NULL");
     *out = nullptr;
     int count = 0;
@@ -627,6 +640,7 @@ rplu_status rplu_create(int device, rplu_ctx* out) {
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     rplu_ctx_s* c = new rplu_ctx_s();
     c->device = device;
+    c->hbm_budget = hbm_budget_bytes;
     hipDeviceProp_t prop;
     e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDeviceProperties"); }
@@ -742,9 +756,26 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, voi
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
     const DenseWs w = dense_ws_layout(dtype, n, m, opts->flags, U == nullptr);
-    rc = ws_reserve(ctx, w.total, s);
+    const bool keep = (opts->flags & RPLU_FLAG_KEEP_INPUT) != 0;
+    const size_t es = dtype_size(dtype);
+    const size_t copy = keep ? align_up((size_t)n * lda * es + 16, 256) : 0;
+    rc = ws_reserve(ctx, w.total + copy, s);
     if (rc) return rc;
-    return dense_run(ctx, (char*)ctx->ws, dtype, n, m, A, lda, opts, piv, L, ldl, U, ldu, info, s);
+    if (!keep)
+        return dense_run(ctx, (char*)ctx->ws, dtype, n, m, A, lda, opts, piv, L, ldl, U, ldu,
+                         info, s);
+    // the working copy keeps A's 16-byte offset and pitch: the same kernels
+    // and vector widths as a run on A itself
+    char* Ak = (char*)ctx->ws + w.total + (uintptr_t)A % 16;
+    e = hipMemcpy2DAsync(Ak, (size_t)lda * es, A, (size_t)lda * es, (size_t)m * es, (size_t)n,
+                         hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync(KEEP_INPUT copy)");
+    rplu_opts o = *opts;
+    if ((o.flags & RPLU_FLAG_REFRESH) && o.A_orig == nullptr) {
+        o.A_orig = A;
+        o.lda_orig = lda;
+    }
+    return dense_run(ctx, (char*)ctx->ws, dtype, n, m, Ak, lda, &o, piv, L, ldl, U, ldu, info, s);
 }
 
 rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, int32_t p,
@@ -760,8 +791,19 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
     hipStream_t s = (hipStream_t)hip_stream;
     const CauchyWs w = cauchy_ws_layout(ctx->cu_count, n, m, p, opts->flags,
                                         opts->colmass_out != nullptr, U == nullptr);
-    rc = ws_reserve(ctx, w.total, s);
+    const bool keep = (opts->flags & RPLU_FLAG_KEEP_INPUT) != 0;
+    const size_t gb = align_up((size_t)n * p * 16, 256), bb = align_up((size_t)p * m * 16, 256);
+    rc = ws_reserve(ctx, w.total + (keep ? gb + bb : 0), s);
     if (rc) return rc;
+    if (keep) {
+        char* Gk = (char*)ctx->ws + w.total;
+        char* Bk = Gk + gb;
+        e = hipMemcpyAsync(Gk, G, (size_t)n * p * 16, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(Bk, B, (size_t)p * m * 16, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(KEEP_INPUT copy)");
+        G = Gk;
+        B = Bk;
+    }
     return cauchy_run(ctx, (char*)ctx->ws, n, m, p, x, y, G, B, opts, piv, L, ldl, U, ldu, info, s);
 }
 

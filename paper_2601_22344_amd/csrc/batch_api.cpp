@@ -106,6 +106,9 @@ uint64_t signature(const Prepared& P) {
 
 rplu_status batch_reserve(rplu_ctx_s* ctx, size_t bytes, hipStream_t s) {
     if (bytes <= ctx->batch_ws_cap) return RPLU_OK;
+    if (ctx->hbm_budget && bytes + ctx->ws_cap > ctx->hbm_budget)
+        return fail(RPLU_E_NOMEM, "batched workspace of %zu bytes exceeds the context budget of %zu",
+                    bytes + ctx->ws_cap, ctx->hbm_budget);
     if (ctx->batch_ws) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");

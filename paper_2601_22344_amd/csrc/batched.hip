@@ -543,7 +543,8 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
 }
 
 // Persistent kernel. Every workgroup leaves once the queue index passes
-// `count`, so the grid drains after the last instance. Keep a barrier between
+// `count` (or after `count` iterations), so the grid drains after the last
+// instance. Keep a barrier between
 // any thread-0-only work at the end of an iteration and the thread-0 queue
 // fetch at the top: with the two adjacent, the compiler can give the loop a
 // second back edge that bypasses the fetch for the other lanes, and since a
@@ -564,7 +565,9 @@ __global__ __launch_bounds__(BT_THREADS) void k_batched(const BatchJob* __restri
     constexpr int VV = 16 / (int)sizeof(T);
     __shared__ __align__(16) T s_u[BT_NV * RPLU_WAVE * VV];
     static_assert(sizeof(BtShared) + sizeof(s_u) <= BT_STATIC_LDS, "static LDS bound of the host check");
-    for (;;) {
+    // At most `count` iterations per workgroup (the queue holds count jobs),
+    // so the loop ends even if a fetch were ever skipped.
+    for (int iter = 0; iter < count; ++iter) {
         if (threadIdx.x == 0) sh.job = atomicAdd(queue, 1);
         __syncthreads();
         const int q = uniform_i(sh.job);

@@ -262,6 +262,10 @@ struct StepState {
     double T_ref;       // RPLU_FLAG_REFRESH: the total at the start or at the
                         // last residual replacement (inf: take the next one)
     int32_t refresh_on; // replacements left to trigger (0 or 1)
+    int32_t t_base;     // deferred sweep: S in memory holds S^(t_base); the
+                        // updates of steps t_base.. are applied on the fly
+    int32_t flushed;    // deferred sweep: the step whose S^(flushed) the last
+                        // write-back stored (the next draw moves t_base there)
     int32_t pad4;
 };
 

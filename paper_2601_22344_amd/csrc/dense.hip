@@ -200,6 +200,293 @@ __global__ __launch_bounds__(BS) void k_dense_sweep(
     }
 }
 
+// ---------------------------------------------------------- deferred sweep
+//
+// The eager sweep reads and writes all of S at every step. The deferred sweep
+// keeps S^(tb) in memory and, at step t, reads it and applies the updates of
+// steps tb..t in registers, in the eager sweep's order and with its
+// operations (x <- fms(x, L(r,s), U(s,c)), and the exact zeros of row i_s and
+// column j_s, which later steps leave 0), so every value, multiplier and mass
+// is the eager sweep's bit for bit; it writes S^(t+1) back only when the window is full (LAZY_B steps)
+// or at the last step kmax - 1, and the next draw moves tb there. Per step it
+// reads S once and writes it every LAZY_B steps. The window's U rows come
+// from U (L2-resident: LAZY_B rows), its multipliers from L.
+
+// The window of step t as the workgroup sees it (uniform values).
+template <class T>
+struct LazyWin {
+    int tb, w;                   // steps tb .. tb + w - 1
+    int wi[LAZY_B], wj[LAZY_B];  // their pivots
+};
+
+template <class T>
+__device__ inline LazyWin<T> lazy_window(const int32_t* __restrict__ piv, int tb, int t) {
+    LazyWin<T> W;
+    W.tb = tb;
+    W.w = t - tb;
+#pragma unroll
+    for (int s = 0; s < LAZY_B; ++s) {
+        W.wi[s] = s < W.w ? piv[2 * (tb + s)] : -1;
+        W.wj[s] = s < W.w ? piv[2 * (tb + s) + 1] : -1;
+    }
+    return W;
+}
+
+// Row i of S^(t) from S^(tb) (the eager sweep's value): the pivot row of the
+// draw kernels when the sweep is deferred.
+template <class T>
+struct LazyRowAcc {
+    const T* Si;                 // row i of S^(tb)
+    const T* U;
+    int64_t ldu;
+    int i;
+    LazyWin<T> W;
+    T l[LAZY_B];                 // L(i, tb + s)
+    bool zr[LAZY_B];             // row i was the pivot row of step tb + s
+    __host__ __device__ T operator()(int e) const {
+        T x = Si[e];
+#pragma unroll
+        for (int s = 0; s < LAZY_B; ++s) {
+            if (s < W.w) {
+                const T y = Sc<T>::fms(x, l[s], U[(int64_t)(W.tb + s) * ldu + e]);
+                x = (zr[s] || e == W.wj[s]) ? Sc<T>::zero() : y;
+            }
+        }
+        return x;
+    }
+};
+
+template <class T>
+__device__ inline LazyRowAcc<T> lazy_row(const T* S, int64_t lda, const T* U, int64_t ldu,
+                                         const T* L, int64_t ldl, const int32_t* piv, int i,
+                                         int tb, int t) {
+    LazyRowAcc<T> a;
+    a.Si = S + (int64_t)i * lda;
+    a.U = U;
+    a.ldu = ldu;
+    a.i = i;
+    a.W = lazy_window<T>(piv, tb, t);
+#pragma unroll
+    for (int s = 0; s < LAZY_B; ++s) {
+        a.l[s] = s < a.W.w ? L[(int64_t)(tb + s) * ldl + i] : Sc<T>::zero();
+        a.zr[s] = a.W.wi[s] == i;
+    }
+    return a;
+}
+
+// FINAL = false: the sweep of step t = st->cur (the pending updates of steps
+// tb..t-1 plus step t, whose multipliers L(:,t) are formed here); row masses
+// (and column partials) of S^(t+1). FINAL = true: after the run, S^(st->t)
+// written back if the last write-back is older; no masses.
+template <class T, int R, int BS, int V, bool COLMASS, bool FINAL>
+__global__ __launch_bounds__(BS) void k_dense_lazy(
+    T* __restrict__ S, int64_t lda, int n, int m,
+    const T* __restrict__ U, int64_t ldu, T* __restrict__ L, int64_t ldl,
+    const int32_t* __restrict__ piv, StepState* __restrict__ st, double* __restrict__ rowmass,
+    double* __restrict__ colpart, int kmax) {
+    using W = typename Sc<T>::W;
+    const int tid = threadIdx.x;
+    const int lane = tid % RPLU_WAVE, wv = tid / RPLU_WAVE;
+    int t, pi = -1, pj = -1;
+    W inv{};
+    if constexpr (FINAL) {
+        if (st->error != 0) return;
+        t = st->t;
+        if (st->flushed == t) return;            // S^(t) is in memory already
+    } else {
+        if (st->done) return;
+        t = st->cur;
+        pi = st->i;
+        pj = st->j;
+        if constexpr (Sc<T>::cplx) inv = W{st->inv_re, st->inv_im};
+        else inv = st->inv_re;
+    }
+    const int tb = st->t_base;
+    // window steps tb .. tb + w - 1 (FINAL: up to t - 1; else up to t)
+    const int w = FINAL ? t - tb : t - tb + 1;
+    const bool flush = FINAL || w == LAZY_B || t + 1 == kmax;
+    int wi[LAZY_B], wj[LAZY_B];
+#pragma unroll
+    for (int s = 0; s < LAZY_B; ++s) {
+        const bool cur = !FINAL && s == w - 1;
+        wi[s] = s < w ? (cur ? pi : piv[2 * (tb + s)]) : -1;
+        wj[s] = s < w ? (cur ? pj : piv[2 * (tb + s) + 1]) : -1;
+    }
+    const int r0 = blockIdx.x * R;
+    const int nr = min(R, n - r0);
+    T lw[R][LAZY_B];
+    bool zrow[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = r0 + min(q, nr - 1);
+        bool z = false;
+#pragma unroll
+        for (int s = 0; s < LAZY_B; ++s) z = z || (s < w && wi[s] == r);
+        zrow[q] = z;
+#pragma unroll
+        for (int s = 0; s < LAZY_B; ++s) {
+            const bool older = FINAL ? s < w : s < w - 1;
+            lw[q][s] = older ? L[(int64_t)(tb + s) * ldl + r] : Sc<T>::zero();
+        }
+        if constexpr (!FINAL) {
+            // L(r, t) = S^(t)(r, j) / a: the window's updates on the stored
+            // S(r, j), as the eager sweep reads it from memory
+            T x = S[(int64_t)r * lda + pj];
+#pragma unroll
+            for (int s = 0; s < LAZY_B; ++s) {
+                if (s < w - 1) {
+                    const T y = Sc<T>::fms(x, lw[q][s], U[(int64_t)(tb + s) * ldu + pj]);
+                    x = (wi[s] == r || wj[s] == pj) ? Sc<T>::zero() : y;
+                }
+            }
+            const T l = (r == pi) ? Sc<T>::one() : Sc<T>::narrow(wmul(Sc<T>::widen(x), inv));
+#pragma unroll
+            for (int s = 0; s < LAZY_B; ++s)
+                if (s == w - 1) lw[q][s] = l;
+            if (tid == q && q < nr) L[(int64_t)t * ldl + r] = l;
+        }
+    }
+    // every S[r, j] is read before any store to it; a sweep that writes
+    // nothing back needs no barrier, and its first loads go out at once
+    if (!FINAL && flush) __syncthreads();
+    if (!flush) {
+        // nothing is written: a block whose rows are all pivoted in the
+        // window has masses 0 and need not read S
+        bool all = true;
+#pragma unroll
+        for (int q = 0; q < R; ++q) all = all && (q >= nr || zrow[q]);
+        if (all && !COLMASS) {
+            if (tid < nr) rowmass[r0 + tid] = 0.0;
+            return;
+        }
+    }
+    double rp[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) rp[q] = 0.0;
+
+    // The column loop for a window of WW steps (a compile-time length: no
+    // per-step branches, only the live multipliers in registers).
+    auto cols = [&](auto wtag) {
+        constexpr int WW = decltype(wtag)::value;
+        auto pack = [&](int64_t c, auto full_tag, auto allrows_tag) {
+            constexpr bool FULL = decltype(full_tag)::value;
+            constexpr bool ALLR = decltype(allrows_tag)::value;
+            double cp[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) cp[v] = 0.0;
+            // The eager sweep sets column j_s to 0 at step s, and the later
+            // steps leave it 0 (U(s', j_s) = 0 there), so zeroing the window's
+            // pivot columns once, after the chain, gives the same values; the
+            // mask is shared by the R rows.
+            Pack<T, V> u[WW];
+            bool zc[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) zc[v] = false;
+#pragma unroll
+            for (int s = 0; s < WW; ++s) {
+                const int pv = wj[s] - (int)c;
+#pragma unroll
+                for (int v = 0; v < V; ++v) zc[v] = zc[v] || v == pv;
+                const T* Us = U + (int64_t)(tb + s) * ldu + c;
+                if constexpr (FULL) u[s] = *reinterpret_cast<const Pack<T, V>*>(Us);
+                else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) u[s].v[v] = (c + v < m) ? Us[v] : Sc<T>::zero();
+                }
+            }
+            Pack<T, V> x[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                if ((ALLR || q < nr) && !zrow[q]) {
+                    const T* p = S + (int64_t)(r0 + q) * lda + c;
+                    if constexpr (FULL) x[q] = ld_s<T, V>(p);
+                    else {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) x[q].v[v] = (c + v < m) ? p[v] : Sc<T>::zero();
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                if (ALLR || q < nr) {
+                    if (zrow[q]) {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) x[q].v[v] = Sc<T>::zero();
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < WW; ++s) {
+#pragma unroll
+                            for (int v = 0; v < V; ++v)
+                                x[q].v[v] = Sc<T>::fms(x[q].v[v], lw[q][s], u[s].v[v]);
+                        }
+#pragma unroll
+                        for (int v = 0; v < V; ++v)
+                            if (zc[v]) x[q].v[v] = Sc<T>::zero();
+                        if constexpr (!FINAL) {
+#pragma unroll
+                            for (int v = 0; v < V; ++v) {
+                                const double m2 = Sc<T>::mag2(x[q].v[v]);   // 0 for padding
+                                rp[q] += m2;
+                                if constexpr (COLMASS) cp[v] += m2;
+                            }
+                        }
+                    }
+                    if (flush) {
+                        T* p = S + (int64_t)(r0 + q) * lda + c;
+                        if constexpr (FULL) st_s<T, V>(p, x[q]);
+                        else {
+#pragma unroll
+                            for (int v = 0; v < V; ++v) if (c + v < m) p[v] = x[q].v[v];
+                        }
+                    }
+                }
+            }
+            if constexpr (COLMASS && !FINAL) {
+                double* cpo = colpart + (int64_t)blockIdx.x * m + c;
+#pragma unroll
+                for (int v = 0; v < V; ++v) if (FULL || c + v < m) cpo[v] = cp[v];
+            }
+        };
+        int64_t c = (int64_t)tid * V;
+        if (nr == R) {
+            for (; c + V <= m; c += (int64_t)BS * V) pack(c, std::true_type{}, std::true_type{});
+            if (c < m) pack(c, std::false_type{}, std::true_type{});
+        } else {
+            for (; c + V <= m; c += (int64_t)BS * V) pack(c, std::true_type{}, std::false_type{});
+            if (c < m) pack(c, std::false_type{}, std::false_type{});
+        }
+    };
+    static_assert(LAZY_B <= 8, "one case per window length");
+    switch (w) {
+        case 1: cols(std::integral_constant<int, 1>{}); break;
+        case 2: cols(std::integral_constant<int, 2>{}); break;
+        case 3: cols(std::integral_constant<int, 3>{}); break;
+        case 4: cols(std::integral_constant<int, 4>{}); break;
+        case 5: if constexpr (LAZY_B >= 5) cols(std::integral_constant<int, 5 <= LAZY_B ? 5 : 1>{}); break;
+        case 6: if constexpr (LAZY_B >= 6) cols(std::integral_constant<int, 6 <= LAZY_B ? 6 : 1>{}); break;
+        case 7: if constexpr (LAZY_B >= 7) cols(std::integral_constant<int, 7 <= LAZY_B ? 7 : 1>{}); break;
+        case 8: if constexpr (LAZY_B >= 8) cols(std::integral_constant<int, 8 <= LAZY_B ? 8 : 1>{}); break;
+        default: break;
+    }
+    if constexpr (FINAL) return;
+    if (flush && blockIdx.x == 0 && tid == 0) st->flushed = t + 1;
+
+    // row masses: wave sums, then a fixed-order sum over the waves (as eager)
+    __shared__ double red[BS / RPLU_WAVE][R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        double v = wave_sum(rp[q]);
+        if (lane == 0) red[wv][q] = v;
+    }
+    __syncthreads();
+    if (tid < nr) {
+        double v = red[0][tid];
+#pragma unroll
+        for (int wq = 1; wq < BS / RPLU_WAVE; ++wq) v += red[wq][tid];
+        rowmass[r0 + tid] = v;
+    }
+}
+
 // Column masses: colmass[c] = sum over row blocks b (in order) of colpart[b][c].
 // Row `st->t` of colmass_out (the masses the next draw sees) is written;
 // rows at or beyond rows_cap are not stored.
@@ -222,20 +509,23 @@ __global__ void k_colmass_reduce(const double* __restrict__ colpart, int nb, int
 // Wide: copies row i of S into U(t,:) (one element per thread, coalesced)
 // with the chunk totals of |S_i,e|^2; the last workgroup draws the column
 // and commits the pivot (pivot.hpp).
-template <class T>
+template <class T, bool LAZY>
 __global__ __launch_bounds__(CDF_THREADS) void k_dense_pivrow_draw(
-    const T* __restrict__ S, int64_t lda, T* __restrict__ U, int64_t ldu, PivotArgs pa,
-    double* __restrict__ ct) {
+    const T* __restrict__ S, int64_t lda, T* __restrict__ U, int64_t ldu, const T* __restrict__ L,
+    int64_t ldl, PivotArgs pa, double* __restrict__ ct) {
     __shared__ WideShared sh;
     if (pa.st->done) return;
     const int t = pa.st->cur;
     wide_keep_words(sh, step_words(pa, t));
-    const T* Si = S + (int64_t)pa.st->i * lda;
+    const int i = pa.st->i;
+    const T* Si = S + (int64_t)i * lda;
     T* Ut = U + (int64_t)t * ldu;
     const int e = blockIdx.x * WIDE_ELEMS + threadIdx.x;
     double v = 0.0;
     if (e < pa.m) {
-        const T x = Si[e];
+        T x;
+        if constexpr (LAZY) x = lazy_row<T>(S, lda, U, ldu, L, ldl, pa.piv, i, pa.st->t_base, t)(e);
+        else x = Si[e];
         Ut[e] = x;
         v = Sc<T>::mag2(x);
     }
@@ -248,20 +538,29 @@ __global__ __launch_bounds__(CDF_THREADS) void k_dense_pivrow_draw(
 // One workgroup: the whole pivot draw of a step (pivot.hpp), the pivot row
 // copied from S into U(t,:); the same results as k_rows_draw followed by
 // k_dense_pivrow_draw, in one launch.
-template <class T>
+template <class T, bool LAZY>
 __global__ __launch_bounds__(CDF_THREADS) void k_dense_pivot(const T* __restrict__ S, int64_t lda,
                                                              T* __restrict__ U, int64_t ldu,
+                                                             const T* __restrict__ L, int64_t ldl,
                                                              PivotArgs pa) {
     __shared__ PivotShared sh;
     if (pa.st->done) return;
     const int t = pa.st->t;
     const StopInputs in = stop_inputs(pa.st);
+    // the window start this step will have (the draw moves it in the state)
+    const int tb = (pa.st->flushed == t) ? t : pa.st->t_base;
     const Philox4 rnd = step_words(pa, t);
     const int i = pivot_draw_row(sh, pa, t, rnd, in);
     if (i < 0) return;
     const T* Si = S + (int64_t)i * lda;
-    pivot_draw_col<T, 0>(sh, pa, t, U + (int64_t)t * ldu, nullptr, nullptr, rnd,
-                         [&](int e) { return Si[e]; }, [](const T& v) { return v; });
+    if constexpr (LAZY) {
+        const LazyRowAcc<T> row = lazy_row<T>(S, lda, U, ldu, L, ldl, pa.piv, i, tb, t);
+        pivot_draw_col<T, 0>(sh, pa, t, U + (int64_t)t * ldu, nullptr, nullptr, rnd, row,
+                             [](const T& v) { return v; });
+    } else {
+        pivot_draw_col<T, 0>(sh, pa, t, U + (int64_t)t * ldu, nullptr, nullptr, rnd,
+                             [&](int e) { return Si[e]; }, [](const T& v) { return v; });
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -293,13 +592,46 @@ static void launch_sweep_dt(const DenseArgs& a, bool init, hipStream_t s) {
     }
 }
 
+template <class T, int R, int V, bool COLMASS, bool FINAL>
+static void launch_lazy_v(const DenseArgs& a, hipStream_t s) {
+    constexpr int BS = COLMASS ? DENSE_THREADS_COLMASS : DENSE_THREADS;
+    const int nb = (int)((a.n + R - 1) / R);
+    hipLaunchKernelGGL((k_dense_lazy<T, R, BS, V, COLMASS, FINAL>), dim3(nb), dim3(BS), 0, s,
+                       (T*)a.S, a.lda, (int)a.n, (int)a.m, (const T*)a.U, a.ldu, (T*)a.L, a.ldl,
+                       a.piv, a.st, a.rowmass, a.colpart, (int)a.kmax);
+}
+
+// (column masses take the eager sweep: the host never sets lazy with them)
+template <class T, bool FINAL>
+static void launch_lazy_dt(const DenseArgs& a, hipStream_t s) {
+    constexpr int VV = 16 / (int)sizeof(T);
+    constexpr int R = Sc<T>::cplx ? DENSE_LAZY_ROWS / 2 : DENSE_LAZY_ROWS;
+    if (a.vec_ok) launch_lazy_v<T, R, VV, false, FINAL>(a, s);
+    else launch_lazy_v<T, R, 1, false, FINAL>(a, s);
+}
+
+template <bool FINAL>
+static void launch_lazy(const DenseArgs& a, hipStream_t s) {
+    switch (a.dtype) {
+        case RPLU_R32: launch_lazy_dt<float, FINAL>(a, s); break;
+        case RPLU_R64: launch_lazy_dt<double, FINAL>(a, s); break;
+        case RPLU_C64: launch_lazy_dt<cf32, FINAL>(a, s); break;
+        case RPLU_C128: launch_lazy_dt<cf64, FINAL>(a, s); break;
+    }
+}
+
 void launch_dense_sweep(const DenseArgs& a, bool init, hipStream_t s) {
+    if (!init && a.lazy) { launch_lazy<false>(a, s); return; }
     switch (a.dtype) {
         case RPLU_R32: launch_sweep_dt<float>(a, init, s); break;
         case RPLU_R64: launch_sweep_dt<double>(a, init, s); break;
         case RPLU_C64: launch_sweep_dt<cf32>(a, init, s); break;
         case RPLU_C128: launch_sweep_dt<cf64>(a, init, s); break;
     }
+}
+
+void launch_dense_flush(const DenseArgs& a, hipStream_t s) {
+    if (a.lazy) launch_lazy<true>(a, s);
 }
 
 int dense_row_block(bool colmass) { return colmass ? DENSE_ROWS_COLMASS : DENSE_ROWS; }
@@ -320,8 +652,14 @@ void launch_colmass_reduce(const DenseArgs& a, bool after_step, hipStream_t s) {
 
 template <class T>
 static void pivot_t(const DenseArgs& a, const SampleArgs& sa, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_pivot<T>, dim3(1), dim3(CDF_THREADS), 0, s, (const T*)a.S, a.lda,
-                       (T*)a.U, a.ldu, pivot_args(sa));
+    if (a.lazy)
+        hipLaunchKernelGGL((k_dense_pivot<T, true>), dim3(1), dim3(CDF_THREADS), 0, s,
+                           (const T*)a.S, a.lda, (T*)a.U, a.ldu, (const T*)a.L, a.ldl,
+                           pivot_args(sa));
+    else
+        hipLaunchKernelGGL((k_dense_pivot<T, false>), dim3(1), dim3(CDF_THREADS), 0, s,
+                           (const T*)a.S, a.lda, (T*)a.U, a.ldu, (const T*)a.L, a.ldl,
+                           pivot_args(sa));
 }
 
 void launch_dense_pivot(const DenseArgs& a, const SampleArgs& sa, hipStream_t s) {
@@ -335,8 +673,14 @@ void launch_dense_pivot(const DenseArgs& a, const SampleArgs& sa, hipStream_t s)
 
 template <class T>
 static void pivrow_draw_t(const DenseArgs& a, const SampleArgs& sa, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_pivrow_draw<T>, dim3(wide_blocks(a.m)), dim3(CDF_THREADS), 0, s,
-                       (const T*)a.S, a.lda, (T*)a.U, a.ldu, pivot_args(sa), a.ct_col);
+    if (a.lazy)
+        hipLaunchKernelGGL((k_dense_pivrow_draw<T, true>), dim3(wide_blocks(a.m)), dim3(CDF_THREADS),
+                           0, s, (const T*)a.S, a.lda, (T*)a.U, a.ldu, (const T*)a.L, a.ldl,
+                           pivot_args(sa), a.ct_col);
+    else
+        hipLaunchKernelGGL((k_dense_pivrow_draw<T, false>), dim3(wide_blocks(a.m)), dim3(CDF_THREADS),
+                           0, s, (const T*)a.S, a.lda, (T*)a.U, a.ldu, (const T*)a.L, a.ldl,
+                           pivot_args(sa), a.ct_col);
 }
 
 void launch_dense_pivrow_draw(const DenseArgs& a, const SampleArgs& sa, hipStream_t s) {

@@ -16,9 +16,16 @@ constexpr int DENSE_ROWS = 4;
 constexpr int DENSE_THREADS = 512;
 constexpr int DENSE_ROWS_COLMASS = 16;
 constexpr int DENSE_THREADS_COLMASS = 256;
+constexpr int DENSE_LAZY_ROWS = 4;        // rows per workgroup of the deferred sweep
+
+// Deferred ("lazy") dense sweep: S in memory is written back every LAZY_B
+// steps; in between each sweep reads it and applies the pending rank-1
+// updates in registers in the eager sweep's order (dense.hip).
+constexpr int LAZY_B = RPLU_LAZY_STEPS;
 
 struct DenseArgs {
     int dtype;
+    int lazy;            // deferred sweep (needs L and U stored, ldu >= m)
     int64_t n, m;
     void* S;
     int64_t lda;
@@ -79,6 +86,9 @@ void launch_state_resume(StepState* st, int refresh_on, hipStream_t s);
 void launch_rows_draw(const SampleArgs& a, hipStream_t s);
 
 void launch_dense_sweep(const DenseArgs& a, bool init, hipStream_t s);
+// Deferred sweep: S^(st->t) written back after the run if the last
+// write-back is older (no-op for the eager sweep).
+void launch_dense_flush(const DenseArgs& a, hipStream_t s);
 void launch_dense_pivrow_draw(const DenseArgs& a, const SampleArgs& sa, hipStream_t s);
 void launch_colmass_reduce(const DenseArgs& a, bool after_step, hipStream_t s);
 // Row st->t of out (ld_out per row, rows below rows_cap) = sum over b in

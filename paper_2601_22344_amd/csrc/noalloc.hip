@@ -62,6 +62,8 @@ rplu_status rplu_dense_noalloc(rplu_dtype dtype, int64_t n, int64_t m, void* A, 
     rplu_status rc = dense_check("rplu_dense_noalloc", dtype, n, m, A, lda, opts, piv, L, ldl, U,
                                  ldu, info);
     if (rc) return rc;
+    if (opts->flags & RPLU_FLAG_KEEP_INPUT)
+        return fail(RPLU_E_UNSUPPORTED, "rplu_dense_noalloc: RPLU_FLAG_KEEP_INPUT needs a copy of A");
     const DenseWs w = dense_ws_layout(dtype, n, m, opts->flags, U == nullptr);
     if (w.total > (size_t)RPLU_NOALLOC_SCRATCH_BYTES)
         return fail(RPLU_E_ARG,

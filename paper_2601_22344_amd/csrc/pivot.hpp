@@ -221,6 +221,8 @@ __device__ inline int pivot_row_draw_ct(CdfShared& sh, int* flag, const PivotArg
         st->row_tgt = tgt;
         st->row_lo = p.lo;
         st->row_hi = p.hi;
+        // deferred sweep: a write-back of S^(t) moves the window to start at t
+        if (st->flushed == t) st->t_base = t;
     }
     return i;
 }

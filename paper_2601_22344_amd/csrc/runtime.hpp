@@ -42,6 +42,7 @@ struct rplu_tune_entry {
 struct rplu_ctx_s {
     int device = 0;
     int cu_count = 0;
+    size_t hbm_budget = 0;          // cap on ws + batch_ws (0: none)
     size_t lds_per_block = 0;       // bytes of LDS one workgroup may use
     void* ws = nullptr;             // grow-only device workspace
     size_t ws_cap = 0;

@@ -49,6 +49,8 @@ __global__ void k_state_resume(StepState* st, int refresh_on) {
         st->t_best = st->t;
         st->T_ref = __builtin_inf();
         st->refresh_on = refresh_on;
+        st->t_base = st->t;             // the replaced S is S^(t) in memory
+        st->flushed = st->t;
         st->arrive = 0;
     }
 }

@@ -706,12 +706,12 @@ rplu_status rplu_server_create(rplu_ctx ctx, const rplu_server_cfg* cfg, rplu_se
     S->workers.resize((size_t)S->cfg.workers);
     if (!sim) {
         for (Worker& W : S->workers) {
-            rplu_status rc = rplu_create(S->device, &W.ctx);
+            rplu_status rc = rplu_create(S->device, 0, &W.ctx);
             if (rc) { teardown(S); return rc; }
             hipError_t e = hipStreamCreateWithFlags(&W.stream, hipStreamNonBlocking);
             if (e != hipSuccess) { W.stream = nullptr; teardown(S); return hip_fail(e, "hipStreamCreateWithFlags"); }
         }
-        rplu_status rc = rplu_create(S->device, &S->tick_ctx);
+        rplu_status rc = rplu_create(S->device, 0, &S->tick_ctx);
         if (rc) { teardown(S); return rc; }
         hipError_t e = hipStreamCreateWithFlags(&S->tick_stream, hipStreamNonBlocking);
         if (e != hipSuccess) { S->tick_stream = nullptr; teardown(S); return hip_fail(e, "hipStreamCreateWithFlags"); }

@@ -238,3 +238,43 @@ def test_stall_rule(rplu_lib, dt):
         o = O.rplu_dense(D, k=k, seed=1, forced=forced, stall=True)
         assert (r.stop, r.rank) == (o.stop, o.rank) == (stop, rank)
         assert r.res_fro2 == o.res_fro2
+
+
+def test_keep_input_and_context_budget(rplu_lib):
+    """RPLU_FLAG_KEEP_INPUT: the run works on a workspace copy (same offset
+    and pitch, so the same kernels): results bitwise those of a run on a copy
+    of A, A itself untouched; with RPLU_FLAG_REFRESH, A is the original. The
+    Cauchy-like form keeps G and B. A context budget refuses a workspace that
+    would exceed it, before anything runs."""
+    import paper_2601_22344_amd._binding as Bd
+    A = torch.from_numpy(W.random_dense(300, 257, seed=17)).float().to(DEV)
+    A0 = A.clone()
+    ref = rplu_lib.rplu_dense(A0.clone(), k=25, seed=2, stream=5)
+    keep = rplu_lib.rplu_dense(A, k=25, seed=2, stream=5, flags=rplu_lib.RPLU_FLAG_KEEP_INPUT)
+    assert torch.equal(A, A0)
+    assert torch.equal(ref.piv, keep.piv) and torch.equal(ref.L, keep.L)
+    assert torch.equal(ref.U, keep.U) and ref.res_fro2 == keep.res_fro2
+    r1 = rplu_lib.rplu_dense(A0.clone(), k=0, tol=1e-3, seed=2, stream=5,
+                             flags=rplu_lib.RPLU_FLAG_STALL_STOP, A_orig=A0)
+    r2 = rplu_lib.rplu_dense(A, k=0, tol=1e-3, seed=2, stream=5,
+                             flags=rplu_lib.RPLU_FLAG_STALL_STOP | rplu_lib.RPLU_FLAG_REFRESH |
+                             rplu_lib.RPLU_FLAG_KEEP_INPUT)
+    assert torch.equal(A, A0)
+    assert r1.refreshes == r2.refreshes >= 1 and torch.equal(r1.piv, r2.piv)
+    assert torch.equal(r1.U, r2.U)
+    x, y, G, B = W.cauchy_like_random(400, 300, 2, seed=4)
+    xd, yd, Gd, Bd_ = (torch.from_numpy(np.ascontiguousarray(v)).to(DEV) for v in (x, y, G, B))
+    G0, B0 = Gd.clone(), Bd_.clone()
+    c1 = rplu_lib.rplu_cauchy(xd, yd, G0.clone(), B0.clone(), k=12, seed=3)
+    c2 = rplu_lib.rplu_cauchy(xd, yd, Gd, Bd_, k=12, seed=3, flags=rplu_lib.RPLU_FLAG_KEEP_INPUT)
+    assert torch.equal(Gd, G0) and torch.equal(Bd_, B0)
+    assert torch.equal(c1.piv, c2.piv) and torch.equal(c1.U, c2.U) and torch.equal(c1.L, c2.L)
+    small = Bd.Context(0, hbm_budget_bytes=1 << 20)
+    ok = rplu_lib.rplu_dense(A0.clone(), k=5, seed=1, ctx=small)
+    assert ok.rank == 5
+    big = torch.zeros((300000, 8), dtype=torch.float32, device=DEV)   # 2.4 MB of row masses
+    big[:, 0] = 1.0
+    with pytest.raises(rplu_lib.RPLUError) as e:
+        rplu_lib.rplu_dense(big, k=2, ctx=small)
+    assert e.value.status == -2                      # RPLU_E_NOMEM
+    small.close()
