@@ -39,6 +39,11 @@ Readings where the paper is silent (each also listed in the design notes):
   i = a row of largest mass ||S_i,:||^2, then j = a column of largest
   |S_ij| in that row; ties go to the smallest index. Same update and stop
   test; no random numbers.
+* CPLU (complete pivoting, Sec. 1 and Sec. 2.3.2): (i, j) = an entry of
+  largest |S_ij| over the whole Schur complement; moduli are compared as
+  |S_ij|^2 in FP64 (squared_magnitude), and ties go to the first entry in
+  row-major order (smallest i, then smallest j). Same update and stop test;
+  no random numbers.
 """
 from __future__ import annotations
 
@@ -109,6 +114,23 @@ def largest(weights: np.ndarray, forced: Optional[int] = None) -> Draw:
     drawn = int(np.argmax(w))
     used = drawn if forced is None else int(forced)
     return Draw(drawn, used, float(np.sum(w)), float("nan"), float("nan"), float("nan"))
+
+
+def largest_entry(S: np.ndarray, forced=(None, None)):
+    """CPLU's choice (Sec. 1, complete pivoting): the entry of largest
+    |S_ij|^2 over all of S, the first in row-major order among equal ones.
+    Returns the row and column Draws (forced: an (i, j) to use instead)."""
+    W = squared_magnitude(S)
+    i, j = np.unravel_index(int(np.argmax(W)), W.shape)   # argmax: first in C order
+    return _entry_draws(int(i), int(j), float(np.sum(W)), forced)
+
+
+def _entry_draws(i: int, j: int, T: float, forced):
+    fi, fj = forced
+    nan = float("nan")
+    rd = Draw(i, i if fi is None else int(fi), T, nan, nan, nan)
+    cd = Draw(j, j if fj is None else int(fj), nan, nan, nan, nan)
+    return rd, cd
 
 
 def inverse_cdf(weights: np.ndarray, u: float, forced: Optional[int] = None) -> Draw:
@@ -201,14 +223,17 @@ def schur_update(S: np.ndarray, i: int, j: int):
 def rplu_dense(A: np.ndarray, k: int = 0, tol: float = 0.0, seed: int = 0,
                stream: int = 0, forced: Optional[Sequence] = None,
                keep_masses: bool = False, stall: bool = False,
-               greedy: bool = False) -> RPLUResult:
+               greedy: bool = False, complete: bool = False) -> RPLUResult:
     """Alg. 1 with two-stage exact sampling (Sec. 4.1).
 
     forced: optional sequence of (i, j) pivots to use instead of the draws
     (the draws are still made and recorded, so a caller can check where a
     draw landed relative to the forced pivot's CDF bin).
     greedy: C2PLU (Sec. 2.3.3) instead of the random draws.
+    complete: CPLU (Sec. 1, complete pivoting) instead of the random draws.
     """
+    if greedy and complete:
+        raise ValueError("C2PLU and CPLU are exclusive")
     S = np.array(A, dtype=np.complex128 if np.iscomplexobj(A) else np.float64,
                  copy=True)
     n, m = S.shape
@@ -234,11 +259,13 @@ def rplu_dense(A: np.ndarray, k: int = 0, tol: float = 0.0, seed: int = 0,
             masses.append(rowmass)
         u1, u2 = step_uniforms(seed, stream, t)
         fi, fj = _forced_at(forced, t)
-        rd = largest(rowmass, fi) if greedy else inverse_cdf(rowmass, u1, fi)
-        i = rd.used
-        w_row = squared_magnitude(S[i, :])
-        cd = largest(w_row, fj) if greedy else inverse_cdf(w_row, u2, fj)
-        j = cd.used
+        if complete:
+            rd, cd = largest_entry(S, (fi, fj))
+        else:
+            rd = largest(rowmass, fi) if greedy else inverse_cdf(rowmass, u1, fi)
+            w_row = squared_magnitude(S[rd.used, :])
+            cd = largest(w_row, fj) if greedy else inverse_cdf(w_row, u2, fj)
+        i, j = rd.used, cd.used
         l, u, a = schur_update(S, i, j)
         L[:, t] = l
         U[t, :] = u
@@ -324,6 +351,22 @@ def cauchy_row_masses(x, y, G, B, rows_per_block: int = 512) -> np.ndarray:
     return out
 
 
+def cauchy_largest_entry(x, y, G, B, rows_per_block: int = 512):
+    """CPLU's choice on a Cauchy-like matrix (Sec. 1, complete pivoting):
+    (i, j) of the largest |s_ij|^2 over all entries, the first in row-major
+    order among equal ones, one block of rows at a time (a later block
+    replaces the best only when strictly larger)."""
+    n = x.shape[0]
+    best, bi, bj = -1.0, -1, -1
+    for i0 in range(0, n, rows_per_block):
+        i1 = min(n, i0 + rows_per_block)
+        W = squared_magnitude((G[i0:i1] @ B) / (x[i0:i1, None] - y[None, :]))
+        r, c = np.unravel_index(int(np.argmax(W)), W.shape)
+        if W[r, c] > best:
+            best, bi, bj = float(W[r, c]), i0 + int(r), int(c)
+    return bi, bj
+
+
 def cauchy_generator_update(x, y, G, B, i: int, j: int):
     """One pivot step on the generators, in place (eqs. generator_update_g,
     generator_update_b): regenerate r = row i and c = column j, then
@@ -346,11 +389,13 @@ def cauchy_generator_update(x, y, G, B, i: int, j: int):
 def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
                 stream: int = 0, forced: Optional[Sequence] = None,
                 keep_masses: bool = False, mass_steps: Optional[set] = None,
-                stall: bool = False, greedy: bool = False) -> RPLUResult:
+                stall: bool = False, greedy: bool = False,
+                complete: bool = False) -> RPLUResult:
     """Alg. 3 with exact row masses (no rejection), generators in complex128.
 
     greedy: C2PLU (Sec. 2.3.3) instead of the random draws (needs the masses
     at every step).
+    complete: CPLU (Sec. 1, complete pivoting) instead of the random draws.
 
     mass_steps: if given, row masses (and hence the draw check) are computed
     only at these steps; elsewhere the run must be forced. This keeps
@@ -370,8 +415,10 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
     T0 = None
     T = float("nan")
     stall_ref = [0.0, 0] if stall else None
-    if greedy and mass_steps is not None:
-        raise ValueError("C2PLU needs the row masses at every step")
+    if (greedy or complete) and mass_steps is not None:
+        raise ValueError("C2PLU and CPLU need the row masses at every step")
+    if greedy and complete:
+        raise ValueError("C2PLU and CPLU are exclusive")
     if stall and mass_steps is not None:
         raise ValueError("the stall rule needs the total at every step")
     t = 0
@@ -393,16 +440,18 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
         fi, fj = _forced_at(forced, t)
         if not need_mass and fi is None:
             raise ValueError("a step without row masses needs a forced pivot")
-        if need_mass:
-            if keep_masses:
-                masses.append(rowmass)
-            rd = largest(rowmass, fi) if greedy else inverse_cdf(rowmass, u1, fi)
+        if need_mass and keep_masses:
+            masses.append(rowmass)
+        if complete:
+            rd, cd = _entry_draws(*cauchy_largest_entry(x, y, G, B), T, (fi, fj))
         else:
-            rd = Draw(-1, fi, float("nan"), float("nan"), float("nan"), float("nan"))
-        i = rd.used
-        r = cauchy_row(x, y, G, B, i)
-        cd = largest(squared_magnitude(r), fj) if greedy else inverse_cdf(squared_magnitude(r), u2, fj)
-        j = cd.used
+            if need_mass:
+                rd = largest(rowmass, fi) if greedy else inverse_cdf(rowmass, u1, fi)
+            else:
+                rd = Draw(-1, fi, float("nan"), float("nan"), float("nan"), float("nan"))
+            w_row = squared_magnitude(cauchy_row(x, y, G, B, rd.used))
+            cd = largest(w_row, fj) if greedy else inverse_cdf(w_row, u2, fj)
+        i, j = rd.used, cd.used
         c, r, a = cauchy_generator_update(x, y, G, B, i, j)
         l = c / a
         l[i] = 1.0

@@ -470,6 +470,83 @@ def pin_c2plu():
         assert np.allclose(rc.U, rd.U, rtol=0, atol=1e-12 * np.abs(A).max())
 
 
+def _first_largest_bruteforce(S):
+    """The first row-major (i, j) of largest |S_ij|^2, by explicit loops."""
+    best, bi, bj = -1.0, -1, -1
+    for i in range(S.shape[0]):
+        for j in range(S.shape[1]):
+            z = complex(S[i, j])
+            v = z.real * z.real + z.imag * z.imag
+            if v > best:
+                best, bi, bj = v, i, j
+    return bi, bj
+
+
+def pin_cplu():
+    """CPLU (complete pivoting, Sec. 1): on diag(d) the pivots are the
+    diagonal in decreasing |d_i| and S ends exactly 0; where the largest
+    entry is not in the row of largest norm CPLU and C2PLU differ; on a
+    rank-one u v^T with dyadic entries the pivot is (argmax |u_i|,
+    argmax |v_j|) and one step leaves S exactly 0; ties go to the first entry
+    in row-major order, not column-major ([[1, 2], [2, 0]]) nor the last
+    (Sylvester-Hadamard 8 x 8: (0,0) then (1,1), |a| = 1 then 2); at every
+    step of random real and complex runs the pivot is the first largest
+    entry found by explicit loops and |a_t| <= 2 |a_(t-1)| (an entry of the
+    next Schur complement is at most twice the largest one); the Schur
+    relations hold as for RPLU; the Cauchy-like form makes the dense form's
+    choices, also for equal entries in different row blocks."""
+    d = np.array([3.0, -5.0, 1.0, 4.0])
+    r = O.rplu_dense(np.diag(d), complete=True)
+    assert [tuple(int(v) for v in p_) for p_ in r.piv] == [(1, 1), (3, 3), (0, 0), (2, 2)]
+    assert r.stop == O.STOP_EXHAUSTED and np.all(r.S == 0.0)
+    A = np.array([[3.0, 0.0, 0.0], [2.0, 2.0, 2.0]])
+    assert tuple(int(v) for v in O.rplu_dense(A, k=1, complete=True).piv[0]) == (0, 0)
+    assert tuple(int(v) for v in O.rplu_dense(A, k=1, greedy=True).piv[0]) == (1, 0)
+    u = np.array([1.0, 2.0, -4.0, 3.0])
+    v = np.array([2.0, -1.0, 5.0])
+    r = O.rplu_dense(np.outer(u, v), complete=True)
+    assert r.rank == 1 and tuple(int(x) for x in r.piv[0]) == (2, 2)
+    assert r.stop == O.STOP_EXHAUSTED and np.all(r.S == 0.0)
+    r = O.rplu_dense(np.array([[1.0, 2.0], [2.0, 0.0]]), k=1, complete=True)
+    assert tuple(int(x) for x in r.piv[0]) == (0, 1)
+    H = np.array([[(-1.0) ** bin(i & j).count("1") for j in range(8)] for i in range(8)])
+    r = O.rplu_dense(H, k=2, complete=True)
+    assert [tuple(int(x) for x in p_) for p_ in r.piv] == [(0, 0), (1, 1)]
+    assert abs(r.U[0, 0]) == 1.0 and abs(r.U[1, 1]) == 2.0
+    rng = np.random.default_rng(37)
+    for trial in range(8):
+        n, m = int(rng.integers(3, 12)), int(rng.integers(3, 12))
+        A = W.random_dense(n, m, seed=500 + trial, complex_=bool(trial % 2))
+        if trial == 2:
+            A = np.round(A * 2.0)                # small integers: many equal moduli
+        k = int(rng.integers(1, min(n, m) + 1))
+        res = O.rplu_dense(A, k=k, complete=True)
+        S = np.array(A, dtype=np.complex128 if np.iscomplexobj(A) else np.float64)
+        prev = None
+        for t in range(res.rank):
+            assert tuple(int(x) for x in res.piv[t]) == _first_largest_bruteforce(S), (trial, t)
+            i, j = (int(x) for x in res.piv[t])
+            a = abs(S[i, j])
+            assert prev is None or a <= 2.0 * prev * (1 + 1e-12)
+            prev = a
+            O.schur_update(S, i, j)
+        _check_schur_relations(A, res, 1e-10)
+    for p_, (n, m) in ((1, (30, 24)), (2, (21, 35))):
+        x, y, G, B = W.cauchy_like_random(n, m, p_, seed=60 + p_)
+        A = O.cauchy_entries(x, y, G, B)
+        rc = O.rplu_cauchy(x, y, G, B, k=10, complete=True)
+        rd = O.rplu_dense(A, k=10, complete=True)
+        assert np.array_equal(rc.piv, rd.piv), (rc.piv, rd.piv)
+        assert np.allclose(rc.U, rd.U, rtol=0, atol=1e-12 * np.abs(A).max())
+    # equal largest entries in different row blocks: rows 0 and 2 repeat
+    x = np.array([1.0, 2.0, 1.0, 2.0, 3.0], dtype=np.complex128)
+    y = np.array([0.0, -1.0], dtype=np.complex128)
+    G = np.ones((5, 1), dtype=np.complex128)
+    B = np.ones((1, 2), dtype=np.complex128)
+    assert O.cauchy_largest_entry(x, y, G, B, rows_per_block=2) == (0, 0)
+    assert O.cauchy_largest_entry(x, y, G, B, rows_per_block=1) == (0, 0)
+
+
 ALL_PINS = [
     pin_stall_rule,
     pin_philox_numpy, pin_inverse_cdf_bruteforce, pin_chi2_first_pivot,
@@ -477,5 +554,5 @@ ALL_PINS = [
     pin_doubling_enumeration, pin_closed_form_schur, pin_exact_recovery,
     pin_eckart_young_floor, pin_mass_bookkeeping, pin_stop_rules,
     pin_nonfinite, pin_cauchy_vs_dense, pin_cauchy_determinant,
-    pin_loewner_entries, pin_c2plu,
+    pin_loewner_entries, pin_c2plu, pin_cplu,
 ]

@@ -208,6 +208,37 @@ def _largest_min(weights, forced=None):
     return O.Draw(drawn, used, float(np.sum(w)), float("nan"), float("nan"), float("nan"))
 
 
+def _entry_ties_last(S, forced=(None, None)):
+    Wm = O.squared_magnitude(S)
+    flat = Wm.size - 1 - int(np.argmax(Wm.ravel()[::-1]))   # ties to the last entry
+    i, j = divmod(flat, Wm.shape[1])
+    return O._entry_draws(i, j, float(np.sum(Wm)), forced)
+
+
+def _entry_col_major(S, forced=(None, None)):
+    Wm = O.squared_magnitude(S)
+    j, i = np.unravel_index(int(np.argmax(Wm.T)), Wm.T.shape)   # first in column-major order
+    return O._entry_draws(int(i), int(j), float(np.sum(Wm)), forced)
+
+
+def _entry_abs_rowmax_of_norm_row(S, forced=(None, None)):
+    Wm = O.squared_magnitude(S)
+    i = int(np.argmax(np.sum(Wm, axis=1)))                  # C2PLU's row instead
+    return O._entry_draws(i, int(np.argmax(Wm[i])), float(np.sum(Wm)), forced)
+
+
+def _cauchy_entry_later_block(x, y, G, B, rows_per_block=512):
+    n = x.shape[0]
+    best, bi, bj = -1.0, -1, -1
+    for i0 in range(0, n, rows_per_block):
+        i1 = min(n, i0 + rows_per_block)
+        Wm = O.squared_magnitude((G[i0:i1] @ B) / (x[i0:i1, None] - y[None, :]))
+        r, c = np.unravel_index(int(np.argmax(Wm)), Wm.shape)
+        if Wm[r, c] >= best:                                 # a later block wins ties
+            best, bi, bj = float(Wm[r, c]), i0 + int(r), int(c)
+    return bi, bj
+
+
 MUTATIONS = [
     ("schur_sign", "schur_update", _schur_plus, [pins.pin_closed_form_schur, pins.pin_one_step_expectation]),
     ("schur_conj_u", "schur_update", _schur_conj, [pins.pin_one_step_expectation, pins.pin_unitary_dft, pins.pin_closed_form_schur]),
@@ -225,6 +256,10 @@ MUTATIONS = [
     ("col_stage_transposed", "rplu_dense", _rplu_dense_colstage_from_column, [pins.pin_chi2_first_pivot, pins.pin_mass_bookkeeping]),
     ("c2plu_ties_last", "largest", _largest_last, [pins.pin_c2plu]),
     ("c2plu_argmin", "largest", _largest_min, [pins.pin_c2plu]),
+    ("cplu_ties_last", "largest_entry", _entry_ties_last, [pins.pin_cplu]),
+    ("cplu_column_major", "largest_entry", _entry_col_major, [pins.pin_cplu]),
+    ("cplu_norm_row", "largest_entry", _entry_abs_rowmax_of_norm_row, [pins.pin_cplu]),
+    ("cplu_cauchy_later_block", "cauchy_largest_entry", _cauchy_entry_later_block, [pins.pin_cplu]),
 ]
 
 
