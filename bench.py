@@ -441,9 +441,10 @@ def main() -> int:
                          "adds under extra_workloads")
     ap.add_argument("--extra-steps", type=int, default=3,
                     help="timed steps of each extra workload")
-    ap.add_argument("--pivoting", default="rplu", choices=["rplu", "c2plu"],
+    ap.add_argument("--pivoting", default="rplu", choices=["rplu", "c2plu", "cplu"],
                     help="cauchy20k / dense workloads: c2plu = complete 2-norm pivoting "
-                         "(RPLU_FLAG_C2PLU) instead of the random draws; no CPU baseline")
+                         "(RPLU_FLAG_C2PLU), cplu (dense only) = complete pivoting "
+                         "(RPLU_FLAG_CPLU) instead of the random draws; no CPU baseline")
     ap.add_argument("--no-fp64-baseline", action="store_true",
                     help="batched4096/serve: skip the one-at-a-time FP64 GPU baseline")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
@@ -469,6 +470,9 @@ def main() -> int:
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the method runs on a single device here)", file=sys.stderr)
+        return 2
+    if args.pivoting == "cplu" and args.workload == "cauchy20k":
+        print("--pivoting cplu applies to the dense workloads only", file=sys.stderr)
         return 2
     if args.pivoting != "rplu" and args.workload in ("batched4096", "serve"):
         print(f"--pivoting {args.pivoting} applies to the dense and Cauchy workloads only",
@@ -514,9 +518,9 @@ def _run_workload(args, torch, rplu, workload) -> dict:
         wl = _setup_dense(torch, rplu, workload)
     ctx = rplu.default_context(0)
     flags = rplu.RPLU_FLAG_NO_GRAPH if args.no_graph else 0
-    if args.pivoting == "c2plu":
-        flags |= rplu.RPLU_FLAG_C2PLU
-        wl["config"] = dict(wl["config"], pivoting="c2plu")
+    if args.pivoting != "rplu":
+        flags |= rplu.RPLU_FLAG_C2PLU if args.pivoting == "c2plu" else rplu.RPLU_FLAG_CPLU
+        wl["config"] = dict(wl["config"], pivoting=args.pivoting)
         args.no_cpu_baseline = True
     res = None
     # warm-up also builds the step-loop graphs (cached in the context)

@@ -136,6 +136,21 @@ enum {
                                      RPLU_FLAG_COLMASS (then eager)          */
     RPLU_FLAG_EAGER_SWEEP = 1u << 10, /* dense: read and write S every step
                                      (the default below RPLU_LAZY_MIN_BYTES) */
+    RPLU_FLAG_CPLU = 1u << 11,      /* dense (rplu_dense): complete pivoting
+                                     (Sec. 1; Sec. 2.3.2) instead of the
+                                     random draws: (i, j) = the entry of
+                                     largest |S_ij|^2 (FP64) over all of S,
+                                     the first in row-major order among
+                                     equal ones. Each sweep also keeps the
+                                     largest |S_ij|^2 of every row; i is the
+                                     first row of largest such value, j the
+                                     first column of largest |S_ij| in it.
+                                     Same update and stop test, seed and
+                                     stream unused. Not with RPLU_FLAG_C2PLU
+                                     (RPLU_E_ARG) or RPLU_FLAG_COLMASS;
+                                     rplu_cauchy, rplu_batched and the
+                                     server reject it (RPLU_E_UNSUPPORTED,
+                                     RPLU_E_ARG).                            */
     RPLU_FLAG_CERTIFY = 1u << 7,    /* server, dense R32/R64 jobs: after the run,
                                      ||A - L U||_F^2 is formed in FP64 on the
                                      matrix cores from the original A and

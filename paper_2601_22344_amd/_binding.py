@@ -49,6 +49,7 @@ RPLU_FLAG_CERTIFY = 128
 RPLU_FLAG_KEEP_INPUT = 256
 RPLU_FLAG_LAZY_SWEEP = 512
 RPLU_FLAG_EAGER_SWEEP = 1024
+RPLU_FLAG_CPLU = 2048
 RPLU_LAZY_STEPS = 4
 RPLU_MAX_REFRESH = 8
 RPLU_REFRESH_DROP2 = 1e-4

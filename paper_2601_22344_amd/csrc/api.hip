@@ -265,6 +265,7 @@ DenseWs dense_ws_layout(int dtype, int64_t n, int64_t m, uint32_t flags, bool ne
     DenseWs w;
     w.o_st = cv.take(sizeof(StepState));
     w.o_rm = cv.take((size_t)n * 8);
+    w.o_rx = (flags & RPLU_FLAG_CPLU) ? cv.take((size_t)n * 8) : 0;
     w.o_ctr = cv.take((size_t)cdf_chunks((int)n) * 8);
     w.o_ctc = cv.take((size_t)cdf_chunks((int)m) * 8);
     const int64_t nbc = (n + DENSE_ROWS_COLMASS - 1) / DENSE_ROWS_COLMASS;
@@ -294,6 +295,12 @@ rplu_status dense_check(const char* who, int dtype, int64_t n, int64_t m, const 
     if (n > RPLU_MAX_DIM || m > RPLU_MAX_DIM)
         return fail(RPLU_E_UNSUPPORTED, "%s: n and m must be <= %lld", who,
                     (long long)RPLU_MAX_DIM);
+    if (opts->flags & RPLU_FLAG_CPLU) {
+        if (opts->flags & RPLU_FLAG_C2PLU)
+            return fail(RPLU_E_ARG, "%s: RPLU_FLAG_CPLU with RPLU_FLAG_C2PLU", who);
+        if (opts->flags & RPLU_FLAG_COLMASS)
+            return fail(RPLU_E_UNSUPPORTED, "%s: RPLU_FLAG_CPLU with RPLU_FLAG_COLMASS", who);
+    }
     if (opts->flags & RPLU_FLAG_REFRESH) {
         if (dtype != RPLU_R32 && dtype != RPLU_R64)
             return fail(RPLU_E_UNSUPPORTED, "%s: RPLU_FLAG_REFRESH needs R32 or R64", who);
@@ -340,6 +347,7 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
     a.piv = piv;
     a.st = (StepState*)(ws + w.o_st);
     a.rowmass = (double*)(ws + w.o_rm);
+    a.rowmax = (opts->flags & RPLU_FLAG_CPLU) ? (double*)(ws + w.o_rx) : nullptr;
     a.ct_col = (double*)(ws + w.o_ctc);
     a.colpart = colmass ? (double*)(ws + w.o_cp) : nullptr;
     a.colmass = colmass;
@@ -379,7 +387,8 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
     sa.kmax = kmax;
     sa.tol2 = a.tol2;
     sa.stall = (opts->flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
-    sa.greedy = (opts->flags & RPLU_FLAG_C2PLU) ? 1 : 0;
+    sa.greedy = (opts->flags & RPLU_FLAG_C2PLU) ? 1 : (opts->flags & RPLU_FLAG_CPLU) ? 2 : 0;
+    sa.rowmax = a.rowmax;
     sa.forced = opts->forced;
     sa.trace = opts->trace;
     sa.rowmass_out = opts->rowmass_out;
@@ -458,6 +467,8 @@ rplu_status cauchy_check(const char* who, int dtype, int64_t n, int64_t m, int p
     if (opts == nullptr || info == nullptr)
         return fail(RPLU_E_ARG, "%s: opts and info are required", who);
     if (dtype != RPLU_C128) return fail(RPLU_E_UNSUPPORTED, "%s: only RPLU_C128", who);
+    if (opts->flags & RPLU_FLAG_CPLU)
+        return fail(RPLU_E_UNSUPPORTED, "%s: RPLU_FLAG_CPLU is for dense matrices", who);
     if (n < 1 || m < 1 || n > INT32_MAX || m > INT32_MAX)
         return fail(RPLU_E_ARG, "%s: shape out of range", who);
     if (p < 1 || p > 4) return fail(RPLU_E_UNSUPPORTED, "%s: p must be in [1, 4]", who);

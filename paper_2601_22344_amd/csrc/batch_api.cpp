@@ -43,8 +43,9 @@ rplu_status prepare(int64_t count, const rplu_job* jobs, Prepared& P, const char
         if (j.L != nullptr && j.ldl < j.n) return fail(RPLU_E_ARG, "%s: job %lld: ldl < n", who, lb);
         if (j.U != nullptr && j.ldu < j.m) return fail(RPLU_E_ARG, "%s: job %lld: ldu < m", who, lb);
         if (!(j.rel_tol >= 0.0)) return fail(RPLU_E_ARG, "%s: job %lld: rel_tol must be >= 0", who, lb);
-        if (j.flags & RPLU_FLAG_C2PLU)
-            return fail(RPLU_E_ARG, "%s: job %lld: RPLU_FLAG_C2PLU is not available in batches", who, lb);
+        if (j.flags & (RPLU_FLAG_C2PLU | RPLU_FLAG_CPLU))
+            return fail(RPLU_E_ARG, "%s: job %lld: RPLU_FLAG_C2PLU and RPLU_FLAG_CPLU are not "
+                        "available in batches", who, lb);
         if ((j.flags & RPLU_FLAG_REFRESH) &&
             (j.A_orig == nullptr || j.lda_orig < j.m || j.L == nullptr || j.U == nullptr))
             return fail(RPLU_E_ARG, "%s: job %lld: RPLU_FLAG_REFRESH needs A_orig (lda_orig >= m), "

@@ -67,14 +67,40 @@ __device__ inline void st_s(T* p, const Pack<T, V>& v) {
     }
 }
 
+// Whole workgroup: out[q] = the largest of rx[q] over all threads, for the
+// nr rows of the block (a maximum is exact, so the order does not matter).
+template <int R, int BS>
+__device__ inline void row_max_reduce(double (&rx)[R], int nr, double* out) {
+    __shared__ double mx[BS / RPLU_WAVE][R];
+    const int lane = threadIdx.x % RPLU_WAVE, wv = threadIdx.x / RPLU_WAVE;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        double v = rx[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(v, off, RPLU_WAVE);
+            v = o > v ? o : v;
+        }
+        if (lane == 0) mx[wv][q] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nr) {
+        double v = mx[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < BS / RPLU_WAVE; ++w) v = mx[w][threadIdx.x] > v ? mx[w][threadIdx.x] : v;
+        out[threadIdx.x] = v;
+    }
+}
+
 // ----------------------------------------------------------------- sweep
 
-template <class T, int R, int BS, int V, bool INIT, bool COLMASS>
+// CMAX (RPLU_FLAG_CPLU): also the largest |S_ij|^2 of every row, into rowmax.
+template <class T, int R, int BS, int V, bool INIT, bool COLMASS, bool CMAX>
 __global__ __launch_bounds__(BS) void k_dense_sweep(
     T* __restrict__ S, int64_t lda, int n, int m,
     const T* __restrict__ U, int64_t ldu, T* __restrict__ L, int64_t ldl,
     const StepState* __restrict__ st, double* __restrict__ rowmass,
-    double* __restrict__ colpart) {
+    double* __restrict__ colpart, double* __restrict__ rowmax) {
     using W = typename Sc<T>::W;
     const int tid = threadIdx.x;
     const int lane = tid % RPLU_WAVE, wv = tid / RPLU_WAVE;
@@ -106,9 +132,9 @@ __global__ __launch_bounds__(BS) void k_dense_sweep(
         }
         __syncthreads();   // every S[r, j] is read before any store to it
     }
-    double rp[R];
+    double rp[R], rx[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) rp[q] = 0.0;
+    for (int q = 0; q < R; ++q) { rp[q] = 0.0; rx[q] = 0.0; }
 
     // One pack of V elements at column c for the R rows: update, exact zeros
     // on the pivot row and column, masses. FULL packs use unguarded 16-byte
@@ -157,6 +183,7 @@ __global__ __launch_bounds__(BS) void k_dense_sweep(
                     const double m2 = Sc<T>::mag2(s[q].v[v]);   // 0 for padding
                     rp[q] += m2;
                     if constexpr (COLMASS) cp[v] += m2;
+                    if constexpr (CMAX) rx[q] = m2 > rx[q] ? m2 : rx[q];
                 }
                 if constexpr (!INIT) {
                     T* p = S + (int64_t)(r0 + q) * lda + c;
@@ -191,6 +218,7 @@ __global__ __launch_bounds__(BS) void k_dense_sweep(
         double v = wave_sum(rp[q]);
         if (lane == 0) red[wv][q] = v;
     }
+    if constexpr (CMAX) row_max_reduce<R, BS>(rx, nr, rowmax + r0);
     __syncthreads();
     if (tid < nr) {
         double v = red[0][tid];
@@ -278,12 +306,12 @@ __device__ inline LazyRowAcc<T> lazy_row(const T* S, int64_t lda, const T* U, in
 // tb..t-1 plus step t, whose multipliers L(:,t) are formed here); row masses
 // (and column partials) of S^(t+1). FINAL = true: after the run, S^(st->t)
 // written back if the last write-back is older; no masses.
-template <class T, int R, int BS, int V, bool COLMASS, bool FINAL>
+template <class T, int R, int BS, int V, bool COLMASS, bool FINAL, bool CMAX>
 __global__ __launch_bounds__(BS) void k_dense_lazy(
     T* __restrict__ S, int64_t lda, int n, int m,
     const T* __restrict__ U, int64_t ldu, T* __restrict__ L, int64_t ldl,
     const int32_t* __restrict__ piv, StepState* __restrict__ st, double* __restrict__ rowmass,
-    double* __restrict__ colpart, int kmax) {
+    double* __restrict__ colpart, int kmax, double* __restrict__ rowmax) {
     using W = typename Sc<T>::W;
     const int tid = threadIdx.x;
     const int lane = tid % RPLU_WAVE, wv = tid / RPLU_WAVE;
@@ -356,13 +384,16 @@ __global__ __launch_bounds__(BS) void k_dense_lazy(
 #pragma unroll
         for (int q = 0; q < R; ++q) all = all && (q >= nr || zrow[q]);
         if (all && !COLMASS) {
-            if (tid < nr) rowmass[r0 + tid] = 0.0;
+            if (tid < nr) {
+                rowmass[r0 + tid] = 0.0;
+                if constexpr (CMAX) rowmax[r0 + tid] = 0.0;
+            }
             return;
         }
     }
-    double rp[R];
+    double rp[R], rx[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) rp[q] = 0.0;
+    for (int q = 0; q < R; ++q) { rp[q] = 0.0; rx[q] = 0.0; }
 
     // The column loop for a window of WW steps (a compile-time length: no
     // per-step branches, only the live multipliers in registers).
@@ -428,6 +459,7 @@ __global__ __launch_bounds__(BS) void k_dense_lazy(
                                 const double m2 = Sc<T>::mag2(x[q].v[v]);   // 0 for padding
                                 rp[q] += m2;
                                 if constexpr (COLMASS) cp[v] += m2;
+                                if constexpr (CMAX) rx[q] = m2 > rx[q] ? m2 : rx[q];
                             }
                         }
                     }
@@ -478,6 +510,7 @@ __global__ __launch_bounds__(BS) void k_dense_lazy(
         double v = wave_sum(rp[q]);
         if (lane == 0) red[wv][q] = v;
     }
+    if constexpr (CMAX) row_max_reduce<R, BS>(rx, nr, rowmax + r0);
     __syncthreads();
     if (tid < nr) {
         double v = red[0][tid];
@@ -565,25 +598,29 @@ __global__ __launch_bounds__(CDF_THREADS) void k_dense_pivot(const T* __restrict
 
 // ---------------------------------------------------------------- launchers
 
-template <class T, int R, int V, bool INIT, bool COLMASS>
+template <class T, int R, int V, bool INIT, bool COLMASS, bool CMAX>
 static void launch_sweep_v(const DenseArgs& a, hipStream_t s) {
     constexpr int BS = COLMASS ? DENSE_THREADS_COLMASS : DENSE_THREADS;
     const int nb = (int)((a.n + R - 1) / R);
-    hipLaunchKernelGGL((k_dense_sweep<T, R, BS, V, INIT, COLMASS>), dim3(nb), dim3(BS), 0, s,
+    hipLaunchKernelGGL((k_dense_sweep<T, R, BS, V, INIT, COLMASS, CMAX>), dim3(nb), dim3(BS), 0, s,
                        (T*)a.S, a.lda, (int)a.n, (int)a.m, (const T*)a.U, a.ldu, (T*)a.L, a.ldl,
-                       a.st, a.rowmass, a.colpart);
+                       a.st, a.rowmass, a.colpart, a.rowmax);
 }
 
-template <class T, int R, bool INIT, bool COLMASS>
+template <class T, int R, bool INIT, bool COLMASS, bool CMAX = false>
 static void launch_sweep_t(const DenseArgs& a, hipStream_t s) {
     constexpr int VV = 16 / (int)sizeof(T);
-    if (a.vec_ok) launch_sweep_v<T, R, VV, INIT, COLMASS>(a, s);
-    else launch_sweep_v<T, R, 1, INIT, COLMASS>(a, s);
+    if (a.vec_ok) launch_sweep_v<T, R, VV, INIT, COLMASS, CMAX>(a, s);
+    else launch_sweep_v<T, R, 1, INIT, COLMASS, CMAX>(a, s);
 }
 
+// (the host never asks for column masses with CPLU's row maxima)
 template <class T>
 static void launch_sweep_dt(const DenseArgs& a, bool init, hipStream_t s) {
-    if (a.colmass) {
+    if (a.rowmax) {
+        if (init) launch_sweep_t<T, DENSE_ROWS, true, false, true>(a, s);
+        else launch_sweep_t<T, DENSE_ROWS, false, false, true>(a, s);
+    } else if (a.colmass) {
         if (init) launch_sweep_t<T, DENSE_ROWS_COLMASS, true, true>(a, s);
         else launch_sweep_t<T, DENSE_ROWS_COLMASS, false, true>(a, s);
     } else {
@@ -592,22 +629,28 @@ static void launch_sweep_dt(const DenseArgs& a, bool init, hipStream_t s) {
     }
 }
 
-template <class T, int R, int V, bool COLMASS, bool FINAL>
+template <class T, int R, int V, bool COLMASS, bool FINAL, bool CMAX>
 static void launch_lazy_v(const DenseArgs& a, hipStream_t s) {
     constexpr int BS = COLMASS ? DENSE_THREADS_COLMASS : DENSE_THREADS;
     const int nb = (int)((a.n + R - 1) / R);
-    hipLaunchKernelGGL((k_dense_lazy<T, R, BS, V, COLMASS, FINAL>), dim3(nb), dim3(BS), 0, s,
+    hipLaunchKernelGGL((k_dense_lazy<T, R, BS, V, COLMASS, FINAL, CMAX>), dim3(nb), dim3(BS), 0, s,
                        (T*)a.S, a.lda, (int)a.n, (int)a.m, (const T*)a.U, a.ldu, (T*)a.L, a.ldl,
-                       a.piv, a.st, a.rowmass, a.colpart, (int)a.kmax);
+                       a.piv, a.st, a.rowmass, a.colpart, (int)a.kmax, a.rowmax);
 }
 
-// (column masses take the eager sweep: the host never sets lazy with them)
+// (column masses take the eager sweep: the host never sets lazy with them;
+// the final write-back forms no masses)
 template <class T, bool FINAL>
 static void launch_lazy_dt(const DenseArgs& a, hipStream_t s) {
     constexpr int VV = 16 / (int)sizeof(T);
     constexpr int R = Sc<T>::cplx ? DENSE_LAZY_ROWS / 2 : DENSE_LAZY_ROWS;
-    if (a.vec_ok) launch_lazy_v<T, R, VV, false, FINAL>(a, s);
-    else launch_lazy_v<T, R, 1, false, FINAL>(a, s);
+    if (!FINAL && a.rowmax) {
+        if (a.vec_ok) launch_lazy_v<T, R, VV, false, FINAL, true>(a, s);
+        else launch_lazy_v<T, R, 1, false, FINAL, true>(a, s);
+    } else {
+        if (a.vec_ok) launch_lazy_v<T, R, VV, false, FINAL, false>(a, s);
+        else launch_lazy_v<T, R, 1, false, FINAL, false>(a, s);
+    }
 }
 
 template <bool FINAL>

@@ -36,6 +36,7 @@ struct DenseArgs {
     int32_t* piv;
     StepState* st;
     double* rowmass;     // n
+    double* rowmax;      // n: largest |S_ij|^2 of each row (RPLU_FLAG_CPLU), or null
     double* ct_col;      // chunk totals of the pivot row's masses
     double* colpart;     // ceil(n / DENSE_ROWS_COLMASS) * m, when colmass
     bool colmass;
@@ -62,6 +63,7 @@ struct SampleArgs {
     int p;               // 0: dense; >= 1: Cauchy-like displacement rank
     int64_t n, m;
     const double* rowmass;
+    const double* rowmax;   // greedy == 2: largest |S_ij|^2 of each row
     double* ct_row;      // chunk totals of the row masses
     double* ct_col;      // chunk totals of the pivot row's masses
     StepState* st;
@@ -78,7 +80,9 @@ struct SampleArgs {
     double* trace;
     double* rowmass_out;
     int fused;           // dense: one fused pivot kernel per step (n, m <= PIVOT_FUSED_MAX)
-    int greedy;          // RPLU_FLAG_C2PLU: the largest masses instead of the draws
+    int greedy;          // 1: C2PLU, the largest masses instead of the draws;
+                         // 2: CPLU, the row of the largest entry (rowmax), then
+                         // the largest entry of that row
 };
 
 void launch_state_init(StepState* st, hipStream_t s, int refresh_on = 0);

@@ -43,7 +43,10 @@ struct PivotArgs {
     const int32_t* forced;
     double* trace;
     double* rowmass_out;
-    int greedy;             // C2PLU (Sec. 2.3.3): the largest masses instead of the draws
+    int greedy;             // 1: C2PLU (Sec. 2.3.3), the largest masses instead of
+                            // the draws; 2: CPLU (Sec. 1, complete pivoting), the
+                            // first row of largest rowmax, then as C2PLU's column
+    const double* rowmax;   // greedy == 2: largest |S_ij|^2 of each row
 };
 
 // What the stop test reads from the state besides t, loaded at the start of
@@ -208,8 +211,11 @@ __device__ inline int pivot_row_draw_ct(CdfShared& sh, int* flag, const PivotArg
         for (int e = threadIdx.x; e < a.n; e += CDF_THREADS)
             a.rowmass_out[(int64_t)t * a.n + e] = a.rowmass[e];
     const double tgt = unit_from_word(rnd.w[0]) * T;
-    const CdfPick p = a.greedy ? CdfPick{wg_argmax(sh, a.n, mass), 0.0, 0.0}
-                               : cdf_draw(sh, ct, K, a.n, mass, tgt);
+    // CPLU: the first row holding the largest entry; with C2PLU's column
+    // choice in that row this is the first largest entry in row-major order
+    const CdfPick p = a.greedy == 2 ? CdfPick{wg_argmax(sh, a.n, RowMassGlobal{a.rowmax}), 0.0, 0.0}
+                    : a.greedy     ? CdfPick{wg_argmax(sh, a.n, mass), 0.0, 0.0}
+                                   : cdf_draw(sh, ct, K, a.n, mass, tgt);
     const int i = a.forced ? a.forced[2 * t] : p.idx;
     if (i < 0 || i >= a.n) {
         if (threadIdx.x == 0) { st->error = RPLU_E_ARG; st->done = 1; }
@@ -431,6 +437,7 @@ inline PivotArgs pivot_args(const SampleArgs& sa) {
     p.trace = sa.trace;
     p.rowmass_out = sa.rowmass_out;
     p.greedy = sa.greedy;
+    p.rowmax = sa.rowmax;
     return p;
 }
 

@@ -88,7 +88,7 @@ inline void timed(rplu_ctx_s* ctx, int cls, hipStream_t s, F&& launch) {
 // Dense-run workspace layout and the shared dense step loop (api.hip); the
 // context-free caller (rplu_dense_noalloc) passes ctx == nullptr.
 struct DenseWs {
-    size_t o_st, o_rm, o_ctr, o_ctc, o_cp, o_u, total;
+    size_t o_st, o_rm, o_rx, o_ctr, o_ctc, o_cp, o_u, total;
 };
 DenseWs dense_ws_layout(int dtype, int64_t n, int64_t m, uint32_t flags, bool need_u);
 rplu_status dense_check(const char* who, int dtype, int64_t n, int64_t m, const void* A,

@@ -645,7 +645,8 @@ rplu_status plan_job(const rplu_server_s* S, const rplu_job& d, SJob* j) {
         j->out_bytes = off;
     }
     if (!(d.rel_tol >= 0.0)) return fail(RPLU_E_ARG, "rplu_server_submit: rel_tol must be >= 0");
-    if (d.flags & RPLU_FLAG_C2PLU) return fail(RPLU_E_ARG, "rplu_server_submit: RPLU_FLAG_C2PLU is not served");
+    if (d.flags & (RPLU_FLAG_C2PLU | RPLU_FLAG_CPLU))
+        return fail(RPLU_E_ARG, "rplu_server_submit: RPLU_FLAG_C2PLU and RPLU_FLAG_CPLU are not served");
     if (j->work_bytes + j->out_bytes > S->pool_cap)
         return fail(RPLU_E_ARG, "rplu_server_submit: footprint %zu exceeds the pool (%zu bytes)",
                     j->work_bytes + j->out_bytes, S->pool_cap);
