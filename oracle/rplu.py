@@ -39,6 +39,9 @@ Readings where the paper is silent (each also listed in the design notes):
   i = a row of largest mass ||S_i,:||^2, then j = a column of largest
   |S_ij| in that row; ties go to the smallest index. Same update and stop
   test; no random numbers.
+* RPLU in CUR form, Alg. 2 (Sec. 4.1): the same draws on row norms of the
+  residual that are updated from A, the index sets and the core matrix
+  U_k = A[I, J]^{-1} (eq. block-inverse-update), A never written.
 * CPLU (complete pivoting, Sec. 1 and Sec. 2.3.2): (i, j) = an entry of
   largest |S_ij| over the whole Schur complement; moduli are compared as
   |S_ij|^2 in FP64 (squared_magnitude), and ties go to the first entry in
@@ -319,6 +322,126 @@ def schur_closed_form_masses(get_rows, n: int, I: Sequence[int], J: Sequence[int
 def get_rows_at(get_rows, idx):
     """Rows idx of A (FP64) through a row-range accessor."""
     return np.stack([get_rows(int(r), int(r) + 1)[0] for r in idx]) if len(idx) else None
+
+
+# ------------------------------------------------------------- CUR form
+
+@dataclass
+class CURResult:
+    """RPLU in CUR form: A ~ A[:, J] Uc A[I, :] with Uc = A[I, J]^{-1}."""
+    I: np.ndarray                 # rank row indices, in selection order
+    J: np.ndarray                 # rank column indices
+    Uc: np.ndarray                # rank x rank core matrix
+    rank: int
+    stop: int
+    a_fro2: float                 # sum of the initial row norms, ||A||_F^2
+    res_fro2: float               # sum of the row-norm estimates at the stop test
+    rownorms: np.ndarray          # the row-norm estimates at the stop test
+    trace: list = field(default_factory=list)
+    masses: list = field(default_factory=list)
+
+    @property
+    def piv(self) -> np.ndarray:
+        return np.stack([self.I, self.J], axis=1) if self.rank else np.zeros((0, 2), np.int64)
+
+
+def block_inverse_update(Uc: np.ndarray, z: np.ndarray, w: np.ndarray, omega):
+    """U_{k+1} = A[I+i, J+j]^{-1} from U_k = A[I, J]^{-1} (eq.
+    block-inverse-update): with W_{k+1} = [[W_k, w], [z^T, omega]] and
+    sigma = omega - z^T U_k w, the blocks U_k + U_k w z^T U_k / sigma,
+    -U_k w / sigma, -z^T U_k / sigma and 1 / sigma. Returns (U_{k+1}, sigma)."""
+    Uw = Uc @ w
+    zU = z @ Uc
+    sigma = omega - zU @ w
+    if sigma == 0:
+        raise ZeroPivot("zero Schur complement of the core matrix")
+    k = Uc.shape[0]
+    out = np.empty((k + 1, k + 1), dtype=np.result_type(Uc, z, w, omega))
+    out[:k, :k] = Uc + np.outer(Uw, zU) / sigma
+    out[:k, k] = -Uw / sigma
+    out[k, :k] = -zU / sigma
+    out[k, k] = 1.0 / sigma
+    return out, sigma
+
+
+def cur_rownorm_update(A, I, J, Uc, nrm, l, chat):
+    """Row norms of A^(k+1) = A^(k) - chat l^T from those of A^(k) (Sec. 4.1,
+    row-norm updates): n - 2 Re((g - v) conj(chat)) + ||l||^2 |chat|^2 with
+    g = A conj(l) and v = A[:, J] U_k g[I], so that g - v = A^(k) conj(l)."""
+    g = A @ np.conj(l)
+    v = A[:, J] @ (Uc @ g[I]) if I else np.zeros_like(g)
+    l2 = float(np.sum(squared_magnitude(l)))
+    return nrm - 2.0 * np.real((g - v) * np.conj(chat)) + l2 * squared_magnitude(chat)
+
+
+def rplu_cur(A: np.ndarray, k: int = 0, tol: float = 0.0, seed: int = 0, stream: int = 0,
+             forced: Optional[Sequence] = None, keep_masses: bool = False, stall: bool = False,
+             greedy: bool = False) -> CURResult:
+    """Alg. 2 (Sec. 4.1, RPLU in CUR form): A is only read. The state is the
+    index sets I, J, the core U_k = A[I, J]^{-1} and the row norms n_k of
+    the residual A^(k) = A - A[:, J] U_k A[I, :], which are updated (not
+    recomputed) each step. Same draws, stop test and stall rule as
+    rplu_dense; greedy: C2PLU (Sec. 2.3.3) instead of the draws.
+
+    Readings: the residual's entries in the selected columns (of its pivot
+    row) and selected rows (of its pivot column) are set to exactly 0, as in
+    the dense form; the row-norm step uses g = A conj(l) (the derivation of
+    the row-norm recurrence for complex A; Alg. 2 prints A l, the same for
+    real A); the estimates of selected rows are set to 0 and negative
+    estimates (rounding) to 0."""
+    A = np.asarray(A)
+    A = A.astype(np.complex128 if np.iscomplexobj(A) else np.float64, copy=False)
+    n, m = A.shape
+    kmax = _kmax(n, m, k)
+    I: list = []
+    J: list = []
+    Uc = np.zeros((0, 0), dtype=A.dtype)
+    nrm = np.sum(squared_magnitude(A), axis=1)           # initial row norms
+    sel = np.zeros(n, dtype=bool)
+    trace, masses = [], []
+    T0 = None
+    stall_ref = [0.0, 0] if stall else None
+    t = 0
+    while True:
+        T = float(np.cumsum(nrm)[-1]) if n else 0.0
+        if not np.isfinite(T):
+            raise NonFiniteInput("non-finite entry in the input")
+        if t == 0:
+            T0 = T
+        stop = _stop_reason(t, T, T0, kmax, tol, stall_ref)
+        if stop:
+            break
+        if keep_masses:
+            masses.append(nrm.copy())
+        u1, u2 = step_uniforms(seed, stream, t)
+        fi, fj = _forced_at(forced, t)
+        # Step 1: pivot row of the residual, its column
+        rd = largest(nrm, fi) if greedy else inverse_cdf(nrm, u1, fi)
+        i = rd.used
+        r = A[i, :]
+        rhat = r - A[I, :].T @ (Uc.T @ r[J]) if I else r.copy()
+        rhat[J] = 0.0
+        w_row = squared_magnitude(rhat)
+        cd = largest(w_row, fj) if greedy else inverse_cdf(w_row, u2, fj)
+        j = cd.used
+        if rhat[j] == 0:
+            raise ZeroPivot(f"pivot ({i},{j}) is zero")
+        c = A[:, j]
+        chat = c - A[:, J] @ (Uc @ c[I]) if I else c.copy()
+        chat[I] = 0.0
+        # Step 2: row norms of A^(k+1) = A^(k) - chat l^T
+        nrm = cur_rownorm_update(A, I, J, Uc, nrm, rhat / rhat[j], chat)
+        sel[i] = True
+        nrm[sel] = 0.0
+        nrm = np.maximum(nrm, 0.0)
+        # Step 3: core matrix
+        Uc, _ = block_inverse_update(Uc, A[i, J], A[I, j], A[i, j])
+        I.append(i)
+        J.append(j)
+        trace.append(StepTrace(t, rd, cd, complex(rhat[j])))
+        t += 1
+    return CURResult(np.array(I, dtype=np.int64), np.array(J, dtype=np.int64), Uc, t, stop,
+                     T0, T, nrm, trace=trace, masses=masses)
 
 
 # -------------------------------------------------------- Cauchy-like form

@@ -547,6 +547,54 @@ def pin_cplu():
     assert O.cauchy_largest_entry(x, y, G, B, rows_per_block=1) == (0, 0)
 
 
+def pin_cur_form():
+    """RPLU in CUR form (Alg. 2): at every step of real and complex runs the
+    core U_k equals numpy.linalg.inv(A[I, J]) and the updated row norms equal
+    the row norms of the closed-form Schur complement
+    A - A[:, J] A[I, J]^{-1} A[I, :] (1e-12 of ||A||^2); the pivots are the
+    dense Alg. 1's for the same seed and stream (the same two-stage
+    distribution), also for C2PLU; a rank-r input is reproduced by
+    A[:, J] U_r A[I, :] after r steps; a tolerance run stops where the dense
+    form does; A is not written; eq. block-inverse-update grows W^{-1} as the
+    library inverse does."""
+    for trial, cplx in enumerate((False, True, False, True)):
+        n, m = (37, 29) if trial < 2 else (23, 41)
+        A = W.random_dense(n, m, seed=600 + trial, complex_=cplx)
+        A0 = A.copy()
+        kk = min(n, m) - 3
+        r = O.rplu_cur(A, k=kk, seed=trial, stream=5)
+        assert np.array_equal(A, A0)
+        d = O.rplu_dense(A, k=kk, seed=trial, stream=5)
+        assert np.array_equal(r.piv, d.piv), trial
+        for t in (1, 2, kk // 2, kk):
+            rt = O.rplu_cur(A, k=t, seed=trial, stream=5)
+            W_ = A[np.ix_(rt.I, rt.J)]
+            Winv = np.linalg.inv(W_)
+            assert np.abs(rt.Uc - Winv).max() <= 1e-10 * np.abs(Winv).max() * np.linalg.cond(W_)
+            S = O.schur_closed_form(A, rt.I, rt.J)
+            exact = np.sum(np.abs(S) ** 2, axis=1)
+            assert np.abs(rt.rownorms - exact).max() <= 1e-12 * r.a_fro2, (trial, t)
+            assert np.all(rt.rownorms[rt.I] == 0.0)
+        g = O.rplu_cur(A, k=kk, greedy=True)
+        assert np.array_equal(g.piv, O.rplu_dense(A, k=kk, greedy=True).piv)
+    Ar = W.rank_r_dense(30, 26, 5, seed=7)
+    r = O.rplu_cur(Ar, k=5, seed=2)
+    approx = Ar[:, r.J] @ r.Uc @ Ar[r.I, :]
+    assert np.abs(approx - Ar).max() <= 1e-12 * np.abs(Ar).max()
+    assert r.res_fro2 <= 1e-13 * r.a_fro2          # the downdates cancel to rounding
+    Ad = W.dense_with_spectrum(60, 50, 0.6 ** np.arange(50), seed=8)
+    rc = O.rplu_cur(Ad, tol=1e-5, seed=4)
+    rd = O.rplu_dense(Ad, tol=1e-5, seed=4)
+    assert rc.stop == rd.stop == O.STOP_TOL and rc.rank == rd.rank
+    assert np.array_equal(rc.piv, rd.piv)
+    rng = np.random.default_rng(9)
+    M = rng.standard_normal((8, 8))
+    U = np.zeros((0, 0))
+    for q in range(8):
+        U, sig = O.block_inverse_update(U, M[q, :q], M[:q, q], M[q, q])
+        assert np.allclose(U, np.linalg.inv(M[:q + 1, :q + 1]), rtol=0, atol=1e-11)
+
+
 ALL_PINS = [
     pin_stall_rule,
     pin_philox_numpy, pin_inverse_cdf_bruteforce, pin_chi2_first_pivot,
@@ -554,5 +602,5 @@ ALL_PINS = [
     pin_doubling_enumeration, pin_closed_form_schur, pin_exact_recovery,
     pin_eckart_young_floor, pin_mass_bookkeeping, pin_stop_rules,
     pin_nonfinite, pin_cauchy_vs_dense, pin_cauchy_determinant,
-    pin_loewner_entries, pin_c2plu, pin_cplu,
+    pin_loewner_entries, pin_c2plu, pin_cplu, pin_cur_form,
 ]

@@ -239,6 +239,38 @@ def _cauchy_entry_later_block(x, y, G, B, rows_per_block=512):
     return bi, bj
 
 
+def _cur_norm_plus(A, I, J, Uc, nrm, l, chat):
+    g = A @ np.conj(l)
+    v = A[:, J] @ (Uc @ g[I]) if I else np.zeros_like(g)
+    l2 = float(np.sum(O.squared_magnitude(l)))
+    return nrm + 2.0 * np.real((g - v) * np.conj(chat)) + l2 * O.squared_magnitude(chat)
+
+
+def _cur_norm_no_conj(A, I, J, Uc, nrm, l, chat):
+    g = A @ l                                            # Alg. 2 as printed, for complex A
+    v = A[:, J] @ (Uc @ g[I]) if I else np.zeros_like(g)
+    l2 = float(np.sum(O.squared_magnitude(l)))
+    return nrm - 2.0 * np.real((g - v) * np.conj(chat)) + l2 * O.squared_magnitude(chat)
+
+
+def _cur_norm_no_v(A, I, J, Uc, nrm, l, chat):
+    g = A @ np.conj(l)                                   # A l instead of A^(k) l
+    l2 = float(np.sum(O.squared_magnitude(l)))
+    return nrm - 2.0 * np.real(g * np.conj(chat)) + l2 * O.squared_magnitude(chat)
+
+
+def _core_sign(Uc, z, w, omega):
+    Uw, zU = Uc @ w, z @ Uc
+    sigma = omega - zU @ w
+    k = Uc.shape[0]
+    out = np.empty((k + 1, k + 1), dtype=np.result_type(Uc, z, w, omega))
+    out[:k, :k] = Uc + np.outer(Uw, zU) / sigma
+    out[:k, k] = Uw / sigma                              # sign of the new column
+    out[k, :k] = -zU / sigma
+    out[k, k] = 1.0 / sigma
+    return out, sigma
+
+
 MUTATIONS = [
     ("schur_sign", "schur_update", _schur_plus, [pins.pin_closed_form_schur, pins.pin_one_step_expectation]),
     ("schur_conj_u", "schur_update", _schur_conj, [pins.pin_one_step_expectation, pins.pin_unitary_dft, pins.pin_closed_form_schur]),
@@ -260,6 +292,10 @@ MUTATIONS = [
     ("cplu_column_major", "largest_entry", _entry_col_major, [pins.pin_cplu]),
     ("cplu_norm_row", "largest_entry", _entry_abs_rowmax_of_norm_row, [pins.pin_cplu]),
     ("cplu_cauchy_later_block", "cauchy_largest_entry", _cauchy_entry_later_block, [pins.pin_cplu]),
+    ("cur_norm_sign", "cur_rownorm_update", _cur_norm_plus, [pins.pin_cur_form]),
+    ("cur_norm_no_conj", "cur_rownorm_update", _cur_norm_no_conj, [pins.pin_cur_form]),
+    ("cur_norm_no_v", "cur_rownorm_update", _cur_norm_no_v, [pins.pin_cur_form]),
+    ("cur_core_sign", "block_inverse_update", _core_sign, [pins.pin_cur_form]),
 ]
 
 
