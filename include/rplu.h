@@ -281,6 +281,34 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m,
                        int32_t* piv, void* L, int64_t ldl, void* U, int64_t ldu,
                        rplu_info* info, void* hip_stream);
 
+/* RPLU in CUR form (Alg. 2, Sec. 4.1): the approximation is kept as
+ * A[:, J] U A[I, :] with the core U = A[I, J]^{-1}, grown each step by block
+ * inversion (eq. block-inverse-update); the residual A - A[:, J] U A[I, :] is
+ * never formed, its row norms are updated from products with A (Sec. 4.1,
+ * row-norm updates). A is only READ: n x m, dtype, row-major, lda >= m.
+ * Each step reads A once (the rows not yet selected) plus O(k m + n k)
+ * other data. The draws, stop test and stall rule are those of rplu_dense on
+ * the row-norm estimates (info.a_fro2 = their sum at step 0 = ||A||_F^2,
+ * info.res_fro2 = their sum at the stop test).
+ * piv: 2*kmax int32: piv[2t] = i_t (I in selection order), piv[2t+1] = j_t.
+ * Ucore: kmax x kmax row-major, ldc >= kmax, FP64 for R32/R64 and complex
+ * FP64 for C64/C128; on return its leading rank x rank block is
+ * A[I, J]^{-1}. All arithmetic other than the storage of A is FP64.
+ * kmax <= RPLU_CUR_MAX_RANK. Flags: RPLU_FLAG_C2PLU (greedy choices, Sec.
+ * 2.3.3), RPLU_FLAG_STALL_STOP, RPLU_FLAG_NO_GRAPH; RPLU_FLAG_KEEP_INPUT is
+ * implied; RPLU_FLAG_COLMASS, _REFRESH and _CPLU are rejected
+ * (RPLU_E_UNSUPPORTED). opts.forced, opts.trace and opts.rowmass_out (the
+ * estimates before each draw) as for rplu_dense. Workspace: about
+ * n (9 + kmax s) + 16 kmax^2 + 48 (m + kmax) bytes (s = element size of A;
+ * it holds the compact copy of A[:, J] and the transpose of the core).
+ * The row-norm estimates are accurate to about 1e-16 ||A||_F^2 (rounding of
+ * the updates); a drawn row whose residual row is exactly 0 ends the run
+ * with RPLU_E_ZERO_PIVOT. */
+#define RPLU_CUR_MAX_RANK 2048
+rplu_status rplu_cur(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, const void* A,
+                     int64_t lda, const rplu_opts* opts, int32_t* piv, void* Ucore,
+                     int64_t ldc, rplu_info* info, void* hip_stream);
+
 /* Cauchy-like RPLU (Alg. 3 with exact row masses, Sec. 5.1), C128 only.
  * x: n complex nodes, y: m complex nodes (x_i != y_j required), G: n x p
  * row-major, B: p x m row-major, 1 <= p <= 4. G and B are OVERWRITTEN with the

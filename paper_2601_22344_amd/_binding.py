@@ -50,6 +50,7 @@ RPLU_FLAG_KEEP_INPUT = 256
 RPLU_FLAG_LAZY_SWEEP = 512
 RPLU_FLAG_EAGER_SWEEP = 1024
 RPLU_FLAG_CPLU = 2048
+RPLU_CUR_MAX_RANK = 2048
 RPLU_LAZY_STEPS = 4
 RPLU_MAX_REFRESH = 8
 RPLU_REFRESH_DROP2 = 1e-4
@@ -122,6 +123,8 @@ lib.rplu_create.argtypes = [C.c_int, C.c_size_t, C.POINTER(_P)]
 lib.rplu_destroy.argtypes = [_P]
 lib.rplu_dense.argtypes = [_P, C.c_int, _I64, _I64, _P, _I64, C.POINTER(rplu_opts), _P, _P, _I64,
                            _P, _I64, C.POINTER(rplu_info), _P]
+lib.rplu_cur.argtypes = [_P, C.c_int, _I64, _I64, _P, _I64, C.POINTER(rplu_opts), _P, _P, _I64,
+                         C.POINTER(rplu_info), _P]
 lib.rplu_cauchy.argtypes = [_P, C.c_int, _I64, _I64, C.c_int32, _P, _P, _P, _P,
                             C.POINTER(rplu_opts), _P, _P, _I64, _P, _I64, C.POINTER(rplu_info), _P]
 lib.rplu_batched.argtypes = [_P, _I64, C.POINTER(rplu_job), C.POINTER(rplu_info), _P]
@@ -148,7 +151,9 @@ lib.rplu_dense_noalloc_bytes.restype = C.c_size_t
 lib.rplu_status_str.argtypes = [C.c_int32]
 lib.rplu_status_str.restype = C.c_char_p
 lib.rplu_last_error.restype = C.c_char_p
+lib.rplu_last_error.argtypes = []
 for _fn in ("rplu_create", "rplu_destroy", "rplu_dense", "rplu_dense_noalloc", "rplu_cauchy",
+            "rplu_cur",
             "rplu_batched",
             "rplu_batched_ex", "rplu_batched_tune", "rplu_verify",
             "rplu_server_create", "rplu_server_submit", "rplu_server_poll",
@@ -280,6 +285,58 @@ def rplu_dense(A: torch.Tensor, k: int = 0, tol: float = 0.0, seed: int = 0, str
                   trace[:r] if trace is not None else None, rmo[:r] if rmo is not None else None,
                   cmo[:r] if cmo is not None else None, refreshes=int(info.refreshes),
                   first_refresh=int(info.first_refresh))
+
+
+@dataclass
+class CURResult:
+    """RPLU in CUR form: A ~ A[:, J] Ucore A[I, :] with Ucore = A[I, J]^{-1}."""
+    piv: torch.Tensor              # rank x 2 int32 (device): I_t, J_t
+    Ucore: torch.Tensor            # rank x rank float64 / complex128 (device)
+    rank: int
+    stop: int
+    a_fro2: float
+    res_fro2: float                # sum of the row-norm estimates at the stop test
+    trace: Optional[torch.Tensor] = None      # rank x 12 float64
+    rowmass: Optional[torch.Tensor] = None    # rank x n float64 (estimates before each draw)
+
+    @property
+    def I(self) -> torch.Tensor:   # noqa: E743
+        return self.piv[:, 0]
+
+    @property
+    def J(self) -> torch.Tensor:
+        return self.piv[:, 1]
+
+
+def rplu_cur(A: torch.Tensor, k: int = 0, tol: float = 0.0, seed: int = 0, stream: int = 0,
+             flags: int = 0, forced: Optional[torch.Tensor] = None, want_trace: bool = False,
+             want_rowmass: bool = False, ctx: Optional[Context] = None) -> CURResult:
+    """RPLU in CUR form (Alg. 2) of A (n x m CUDA tensor, row stride >= m),
+    which is only read. Returns the pivot pairs and the core A[I, J]^{-1}."""
+    if A.dim() != 2 or A.stride(1) != 1 or A.dtype not in _DTYPES or not A.is_cuda:
+        raise ValueError("A must be a 2-D CUDA tensor (float32/64, complex64/128), unit column stride")
+    n, m = A.shape
+    dev = A.device
+    ctx = ctx or default_context(dev.index or 0)
+    kmax = min(n, m) if k <= 0 else min(k, n, m)
+    cdt = torch.complex128 if A.is_complex() else torch.float64
+    piv = torch.empty((kmax, 2), dtype=torch.int32, device=dev)
+    Uc = torch.empty((kmax, kmax), dtype=cdt, device=dev)
+    trace = torch.empty((kmax, RPLU_TRACE_WORDS), dtype=torch.float64, device=dev) if want_trace else None
+    rmo = torch.empty((kmax, n), dtype=torch.float64, device=dev) if want_rowmass else None
+    if forced is not None:
+        forced = forced.to(device=dev, dtype=torch.int32).contiguous()
+        if forced.numel() < 2 * kmax:
+            raise ValueError("forced needs 2*kmax entries")
+    opts = _opts(k, tol, seed, stream, flags, forced, trace, rmo, None)
+    info = rplu_info()
+    st = lib.rplu_cur(ctx.handle, _DTYPES[A.dtype], n, m, _ptr(A), A.stride(0), C.byref(opts),
+                      _ptr(piv), _ptr(Uc), max(kmax, 1), C.byref(info), _cur_stream(dev))
+    _check(st, "rplu_cur")
+    r = int(info.rank)
+    return CURResult(piv[:r], Uc[:r, :r], r, int(info.stop), float(info.a_fro2),
+                     float(info.res_fro2), trace[:r] if trace is not None else None,
+                     rmo[:r] if rmo is not None else None)
 
 
 def rplu_dense_noalloc(A: torch.Tensor, piv: torch.Tensor, L: Optional[torch.Tensor] = None,

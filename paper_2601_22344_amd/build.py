@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["api.hip", "sample.hip", "dense.hip", "cauchy.hip", "batched.hip", "batch_api.cpp",
-           "verify.hip", "server.cpp", "noalloc.hip"]
+           "verify.hip", "server.cpp", "noalloc.hip", "cur.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"-I{INCLUDE}", f"-I{CSRC}"]

@@ -616,6 +616,140 @@ rplu_status cauchy_run(rplu_ctx_s* ctx, char* ws, int64_t n, int64_t m, int p, c
 }
 
 
+// RPLU in CUR form (Alg. 2): argument checks, workspace and the step loop.
+static rplu_status cur_run(rplu_ctx_s* ctx, int dtype, int64_t n, int64_t m, const void* A,
+                           int64_t lda, const rplu_opts* opts, int32_t* piv, void* Ucore,
+                           int64_t ldc, rplu_info* info, hipStream_t s) {
+    const char* who = "rplu_cur";
+    if (opts == nullptr || info == nullptr)
+        return fail(RPLU_E_ARG, "%s: opts and info are required", who);
+    if (dtype_size(dtype) == 0) return fail(RPLU_E_ARG, "%s: unknown dtype %d", who, dtype);
+    if (n < 1 || m < 1 || n > INT32_MAX || m > INT32_MAX)
+        return fail(RPLU_E_ARG, "%s: shape %lld x %lld out of range", who, (long long)n,
+                    (long long)m);
+    if (n > RPLU_MAX_DIM || m > RPLU_MAX_DIM)
+        return fail(RPLU_E_UNSUPPORTED, "%s: n and m must be <= %lld", who,
+                    (long long)RPLU_MAX_DIM);
+    if (A == nullptr || lda < m) return fail(RPLU_E_ARG, "%s: A NULL or lda < m", who);
+    if (piv == nullptr || Ucore == nullptr)
+        return fail(RPLU_E_ARG, "%s: piv and Ucore are required", who);
+    const int64_t kmax = kmax_of(n, m, opts->max_rank);
+    if (kmax > RPLU_CUR_MAX_RANK)
+        return fail(RPLU_E_UNSUPPORTED, "%s: rank %lld above RPLU_CUR_MAX_RANK (%d)", who,
+                    (long long)kmax, RPLU_CUR_MAX_RANK);
+    if (ldc < kmax) return fail(RPLU_E_ARG, "%s: ldc < kmax", who);
+    if (opts->rel_tol < 0 || !(opts->rel_tol == opts->rel_tol))
+        return fail(RPLU_E_ARG, "%s: rel_tol must be >= 0", who);
+    if (opts->flags & (RPLU_FLAG_COLMASS | RPLU_FLAG_REFRESH | RPLU_FLAG_CPLU) ||
+        opts->colmass_out != nullptr)
+        return fail(RPLU_E_UNSUPPORTED, "%s: column masses, residual replacement and CPLU "
+                    "are not available in CUR form", who);
+
+    const size_t es = dtype_size(dtype);
+    const size_t ws_ = (dtype == RPLU_C64 || dtype == RPLU_C128) ? 16 : 8;   // FP64 form
+    const int nbl = cur_l_blocks(m);
+    Carver cv;
+    const size_t o_st = cv.take(sizeof(StepState));
+    const size_t o_nrm = cv.take((size_t)n * 8);
+    const size_t o_selr = cv.take((size_t)n);
+    const size_t o_selc = cv.take((size_t)m);
+    const size_t o_ctr = cv.take((size_t)cdf_chunks((int)n) * 8);
+    const size_t o_ctc = cv.take((size_t)cdf_chunks((int)m) * 8);
+    const size_t o_rh = cv.take((size_t)m * ws_);
+    const size_t o_l = cv.take((size_t)m * ws_);
+    const size_t o_vec = cv.take((size_t)6 * kmax * ws_);
+    const size_t o_l2 = cv.take((size_t)nbl * 8);
+    const size_t o_ut = cv.take((size_t)kmax * kmax * ws_);
+    const size_t o_c = cv.take((size_t)n * kmax * es);
+    rplu_status rc = ws_reserve(ctx, cv.off, s);
+    if (rc) return rc;
+    char* ws = (char*)ctx->ws;
+
+    CurArgs c;
+    std::memset(&c, 0, sizeof c);        // padding too: the struct keys the graph cache
+    c.dtype = dtype;
+    c.vec_ok = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)es) % 16 == 0);
+    c.n = n;
+    c.m = m;
+    c.kmax = kmax;
+    c.A = A;
+    c.lda = lda;
+    c.Uc = Ucore;
+    c.ldc = ldc;
+    c.Ut = ws + o_ut;
+    c.C = ws + o_c;
+    c.nrm = (double*)(ws + o_nrm);
+    c.selr = (uint8_t*)(ws + o_selr);
+    c.selc = (uint8_t*)(ws + o_selc);
+    c.rhat = ws + o_rh;
+    c.l = ws + o_l;
+    char* vec = ws + o_vec;
+    c.zv = vec;
+    c.zU = vec + 1 * kmax * ws_;
+    c.gI = vec + 2 * kmax * ws_;
+    c.wv = vec + 3 * kmax * ws_;
+    c.y = vec + 4 * kmax * ws_;
+    c.Uw = vec + 5 * kmax * ws_;
+    c.l2part = (double*)(ws + o_l2);
+    c.ct_col = (double*)(ws + o_ctc);
+    c.piv = piv;
+    c.st = (StepState*)(ws + o_st);
+
+    // initial row norms ||A_i,:||^2: the dense path's first mass pass (it
+    // only reads A)
+    DenseArgs d;
+    std::memset(&d, 0, sizeof d);
+    d.dtype = dtype;
+    d.n = n;
+    d.m = m;
+    d.S = const_cast<void*>(A);
+    d.lda = lda;
+    d.st = c.st;
+    d.rowmass = c.nrm;
+    d.vec_ok = c.vec_ok != 0;
+    launch_state_init(c.st, s);
+    hipError_t e = hipMemsetAsync(c.selr, 0, (size_t)n, s);
+    if (e == hipSuccess) e = hipMemsetAsync(c.selc, 0, (size_t)m, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(selection masks)");
+    timed(ctx, 3, s, [&] { launch_dense_sweep(d, /*init=*/true, s); });
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "initial row-norm launch");
+
+    SampleArgs sa;
+    std::memset(&sa, 0, sizeof sa);
+    sa.dtype = dtype;
+    sa.n = n;
+    sa.m = m;
+    sa.rowmass = c.nrm;
+    sa.ct_row = (double*)(ws + o_ctr);
+    sa.ct_col = c.ct_col;
+    sa.st = c.st;
+    sa.piv = piv;
+    sa.seed = opts->seed;
+    sa.stream = opts->stream;
+    sa.kmax = kmax;
+    sa.tol2 = opts->rel_tol * opts->rel_tol;
+    sa.stall = (opts->flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
+    sa.greedy = (opts->flags & RPLU_FLAG_C2PLU) ? 1 : 0;
+    sa.forced = opts->forced;
+    sa.trace = opts->trace;
+    sa.rowmass_out = opts->rowmass_out;
+    (void)nbl;
+
+    const bool graph = !(opts->flags & RPLU_FLAG_NO_GRAPH);
+    const uint64_t key = fnv1a(&sa, sizeof sa, fnv1a(&c, sizeof c, 0x637572ull));
+    auto step = [&](hipStream_t q) {
+        timed(ctx, 1, q, [&] { launch_rows_draw(sa, q); });
+        timed(ctx, 0, q, [&] { launch_cur_step(c, sa, q); });
+    };
+    rc = run_loop(ctx, c.st, kmax + 1, graph, key, s, step);
+    if (rc) return rc;
+    StepState hs;
+    rc = read_state(ctx, c.st, s, &hs);
+    if (rc) return rc;
+    return finish(hs, info);
+}
+
 }  // namespace rplu
 
 using namespace rplu;
@@ -787,6 +921,16 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, voi
         o.lda_orig = lda;
     }
     return dense_run(ctx, (char*)ctx->ws, dtype, n, m, Ak, lda, &o, piv, L, ldl, U, ldu, info, s);
+}
+
+rplu_status rplu_cur(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, const void* A,
+                     int64_t lda, const rplu_opts* opts, int32_t* piv, void* Ucore, int64_t ldc,
+                     rplu_info* info, void* hip_stream) {
+    if (ctx == nullptr) return fail(RPLU_E_ARG, "rplu_cur: ctx is required");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return cur_run(ctx, dtype, n, m, A, lda, opts, piv, Ucore, ldc, info,
+                   (hipStream_t)hip_stream);
 }
 
 rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, int32_t p,

@@ -267,6 +267,8 @@ struct StepState {
     int32_t flushed;    // deferred sweep: the step whose S^(flushed) the last
                         // write-back stored (the next draw moves t_base there)
     int32_t pad4;
+    double sig_re, sig_im;  // CUR form: sigma = A[i, j] - z^T U_k w of the step
+    double l2;              // CUR form: ||l||^2 of the step
 };
 
 }  // namespace rplu

@@ -141,6 +141,38 @@ void launch_cauchy_rowgen_draw(const CauchyArgs& a, const SampleArgs& sa, hipStr
 void launch_cauchy_update(const CauchyArgs& a, hipStream_t s);
 int cauchy_rows_per_block();
 
+// RPLU in CUR form (cur.hip). W below is the FP64 form of the element type
+// (double, or complex FP64 for complex inputs).
+struct CurArgs {
+    int dtype;
+    int vec_ok;          // rows of A 16-byte aligned
+    int64_t n, m, kmax;
+    const void* A;       // n x m row-major (lda), read only
+    int64_t lda;
+    void* Uc;            // the core U_k (W), row-major, ldc
+    int64_t ldc;
+    void* Ut;            // its transpose (W), kmax x kmax
+    void* C;             // A[:, J] row-major n x kmax, element type
+    double* nrm;         // n row-norm estimates (the draws' row masses)
+    uint8_t* selr;       // n: row selected
+    uint8_t* selc;       // m: column selected
+    void* rhat;          // m (W): the residual's pivot row
+    void* l;             // m (W): rhat / rhat_j
+    void* zv;            // kmax (W): A[i, J]
+    void* zU;            // kmax (W): z^T U_k
+    void* gI;            // kmax (W): (A conj(l))[I]
+    void* wv;            // kmax (W): A[I, j]
+    void* y;             // kmax (W): U_k gI
+    void* Uw;            // kmax (W): U_k w
+    double* l2part;      // cur_l_blocks(m) partial sums of |l|^2
+    double* ct_col;
+    int32_t* piv;
+    StepState* st;
+};
+
+void launch_cur_step(const CurArgs& a, const SampleArgs& sa, hipStream_t s);
+int cur_l_blocks(int64_t m);
+
 // Batched dense instances (batched.hip): one workgroup runs a whole instance.
 constexpr int RPLU_BATCH_MAX_DIM = 8192;
 

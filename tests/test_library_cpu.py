@@ -68,3 +68,15 @@ def test_binding_constants_match_header():
             assert getattr(B, name) == val, name
             checked += 1
     assert checked >= 20
+
+
+def test_binding_declares_every_signature():
+    """Every C function the binding calls has its argument types declared:
+    without them ctypes passes a Python int as a 32-bit C int, and an int64_t
+    parameter passed on the stack then carries undefined upper bits."""
+    import paper_2601_22344_amd._binding as B
+    src = open(B.__file__).read()
+    called = sorted(set(re.findall(r"\blib\.(rplu_[a-z_]+)\(", src)))
+    assert "rplu_cur" in called and "rplu_dense" in called
+    missing = [n for n in called if getattr(B.lib, n).argtypes is None]
+    assert not missing, missing
