@@ -51,7 +51,7 @@ FP64_VECTOR_PEAK_TF = 78.6     # MI355X FP64 vector, TFLOP/s
 # Hermitian form 4 p^2 = 11. The reciprocal of |d|^2 (one per pair) is
 # reported separately and not counted as a FLOP.
 CAUCHY_FLOP_PER_PAIR = 7 + 4 * 1 * 1
-KERNEL_SOURCES = ["common.hpp", "cdf.hpp", "dense.hip", "cauchy.hip", "batched.hip"]
+KERNEL_SOURCES = ["common.hpp", "cdf.hpp", "dense.hip", "cauchy.hip", "batched.hip", "cur.hip"]
 
 
 def _source_sha() -> str:
@@ -64,7 +64,7 @@ def _source_sha() -> str:
 
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
 HOT_KERNEL = {"cauchy20k": "k_cauchy_mass", "dense32k": "k_dense_lazy",
-              "dense512": "k_dense_sweep", "batched4096": "k_batched"}
+              "dense512": "k_dense_sweep", "batched4096": "k_batched", "cur32k": "k_cur_sweep"}
 CALIBRATION_BYTES = 1 << 30
 
 
@@ -256,6 +256,53 @@ def _setup_dense(torch, rplu, which):
                 config={"workload": desc, "n": n, "m": m, "k": k, "seed": 0})
 
 
+def _setup_cur(torch, rplu):
+    """RPLU in CUR form (Alg. 2) on the 32768^2 FP32 matrix of dense32k, k = 512.
+    A is only read, so the same array serves every step."""
+    import workloads as W
+    dev = "cuda:0"
+    n = m = 32768
+    k = 512
+    es = 4
+    A = W.dense_reflector_matrix_device(n, sigma_power=-2.0, q=256, seed=3, device=dev,
+                                        dtype=torch.float32)
+
+    def step(flags=0):
+        return rplu.rplu_cur(A, k=k, seed=0, flags=flags)
+
+    def verify(res):
+        """The true error ||A - A[:, J] U A[I, :]|| of the last run, formed in
+        FP64 on the matrix cores (rplu_verify with L = A[:, J] and
+        U = Ucore A[I, :] in FP64)."""
+        I = res.piv[:, 0].long()
+        J = res.piv[:, 1].long()
+        A64 = A.double()
+        L = A64[:, J].contiguous()
+        U = (res.Ucore @ A64[I, :]).contiguous()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        v = rplu.rplu_verify(A64, L.T.contiguous().T, U)
+        ev1.record()
+        torch.cuda.synchronize()
+        out = {"kernel": "k_verify (v_mfma_f64_16x16x4f64)", "ms": ev0.elapsed_time(ev1),
+               "rel_err": math.sqrt(v["err_fro2"] / v["a_fro2"]),
+               "note": "true error of the CUR approximation in FP64 (A in FP64, "
+                       "A[:, J] and Ucore A[I, :])"}
+        del A64, L, U
+        torch.cuda.empty_cache()
+        return out
+
+    # per step t the pass reads the live rows of A (not yet selected, pivot
+    # row excluded) and their t entries of the compact A[:, J], writes their
+    # new column of it, and reads and writes their row-norm estimates
+    per_step = [(n - t - 1) * (m + t + 1) * es + 16 * (n - t - 1) + n for t in range(k)]
+    return dict(step=step, k=k, n=n, m=m, kind="cur", dtype="f32", per_launch=sum(per_step) / k,
+                verify=verify, sweep="cur", live_total=sum(per_step) + n * m * es,
+                config={"workload": "cur-form fp32 32768x32768 sigma_i=i^-2 (256-reflector "
+                                    "U,V) k=512, A read-only (Alg. 2)",
+                        "n": n, "m": m, "k": k, "seed": 0})
+
+
 def _setup_batched(torch, rplu):
     import workloads as W
     specs = W.batched_instance_specs()
@@ -434,7 +481,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cauchy20k", choices=["cauchy20k", "dense32k", "dense512", "batched4096", "serve"])
+    ap.add_argument("--workload", default="cauchy20k",
+                    choices=["cauchy20k", "dense32k", "dense512", "batched4096", "cur32k", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="cauchy20k: skip the dense32k and batched4096 lines the default run "
@@ -496,7 +544,7 @@ def main() -> int:
         ex.steps, ex.warmup, ex.no_cpu_baseline = args.extra_steps, 1, True
         torch.cuda.empty_cache()
         extras = {}
-        for name in ("dense32k", "batched4096"):
+        for name in ("dense32k", "batched4096", "cur32k"):
             print(f"[bench] extra workload {name}", file=sys.stderr, flush=True)
             ex.workload = name
             r = _run_batched(ex, torch, rplu) if name == "batched4096" else \
@@ -514,6 +562,9 @@ def main() -> int:
 def _run_workload(args, torch, rplu, workload) -> dict:
     if workload == "cauchy20k":
         wl = _setup_cauchy20k(torch, rplu)
+    elif workload == "cur32k":
+        wl = _setup_cur(torch, rplu)
+        args.no_cpu_baseline = True          # the oracle's CUR form has no bounded sample
     else:
         wl = _setup_dense(torch, rplu, workload)
     ctx = rplu.default_context(0)
@@ -563,8 +614,13 @@ def _run_workload(args, torch, rplu, workload) -> dict:
                           if wl["sweep"] == "deferred" else
                           "live S^(t) block read and written at every step"),
                 "eager_equivalent_GBs": (wl["eager_per_launch"] / (hot_ms * 1e-3) / 1e9
-                                         if hot_launches else None)}
-        kernel = "k_dense_lazy" if wl["sweep"] == "deferred" else "k_dense_sweep"
+                                         if hot_launches and "eager_per_launch" in wl else None)}
+        kernel = {"deferred": "k_dense_lazy", "eager": "k_dense_sweep", "cur": "k_cur_sweep"}[
+            wl["sweep"]]
+        if wl["sweep"] == "cur":
+            roof["count"] = ("live rows of A (not yet selected) read once per step, with their "
+                             "entries of the compact A[:, J] and row-norm estimates")
+            roof.pop("eager_equivalent_GBs", None)
     roof["traffic"] = _traffic(workload, hot_launches)
     roof["kernel"] = kernel
     roof["avg_launch_us"] = hot_ms * 1e3
@@ -581,7 +637,7 @@ def _run_workload(args, torch, rplu, workload) -> dict:
                                "update": prof["ms"][2] / prof_steps, "init": prof["ms"][3] / prof_steps,
                                "timing": f"HIP events, separate plain-launch pass of {prof_steps} steps"},
     }
-    if wl["kind"] == "dense":
+    if wl["kind"] in ("dense", "cur"):
         out["GB_per_s_live"] = wl["live_total"] / (elapsed / args.steps) / 1e9
         out["verify"] = wl["verify"](res)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(workload)

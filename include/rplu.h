@@ -556,10 +556,12 @@ rplu_status rplu_verify(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
  * rplu_profile_end. While profiling is on, runs use plain launches (events
  * time individual kernels; a replayed graph cannot be timed per kernel).
  * Class 0: the hot kernel (dense sweep / Cauchy all-pairs mass / the batched
- * persistent kernel, queue reset included), 1: the pivot draws (with the
- * kernels that produce their chunk totals: the Cauchy-like row-mass
- * reduction and pivot-row regeneration), 2: the Cauchy-like generator update
- * and the dense column-mass reduction, 3: initial mass pass. */
+ * persistent kernel, queue reset included / the CUR form's pass over A),
+ * 1: the pivot draws (with the kernels that produce their chunk totals: the
+ * Cauchy-like row-mass reduction and pivot-row regeneration, the CUR form's
+ * residual pivot row), 2: the Cauchy-like generator update, the dense
+ * column-mass reduction, the CUR form's k-vector and core-update kernels,
+ * 3: initial mass pass. */
 #define RPLU_PROFILE_CLASSES 4
 typedef struct {
     int64_t launches[RPLU_PROFILE_CLASSES];

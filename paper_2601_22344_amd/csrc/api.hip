@@ -738,9 +738,15 @@ static rplu_status cur_run(rplu_ctx_s* ctx, int dtype, int64_t n, int64_t m, con
 
     const bool graph = !(opts->flags & RPLU_FLAG_NO_GRAPH);
     const uint64_t key = fnv1a(&sa, sizeof sa, fnv1a(&c, sizeof c, 0x637572ull));
+    // profile classes: 0 the pass over A, 1 the draws, 2 the O(k m + k^2) rest
     auto step = [&](hipStream_t q) {
-        timed(ctx, 1, q, [&] { launch_rows_draw(sa, q); });
-        timed(ctx, 0, q, [&] { launch_cur_step(c, sa, q); });
+        timed(ctx, 1, q, [&] {
+            launch_rows_draw(sa, q);
+            launch_cur_part(c, sa, CUR_PART_PIVOT, q);
+        });
+        timed(ctx, 2, q, [&] { launch_cur_part(c, sa, CUR_PART_VECTORS, q); });
+        timed(ctx, 0, q, [&] { launch_cur_part(c, sa, CUR_PART_SWEEP, q); });
+        timed(ctx, 2, q, [&] { launch_cur_part(c, sa, CUR_PART_CORE, q); });
     };
     rc = run_loop(ctx, c.st, kmax + 1, graph, key, s, step);
     if (rc) return rc;

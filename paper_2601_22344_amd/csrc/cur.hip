@@ -430,35 +430,41 @@ static unsigned cur_small_grid(int64_t kmax, int per) {
 int cur_l_blocks(int64_t m) { return (int)((m + CUR_THREADS - 1) / CUR_THREADS); }
 
 template <class T>
-static void cur_step_t(const CurArgs& a, const PivotArgs& pa, hipStream_t s) {
+static void cur_part_t(const CurArgs& a, const PivotArgs& pa, int part, hipStream_t s) {
     constexpr int NW = CUR_THREADS / RPLU_WAVE;
     const int nbl = cur_l_blocks(a.m);
-    hipLaunchKernelGGL((k_cur_zu<T>), dim3(cur_small_grid(a.kmax, NW)), dim3(CUR_THREADS), 0, s, a);
-    hipLaunchKernelGGL((k_cur_pivrow_draw<T>), dim3(wide_blocks(a.m)), dim3(CDF_THREADS), 0, s, a,
-                       pa);
-    hipLaunchKernelGGL((k_cur_l_gi<T>), dim3(nbl + cur_small_grid(a.kmax, 1)), dim3(CUR_THREADS),
-                       0, s, a, nbl);
-    hipLaunchKernelGGL((k_cur_core_mv<T>), dim3(cur_small_grid(a.kmax, NW)), dim3(CUR_THREADS), 0,
-                       s, a, nbl);
-    const unsigned nb = (unsigned)((a.n + CUR_ROWS - 1) / CUR_ROWS);
-    if (a.vec_ok)
-        hipLaunchKernelGGL((k_cur_sweep<T, CUR_ROWS, CUR_SWEEP_THREADS, 16 / (int)sizeof(T)>),
-                           dim3(nb), dim3(CUR_SWEEP_THREADS), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_cur_sweep<T, CUR_ROWS, CUR_SWEEP_THREADS, 1>), dim3(nb),
-                           dim3(CUR_SWEEP_THREADS), 0, s, a);
-    const int64_t k1 = a.kmax * a.kmax;
-    const unsigned gu = (unsigned)std::max<int64_t>(1, std::min<int64_t>((k1 + 255) / 256, 2048));
-    hipLaunchKernelGGL((k_cur_core_update<T>), dim3(gu), dim3(256), 0, s, a);
+    if (part == CUR_PART_PIVOT) {
+        hipLaunchKernelGGL((k_cur_zu<T>), dim3(cur_small_grid(a.kmax, NW)), dim3(CUR_THREADS), 0,
+                           s, a);
+        hipLaunchKernelGGL((k_cur_pivrow_draw<T>), dim3(wide_blocks(a.m)), dim3(CDF_THREADS), 0, s,
+                           a, pa);
+    } else if (part == CUR_PART_VECTORS) {
+        hipLaunchKernelGGL((k_cur_l_gi<T>), dim3(nbl + cur_small_grid(a.kmax, 1)),
+                           dim3(CUR_THREADS), 0, s, a, nbl);
+        hipLaunchKernelGGL((k_cur_core_mv<T>), dim3(cur_small_grid(a.kmax, NW)), dim3(CUR_THREADS),
+                           0, s, a, nbl);
+    } else if (part == CUR_PART_SWEEP) {
+        const unsigned nb = (unsigned)((a.n + CUR_ROWS - 1) / CUR_ROWS);
+        if (a.vec_ok)
+            hipLaunchKernelGGL((k_cur_sweep<T, CUR_ROWS, CUR_SWEEP_THREADS, 16 / (int)sizeof(T)>),
+                               dim3(nb), dim3(CUR_SWEEP_THREADS), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_cur_sweep<T, CUR_ROWS, CUR_SWEEP_THREADS, 1>), dim3(nb),
+                               dim3(CUR_SWEEP_THREADS), 0, s, a);
+    } else {
+        const int64_t k1 = a.kmax * a.kmax;
+        const unsigned gu = (unsigned)std::max<int64_t>(1, std::min<int64_t>((k1 + 255) / 256, 2048));
+        hipLaunchKernelGGL((k_cur_core_update<T>), dim3(gu), dim3(256), 0, s, a);
+    }
 }
 
-void launch_cur_step(const CurArgs& a, const SampleArgs& sa, hipStream_t s) {
+void launch_cur_part(const CurArgs& a, const SampleArgs& sa, int part, hipStream_t s) {
     const PivotArgs pa = pivot_args(sa);
     switch (a.dtype) {
-        case RPLU_R32: cur_step_t<float>(a, pa, s); break;
-        case RPLU_R64: cur_step_t<double>(a, pa, s); break;
-        case RPLU_C64: cur_step_t<cf32>(a, pa, s); break;
-        case RPLU_C128: cur_step_t<cf64>(a, pa, s); break;
+        case RPLU_R32: cur_part_t<float>(a, pa, part, s); break;
+        case RPLU_R64: cur_part_t<double>(a, pa, part, s); break;
+        case RPLU_C64: cur_part_t<cf32>(a, pa, part, s); break;
+        case RPLU_C128: cur_part_t<cf64>(a, pa, part, s); break;
     }
 }
 

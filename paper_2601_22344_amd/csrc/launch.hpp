@@ -170,7 +170,12 @@ struct CurArgs {
     StepState* st;
 };
 
-void launch_cur_step(const CurArgs& a, const SampleArgs& sa, hipStream_t s);
+// The kernels of a step after the row draw, in four parts launched in this
+// order: the pivot row and column draw (k_cur_zu, k_cur_pivrow_draw), the
+// k-vectors (k_cur_l_gi, k_cur_core_mv), the pass over A (k_cur_sweep), the
+// core update (k_cur_core_update).
+enum { CUR_PART_PIVOT = 0, CUR_PART_VECTORS = 1, CUR_PART_SWEEP = 2, CUR_PART_CORE = 3 };
+void launch_cur_part(const CurArgs& a, const SampleArgs& sa, int part, hipStream_t s);
 int cur_l_blocks(int64_t m);
 
 // Batched dense instances (batched.hip): one workgroup runs a whole instance.
