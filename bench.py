@@ -51,12 +51,18 @@ FP64_VECTOR_PEAK_TF = 78.6     # MI355X FP64 vector, TFLOP/s
 # Hermitian form 4 p^2 = 11. The reciprocal of |d|^2 (one per pair) is
 # reported separately and not counted as a FLOP.
 CAUCHY_FLOP_PER_PAIR = 7 + 4 * 1 * 1
-KERNEL_SOURCES = ["common.hpp", "cdf.hpp", "dense.hip", "cauchy.hip", "batched.hip", "cur.hip"]
+# The sources each workload's hot kernel is compiled from (a change to any of
+# them makes its committed counter figures stale).
+KERNEL_SOURCES = {"cauchy20k": ["common.hpp", "cdf.hpp", "cauchy.hip"],
+                  "dense32k": ["common.hpp", "cdf.hpp", "dense.hip"],
+                  "dense512": ["common.hpp", "cdf.hpp", "dense.hip"],
+                  "batched4096": ["common.hpp", "cdf.hpp", "batched.hip"],
+                  "cur32k": ["common.hpp", "cdf.hpp", "cur.hip"]}
 
 
-def _source_sha() -> str:
+def _source_sha(workload: str) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[workload]:
         with open(os.path.join(ROOT, "paper_2601_22344_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -78,7 +84,7 @@ def _traffic(workload: str, launches: int):
     except (OSError, ValueError):
         return None
     e = tab.get(workload)
-    if not e or e.get("source_sha") != _source_sha():
+    if not e or e.get("source_sha") != _source_sha(workload):
         return None
     return e.get("bytes_per_launch")
 
@@ -159,7 +165,7 @@ def _ingest_pmc(workload: str, dirs, command: str) -> int:
                      "fetch_bytes": fetch_b, "write_bytes": write_b,
                      "fetch_kib_raw": f_kib, "write_kib_raw": w_kib,
                      "dispatches": [nf, nw], "copy_factor_fetch": fac_f,
-                     "copy_factor_write": fac_w, "source_sha": _source_sha(),
+                     "copy_factor_write": fac_w, "source_sha": _source_sha(workload),
                      "command": command}
     with open(TRAFFIC_PATH, "w") as fh:
         json.dump(tab, fh, indent=1, sort_keys=True)
