@@ -14,7 +14,10 @@ convention used on both sides of the parity tests is:
   u1 = (w0 >> 11) * 2^-53           row draw, in [0, 1)
   u2 = (w1 >> 11) * 2^-53           column draw, in [0, 1)
 
-w2 and w3 are unused. numpy.random.Philox implements the same generator but
+With row-norm bounds and rejection sampling (Cauchy-like form), trial q of
+step t uses counter (t, stream, q, 0): w0 draws the row, w2 gives the
+acceptance uniform v = (w2 >> 11) * 2^-53; the column draw uses u2 of trial 0.
+w3 is unused. numpy.random.Philox implements the same generator but
 increments its 256-bit counter before each block; the pin test accounts for
 that offset.
 """
@@ -56,3 +59,10 @@ def step_uniforms(seed: int, stream: int, t: int):
     """(u1, u2) for step t of the run keyed by (seed, stream)."""
     w = philox4x64_10((t, stream, 0, 0), (seed, 0))
     return word_to_unit(w[0]), word_to_unit(w[1])
+
+
+def trial_uniforms(seed: int, stream: int, t: int, q: int):
+    """(row uniform, acceptance uniform) of trial q of step t (words w0, w2
+    of counter (t, stream, q, 0))."""
+    w = philox4x64_10((t, stream, q, 0), (seed, 0))
+    return word_to_unit(w[0]), word_to_unit(w[2])

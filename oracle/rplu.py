@@ -55,7 +55,8 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-from .philox import step_uniforms
+from . import cauchy_bounds as CB
+from .philox import step_uniforms, trial_uniforms
 
 STOP_RANK = 1
 STOP_TOL = 2
@@ -170,6 +171,7 @@ class RPLUResult:
     B: Optional[np.ndarray] = None
     trace: list = field(default_factory=list)
     masses: list = field(default_factory=list)   # rowmass per step if asked
+    trials: list = field(default_factory=list)   # rejection trials per step (bounds)
 
 
 def _stop_reason(t: int, T: float, T0: float, kmax: int, tol: float, stall_ref=None) -> int:
@@ -513,8 +515,14 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
                 stream: int = 0, forced: Optional[Sequence] = None,
                 keep_masses: bool = False, mass_steps: Optional[set] = None,
                 stall: bool = False, greedy: bool = False,
-                complete: bool = False) -> RPLUResult:
+                complete: bool = False, bounds=None) -> RPLUResult:
     """Alg. 3 with exact row masses (no rejection), generators in complex128.
+
+    bounds: (nu, leaf) for Alg. 3 as printed: certified row-norm upper
+    bounds (App. C, oracle.cauchy_bounds) and the rejection-sampled row draw
+    (Step 1); the trace's row Draw is then the accepted trial's, over the
+    bounds, and result.trials counts the trials of every step. The stop test
+    runs on the bound total with tol^2 / nu (see oracle.cauchy_bounds).
 
     greedy: C2PLU (Sec. 2.3.3) instead of the random draws (needs the masses
     at every step).
@@ -538,6 +546,11 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
     T0 = None
     T = float("nan")
     stall_ref = [0.0, 0] if stall else None
+    if bounds is not None and (complete or mass_steps is not None or keep_masses):
+        raise ValueError("row-norm bounds replace the exact masses")
+    plan = CB.interaction_lists(x, y, bounds[0], bounds[1]) if bounds is not None else None
+    tol2_scale = 1.0 / bounds[0] if bounds is not None else 1.0
+    trials = []
     if (greedy or complete) and mass_steps is not None:
         raise ValueError("C2PLU and CPLU need the row masses at every step")
     if greedy and complete:
@@ -548,13 +561,14 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
     while True:
         need_mass = mass_steps is None or t in mass_steps or t == 0
         if need_mass:
-            rowmass = cauchy_row_masses(x, y, G, B)
+            rowmass = (CB.row_norm_bounds(plan, x, y, G, B) if plan is not None
+                       else cauchy_row_masses(x, y, G, B))
             T = float(np.cumsum(rowmass)[-1])
             if not np.isfinite(T):
                 raise NonFiniteInput("non-finite generator or node data")
             if t == 0:
                 T0 = T
-            stop = _stop_reason(t, T, T0, kmax, tol, stall_ref)
+            stop = _stop_reason(t, T, T0, kmax, tol * np.sqrt(tol2_scale), stall_ref)
         else:
             stop = STOP_RANK if t == kmax else 0
         if stop:
@@ -568,7 +582,10 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
         if complete:
             rd, cd = _entry_draws(*cauchy_largest_entry(x, y, G, B), T, (fi, fj))
         else:
-            if need_mass:
+            if plan is not None and not greedy and fi is None:
+                rd, q = _rejection_row(x, y, G, B, rowmass, seed, stream, t)
+                trials.append(q)
+            elif need_mass:
                 rd = largest(rowmass, fi) if greedy else inverse_cdf(rowmass, u1, fi)
             else:
                 rd = Draw(-1, fi, float("nan"), float("nan"), float("nan"), float("nan"))
@@ -584,4 +601,17 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
         trace.append(StepTrace(t, rd, cd, complex(a)))
         t += 1
     return RPLUResult(L[:, :t].copy(), U[:t].copy(), piv[:t].copy(), t, stop,
-                      T0, T, G=G, B=B, trace=trace, masses=masses)
+                      T0, T, G=G, B=B, trace=trace, masses=masses, trials=trials)
+
+
+def _rejection_row(x, y, G, B, u, seed, stream, t):
+    """Alg. 3, Step 1: draw i from the bounds u, regenerate row i, accept
+    with probability ||row||^2 / u_i; repeat. Returns (Draw of the accepted
+    trial over u, number of trials)."""
+    for q in range(CB.MAX_TRIALS):
+        v_row, v_acc = trial_uniforms(seed, stream, t, q)
+        d = inverse_cdf(u, v_row)
+        rho = float(np.sum(squared_magnitude(cauchy_row(x, y, G, B, d.used))))
+        if v_acc * u[d.used] < rho:
+            return d, q + 1
+    raise ValueError(f"step {t}: no row accepted in {CB.MAX_TRIALS} trials (bounds below the masses?)")

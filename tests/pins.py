@@ -595,6 +595,121 @@ def pin_cur_form():
         assert np.allclose(U, np.linalg.inv(M[:q + 1, :q + 1]), rtol=0, atol=1e-11)
 
 
+def _bounds_geometries():
+    """(name, x, y, G, B) on separated, interleaved and degenerate point sets."""
+    from oracle import cauchy_bounds as CB  # noqa: F401
+    out = []
+    for p_ in (1, 2, 3):
+        x, y, G, B = W.cauchy_like_random(300, 260, p_, seed=700 + p_)
+        out.append((f"separated p={p_}", x, y, G, B))
+    x, y, G, B = W.cauchy_like_random(280, 240, 2, seed=710, separated=False)
+    out.append(("near annulus", x, y, G, B))
+    x, y = W.spiral_cluster_points(400, 400, seed=2)
+    out.append(("spirals vs cluster", x, y, np.ones((400, 1), np.complex128),
+                np.ones((1, 400), np.complex128)))
+    rng = np.random.default_rng(711)
+    z = rng.standard_normal(500) + 1j * rng.standard_normal(500)
+    x, y = z[::2], z[1::2] + 1e-3                 # interleaved in one cloud
+    G = rng.standard_normal((250, 2)) + 1j * rng.standard_normal((250, 2))
+    B = rng.standard_normal((2, 250)) + 1j * rng.standard_normal((2, 250))
+    out.append(("interleaved", x, y, G, B))
+    x = np.concatenate([np.full(70, 0.25 + 0.5j), rng.random(50) + 1j * rng.random(50)])
+    y = 3.0 + rng.random(90) + 1j * rng.random(90)
+    G = rng.standard_normal((120, 1)) + 0j
+    B = rng.standard_normal((1, 90)) + 0j
+    out.append(("repeated targets", x, y, G, B))
+    return out
+
+
+def pin_cauchy_bounds():
+    """Certified row-norm bounds (App. C, Alg. C.1 and C.2): on separated,
+    interleaved, spiral-vs-cluster and repeated-point geometries, every
+    u_i lies between the exact row mass (brute force) and nu times it; the
+    source points reached from every target leaf through A_l and E_l are all
+    m points, each once; every aggregated pair is admissible over its actual
+    points and alpha is at least 1 / (smallest squared distance); leaves hold
+    at most `leaf` points (or identical points) and the leaves of each tree
+    partition its points; every H_s equals B[:, s] B[:, s]^* (library
+    product)."""
+    from oracle import cauchy_bounds as CB
+    nu, leaf = 5.0, 16
+    for name, x, y, G, B in _bounds_geometries():
+        plan = CB.interaction_lists(x, y, nu, leaf)
+        u = CB.row_norm_bounds(plan, x, y, G, B)
+        ex = O.cauchy_row_masses(x, y, G, B)
+        assert np.all(ex <= u * (1 + 1e-12)), name
+        assert np.all(u <= nu * ex * (1 + 1e-12)), name
+        m = y.shape[0]
+        for l in plan.tgt_leaves:
+            cover = np.concatenate([plan.src[s].idx for s, _ in plan.A[l]] +
+                                   [plan.src[s].idx for s in plan.E[l]])
+            assert np.array_equal(np.sort(cover), np.arange(m)), (name, l)
+            xl = x[plan.tgt[l].idx]
+            for s, alpha in plan.A[l]:
+                d2 = np.abs(xl[:, None] - y[None, plan.src[s].idx]) ** 2
+                assert d2.max() <= nu * d2.min() * (1 + 1e-12), (name, l, s)
+                assert alpha * d2.min() >= 1 - 1e-12
+        for tree, pts in ((plan.tgt, x), (plan.src, y)):
+            leaves = CB.leaves_under(tree, 0)
+            allidx = np.concatenate([tree[l].idx for l in leaves])
+            assert np.array_equal(np.sort(allidx), np.arange(pts.shape[0]))
+            for l in leaves:
+                q = pts[tree[l].idx]
+                assert len(q) <= leaf or np.all(q == q[0]), name
+        H = CB.gram_matrices(plan.src, B)
+        for s, nd in enumerate(plan.src):
+            Bs = B[:, nd.idx]
+            assert np.allclose(H[s], Bs @ Bs.conj().T, rtol=1e-12, atol=1e-12 * np.abs(Bs).max() ** 2)
+
+
+def _bounds_chi2_case():
+    """A 10 x 96 Cauchy-like problem whose bounds are far from proportional
+    to the masses (u_i / ||S_i,:||^2 from 1.0 to 3.8 with leaf size 4):
+    targets on a segment, sources in a square cluster beside its middle."""
+    rng = np.random.default_rng(720)
+    x = np.linspace(0, 3, 10) + 0.05j * rng.random(10)
+    y = 1.5 + 0.8j + 0.6 * (rng.random(96) - 0.5) + 0.6j * (rng.random(96) - 0.5)
+    G = rng.standard_normal((10, 2)) + 1j * rng.standard_normal((10, 2))
+    B = rng.standard_normal((2, 96)) + 1j * rng.standard_normal((2, 96))
+    return x, y, G, B
+
+
+def pin_rejection_sampling(N=20000):
+    """Alg. 3, Step 1 with the bounds: over N streams the accepted first row
+    follows the exact row masses (chi-square p > 1e-3) and not the bounds
+    (p < 1e-6); the mean number of trials is sum(u) / sum(rho) within 5
+    standard errors; with leaves holding every point (no aggregation) the
+    bounds are the exact masses, every step accepts its first trial and the
+    run takes the exact form's pivots; a tolerance run stops at TOL with the
+    exact residual within the tolerance."""
+    from oracle import cauchy_bounds as CB
+    x, y, G, B = _bounds_chi2_case()
+    plan = CB.interaction_lists(x, y, 5.0, 4)
+    u = CB.row_norm_bounds(plan, x, y, G, B)
+    ex = O.cauchy_row_masses(x, y, G, B)
+    assert (u / ex).max() / (u / ex).min() > 1.3
+    counts = np.zeros(10)
+    trials = []
+    for s in range(N):
+        d, q = O._rejection_row(x, y, G, B, u, 0, s, 0)
+        counts[d.used] += 1
+        trials.append(q)
+    assert _chi2_pvalue(counts, ex / ex.sum()) > 1e-3
+    assert _chi2_pvalue(counts, u / u.sum()) < 1e-6
+    mean_q = u.sum() / ex.sum()
+    se = np.std(trials) / np.sqrt(N)
+    assert abs(np.mean(trials) - mean_q) <= 5 * se + 1e-9, (np.mean(trials), mean_q)
+    xs, ys, Gs, Bs = W.cauchy_like_random(60, 50, 2, seed=721)
+    r_all = O.rplu_cauchy(xs, ys, Gs, Bs, k=12, seed=3, bounds=(5.0, 1000))
+    r_ex = O.rplu_cauchy(xs, ys, Gs, Bs, k=12, seed=3)
+    assert r_all.trials == [1] * 12 and np.array_equal(r_all.piv, r_ex.piv)
+    r = O.rplu_cauchy(xs, ys, Gs, Bs, tol=1e-6, seed=4, bounds=(5.0, 8))
+    assert r.stop == O.STOP_TOL
+    A = O.cauchy_entries(xs, ys, Gs, Bs)
+    S = O.schur_closed_form(A, r.piv[:, 0], r.piv[:, 1])
+    assert np.linalg.norm(S) <= 1e-6 * np.linalg.norm(A)
+
+
 ALL_PINS = [
     pin_stall_rule,
     pin_philox_numpy, pin_inverse_cdf_bruteforce, pin_chi2_first_pivot,
@@ -602,5 +717,6 @@ ALL_PINS = [
     pin_doubling_enumeration, pin_closed_form_schur, pin_exact_recovery,
     pin_eckart_young_floor, pin_mass_bookkeeping, pin_stop_rules,
     pin_nonfinite, pin_cauchy_vs_dense, pin_cauchy_determinant,
-    pin_loewner_entries, pin_c2plu, pin_cplu, pin_cur_form,
+    pin_loewner_entries, pin_c2plu, pin_cplu, pin_cur_form, pin_cauchy_bounds,
+    pin_rejection_sampling,
 ]

@@ -271,6 +271,55 @@ def _core_sign(Uc, z, w, omega):
     return out, sigma
 
 
+from oracle import cauchy_bounds as CB  # noqa: E402
+
+
+def _lists_alpha_dmax(x, y, nu, leaf):
+    plan = _REAL_LISTS(x, y, nu, leaf)
+    for l in plan.tgt_leaves:                          # 1 / d_max^2 instead of 1 / d_min^2
+        plan.A[l] = [(s_, 1.0 / CB.dmax2(plan.src[s_], plan.tgt[l])) for s_, _ in plan.A[l]]
+    return plan
+
+
+def _lists_unsquared(x, y, nu, leaf):
+    plan = _REAL_LISTS(x, y, nu * nu, leaf)            # d_max <= nu d_min, unsquared
+    plan.nu = nu
+    return plan
+
+
+def _gram_noconj(src, B):
+    B = np.asarray(B, dtype=np.complex128)
+    return [B[:, nd.idx] @ B[:, nd.idx].T for nd in src]
+
+
+def _bounds_no_exact(plan, x, y, G, B):
+    u = np.zeros(np.asarray(x).shape[0])
+    H = CB.gram_matrices(plan.src, B)
+    G = np.asarray(G, dtype=np.complex128)
+    for l in plan.tgt_leaves:                          # the E lists left out
+        rows = plan.tgt[l].idx
+        for s_, alpha in plan.A[l]:
+            u[rows] += alpha * np.real(np.einsum("ia,ab,ib->i", G[rows], H[s_], np.conj(G[rows])))
+    return u
+
+
+def _reject_inverted(x, y, G, B, u, seed, stream, t):
+    for q in range(CB.MAX_TRIALS):
+        v_row, v_acc = PH.trial_uniforms(seed, stream, t, q)
+        d = O.inverse_cdf(u, v_row)
+        rho = float(np.sum(O.squared_magnitude(O.cauchy_row(x, y, G, B, d.used))))
+        if v_acc * u[d.used] >= rho:                   # accepts with 1 - rho / u
+            return d, q + 1
+    raise ValueError("no row accepted")
+
+
+def _reject_first(x, y, G, B, u, seed, stream, t):
+    v_row, _ = PH.trial_uniforms(seed, stream, t, 0)   # no rejection: rows drawn by the bounds
+    return O.inverse_cdf(u, v_row), 1
+
+
+_REAL_LISTS = CB.interaction_lists
+
 MUTATIONS = [
     ("schur_sign", "schur_update", _schur_plus, [pins.pin_closed_form_schur, pins.pin_one_step_expectation]),
     ("schur_conj_u", "schur_update", _schur_conj, [pins.pin_one_step_expectation, pins.pin_unitary_dft, pins.pin_closed_form_schur]),
@@ -296,16 +345,30 @@ MUTATIONS = [
     ("cur_norm_no_conj", "cur_rownorm_update", _cur_norm_no_conj, [pins.pin_cur_form]),
     ("cur_norm_no_v", "cur_rownorm_update", _cur_norm_no_v, [pins.pin_cur_form]),
     ("cur_core_sign", "block_inverse_update", _core_sign, [pins.pin_cur_form]),
+    ("bounds_alpha_dmax", CB, "interaction_lists", _lists_alpha_dmax, [pins.pin_cauchy_bounds]),
+    ("bounds_unsquared", CB, "interaction_lists", _lists_unsquared, [pins.pin_cauchy_bounds]),
+    ("bounds_gram_noconj", CB, "gram_matrices", _gram_noconj, [pins.pin_cauchy_bounds]),
+    ("bounds_no_exact_lists", CB, "row_norm_bounds", _bounds_no_exact, [pins.pin_cauchy_bounds]),
+    ("reject_inverted", "_rejection_row", _reject_inverted, [pins.pin_rejection_sampling]),
+    ("reject_none", "_rejection_row", _reject_first, [pins.pin_rejection_sampling]),
 ]
 
 
-@pytest.mark.parametrize("name,attr,impl,catchers", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_planted_mistake_is_caught(monkeypatch, name, attr, impl, catchers):
-    monkeypatch.setattr(O, attr, impl)
+def _norm(m):
+    """(name, module, attr, impl, catchers); entries without a module patch
+    the oracle's rplu module."""
+    return m if len(m) == 5 else (m[0], O, m[1], m[2], m[3])
+
+
+@pytest.mark.parametrize("name,mod,attr,impl,catchers", [_norm(m) for m in MUTATIONS],
+                         ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(monkeypatch, name, mod, attr, impl, catchers):
+    monkeypatch.setattr(mod, attr, impl)
     caught = []
     for pin in catchers:
         try:
-            if pin in (pins.pin_chi2_first_pivot, pins.pin_chi2_second_pivot):
+            if pin in (pins.pin_chi2_first_pivot, pins.pin_chi2_second_pivot,
+                       pins.pin_rejection_sampling):
                 pin(N=8000)
             else:
                 pin()
