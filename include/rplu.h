@@ -75,7 +75,10 @@ enum {
     RPLU_E_NONFINITE = -4,     /* NaN/Inf in the input or a pivot           */
     RPLU_E_BUSY = -5,          /* server queue full                         */
     RPLU_E_UNSUPPORTED = -6,   /* valid but not implemented combination     */
-    RPLU_E_ZERO_PIVOT = -7     /* a forced pivot has S_ij == 0              */
+    RPLU_E_ZERO_PIVOT = -7,    /* a forced pivot has S_ij == 0              */
+    RPLU_E_BOUND = -8          /* RPLU_FLAG_BOUNDS: no row accepted in
+                                  RPLU_BOUND_MAX_TRIALS trials (a bound
+                                  below a row mass)                         */
 };
 
 typedef enum {
@@ -136,6 +139,27 @@ enum {
                                      RPLU_FLAG_COLMASS (then eager)          */
     RPLU_FLAG_EAGER_SWEEP = 1u << 10, /* dense: read and write S every step
                                      (the default below RPLU_LAZY_MIN_BYTES) */
+    RPLU_FLAG_BOUNDS = 1u << 12,    /* rplu_cauchy: Alg. 3 as printed: certified
+                                     row-norm upper bounds u_i with
+                                     ||S_i,:||^2 <= u_i <= nu ||S_i,:||^2
+                                     (App. C: quadtrees and interaction lists
+                                     built once per run on the host, bounds
+                                     per step on the device) in place of the
+                                     exact all-pairs masses, and the row
+                                     drawn by rejection: trial q of step t
+                                     draws i from u with word w0 of Philox
+                                     counter (t, stream, q, 0) and accepts
+                                     when v u_i < ||S_i,:||^2, v from its word
+                                     w2 (at most RPLU_BOUND_MAX_TRIALS); the
+                                     column draw keeps w1 of trial 0. The stop
+                                     test runs on sum(u): the tolerance stop
+                                     is sum(u) <= (rel_tol^2 / nu) sum(u_0),
+                                     which certifies ||S|| <= rel_tol ||A||;
+                                     info.a_fro2 / res_fro2 are then the
+                                     bound sums, info.trials the trials.
+                                     opts.bound_nu (0: 5) and bound_leaf
+                                     (0: 32, at most 64). Not with
+                                     RPLU_FLAG_COLMASS; rplu_cauchy only.   */
     RPLU_FLAG_CPLU = 1u << 11,      /* dense (rplu_dense): complete pivoting
                                      (Sec. 1; Sec. 2.3.2) instead of the
                                      random draws: (i, j) = the entry of
@@ -222,6 +246,12 @@ enum {
  * 11 j        pivot column (as a double)                                   */
 #define RPLU_TRACE_WORDS 12
 
+/* RPLU_FLAG_BOUNDS: defaults and limits. */
+#define RPLU_BOUND_NU_DEFAULT 5.0
+#define RPLU_BOUND_LEAF_DEFAULT 32
+#define RPLU_BOUND_LEAF_MAX 64
+#define RPLU_BOUND_MAX_TRIALS 256
+
 typedef struct {
     int64_t max_rank;       /* k; 0 => min(n, m)                                */
     double rel_tol;         /* stop when ||S||_F <= rel_tol ||A||_F; 0 => off   */
@@ -240,6 +270,9 @@ typedef struct {
                                n x m row-major with lda_orig >= m, not
                                overlapping A; otherwise ignored                 */
     int64_t lda_orig;
+    double bound_nu;        /* RPLU_FLAG_BOUNDS: the factor nu >= 1 (0: 5)      */
+    int32_t bound_leaf;     /* RPLU_FLAG_BOUNDS: quadtree leaf size, 1..64 (0: 32) */
+    uint32_t reserved2;
 } rplu_opts;
 
 typedef struct {
@@ -254,6 +287,7 @@ typedef struct {
                                contraction); -1 otherwise                      */
     int32_t refreshes;      /* residual replacements made (RPLU_FLAG_REFRESH)   */
     int32_t first_refresh;  /* step of the first one, or -1                    */
+    int64_t trials;         /* RPLU_FLAG_BOUNDS: row trials over all steps      */
 } rplu_info;
 
 typedef struct rplu_ctx_s* rplu_ctx;

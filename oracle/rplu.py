@@ -521,8 +521,9 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
     bounds: (nu, leaf) for Alg. 3 as printed: certified row-norm upper
     bounds (App. C, oracle.cauchy_bounds) and the rejection-sampled row draw
     (Step 1); the trace's row Draw is then the accepted trial's, over the
-    bounds, and result.trials counts the trials of every step. The stop test
-    runs on the bound total with tol^2 / nu (see oracle.cauchy_bounds).
+    bounds, result.trials counts the trials of every step and keep_masses
+    keeps the bounds. The stop test runs on the bound total with tol^2 / nu
+    (see oracle.cauchy_bounds).
 
     greedy: C2PLU (Sec. 2.3.3) instead of the random draws (needs the masses
     at every step).
@@ -546,7 +547,7 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
     T0 = None
     T = float("nan")
     stall_ref = [0.0, 0] if stall else None
-    if bounds is not None and (complete or mass_steps is not None or keep_masses):
+    if bounds is not None and (complete or mass_steps is not None):
         raise ValueError("row-norm bounds replace the exact masses")
     plan = CB.interaction_lists(x, y, bounds[0], bounds[1]) if bounds is not None else None
     tol2_scale = 1.0 / bounds[0] if bounds is not None else 1.0

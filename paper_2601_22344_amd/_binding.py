@@ -50,6 +50,8 @@ RPLU_FLAG_KEEP_INPUT = 256
 RPLU_FLAG_LAZY_SWEEP = 512
 RPLU_FLAG_EAGER_SWEEP = 1024
 RPLU_FLAG_CPLU = 2048
+RPLU_FLAG_BOUNDS = 4096
+RPLU_E_BOUND = -8
 RPLU_CUR_MAX_RANK = 2048
 RPLU_LAZY_STEPS = 4
 RPLU_MAX_REFRESH = 8
@@ -69,13 +71,14 @@ class rplu_opts(C.Structure):
     _fields_ = [("max_rank", C.c_int64), ("rel_tol", C.c_double), ("seed", C.c_uint64),
                 ("stream", C.c_uint64), ("flags", C.c_uint32), ("reserved", C.c_uint32),
                 ("forced", C.c_void_p), ("trace", C.c_void_p), ("rowmass_out", C.c_void_p),
-                ("colmass_out", C.c_void_p), ("A_orig", C.c_void_p), ("lda_orig", C.c_int64)]
+                ("colmass_out", C.c_void_p), ("A_orig", C.c_void_p), ("lda_orig", C.c_int64),
+                ("bound_nu", C.c_double), ("bound_leaf", C.c_int32), ("reserved2", C.c_uint32)]
 
 
 class rplu_info(C.Structure):
     _fields_ = [("rank", C.c_int64), ("stop", C.c_int32), ("status", C.c_int32),
                 ("a_fro2", C.c_double), ("res_fro2", C.c_double), ("err_fro2", C.c_double),
-                ("refreshes", C.c_int32), ("first_refresh", C.c_int32)]
+                ("refreshes", C.c_int32), ("first_refresh", C.c_int32), ("trials", C.c_int64)]
 
 
 class rplu_job(C.Structure):
@@ -234,13 +237,16 @@ class Result:
     refreshes: int = 0                        # residual replacements (RPLU_FLAG_REFRESH)
     first_refresh: int = -1                   # step of the first one, or -1
     err_fro2: float = -1.0                    # certified ||A - L U||^2 (server), or -1
+    trials: int = 0                           # rejection trials (RPLU_FLAG_BOUNDS)
 
 
-def _opts(k, tol, seed, stream, flags, forced, trace, rowmass_out, colmass_out, A_orig=None):
+def _opts(k, tol, seed, stream, flags, forced, trace, rowmass_out, colmass_out, A_orig=None,
+          bound_nu=0.0, bound_leaf=0):
     return rplu_opts(int(k), float(tol), int(seed) & (2**64 - 1), int(stream) & (2**64 - 1),
                      int(flags), 0, _ptr(forced), _ptr(trace), _ptr(rowmass_out),
                      _ptr(colmass_out), _ptr(A_orig),
-                     A_orig.stride(0) if A_orig is not None else 0)
+                     A_orig.stride(0) if A_orig is not None else 0, float(bound_nu),
+                     int(bound_leaf), 0)
 
 
 def rplu_dense(A: torch.Tensor, k: int = 0, tol: float = 0.0, seed: int = 0, stream: int = 0,
@@ -371,10 +377,16 @@ def rplu_cauchy(x: torch.Tensor, y: torch.Tensor, G: torch.Tensor, B: torch.Tens
                 tol: float = 0.0, seed: int = 0, stream: int = 0, flags: int = 0,
                 forced: Optional[torch.Tensor] = None, want_trace: bool = False,
                 want_rowmass: bool = False, want_colmass: bool = False, store_L: bool = True,
-                store_U: bool = True, ctx: Optional[Context] = None) -> Result:
+                store_U: bool = True, ctx: Optional[Context] = None,
+                bounds: Optional[tuple] = None) -> Result:
     """Cauchy-like RPLU from nodes x (n), y (m) and generators G (n x p),
     B (p x m), complex128 CUDA tensors; G and B are overwritten by the
-    generators of the final Schur complement."""
+    generators of the final Schur complement. bounds = (nu, leaf):
+    RPLU_FLAG_BOUNDS (certified row-norm bounds and rejection sampling)."""
+    bound_nu, bound_leaf = 0.0, 0
+    if bounds is not None:
+        flags |= RPLU_FLAG_BOUNDS
+        bound_nu, bound_leaf = float(bounds[0]), int(bounds[1])
     for t_ in (x, y, G, B):
         if t_.dtype != torch.complex128 or not t_.is_cuda or not t_.is_contiguous():
             raise ValueError("x, y, G, B must be contiguous complex128 CUDA tensors")
@@ -394,7 +406,7 @@ def rplu_cauchy(x: torch.Tensor, y: torch.Tensor, G: torch.Tensor, B: torch.Tens
         flags |= RPLU_FLAG_COLMASS
     if forced is not None:
         forced = forced.to(device=dev, dtype=torch.int32).contiguous()
-    opts = _opts(k, tol, seed, stream, flags, forced, trace, rmo, cmo)
+    opts = _opts(k, tol, seed, stream, flags, forced, trace, rmo, cmo, None, bound_nu, bound_leaf)
     info = rplu_info()
     st = lib.rplu_cauchy(ctx.handle, RPLU_C128, n, m, p, _ptr(x), _ptr(y), _ptr(G), _ptr(B),
                          C.byref(opts), _ptr(piv), _ptr(Lt), n, _ptr(U), m, C.byref(info),
@@ -405,7 +417,7 @@ def rplu_cauchy(x: torch.Tensor, y: torch.Tensor, G: torch.Tensor, B: torch.Tens
                   r, int(info.stop), float(info.a_fro2), float(info.res_fro2),
                   trace[:r] if trace is not None else None, rmo[:r] if rmo is not None else None,
                   cmo[:r] if cmo is not None else None, refreshes=int(info.refreshes),
-                  first_refresh=int(info.first_refresh))
+                  first_refresh=int(info.first_refresh), trials=int(info.trials))
 
 
 def rplu_profile_begin(ctx: Context) -> None:

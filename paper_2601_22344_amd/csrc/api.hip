@@ -20,6 +20,7 @@
 #include "common.hpp"
 #include "launch.hpp"
 #include "runtime.hpp"
+#include "bounds_plan.hpp"
 
 namespace rplu {
 
@@ -112,11 +113,15 @@ static rplu_status finish(const StepState& hs, rplu_info* info, int refreshes = 
     info->err_fro2 = -1.0;
     info->refreshes = refreshes;
     info->first_refresh = first_refresh;
+    info->trials = hs.trials_total;
     switch (hs.error) {
         case 0: return RPLU_OK;
         case RPLU_E_NONFINITE: return fail(RPLU_E_NONFINITE, "non-finite mass or pivot at step %d", hs.t);
         case RPLU_E_ZERO_PIVOT: return fail(RPLU_E_ZERO_PIVOT, "forced pivot is zero at step %d", hs.t);
         case RPLU_E_ARG: return fail(RPLU_E_ARG, "forced pivot out of range at step %d", hs.t);
+        case RPLU_E_BOUND:
+            return fail(RPLU_E_BOUND, "no row accepted in %d trials at step %d",
+                        RPLU_BOUND_MAX_TRIALS, hs.t);
         default: return fail(hs.error, "device error %d at step %d", hs.error, hs.t);
     }
 }
@@ -482,6 +487,14 @@ rplu_status cauchy_check(const char* who, int dtype, int64_t n, int64_t m, int p
         return fail(RPLU_E_ARG, "%s: colmass_out needs RPLU_FLAG_COLMASS", who);
     if (opts->flags & RPLU_FLAG_REFRESH)
         return fail(RPLU_E_UNSUPPORTED, "%s: RPLU_FLAG_REFRESH is for dense runs", who);
+    if (opts->flags & RPLU_FLAG_BOUNDS) {
+        if (opts->flags & RPLU_FLAG_COLMASS)
+            return fail(RPLU_E_UNSUPPORTED, "%s: RPLU_FLAG_BOUNDS with RPLU_FLAG_COLMASS", who);
+        if (!(opts->bound_nu == 0.0 || opts->bound_nu >= 1.0) || !std::isfinite(opts->bound_nu))
+            return fail(RPLU_E_ARG, "%s: bound_nu must be 0 (default) or >= 1", who);
+        if (opts->bound_leaf < 0 || opts->bound_leaf > RPLU_BOUND_LEAF_MAX)
+            return fail(RPLU_E_ARG, "%s: bound_leaf must be in [0, %d]", who, RPLU_BOUND_LEAF_MAX);
+    }
     if (n > RPLU_MAX_DIM || m > RPLU_MAX_DIM)
         return fail(RPLU_E_UNSUPPORTED, "%s: n and m must be <= %lld", who,
                     (long long)RPLU_MAX_DIM);
@@ -513,7 +526,7 @@ CauchyWs cauchy_ws_layout(int cu_count, int64_t n, int64_t m, int p, uint32_t fl
 rplu_status cauchy_run(rplu_ctx_s* ctx, char* ws, int64_t n, int64_t m, int p, const void* x,
                        const void* y, void* G, void* B, const rplu_opts* opts, int32_t* piv,
                        void* L, int64_t ldl, void* U, int64_t ldu, rplu_info* info,
-                       hipStream_t s) {
+                       hipStream_t s, const BoundsPlan* bp) {
     const bool colmass = opts->colmass_out != nullptr;
     const int64_t kmax = kmax_of(n, m, opts->max_rank);
     const CauchyWs w = cauchy_ws_layout(ctx->cu_count, n, m, p, opts->flags, colmass, U == nullptr);
@@ -546,7 +559,8 @@ rplu_status cauchy_run(rplu_ctx_s* ctx, char* ws, int64_t n, int64_t m, int p, c
     a.seed = opts->seed;
     a.stream = opts->stream;
     a.kmax = kmax;
-    a.tol2 = opts->rel_tol * opts->rel_tol;
+    // with bounds the stop test runs on sum(u), with tol^2 / nu (certified)
+    a.tol2 = opts->rel_tol * opts->rel_tol / (bp ? bp->nu : 1.0);
 
     CauchyArgs ac;                       // the column pass
     std::memset(&ac, 0, sizeof ac);
@@ -573,7 +587,7 @@ rplu_status cauchy_run(rplu_ctx_s* ctx, char* ws, int64_t n, int64_t m, int p, c
     sa.p = p;
     sa.n = n;
     sa.m = m;
-    sa.rowmass = a.rowmass;
+    sa.rowmass = bp ? bp->u : a.rowmass;
     sa.ct_row = (double*)(wsb + w.o_ctr);
     sa.ct_col = a.ct_col;
     sa.st = a.st;
@@ -592,9 +606,27 @@ rplu_status cauchy_run(rplu_ctx_s* ctx, char* ws, int64_t n, int64_t m, int p, c
     sa.trace = opts->trace;
     sa.rowmass_out = opts->rowmass_out;
     const bool graph = !(opts->flags & RPLU_FLAG_NO_GRAPH);
-    const uint64_t key = fnv1a(&ac, sizeof ac, fnv1a(&sa, sizeof sa,
-                                                    fnv1a(&a, sizeof a, 0x636175636879ull)));
-    rplu_status rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
+    uint64_t key = fnv1a(&ac, sizeof ac, fnv1a(&sa, sizeof sa,
+                                              fnv1a(&a, sizeof a, 0x636175636879ull)));
+    if (bp) key = fnv1a(bp, sizeof *bp, key);
+    rplu_status rc;
+    if (bp) {
+        rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
+            timed(ctx, 0, q, [&] { launch_bh_bounds(*bp, a, q); });
+            timed(ctx, 1, q, [&] {
+                launch_rows_draw(sa, q);
+                launch_bh_reject(*bp, a, sa, q);
+                launch_cauchy_rowgen_draw(a, sa, q);
+            });
+            timed(ctx, 2, q, [&] { launch_cauchy_update(a, q); });
+        });
+        if (rc) return rc;
+        StepState hs;
+        rc = read_state(ctx, a.st, s, &hs);
+        if (rc) return rc;
+        return finish(hs, info);
+    }
+    rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
         timed(ctx, 0, q, [&] { launch_cauchy_mass(a, q); });
         if (colmass)
             timed(ctx, 2, q, [&] {
@@ -775,6 +807,7 @@ const char* rplu_status_str(rplu_status s) {
         case RPLU_E_BUSY: return "RPLU_E_BUSY";
         case RPLU_E_UNSUPPORTED: return "RPLU_E_UNSUPPORTED";
         case RPLU_E_ZERO_PIVOT: return "RPLU_E_ZERO_PIVOT";
+        case RPLU_E_BOUND: return "RPLU_E_BOUND";
         default: return "RPLU_E_UNKNOWN";
     }
 }
@@ -954,10 +987,32 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
                                         opts->colmass_out != nullptr, U == nullptr);
     const bool keep = (opts->flags & RPLU_FLAG_KEEP_INPUT) != 0;
     const size_t gb = align_up((size_t)n * p * 16, 256), bb = align_up((size_t)p * m * 16, 256);
-    rc = ws_reserve(ctx, w.total + (keep ? gb + bb : 0), s);
+    // RPLU_FLAG_BOUNDS: the plan (quadtrees and interaction lists) is built
+    // on the host from the nodes and placed after the run's workspace
+    HostBoundsPlan hp;
+    size_t plan_bytes = 0;
+    if (opts->flags & RPLU_FLAG_BOUNDS) {
+        std::vector<CPoint> hx((size_t)n), hy((size_t)m);
+        e = hipMemcpyAsync(hx.data(), x, (size_t)n * 16, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hy.data(), y, (size_t)m * 16, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "reading the nodes for the bound plan");
+        const double nu = opts->bound_nu > 0.0 ? opts->bound_nu : RPLU_BOUND_NU_DEFAULT;
+        const int leaf = opts->bound_leaf > 0 ? opts->bound_leaf : RPLU_BOUND_LEAF_DEFAULT;
+        build_bounds_plan(hx.data(), n, hy.data(), m, nu, leaf, &hp);
+        plan_bytes = align_up(bounds_plan_bytes(hp, n, p), 256);
+    }
+    rc = ws_reserve(ctx, w.total + plan_bytes + (keep ? gb + bb : 0), s);
     if (rc) return rc;
+    BoundsPlan bp;
+    std::vector<int32_t> staging;
+    if (plan_bytes) {
+        e = upload_bounds_plan(hp, n, p, (char*)ctx->ws + w.total, s, &staging, &bp);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "bound plan upload");
+    }
     if (keep) {
-        char* Gk = (char*)ctx->ws + w.total;
+        char* Gk = (char*)ctx->ws + w.total + plan_bytes;
         char* Bk = Gk + gb;
         e = hipMemcpyAsync(Gk, G, (size_t)n * p * 16, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipMemcpyAsync(Bk, B, (size_t)p * m * 16, hipMemcpyDeviceToDevice, s);
@@ -965,7 +1020,8 @@ rplu_status rplu_cauchy(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, in
         G = Gk;
         B = Bk;
     }
-    return cauchy_run(ctx, (char*)ctx->ws, n, m, p, x, y, G, B, opts, piv, L, ldl, U, ldu, info, s);
+    return cauchy_run(ctx, (char*)ctx->ws, n, m, p, x, y, G, B, opts, piv, L, ldl, U, ldu, info, s,
+                      plan_bytes ? &bp : nullptr);
 }
 
 }  // extern "C"

@@ -487,6 +487,7 @@ rplu_status rplu_batched_ex(rplu_ctx ctx, int64_t count, const rplu_job* jobs,
         inf.err_fro2 = -1.0;
         inf.refreshes = refreshes[(size_t)b];
         inf.first_refresh = first_ref[(size_t)b];
+        inf.trials = 0;
         if (out[b].error != 0 && first_b < 0) { first = out[b].error; first_b = b; }
     }
     if (first_b >= 0)

@@ -1,0 +1,327 @@
+// Certified row-norm upper bounds for the Cauchy-like form (App. C, Alg.
+// C.2) and the rejection-sampled row draw (Alg. 3, Step 1).
+//
+// Per step, on the plan built once per run (bounds_plan.cpp):
+//   k_bh_gram_leaves  H_s = sum_{j in s} B_:,j B_:,j^* for every source leaf
+//                     (one wave per leaf, fixed-order wave sums)
+//   k_bh_gram_tree    inner source nodes, deepest level first: H_s = the sum
+//                     of its children's (one workgroup, a barrier per level)
+//   k_bh_bounds       u_i = sum over the aggregated entries (s, alpha) of the
+//                     target leaf of alpha G_i,: H_s G_i,:^* plus the exact
+//                     terms |G_i,: B_:,j|^2 / |x_i - y_j|^2 of its exact source
+//                     leaves; one wave per target leaf, a lane per target
+//                     point, the source data as wave-uniform loads
+//   k_rows_draw (sample.hip)  the stop test on sum(u) and the row draw of
+//                     trial 0 (the bounds are the row masses of the draw)
+//   k_bh_reject       one workgroup: rho_i = ||S_i,:||^2 of the drawn row,
+//                     accepted when v u_i < rho_i (v from word w2 of the
+//                     trial's Philox block); otherwise the next trial q draws
+//                     a row from the same CDF with word w0 of counter
+//                     (t, stream, q, 0)
+// The accepted row then takes the exact form's kernels: regeneration with
+// the column draw, and the generator update.
+#include "common.hpp"
+#include "cdf.hpp"
+#include "launch.hpp"
+#include "pivot.hpp"
+#include "bounds_plan.hpp"
+
+namespace rplu {
+
+constexpr int BH_TREE_THREADS = 256;
+
+// c + a conj(b)
+__device__ inline cf64 cmad_conj(cf64 a, cf64 b, cf64 c) {
+    return {fma(a.re, b.re, fma(a.im, b.im, c.re)), fma(a.im, b.re, fma(-a.re, b.im, c.im))};
+}
+
+template <int P>
+__global__ __launch_bounds__(RPLU_WAVE) void k_bh_gram_leaves(BoundsPlan bp,
+                                                              const cf64* __restrict__ B, int m,
+                                                              const StepState* __restrict__ st) {
+    if (st->done) return;
+    const int s = bp.src_leaves[blockIdx.x];
+    const int lane = threadIdx.x;
+    cf64 h[P][P];
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int c = 0; c < P; ++c) h[a][c] = cf64{0.0, 0.0};
+    for (int q = bp.node_beg[s] + lane; q < bp.node_end[s]; q += RPLU_WAVE) {
+        const int j = bp.src_perm[q];
+        cf64 b[P];
+#pragma unroll
+        for (int l = 0; l < P; ++l) b[l] = B[(int64_t)l * m + j];
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+            for (int c = 0; c < P; ++c) h[a][c] = cmad_conj(b[a], b[c], h[a][c]);
+    }
+    cf64* H = (cf64*)bp.H + (int64_t)s * P * P;
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            const double re = wave_sum(h[a][c].re), im = wave_sum(h[a][c].im);
+            if (lane == 0) H[a * P + c] = cf64{re, im};
+        }
+}
+
+template <int P>
+__global__ __launch_bounds__(BH_TREE_THREADS) void k_bh_gram_tree(BoundsPlan bp,
+                                                                  const StepState* __restrict__ st) {
+    if (st->done) return;
+    cf64* H = (cf64*)bp.H;
+    for (int d = bp.max_depth; d >= 0; --d) {
+        for (int q = bp.level_off[d] + threadIdx.x; q < bp.level_off[d + 1]; q += BH_TREE_THREADS) {
+            const int s = bp.inner[q];
+            cf64 acc[P * P];
+#pragma unroll
+            for (int e = 0; e < P * P; ++e) acc[e] = cf64{0.0, 0.0};
+            for (int c = 0; c < 4; ++c) {
+                const int ch = bp.node_child[4 * s + c];
+                if (ch < 0) break;
+#pragma unroll
+                for (int e = 0; e < P * P; ++e) acc[e] = cadd(acc[e], H[(int64_t)ch * P * P + e]);
+            }
+#pragma unroll
+            for (int e = 0; e < P * P; ++e) H[(int64_t)s * P * P + e] = acc[e];
+        }
+        __syncthreads();
+    }
+}
+
+template <int P>
+__device__ inline void bh_point(const BoundsPlan& bp, const cf64* __restrict__ x,
+                                const cf64* __restrict__ y, const cf64* __restrict__ G,
+                                const cf64* __restrict__ B, int m, int l, bool act, int i) {
+    const cf64 xi = x[i];
+    cf64 g[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) g[a] = G[(int64_t)i * P + a];
+    double acc = 0.0;
+    const cf64* H = (const cf64*)bp.H;
+    for (int e = bp.A_off[l]; e < bp.A_off[l + 1]; ++e) {
+        const cf64* Hs = H + (int64_t)bp.A_node[e] * P * P;
+        // G_i H_s G_i^* = sum_a g_a (sum_c H_ac conj(g_c)), real
+        double q = 0.0;
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+            cf64 w{0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < P; ++c) w = cmad_conj(Hs[a * P + c], g[c], w);
+            q = fma(g[a].re, w.re, fma(-g[a].im, w.im, q));
+        }
+        acc = fma(bp.A_alpha[e], q, acc);
+    }
+    for (int e = bp.E_off[l]; e < bp.E_off[l + 1]; ++e) {
+        const int s = bp.E_node[e];
+        for (int q = bp.node_beg[s]; q < bp.node_end[s]; ++q) {
+            const int j = bp.src_perm[q];
+            cf64 dot{0.0, 0.0};
+#pragma unroll
+            for (int a = 0; a < P; ++a) dot = cadd(dot, wmul(g[a], B[(int64_t)a * m + j]));
+            const cf64 d = csub(xi, y[j]);
+            acc += Sc<cf64>::mag2(dot) / Sc<cf64>::mag2(d);
+        }
+    }
+    if (act) bp.u[i] = acc;
+}
+
+template <int P>
+__global__ __launch_bounds__(RPLU_WAVE) void k_bh_bounds(BoundsPlan bp, const cf64* __restrict__ x,
+                                                         const cf64* __restrict__ y,
+                                                         const cf64* __restrict__ G,
+                                                         const cf64* __restrict__ B, int m,
+                                                         const StepState* __restrict__ st) {
+    if (st->done) return;
+    const int l = blockIdx.x, lane = threadIdx.x;
+    const int beg = bp.tl_beg[l], end = bp.tl_end[l];
+    // a lane per target point (a leaf of identical points may hold more than
+    // a wave: chunks of 64)
+    for (int q0 = beg; q0 < end; q0 += RPLU_WAVE)
+        bh_point<P>(bp, x, y, G, B, m, l, q0 + lane < end, bp.tgt_perm[min(q0 + lane, end - 1)]);
+}
+
+// ||row i||^2 of the Cauchy-like matrix, the row regenerated as in
+// k_cauchy_rowgen_draw; whole workgroup, fixed-order sum, in every thread.
+template <int P>
+__device__ inline double bh_row_mass(const cf64* __restrict__ x, const cf64* __restrict__ y,
+                                     const cf64* __restrict__ G, const cf64* __restrict__ B,
+                                     int m, int i, double* red) {
+    cf64 gi[P];
+#pragma unroll
+    for (int l = 0; l < P; ++l) gi[l] = G[(int64_t)i * P + l];
+    const cf64 xi = x[i];
+    double v = 0.0;
+    for (int c = threadIdx.x; c < m; c += CDF_THREADS) {
+        cf64 s{0.0, 0.0};
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            const cf64 b = B[(int64_t)l * m + c];
+            s.re = fma(gi[l].re, b.re, s.re);
+            s.re = fma(-gi[l].im, b.im, s.re);
+            s.im = fma(gi[l].re, b.im, s.im);
+            s.im = fma(gi[l].im, b.re, s.im);
+        }
+        v += Sc<cf64>::mag2(cdiv_fast(s, csub(xi, y[c])));
+    }
+    v = wave_sum(v);
+    const int lane = threadIdx.x % RPLU_WAVE, w = threadIdx.x / RPLU_WAVE;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int q = 1; q < CDF_THREADS / RPLU_WAVE; ++q) r += red[q];
+    return r;
+}
+
+template <int P>
+__global__ __launch_bounds__(CDF_THREADS) void k_bh_reject(BoundsPlan bp, const cf64* __restrict__ x,
+                                                           const cf64* __restrict__ y,
+                                                           const cf64* __restrict__ G,
+                                                           const cf64* __restrict__ B, PivotArgs pa,
+                                                           const double* __restrict__ ct_row) {
+    __shared__ CdfShared sh;
+    __shared__ double red[CDF_THREADS / RPLU_WAVE];
+    StepState* st = pa.st;
+    if (st->done) return;
+    const int t = st->cur;
+    if (pa.greedy || pa.forced) {                 // the draw kernel's row stands
+        if (threadIdx.x == 0) { st->trials = 1; st->trials_total += 1; }
+        return;
+    }
+    const int K = cdf_chunks(pa.n);
+    const double T = cdf_levels(sh, ct_row, K);
+    int i = st->i;
+    double tgt = st->row_tgt, lo = st->row_lo, hi = st->row_hi;
+    for (int q = 0; q < RPLU_BOUND_MAX_TRIALS; ++q) {
+        const Philox4 w = philox4x64_10((uint64_t)t, pa.stream, (uint64_t)q, 0, pa.seed, 0);
+        if (q > 0) {
+            tgt = unit_from_word(w.w[0]) * T;
+            const CdfPick p = cdf_draw(sh, ct_row, K, pa.n, RowMassGlobal{bp.u}, tgt);
+            i = p.idx;
+            lo = p.lo;
+            hi = p.hi;
+        }
+        const double rho = bh_row_mass<P>(x, y, G, B, pa.m, i, red);
+        if (unit_from_word(w.w[2]) * bp.u[i] < rho) {
+            if (threadIdx.x == 0) {
+                st->i = i;
+                st->row_tgt = tgt;
+                st->row_lo = lo;
+                st->row_hi = hi;
+                st->trials = q + 1;
+                st->trials_total += q + 1;
+            }
+            return;
+        }
+    }
+    if (threadIdx.x == 0) {
+        st->error = RPLU_E_BOUND;
+        st->done = 1;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+size_t bounds_plan_bytes(const HostBoundsPlan& P, int64_t n, int p) {
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t ns = P.src.size();
+    return up(P.tgt_perm.size() * 4) + up(P.src_perm.size() * 4) + 3 * up(ns * 4) + up(ns * 16) +
+           up(P.src_leaves.size() * 4) + up(P.inner.size() * 4) + up(P.level_off.size() * 4) +
+           2 * up(P.tl_beg.size() * 4) + up(P.A_off.size() * 4) + up(P.A_node.size() * 4) +
+           up(P.A_alpha.size() * 8) + up(P.E_off.size() * 4) + up(P.E_node.size() * 4) +
+           up(ns * (size_t)p * p * 16) + up((size_t)n * 8);
+}
+
+// Copies the host plan into `dev` (bounds_plan_bytes bytes) on stream s and
+// fills the device descriptor; the host vectors must live until the copies
+// have run (the caller synchronises).
+hipError_t upload_bounds_plan(const HostBoundsPlan& P, int64_t n, int p, char* dev, hipStream_t s,
+                              std::vector<int32_t>* staging, BoundsPlan* out) {
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char* r = dev + off;
+        off += (b + 255) / 256 * 256;
+        return r;
+    };
+    hipError_t e = hipSuccess;
+    auto put = [&](const void* src, size_t b) -> void* {
+        char* d = take(b);
+        if (b && e == hipSuccess) e = hipMemcpyAsync(d, src, b, hipMemcpyHostToDevice, s);
+        return d;
+    };
+    const int ns = (int)P.src.size();
+    staging->assign((size_t)ns * 7, -1);      // node_beg, node_end, node_child (4)
+    for (int v = 0; v < ns; ++v) {
+        (*staging)[v] = P.src[v].beg;
+        (*staging)[ns + v] = P.src[v].end;
+        for (int c = 0; c < 4; ++c) (*staging)[2 * ns + 4 * v + c] = P.src[v].child[c];
+    }
+    BoundsPlan b;
+    b.n_src_nodes = ns;
+    b.n_src_leaves = (int)P.src_leaves.size();
+    b.n_tgt_leaves = (int)P.tl_beg.size();
+    b.max_depth = P.max_depth;
+    b.nu = P.nu;
+    b.tgt_perm = (const int32_t*)put(P.tgt_perm.data(), P.tgt_perm.size() * 4);
+    b.src_perm = (const int32_t*)put(P.src_perm.data(), P.src_perm.size() * 4);
+    b.node_beg = (const int32_t*)put(staging->data(), (size_t)ns * 4);
+    b.node_end = (const int32_t*)put(staging->data() + ns, (size_t)ns * 4);
+    (void)take((size_t)ns * 4);              // (spare, keeps bounds_plan_bytes' count)
+    b.node_child = (const int32_t*)put(staging->data() + 2 * ns, (size_t)ns * 16);
+    b.src_leaves = (const int32_t*)put(P.src_leaves.data(), P.src_leaves.size() * 4);
+    b.inner = (const int32_t*)put(P.inner.data(), P.inner.size() * 4);
+    b.level_off = (const int32_t*)put(P.level_off.data(), P.level_off.size() * 4);
+    b.tl_beg = (const int32_t*)put(P.tl_beg.data(), P.tl_beg.size() * 4);
+    b.tl_end = (const int32_t*)put(P.tl_end.data(), P.tl_end.size() * 4);
+    b.A_off = (const int32_t*)put(P.A_off.data(), P.A_off.size() * 4);
+    b.A_node = (const int32_t*)put(P.A_node.data(), P.A_node.size() * 4);
+    b.A_alpha = (const double*)put(P.A_alpha.data(), P.A_alpha.size() * 8);
+    b.E_off = (const int32_t*)put(P.E_off.data(), P.E_off.size() * 4);
+    b.E_node = (const int32_t*)put(P.E_node.data(), P.E_node.size() * 4);
+    b.H = take((size_t)ns * p * p * 16);
+    b.u = (double*)take((size_t)n * 8);
+    *out = b;
+    return e;
+}
+
+template <int P>
+static void bounds_p(const BoundsPlan& bp, const CauchyArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_bh_gram_leaves<P>, dim3((unsigned)bp.n_src_leaves), dim3(RPLU_WAVE), 0, s,
+                       bp, (const cf64*)a.B, (int)a.m, a.st);
+    hipLaunchKernelGGL(k_bh_gram_tree<P>, dim3(1), dim3(BH_TREE_THREADS), 0, s, bp, a.st);
+    hipLaunchKernelGGL(k_bh_bounds<P>, dim3((unsigned)bp.n_tgt_leaves), dim3(RPLU_WAVE), 0, s, bp,
+                       (const cf64*)a.x, (const cf64*)a.y, (const cf64*)a.G, (const cf64*)a.B,
+                       (int)a.m, a.st);
+}
+
+template <int P>
+static void reject_p(const BoundsPlan& bp, const CauchyArgs& a, const SampleArgs& sa,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_bh_reject<P>, dim3(1), dim3(CDF_THREADS), 0, s, bp, (const cf64*)a.x,
+                       (const cf64*)a.y, (const cf64*)a.G, (const cf64*)a.B, pivot_args(sa),
+                       (const double*)sa.ct_row);
+}
+
+void launch_bh_bounds(const BoundsPlan& bp, const CauchyArgs& a, hipStream_t s) {
+    switch (a.p) {
+        case 1: bounds_p<1>(bp, a, s); break;
+        case 2: bounds_p<2>(bp, a, s); break;
+        case 3: bounds_p<3>(bp, a, s); break;
+        case 4: bounds_p<4>(bp, a, s); break;
+    }
+}
+
+void launch_bh_reject(const BoundsPlan& bp, const CauchyArgs& a, const SampleArgs& sa,
+                      hipStream_t s) {
+    switch (a.p) {
+        case 1: reject_p<1>(bp, a, sa, s); break;
+        case 2: reject_p<2>(bp, a, sa, s); break;
+        case 3: reject_p<3>(bp, a, sa, s); break;
+        case 4: reject_p<4>(bp, a, sa, s); break;
+    }
+}
+
+}  // namespace rplu

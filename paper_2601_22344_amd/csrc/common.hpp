@@ -269,6 +269,9 @@ struct StepState {
     int32_t pad4;
     double sig_re, sig_im;  // CUR form: sigma = A[i, j] - z^T U_k w of the step
     double l2;              // CUR form: ||l||^2 of the step
+    int32_t trials;         // RPLU_FLAG_BOUNDS: trials of the step's row draw
+    int32_t pad5;
+    int64_t trials_total;   // and over the run
 };
 
 }  // namespace rplu

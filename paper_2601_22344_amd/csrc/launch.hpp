@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "rplu.h"
 
 namespace rplu {
@@ -131,6 +133,17 @@ struct CauchyArgs {
     double tol2;
 };
 
+struct BoundsPlan;
+struct HostBoundsPlan;
+// Copies a host bound plan into dev (bounds_plan_bytes bytes) on stream s;
+// staging holds host data the copies read (keep it until they have run).
+hipError_t upload_bounds_plan(const HostBoundsPlan& P, int64_t n, int p, char* dev, hipStream_t s,
+                              std::vector<int32_t>* staging, BoundsPlan* out);
+// RPLU_FLAG_BOUNDS (cauchy_bounds.hip): the bounds u of the step, and the
+// rejection loop after the trial-0 row draw.
+void launch_bh_bounds(const BoundsPlan& bp, const CauchyArgs& a, hipStream_t s);
+void launch_bh_reject(const BoundsPlan& bp, const CauchyArgs& a, const SampleArgs& sa,
+                      hipStream_t s);
 void launch_cauchy_frame(const CauchyArgs& a, hipStream_t s);
 void launch_cauchy_transpose(const CauchyArgs& a, void* Gt, void* Bt, hipStream_t s);
 void launch_cauchy_mass(const CauchyArgs& a, hipStream_t s);

@@ -108,10 +108,12 @@ rplu_status cauchy_check(const char* who, int dtype, int64_t n, int64_t m, int p
                          int64_t ldu, const rplu_info* info);
 CauchyWs cauchy_ws_layout(int cu_count, int64_t n, int64_t m, int p, uint32_t flags,
                           bool colmass, bool need_u);
+struct BoundsPlan;
+// bp: the device plan of RPLU_FLAG_BOUNDS, or null (exact masses).
 rplu_status cauchy_run(rplu_ctx_s* ctx, char* ws, int64_t n, int64_t m, int p, const void* x,
                        const void* y, void* G, void* B, const rplu_opts* opts, int32_t* piv,
                        void* L, int64_t ldl, void* U, int64_t ldu, rplu_info* info,
-                       hipStream_t s);
+                       hipStream_t s, const BoundsPlan* bp = nullptr);
 
 struct BatchJob;
 struct BatchInfo;
