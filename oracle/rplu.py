@@ -174,12 +174,15 @@ class RPLUResult:
     trials: list = field(default_factory=list)   # rejection trials per step (bounds)
 
 
-def _stop_reason(t: int, T: float, T0: float, kmax: int, tol: float, stall_ref=None) -> int:
+def _stop_reason(t: int, T: float, T0: float, kmax: int, tol: float, stall_ref=None,
+                 M=None, M0=None) -> int:
     """Stop test before the draw of step t. stall_ref: None (no stall rule)
-    or a two-element list [T_best, t_best], updated here."""
+    or a two-element list [T_best, t_best], updated here. M, M0: the largest
+    row mass now and at step 0, for the max-mass rule (CUR-AAA, Alg. 4:
+    stop when max_i u_i <= tol^2 max_i u^(0)_i) in place of the total."""
     if T == 0.0:
         return STOP_EXHAUSTED
-    if tol > 0.0 and T <= (tol * tol) * T0:
+    if tol > 0.0 and ((M <= (tol * tol) * M0) if M is not None else (T <= (tol * tol) * T0)):
         return STOP_TOL
     if stall_ref is not None:
         if t == 0:
@@ -515,7 +518,7 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
                 stream: int = 0, forced: Optional[Sequence] = None,
                 keep_masses: bool = False, mass_steps: Optional[set] = None,
                 stall: bool = False, greedy: bool = False,
-                complete: bool = False, bounds=None) -> RPLUResult:
+                complete: bool = False, bounds=None, maxmass: bool = False) -> RPLUResult:
     """Alg. 3 with exact row masses (no rejection), generators in complex128.
 
     bounds: (nu, leaf) for Alg. 3 as printed: certified row-norm upper
@@ -524,6 +527,8 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
     bounds, result.trials counts the trials of every step and keep_masses
     keeps the bounds. The stop test runs on the bound total with tol^2 / nu
     (see oracle.cauchy_bounds).
+    maxmass: the tolerance stop compares the largest row mass (or bound)
+    with tol^2 times its value at step 0 (Alg. 4), unscaled by nu.
 
     greedy: C2PLU (Sec. 2.3.3) instead of the random draws (needs the masses
     at every step).
@@ -550,7 +555,8 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
     if bounds is not None and (complete or mass_steps is not None):
         raise ValueError("row-norm bounds replace the exact masses")
     plan = CB.interaction_lists(x, y, bounds[0], bounds[1]) if bounds is not None else None
-    tol2_scale = 1.0 / bounds[0] if bounds is not None else 1.0
+    tol2_scale = 1.0 / bounds[0] if bounds is not None and not maxmass else 1.0
+    M0 = None
     trials = []
     if (greedy or complete) and mass_steps is not None:
         raise ValueError("C2PLU and CPLU need the row masses at every step")
@@ -569,7 +575,10 @@ def rplu_cauchy(x, y, G, B, k: int = 0, tol: float = 0.0, seed: int = 0,
                 raise NonFiniteInput("non-finite generator or node data")
             if t == 0:
                 T0 = T
-            stop = _stop_reason(t, T, T0, kmax, tol * np.sqrt(tol2_scale), stall_ref)
+            M = float(np.max(rowmass)) if maxmass else None
+            if t == 0:
+                M0 = M
+            stop = _stop_reason(t, T, T0, kmax, tol * np.sqrt(tol2_scale), stall_ref, M, M0)
         else:
             stop = STOP_RANK if t == kmax else 0
         if stop:

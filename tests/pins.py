@@ -710,6 +710,63 @@ def pin_rejection_sampling(N=20000):
     assert np.linalg.norm(S) <= 1e-6 * np.linalg.norm(A)
 
 
+def _bary_poles(t, w):
+    """Poles of the barycentric form with support t and weights w: the finite
+    eigenvalues of the (k+1) x (k+1) arrowhead pencil (scipy.linalg.eig)."""
+    import scipy.linalg as sl
+    k = len(t)
+    E = np.zeros((k + 1, k + 1), dtype=np.complex128)
+    E[0, 1:] = w
+    E[1:, 0] = 1.0
+    E[1:, 1:] = np.diag(t)
+    Bm = np.eye(k + 1)
+    Bm[0, 0] = 0.0
+    ev = sl.eig(E, Bm, right=False)
+    return ev[np.isfinite(ev)]
+
+
+def pin_cur_aaa():
+    """CUR-AAA (Alg. 4) on 3000 samples in the unit disk: for f = tan(2z)
+    the interpolant's poles include +-pi/4, for f = tan(2z^2) the four
+    points +-sqrt(pi/4), +-i sqrt(pi/4), each within 1e-10; the error is
+    below 1e-7 on the samples and on a hold-out circle of radius 0.95; r
+    equals f at the support points; the Loewner matrix of eq. Laaa times
+    the weights is below 1e-8 of its norm (eq. linearization-aaa); the run
+    stops on the tolerance within 30 steps (ranks 9 and 18); the split
+    has ceil(m/2) and floor(m/2) points, disjoint; the final residual's
+    largest row mass (closed form from the dense Loewner matrix) is within
+    eps^2 of the initial one (the max-mass stop)."""
+    from oracle import cur_aaa as A
+    rng = np.random.default_rng(730)
+    m = 3000
+    z = np.sqrt(rng.random(m)) * np.exp(2j * np.pi * rng.random(m))
+    zt = 0.95 * np.exp(2j * np.pi * np.linspace(0, 1, 300))
+    r0 = np.sqrt(np.pi / 4)
+    for fn, poles in ((lambda q: np.tan(2 * q), [np.pi / 4, -np.pi / 4]),
+                      (lambda q: np.tan(2 * q * q), [r0, -r0, 1j * r0, -1j * r0])):
+        f = fn(z)
+        eps = 1e-11
+        r = A.cur_aaa(z, f, eps, seed=3, kmax=60)
+        assert r.cur.stop == O.STOP_TOL and r.cur.rank <= 30, (r.cur.stop, r.cur.rank)
+        t, w = z[r.support], r.weights
+        ev = _bary_poles(t, w)
+        for p_ in poles:
+            assert np.abs(ev - p_).min() <= 1e-10, (p_, np.abs(ev - p_).min())
+        assert r.max_err <= 1e-7
+        assert np.abs(A.bary_eval(zt, t, f[r.support], w) - fn(zt)).max() <= 1e-7
+        assert np.array_equal(A.bary_eval(t, t, f[r.support], w), f[r.support])
+        rest = np.setdiff1d(np.arange(m), r.support)
+        Lm = (f[rest, None] - f[r.support][None, :]) / (z[rest, None] - t[None, :])
+        assert np.linalg.norm(Lm @ w) <= 1e-8 * np.linalg.norm(Lm, 2)
+        X, Y = r.X, r.Y
+        assert len(X) == (m + 1) // 2 and len(Y) == m // 2
+        assert np.array_equal(np.sort(np.concatenate([X, Y])), np.arange(m))
+        Lt = (f[X, None] - f[Y][None, :]) / (z[X, None] - z[Y][None, :])
+        S = O.schur_closed_form(Lt, r.cur.piv[:, 0], r.cur.piv[:, 1])
+        M0 = np.max(np.sum(np.abs(Lt) ** 2, axis=1))
+        assert np.max(np.sum(np.abs(S) ** 2, axis=1)) <= eps * eps * M0 * (1 + 1e-3) + 1e-28 * M0
+
+
 ALL_PINS = [
     pin_stall_rule,
     pin_philox_numpy, pin_inverse_cdf_bruteforce, pin_chi2_first_pivot,
@@ -718,5 +775,5 @@ ALL_PINS = [
     pin_eckart_young_floor, pin_mass_bookkeeping, pin_stop_rules,
     pin_nonfinite, pin_cauchy_vs_dense, pin_cauchy_determinant,
     pin_loewner_entries, pin_c2plu, pin_cplu, pin_cur_form, pin_cauchy_bounds,
-    pin_rejection_sampling,
+    pin_rejection_sampling, pin_cur_aaa,
 ]

@@ -320,6 +320,30 @@ def _reject_first(x, y, G, B, u, seed, stream, t):
 
 _REAL_LISTS = CB.interaction_lists
 
+from oracle import cur_aaa as AAA  # noqa: E402
+
+
+def _weights_largest(z, f, support):
+    rest = np.setdiff1d(np.arange(z.shape[0]), support)
+    t, ft = z[support], f[support]
+    Lm = (f[rest, None] - ft[None, :]) / (z[rest, None] - t[None, :])
+    _, s_, Vh = np.linalg.svd(Lm, full_matrices=False)
+    return np.conj(Vh[0]), s_                      # the largest singular vector
+
+
+def _gens_sign(fx, fy):
+    G, B = _REAL_GENS(fx, fy)
+    B[1] = -B[1]                                   # + f^y / alpha in the second row
+    return G, B
+
+
+def _bary_conj(zs, t, ft, w):
+    return _REAL_BARY(zs, t, ft, np.conj(w))
+
+
+_REAL_GENS = AAA.loewner_gens
+_REAL_BARY = AAA.bary_eval
+
 MUTATIONS = [
     ("schur_sign", "schur_update", _schur_plus, [pins.pin_closed_form_schur, pins.pin_one_step_expectation]),
     ("schur_conj_u", "schur_update", _schur_conj, [pins.pin_one_step_expectation, pins.pin_unitary_dft, pins.pin_closed_form_schur]),
@@ -351,6 +375,9 @@ MUTATIONS = [
     ("bounds_no_exact_lists", CB, "row_norm_bounds", _bounds_no_exact, [pins.pin_cauchy_bounds]),
     ("reject_inverted", "_rejection_row", _reject_inverted, [pins.pin_rejection_sampling]),
     ("reject_none", "_rejection_row", _reject_first, [pins.pin_rejection_sampling]),
+    ("aaa_largest_vector", AAA, "aaa_weights", _weights_largest, [pins.pin_cur_aaa]),
+    ("aaa_generator_sign", AAA, "loewner_gens", _gens_sign, [pins.pin_cur_aaa]),
+    ("aaa_conj_weights", AAA, "bary_eval", _bary_conj, [pins.pin_cur_aaa]),
 ]
 
 
