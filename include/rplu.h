@@ -160,6 +160,12 @@ enum {
                                      opts.bound_nu (0: 5) and bound_leaf
                                      (0: 32, at most 64). Not with
                                      RPLU_FLAG_COLMASS; rplu_cauchy only.   */
+    RPLU_FLAG_MAXMASS_STOP = 1u << 13, /* rplu_dense / rplu_cauchy: the tolerance
+                                     stop compares the largest row mass
+                                     (bound, with RPLU_FLAG_BOUNDS) with
+                                     rel_tol^2 times its value at step 0
+                                     (the stop rule of Alg. 4) instead of
+                                     the total                              */
     RPLU_FLAG_CPLU = 1u << 11,      /* dense (rplu_dense): complete pivoting
                                      (Sec. 1; Sec. 2.3.2) instead of the
                                      random draws: (i, j) = the entry of
@@ -342,6 +348,41 @@ rplu_status rplu_dense(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m,
 rplu_status rplu_cur(rplu_ctx ctx, rplu_dtype dtype, int64_t n, int64_t m, const void* A,
                      int64_t lda, const rplu_opts* opts, int32_t* piv, void* Ucore,
                      int64_t ldc, rplu_info* info, void* hip_stream);
+
+/* CUR-AAA (Alg. 4, Sec. 5.3): a rational approximation
+ * r(z) = sum_j w_j f(t_j) / (z - t_j) / sum_j w_j / (z - t_j) of samples
+ * (z_q, f_q), q < m (device, complex FP64), from a CUR decomposition of the
+ * Loewner matrix of a random split of the samples. The split: sample q gets
+ * the key w0 of Philox4x64-10 with key (seed, 1) and counter (q, 0, 0, 0);
+ * the ceil(m/2) smallest keys (ties by index) form X, the others Y, each in
+ * sample order. The generators G = [f^x / alpha, alpha], B = [alpha;
+ * -f^y / alpha] with alpha = sqrt(max |f|) (eq. loewner-generators) go
+ * through rplu_cauchy (p = 2, seed, stream 0) until the largest row mass is
+ * at most eps^2 times its initial value (RPLU_FLAG_MAXMASS_STOP), at most
+ * max_support steps. The selected rows and the selected columns each serve
+ * as support points: the weights are the right singular vector of the
+ * smallest singular value of the Loewner matrix of eq. Laaa over the other
+ * samples (one-sided Jacobi rotations on the device), and the fit with the
+ * smaller largest error |f - r| over all samples is returned (the rows on
+ * ties): support (device, max_support int32: indices into z) and weights
+ * (device, max_support complex FP64), k in info. flags: RPLU_FLAG_C2PLU,
+ * RPLU_FLAG_BOUNDS (bound_opts->bound_nu / bound_leaf; bound_opts may be
+ * NULL), RPLU_FLAG_NO_GRAPH. Synchronous; allocates its own device
+ * buffers. */
+typedef struct {
+    int64_t k;              /* support points returned (= rank)                 */
+    int64_t rank;           /* steps of the CUR run                             */
+    int64_t trials;         /* rejection trials (RPLU_FLAG_BOUNDS)              */
+    int32_t which;          /* 0: the selected rows (points of X), 1: columns   */
+    int32_t stop;           /* the CUR run's RPLU_STOP_*                        */
+    double max_err;         /* max over the samples of |f - r|                  */
+    double err_rows;        /* the same for the fit on the rows                 */
+    double err_cols;        /* and on the columns                               */
+} rplu_aaa_info;
+rplu_status rplu_cur_aaa(rplu_ctx ctx, int64_t m, const void* z, const void* f, double eps,
+                         uint64_t seed, int64_t max_support, uint32_t flags,
+                         const rplu_opts* bound_opts, int32_t* support, void* weights,
+                         rplu_aaa_info* info, void* hip_stream);
 
 /* Cauchy-like RPLU (Alg. 3 with exact row masses, Sec. 5.1), C128 only.
  * x: n complex nodes, y: m complex nodes (x_i != y_j required), G: n x p

@@ -51,6 +51,7 @@ RPLU_FLAG_LAZY_SWEEP = 512
 RPLU_FLAG_EAGER_SWEEP = 1024
 RPLU_FLAG_CPLU = 2048
 RPLU_FLAG_BOUNDS = 4096
+RPLU_FLAG_MAXMASS_STOP = 8192
 RPLU_E_BOUND = -8
 RPLU_CUR_MAX_RANK = 2048
 RPLU_LAZY_STEPS = 4
@@ -79,6 +80,12 @@ class rplu_info(C.Structure):
     _fields_ = [("rank", C.c_int64), ("stop", C.c_int32), ("status", C.c_int32),
                 ("a_fro2", C.c_double), ("res_fro2", C.c_double), ("err_fro2", C.c_double),
                 ("refreshes", C.c_int32), ("first_refresh", C.c_int32), ("trials", C.c_int64)]
+
+
+class rplu_aaa_info(C.Structure):
+    _fields_ = [("k", C.c_int64), ("rank", C.c_int64), ("trials", C.c_int64),
+                ("which", C.c_int32), ("stop", C.c_int32), ("max_err", C.c_double),
+                ("err_rows", C.c_double), ("err_cols", C.c_double)]
 
 
 class rplu_job(C.Structure):
@@ -128,6 +135,8 @@ lib.rplu_dense.argtypes = [_P, C.c_int, _I64, _I64, _P, _I64, C.POINTER(rplu_opt
                            _P, _I64, C.POINTER(rplu_info), _P]
 lib.rplu_cur.argtypes = [_P, C.c_int, _I64, _I64, _P, _I64, C.POINTER(rplu_opts), _P, _P, _I64,
                          C.POINTER(rplu_info), _P]
+lib.rplu_cur_aaa.argtypes = [_P, _I64, _P, _P, C.c_double, C.c_uint64, _I64, C.c_uint32,
+                             C.POINTER(rplu_opts), _P, _P, C.POINTER(rplu_aaa_info), _P]
 lib.rplu_cauchy.argtypes = [_P, C.c_int, _I64, _I64, C.c_int32, _P, _P, _P, _P,
                             C.POINTER(rplu_opts), _P, _P, _I64, _P, _I64, C.POINTER(rplu_info), _P]
 lib.rplu_batched.argtypes = [_P, _I64, C.POINTER(rplu_job), C.POINTER(rplu_info), _P]
@@ -156,7 +165,7 @@ lib.rplu_status_str.restype = C.c_char_p
 lib.rplu_last_error.restype = C.c_char_p
 lib.rplu_last_error.argtypes = []
 for _fn in ("rplu_create", "rplu_destroy", "rplu_dense", "rplu_dense_noalloc", "rplu_cauchy",
-            "rplu_cur",
+            "rplu_cur", "rplu_cur_aaa",
             "rplu_batched",
             "rplu_batched_ex", "rplu_batched_tune", "rplu_verify",
             "rplu_server_create", "rplu_server_submit", "rplu_server_poll",
@@ -418,6 +427,48 @@ def rplu_cauchy(x: torch.Tensor, y: torch.Tensor, G: torch.Tensor, B: torch.Tens
                   trace[:r] if trace is not None else None, rmo[:r] if rmo is not None else None,
                   cmo[:r] if cmo is not None else None, refreshes=int(info.refreshes),
                   first_refresh=int(info.first_refresh), trials=int(info.trials))
+
+
+@dataclass
+class AAAResult:
+    """CUR-AAA: r(z) = sum_j w_j f(t_j) / (z - t_j) / sum_j w_j / (z - t_j)
+    with t = z[support]."""
+    support: torch.Tensor          # k int32 (device): indices into z
+    weights: torch.Tensor          # k complex128 (device)
+    which: int                     # 0: rows (points of X), 1: columns (points of Y)
+    max_err: float
+    err_rows: float
+    err_cols: float
+    rank: int
+    stop: int
+    trials: int
+
+
+def rplu_cur_aaa(z: torch.Tensor, f: torch.Tensor, eps: float, seed: int = 0,
+                 max_support: int = 512, flags: int = 0, bounds: Optional[tuple] = None,
+                 ctx: Optional[Context] = None) -> AAAResult:
+    """CUR-AAA (Alg. 4) on samples z, f (complex128 CUDA vectors)."""
+    for t_ in (z, f):
+        if t_.dtype != torch.complex128 or not t_.is_cuda or not t_.is_contiguous() or t_.dim() != 1:
+            raise ValueError("z and f must be contiguous complex128 CUDA vectors")
+    m = z.shape[0]
+    dev = z.device
+    ctx = ctx or default_context(dev.index or 0)
+    ks = min(max_support, m // 2)
+    sup = torch.empty(ks, dtype=torch.int32, device=dev)
+    w = torch.empty(ks, dtype=torch.complex128, device=dev)
+    bo = None
+    if bounds is not None:
+        flags |= RPLU_FLAG_BOUNDS
+        bo = _opts(0, 0.0, 0, 0, 0, None, None, None, None, None, float(bounds[0]), int(bounds[1]))
+    info = rplu_aaa_info()
+    st = lib.rplu_cur_aaa(ctx.handle, m, _ptr(z), _ptr(f), float(eps), int(seed) & (2**64 - 1),
+                          ks, int(flags), C.byref(bo) if bo is not None else None, _ptr(sup),
+                          _ptr(w), C.byref(info), _cur_stream(dev))
+    _check(st, "rplu_cur_aaa")
+    k = int(info.k)
+    return AAAResult(sup[:k], w[:k], int(info.which), float(info.max_err), float(info.err_rows),
+                     float(info.err_cols), int(info.rank), int(info.stop), int(info.trials))
 
 
 def rplu_profile_begin(ctx: Context) -> None:

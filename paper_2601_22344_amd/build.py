@@ -21,7 +21,7 @@ ARCH = "gfx950"
 
 SOURCES = ["api.hip", "sample.hip", "dense.hip", "cauchy.hip", "batched.hip", "batch_api.cpp",
            "verify.hip", "server.cpp", "noalloc.hip", "cur.hip", "cauchy_bounds.hip",
-           "bounds_plan.cpp"]
+           "bounds_plan.cpp", "aaa.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"-I{INCLUDE}", f"-I{CSRC}"]

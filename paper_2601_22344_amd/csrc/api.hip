@@ -393,6 +393,7 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
     sa.tol2 = a.tol2;
     sa.stall = (opts->flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
     sa.greedy = (opts->flags & RPLU_FLAG_C2PLU) ? 1 : (opts->flags & RPLU_FLAG_CPLU) ? 2 : 0;
+    sa.maxmass = (opts->flags & RPLU_FLAG_MAXMASS_STOP) ? 1 : 0;
     sa.rowmax = a.rowmax;
     sa.forced = opts->forced;
     sa.trace = opts->trace;
@@ -559,8 +560,10 @@ rplu_status cauchy_run(rplu_ctx_s* ctx, char* ws, int64_t n, int64_t m, int p, c
     a.seed = opts->seed;
     a.stream = opts->stream;
     a.kmax = kmax;
-    // with bounds the stop test runs on sum(u), with tol^2 / nu (certified)
-    a.tol2 = opts->rel_tol * opts->rel_tol / (bp ? bp->nu : 1.0);
+    // with bounds the stop test runs on sum(u), with tol^2 / nu (certified);
+    // the max-mass rule takes tol^2 as it is
+    const bool maxmass = (opts->flags & RPLU_FLAG_MAXMASS_STOP) != 0;
+    a.tol2 = opts->rel_tol * opts->rel_tol / (bp && !maxmass ? bp->nu : 1.0);
 
     CauchyArgs ac;                       // the column pass
     std::memset(&ac, 0, sizeof ac);
@@ -602,6 +605,7 @@ rplu_status cauchy_run(rplu_ctx_s* ctx, char* ws, int64_t n, int64_t m, int p, c
     sa.tol2 = a.tol2;
     sa.stall = (opts->flags & RPLU_FLAG_STALL_STOP) ? 1 : 0;
     sa.greedy = (opts->flags & RPLU_FLAG_C2PLU) ? 1 : 0;
+    sa.maxmass = maxmass ? 1 : 0;
     sa.forced = opts->forced;
     sa.trace = opts->trace;
     sa.rowmass_out = opts->rowmass_out;

@@ -272,6 +272,7 @@ struct StepState {
     int32_t trials;         // RPLU_FLAG_BOUNDS: trials of the step's row draw
     int32_t pad5;
     int64_t trials_total;   // and over the run
+    double M0;              // max-mass stop rule: the largest row mass at step 0
 };
 
 }  // namespace rplu

@@ -82,6 +82,7 @@ struct SampleArgs {
     double* trace;
     double* rowmass_out;
     int fused;           // dense: one fused pivot kernel per step (n, m <= PIVOT_FUSED_MAX)
+    int maxmass;         // RPLU_FLAG_MAXMASS_STOP: tolerance on the largest row mass
     int greedy;          // 1: C2PLU, the largest masses instead of the draws;
                          // 2: CPLU, the row of the largest entry (rowmax), then
                          // the largest entry of that row

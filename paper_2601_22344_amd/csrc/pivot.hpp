@@ -47,18 +47,19 @@ struct PivotArgs {
                             // the draws; 2: CPLU (Sec. 1, complete pivoting), the
                             // first row of largest rowmax, then as C2PLU's column
     const double* rowmax;   // greedy == 2: largest |S_ij|^2 of each row
+    int maxmass;            // tolerance stop on the largest row mass (Alg. 4)
 };
 
 // What the stop test reads from the state besides t, loaded at the start of
 // a draw kernel (only earlier kernels write it), and the step's two Philox
 // words: neither depends on the masses, so both are ready before the draw.
 struct StopInputs {
-    double T0, T_best, T_ref;
+    double T0, T_best, T_ref, M0;
     int t_best, refresh_on;
 };
 
 __device__ inline StopInputs stop_inputs(const StepState* st) {
-    return {st->T0, st->T_best, st->T_ref, st->t_best, st->refresh_on};
+    return {st->T0, st->T_best, st->T_ref, st->M0, st->t_best, st->refresh_on};
 }
 
 __device__ inline Philox4 step_words(const PivotArgs& a, int t) {
@@ -68,9 +69,11 @@ __device__ inline Philox4 step_words(const PivotArgs& a, int t) {
 // Thread 0: stop test at the start of step t on the total T. Returns 1 when
 // the run ends here (done, stop or error recorded in the state).
 __device__ inline int pivot_stop_test(StepState* st, int t, double T, int kmax, double tol2,
-                                      int stall, const StopInputs& in) {
+                                      int stall, const StopInputs& in, int maxmass = 0,
+                                      double M = 0.0) {
     int stop = 0, err = 0;
     const double T0 = (t == 0) ? T : in.T0;
+    const double M0 = (t == 0) ? M : in.M0;     // max-mass rule: the step-0 largest mass
     double T_best = in.T_best;
     int t_best = in.t_best;
     if (stall) {
@@ -86,12 +89,12 @@ __device__ inline int pivot_stop_test(StepState* st, int t, double T, int kmax, 
     }
     if (!isfinite(T)) err = RPLU_E_NONFINITE;
     else if (T == 0.0) stop = RPLU_STOP_EXHAUSTED;
-    else if (tol2 > 0.0 && T <= tol2 * T0) stop = RPLU_STOP_TOL;
+    else if (tol2 > 0.0 && (maxmass ? M <= tol2 * M0 : T <= tol2 * T0)) stop = RPLU_STOP_TOL;
     else if (in.refresh_on && t < kmax && T <= RPLU_REFRESH_DROP2 * T_ref) stop = RPLU_STOP_REFRESH;
     else if (stall && t - t_best >= RPLU_STALL_WINDOW) stop = RPLU_STOP_STALL;
     else if (t >= kmax) stop = tol2 > 0.0 ? RPLU_STOP_TOL_UNREACHED : RPLU_STOP_RANK;
     st->T = T;
-    if (t == 0) st->T0 = T;
+    if (t == 0) { st->T0 = T; st->M0 = M; }
     if (err || stop) { st->error = err; st->stop = stop; st->done = 1; }
     return (err || stop) ? 1 : 0;
 }
@@ -204,7 +207,12 @@ __device__ inline int pivot_row_draw_ct(CdfShared& sh, int* flag, const PivotArg
     StepState* st = a.st;
     const int K = cdf_chunks(a.n);
     const double T = cdf_levels(sh, ct, K);
-    if (threadIdx.x == 0) *flag = pivot_stop_test(st, t, T, a.kmax, a.tol2, a.stall, in);
+    // max-mass rule: the largest mass, when the total is finite (the stop
+    // test reports a non-finite one)
+    double M = 0.0;
+    if (a.maxmass && isfinite(T)) M = mass(wg_argmax(sh, a.n, mass));
+    if (threadIdx.x == 0)
+        *flag = pivot_stop_test(st, t, T, a.kmax, a.tol2, a.stall, in, a.maxmass, M);
     __syncthreads();
     if (*flag) return -1;
     if (a.rowmass_out != nullptr)
@@ -438,6 +446,7 @@ inline PivotArgs pivot_args(const SampleArgs& sa) {
     p.rowmass_out = sa.rowmass_out;
     p.greedy = sa.greedy;
     p.rowmax = sa.rowmax;
+    p.maxmass = sa.maxmass;
     return p;
 }
 
