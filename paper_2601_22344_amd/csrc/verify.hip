@@ -37,14 +37,20 @@ __device__ inline double vf_load(const T* p) { return (double)*p; }
 // MODE 0: norms of A and E; 1: also ||E - S||; 2 (refresh): no norms, E
 // rounded to T is written to S (the residual replacement of a run that has
 // stalled in single precision).
+// The k loop is software pipelined: the slice k0 + 16 is loaded from global
+// memory into registers while the matrix cores work on slice k0 from one of
+// two LDS buffers, so one barrier per slice suffices (a buffer is written
+// again only after every wave has passed the barrier that follows its last
+// read). Two workgroups fit on a CU (waves_per_eu 2).
 template <class T, int MODE>
-__global__ __launch_bounds__(VF_THREADS) void k_verify(
+__global__ __launch_bounds__(VF_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_verify(
     int n, int m, int k, const T* __restrict__ A, int64_t lda, const T* __restrict__ L,
     int64_t ldl, const T* __restrict__ U, int64_t ldu, const T* S, int64_t lds,
     double* __restrict__ partial) {
     constexpr bool WITH_S = MODE == 1;
-    __shared__ double sL[VF_KC][VF_TILE + VF_PAD];
-    __shared__ double sU[VF_KC][VF_TILE + VF_PAD];
+    __shared__ double sL[2][VF_KC][VF_TILE + VF_PAD];
+    __shared__ double sU[2][VF_KC][VF_TILE + VF_PAD];
     __shared__ double sred[VF_THREADS / RPLU_WAVE][3];
     const int tid = threadIdx.x, lane = tid % RPLU_WAVE, wv = tid / RPLU_WAVE;
     const int wy = wv / 2, wx = wv % 2;
@@ -57,32 +63,45 @@ __global__ __launch_bounds__(VF_THREADS) void k_verify(
 
     const int lr = tid % VF_TILE;        // row (of L) / column (of U) this thread stages
     const int lk = tid / VF_TILE;        // 0 or 1: first slice column it stages
-    for (int k0 = 0; k0 < k; k0 += VF_KC) {
-        // stage L(r0.., k0..k0+15) and U(k0..k0+15, c0..), zero outside
+    const bool rin = r0 + lr < n, cin = c0 + lr < m;
+    const T* Lp = L + r0 + lr;
+    const T* Up = U + c0 + lr;
+    T pl[VF_KC / 2], pu[VF_KC / 2];
+    // L(r0.., k0..k0+15) and U(k0..k0+15, c0..) into registers, zero outside
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < VF_KC / 2; ++q) {
-            const int kk = lk + 2 * q;
-            const int r = r0 + lr, c = c0 + lr;
-            const bool kin = k0 + kk < k;
-            sL[kk][lr] = (kin && r < n) ? vf_load(L + (int64_t)(k0 + kk) * ldl + r) : 0.0;
-            sU[kk][lr] = (kin && c < m) ? vf_load(U + (int64_t)(k0 + kk) * ldu + c) : 0.0;
+            const int kk = k0 + lk + 2 * q;
+            const bool kin = kk < k;
+            pl[q] = (kin && rin) ? Lp[(int64_t)kk * ldl] : (T)0;
+            pu[q] = (kin && cin) ? Up[(int64_t)kk * ldu] : (T)0;
+        }
+    };
+    fetch(0);
+    int buf = 0;
+    for (int k0 = 0; k0 < k; k0 += VF_KC) {
+#pragma unroll
+        for (int q = 0; q < VF_KC / 2; ++q) {
+            sL[buf][lk + 2 * q][lr] = (double)pl[q];
+            sU[buf][lk + 2 * q][lr] = (double)pu[q];
         }
         __syncthreads();
+        if (k0 + VF_KC < k) fetch(k0 + VF_KC);
 #pragma unroll
         for (int kq = 0; kq < VF_KC / 4; ++kq) {
             const int kr = kq * 4 + lane / 16;
             double a[4], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = sL[kr][wy * 64 + i * 16 + lane % 16];
+            for (int i = 0; i < 4; ++i) a[i] = sL[buf][kr][wy * 64 + i * 16 + lane % 16];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = sU[kr][wx * 64 + j * 16 + lane % 16];
+            for (int j = 0; j < 4; ++j) b[j] = sU[buf][kr][wx * 64 + j * 16 + lane % 16];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        __syncthreads();
+        buf ^= 1;
     }
 
     double sa = 0.0, se = 0.0, ss = 0.0;
