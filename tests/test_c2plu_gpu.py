@@ -5,7 +5,7 @@ The choice is an argmax, taken on both sides in FP64 over masses that agree
 to rounding; the random inputs keep the largest masses well apart, so the
 pivots must be identical. FP64 / complex128: L, U and the final Schur
 complement agree within 1e-10. FP32 / complex64: the oracle runs in FP64 on
-the single-precision input and the factors agree within 1e-4. Ties: on
+the single-precision input and the factors agree within 1e-5 (printed). Ties: on
 +-1 Hadamard inputs every step has exact ties on both sides (small integers
 are exact in every precision), which go to the smallest index. The fused
 and the wide pivot forms agree bit for bit; the Cauchy-like path agrees with
@@ -47,10 +47,12 @@ def test_c2plu_dense_matches_oracle(rplu_lib, dt, shape):
     Ad = t.to(DEV)
     res = rplu_lib.rplu_dense(Ad, k=k, flags=rplu_lib.RPLU_FLAG_C2PLU)
     orc = O.rplu_dense(A_in, k=k, greedy=True)
-    tol = 1e-10 if dt in ("r64", "c128") else 1e-4
+    tol = 1e-10 if dt in ("r64", "c128") else 1e-5
     _check(res, orc, tol)
     S_g = Ad.cpu().to(WIDE[dt]).numpy()
-    assert parity.rel(S_g, orc.S, scale=np.sqrt(orc.a_fro2)) <= tol
+    err = parity.rel(S_g, orc.S, scale=np.sqrt(orc.a_fro2))
+    print(f"c2plu {dt} {n}x{m}: ||S_gpu - S_orc|| / ||A|| = {err:.2e}", flush=True)
+    assert err <= tol
 
 
 def test_c2plu_dense_wide_form_matches_oracle(rplu_lib):
