@@ -32,6 +32,7 @@
 #include "cdf.hpp"
 #include "launch.hpp"
 #include "pivot.hpp"
+#include "runtime.hpp"
 
 namespace rplu {
 
@@ -218,6 +219,16 @@ struct MassFrame {
 
 constexpr double CM_SHORT_RATIO = 0x1p-6;
 
+// Ranges under which the 16-column form of k_cauchy_mass1 can neither
+// overflow nor underflow: with every |x - y|^2 in [2^-28, 2^28] and every
+// w_j = |b_j|^2 zero or in [2^-500, 2^500], each product of up to 16
+// distances lies in [2^-449, 2^449] and each term w_u prod_{v != u} d_v in
+// [2^-921, 2^921].
+constexpr double CM_D_LO = 0x1p-28, CM_D_HI = 0x1p+28;
+constexpr double CM_W_LO = 0x1p-500, CM_W_HI = 0x1p+500;
+
+__device__ inline bool w_in_range(double w) { return w == 0.0 || (w >= CM_W_LO && w <= CM_W_HI); }
+
 __device__ inline double wave_min(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, RPLU_WAVE));
@@ -234,7 +245,8 @@ __device__ inline double wave_max(double v) {
 __global__ __launch_bounds__(1024) void k_cauchy_frame(const cf64* __restrict__ y,
                                                        const cf64* __restrict__ B, int m,
                                                        MassFrame* __restrict__ fr,
-                                                       MassCol* __restrict__ col) {
+                                                       MassCol* __restrict__ col,
+                                                       StepState* __restrict__ st) {
     __shared__ double red[5][16];
     __shared__ double cen[2];
     const int tid = threadIdx.x, lane = tid % RPLU_WAVE, w = tid / RPLU_WAVE;
@@ -261,19 +273,87 @@ __global__ __launch_bounds__(1024) void k_cauchy_frame(const cf64* __restrict__ 
     __syncthreads();
     const double cr = cen[0], ci = cen[1];
     double smax = 0.0;
+    bool bad = false;
     for (int j = tid; j < m; j += 1024) {
         const cf64 v = y[j], b = B[j];
         const double yr = v.re - cr, yi = v.im - ci;
         const double sy = fma(yr, yr, yi * yi);
-        col[j] = MassCol{yr, yi, sy, b.re * b.re + b.im * b.im};
+        const double w = b.re * b.re + b.im * b.im;
+        col[j] = MassCol{yr, yi, sy, w};
         smax = fmax(smax, sy);
+        bad = bad | !w_in_range(w);
     }
+    if (__any(bad) && lane == 0) atomicOr(&st->wbad, 1);
     smax = wave_max(smax);
     if (lane == 0) red[4][w] = smax;
     __syncthreads();
     if (tid == 0) {
         for (int q = 1; q < 16; ++q) smax = fmax(smax, red[4][q]);
         fr->R2 = smax;
+    }
+}
+
+// Level-1 pairs (D_k = d_2k d_2k+1, N_k = w_2k d_2k+1 + w_2k+1 d_2k) of K
+// column pairs merged pairwise, (N, D) of one pair of halves at a time, into
+// one fraction N / D = sum_u w_u / d_u; the result is left in N[0], D[0].
+template <int K>
+__device__ __forceinline__ void pair_tree(double (&N)[K], double (&D)[K]) {
+#pragma unroll
+    for (int h = K; h > 1; h /= 2) {
+#pragma unroll
+        for (int k = 0; k < h / 2; ++k) {
+            const double nk = fma(N[2 * k], D[2 * k + 1], N[2 * k + 1] * D[2 * k]);
+            D[k] = D[2 * k] * D[2 * k + 1];
+            N[k] = nk;
+        }
+    }
+}
+
+// The masses of k_cauchy_mass1 over the columns [c_beg, c_end) in the short
+// form, for waves whose distances and weights keep every product of the
+// reciprocal tree inside the FP64 range (CM_D_*, CM_W_*): sixteen columns
+// share one reciprocal, with no range checks and no recomputation; the last
+// columns of the range go in a group of eight, then one by one.
+template <int K>
+__device__ __forceinline__ void mass1_groups(const MassCol* __restrict__ col, int e,
+                                             const double (&a2)[CM_RT], const double (&b2)[CM_RT],
+                                             const double (&sx)[CM_RT], double (&acc)[CM_RT]) {
+    double N[CM_RT][K], D[CM_RT][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const MassCol u0 = col[e + 2 * k], u1 = col[e + 2 * k + 1];
+#pragma unroll
+        for (int q = 0; q < CM_RT; ++q) {
+            const double d0 = fma(a2[q], u0.yr, fma(b2[q], u0.yi, sx[q] + u0.sy));
+            const double d1 = fma(a2[q], u1.yr, fma(b2[q], u1.yi, sx[q] + u1.sy));
+            D[q][k] = d0 * d1;
+            N[q][k] = fma(u0.w, d1, u1.w * d0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CM_RT; ++q) {
+        pair_tree<K>(N[q], D[q]);
+        acc[q] = fma(N[q][0], rcp_1nr(D[q][0]), acc[q]);
+    }
+}
+
+__device__ __forceinline__ void mass1_fast(const MassCol* __restrict__ col, int c_beg, int c_end,
+                                           const double (&a2)[CM_RT], const double (&b2)[CM_RT],
+                                           const double (&sx)[CM_RT], double (&acc)[CM_RT]) {
+    int e = c_beg;
+#pragma unroll 1
+    for (; e + 16 <= c_end; e += 16) mass1_groups<8>(col, e, a2, b2, sx, acc);
+    if (e + 8 <= c_end) {
+        mass1_groups<4>(col, e, a2, b2, sx, acc);
+        e += 8;
+    }
+    for (; e < c_end; ++e) {
+        const MassCol u = col[e];
+#pragma unroll
+        for (int q = 0; q < CM_RT; ++q) {
+            const double d = fma(a2[q], u.yr, fma(b2[q], u.yi, sx[q] + u.sy));
+            acc[q] = fma(u.w, rcp_refined(d), acc[q]);
+        }
     }
 }
 
@@ -290,6 +370,7 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass1(
 
     double xr[CM_RT], xi[CM_RT], a2[CM_RT], b2[CM_RT], sx[CM_RT], gscale[CM_RT], acc[CM_RT];
     bool safe = true;     // the short form is accurate for this lane's rows
+    bool inrange = true;  // and every |x - y_j|^2 of them lies in [CM_D_LO, CM_D_HI]
 #pragma unroll
     for (int q = 0; q < CM_RT; ++q) {
         const int r = blockIdx.x * CM_ROWS + q * CM_THREADS + tid;
@@ -308,10 +389,18 @@ __global__ __launch_bounds__(CM_THREADS) void k_cauchy_mass1(
         // and max_j (|x - c|^2 + |y_j - c|^2) <= |x - c|^2 + R2
         const double dx = fmax(0.0, fmax(frame->yr0 - xv.re, xv.re - frame->yr1));
         const double dy = fmax(0.0, fmax(frame->yi0 - xv.im, xv.im - frame->yi1));
-        if (valid) safe = safe & (fma(dx, dx, dy * dy) >= CM_SHORT_RATIO * (sx[q] + frame->R2));
+        // and |x - y_j|^2 <= (|x - c| + |y_j - c|)^2 <= 2 (|x - c|^2 + R2)
+        if (valid) {
+            const double dist2 = fma(dx, dx, dy * dy);
+            safe = safe & (dist2 >= CM_SHORT_RATIO * (sx[q] + frame->R2));
+            inrange = inrange & (dist2 >= CM_D_LO) & (2.0 * (sx[q] + frame->R2) <= CM_D_HI);
+        }
     }
     const int shortf = __all(safe) ? 1 : 0;     // the same in every lane of the wave
+    const int fastf = (shortf && __all(inrange) && st->wbad == 0) ? 1 : 0;
 
+    if (fastf) mass1_fast(col, c_beg, c_end, a2, b2, sx, acc);
+    else
     for (int c0 = c_beg; c0 < c_end; c0 += CM_TILE) {
         const int nt = min(CM_TILE, c_end - c0);
         const int ng = nt / CM_GRP * CM_GRP;
@@ -422,6 +511,7 @@ __global__ __launch_bounds__(CDF_THREADS) void k_cauchy_reduce_draw(
     }
     wide_chunk_totals<CDF_CHUNK>(sh, v, n, ct);
     if (!wide_arrive_last(sh, &pa.st->arrive)) return;
+    if (threadIdx.x == 0) pa.st->wbad = 0;      // this step's mass pass has read it
     pivot_row_draw_ct(sh.cdf, &sh.flag, pa, ct, t, wide_words(sh), in, RowMassGlobal{rowmass});
 }
 
@@ -455,11 +545,12 @@ __global__ __launch_bounds__(CDF_THREADS) void k_cauchy_rowgen_draw(
     pivot_col_draw_ct<cf64, P>(sh.cdf, pa, t, Ut, ct, G, B, wide_words(sh), ColMassGlobal<cf64>{Ut});
 }
 
-// For p = 1 it also rewrites w_j = |b_j|^2 of the mass kernel's column data.
+// For p = 1 it also rewrites w_j = |b_j|^2 of the mass kernel's column data
+// and flags a w_j outside the range of the 16-column form (StepState::wbad).
 template <int P>
 __global__ __launch_bounds__(256) void k_cauchy_update(
     const cf64* __restrict__ x, const cf64* __restrict__ y, cf64* __restrict__ G,
-    cf64* __restrict__ B, int n, int m, const StepState* __restrict__ st,
+    cf64* __restrict__ B, int n, int m, StepState* __restrict__ st,
     const cf64* __restrict__ U, int64_t ldu, cf64* __restrict__ L, int64_t ldl,
     MassCol* __restrict__ col) {
     if (st->done) return;
@@ -497,7 +588,11 @@ __global__ __launch_bounds__(256) void k_cauchy_update(
             const cf64 b = B[(int64_t)l * m + c];
             const cf64 nb = (c == pj) ? cf64{0.0, 0.0} : csub(b, wmul(bjl, f));
             B[(int64_t)l * m + c] = nb;
-            if constexpr (P == 1) col[c].w = nb.re * nb.re + nb.im * nb.im;
+            if constexpr (P == 1) {
+                const double w = nb.re * nb.re + nb.im * nb.im;
+                col[c].w = w;
+                if (!w_in_range(w)) atomicOr(&st->wbad, 1);
+            }
         }
     }
 }
@@ -523,6 +618,25 @@ __global__ __launch_bounds__(256) void k_cauchy_transpose(const cf64* __restrict
 // ---------------------------------------------------------------- launchers
 
 int cauchy_rows_per_block() { return CM_ROWS; }
+
+static int mass_wg_per_cu(const void* f) {
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, CM_THREADS, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 2;
+}
+
+MassSlots cauchy_mass_slots(int cu_count) {
+    MassSlots sl;
+    sl.cu_count = cu_count;
+    sl.row_wg[1] = mass_wg_per_cu(reinterpret_cast<const void*>(&k_cauchy_mass1));
+    sl.col_wg[1] = mass_wg_per_cu(reinterpret_cast<const void*>(&k_cauchy_mass<1>));
+    sl.row_wg[2] = sl.col_wg[2] = mass_wg_per_cu(reinterpret_cast<const void*>(&k_cauchy_mass<2>));
+    sl.row_wg[3] = sl.col_wg[3] = mass_wg_per_cu(reinterpret_cast<const void*>(&k_cauchy_mass<3>));
+    sl.row_wg[4] = sl.col_wg[4] = mass_wg_per_cu(reinterpret_cast<const void*>(&k_cauchy_mass<4>));
+    sl.row_wg[0] = sl.row_wg[1];
+    sl.col_wg[0] = sl.col_wg[1];
+    return sl;
+}
 
 template <int P>
 static void mass_p(const CauchyArgs& a, hipStream_t s) {
@@ -551,7 +665,7 @@ void launch_cauchy_transpose(const CauchyArgs& a, void* Gt, void* Bt, hipStream_
 void launch_cauchy_frame(const CauchyArgs& a, hipStream_t s) {
     if (a.p != 1) return;
     hipLaunchKernelGGL(k_cauchy_frame, dim3(1), dim3(1024), 0, s, (const cf64*)a.y,
-                       (const cf64*)a.B, (int)a.m, (MassFrame*)a.mframe, (MassCol*)a.mcol);
+                       (const cf64*)a.B, (int)a.m, (MassFrame*)a.mframe, (MassCol*)a.mcol, a.st);
 }
 
 void launch_cauchy_reduce_draw(const CauchyArgs& a, const SampleArgs& sa, hipStream_t s) {

@@ -270,7 +270,10 @@ struct StepState {
     double sig_re, sig_im;  // CUR form: sigma = A[i, j] - z^T U_k w of the step
     double l2;              // CUR form: ||l||^2 of the step
     int32_t trials;         // RPLU_FLAG_BOUNDS: trials of the step's row draw
-    int32_t pad5;
+    int32_t wbad;           // Cauchy, p = 1: some w_j = |b_j|^2 of the mass
+                            // kernel's column data lies outside {0} and
+                            // [2^-500, 2^500] (set by the generator update,
+                            // cleared by the row draw of every step)
     int64_t trials_total;   // and over the run
     double M0;              // max-mass stop rule: the largest row mass at step 0
 };

@@ -11,6 +11,19 @@
 
 namespace rplu {
 struct StepState;
+
+// Workgroup slots of the all-pairs mass kernels (Cauchy-like form): the CUs
+// and, per generator width p = 1..4, how many workgroups of the row pass and
+// of the column pass one CU holds at once (the kernels' occupancy). They size
+// the column splits so that the grid fills whole rounds of the chip.
+struct MassSlots {
+    int cu_count = 256;
+    int row_wg[5] = {2, 2, 2, 2, 2};
+    int col_wg[5] = {2, 2, 2, 2, 2};
+};
+// Queries the occupancy of the mass kernels on the current device (2 per CU
+// for a kernel whose query fails).
+MassSlots cauchy_mass_slots(int cu_count);
 }
 
 struct rplu_prof_rec {
@@ -58,6 +71,7 @@ struct rplu_ctx_s {
     rplu_graph_entry graphs[RPLU_GRAPH_CACHE];
     uint64_t use_clock = 0;
     std::vector<rplu_tune_entry> tune;       // batched-launch tuning table
+    rplu::MassSlots mass_slots;              // occupancy of the Cauchy mass kernels
 };
 
 namespace rplu {
@@ -106,7 +120,7 @@ rplu_status cauchy_check(const char* who, int dtype, int64_t n, int64_t m, int p
                          const void* y, const void* G, const void* B, const rplu_opts* opts,
                          const int32_t* piv, const void* L, int64_t ldl, const void* U,
                          int64_t ldu, const rplu_info* info);
-CauchyWs cauchy_ws_layout(int cu_count, int64_t n, int64_t m, int p, uint32_t flags,
+CauchyWs cauchy_ws_layout(const MassSlots& slots, int64_t n, int64_t m, int p, uint32_t flags,
                           bool colmass, bool need_u);
 struct BoundsPlan;
 // bp: the device plan of RPLU_FLAG_BOUNDS, or null (exact masses).

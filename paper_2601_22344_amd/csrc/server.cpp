@@ -138,7 +138,7 @@ struct rplu_server_s {
     rplu_server_cfg cfg{};
     bool simulate = false;
     int device = 0;
-    int cu_count = 256;
+    MassSlots mass_slots;                // occupancy of the Cauchy mass kernels
     char* pool_base = nullptr;
     size_t pool_cap = 0;
     SlotPool pool;
@@ -628,7 +628,7 @@ rplu_status plan_job(const rplu_server_s* S, const rplu_job& d, SJob* j) {
         off = rup(off + (size_t)d.p * d.m * 16, 256);
         j->o_ws = off;
         const bool need_u = !own && d.U == nullptr;
-        off = rup(off + cauchy_ws_layout(S->cu_count, d.n, d.m, d.p, d.flags, false, need_u).total, 256);
+        off = rup(off + cauchy_ws_layout(S->mass_slots, d.n, d.m, d.p, d.flags, false, need_u).total, 256);
         j->work_bytes = off;
     } else {
         return fail(RPLU_E_ARG, "rplu_server_submit: unknown job kind %d", d.kind);
@@ -688,7 +688,7 @@ rplu_status rplu_server_create(rplu_ctx ctx, const rplu_server_cfg* cfg, rplu_se
     if (S->cfg.tick_steps <= 0) S->cfg.tick_steps = DEFAULT_TICK;
     S->simulate = sim;
     S->device = ctx ? ctx->device : 0;
-    S->cu_count = ctx ? ctx->cu_count : 256;
+    if (ctx) S->mass_slots = ctx->mass_slots;
     S->pool_cap = rup(cfg->hbm_budget_bytes, 256);
     if (sim) {
         S->pool_base = (char*)std::malloc(256);   // offsets only; never dereferenced

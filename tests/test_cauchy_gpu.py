@@ -97,6 +97,34 @@ def test_cauchy_p1_mixed_waves(rplu_lib):
     _check_small(rplu_lib, x, y, G, B, 30, seed=4)
 
 
+@pytest.mark.parametrize("case", ["plain", "wide_w", "far", "zero_cols"])
+def test_cauchy_p1_range_guards(rplu_lib, case):
+    """The 16-column reciprocal form of the p = 1 mass kernel runs only where
+    no product of its tree can leave the FP64 range: every |x - y|^2 of a
+    wave in [2^-28, 2^28] and every |b_j|^2 zero or in [2^-500, 2^500].
+    Separated discs as above ("plain": the 16-column form everywhere); B
+    scaled by 2^300 and G by 2^-300, the same matrix ("wide_w": the
+    generator update flags |b_j|^2 = 2^600 and every step takes the checked
+    form); nodes 2^15 apart ("far": distances beyond 2^28, the checked form);
+    a third of the columns of B zero ("zero_cols": zero weights stay in the
+    16-column form). Each against the oracle."""
+    rng = np.random.default_rng(17)
+    n, m = 2100, 1700
+    x = np.sqrt(rng.random(n)) * np.exp(2j * np.pi * rng.random(n))
+    y = 4.0 + np.sqrt(rng.random(m)) * np.exp(2j * np.pi * rng.random(m))
+    G = (rng.standard_normal((n, 1)) + 1j * rng.standard_normal((n, 1))) / math.sqrt(2)
+    B = (rng.standard_normal((1, m)) + 1j * rng.standard_normal((1, m))) / math.sqrt(2)
+    if case == "wide_w":
+        G = G * 2.0 ** -300
+        B = B * 2.0 ** 300
+    elif case == "far":
+        x = x * 2.0 ** 15
+        y = y * 2.0 ** 15
+    elif case == "zero_cols":
+        B[0, ::3] = 0.0
+    _check_small(rplu_lib, x, y, G, B, 30, seed=8, stream=2)
+
+
 @pytest.mark.parametrize("bad", ["nan", "inf"])
 def test_cauchy_p1_nonfinite_node(rplu_lib, bad):
     """A non-finite y_j in a geometry where the other waves take the short
