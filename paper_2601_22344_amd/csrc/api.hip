@@ -267,20 +267,35 @@ static int64_t kmax_of(int64_t n, int64_t m, int64_t k) {
     return k <= 0 ? mn : std::min(k, mn);
 }
 
+bool dense_step_eligible(int64_t n, int64_t m, uint32_t flags) {
+    return n <= DENSE_STEP_MAX && m <= DENSE_STEP_MAX &&
+           !(flags & (RPLU_FLAG_COLMASS | RPLU_FLAG_CPLU | RPLU_FLAG_REFRESH |
+                      RPLU_FLAG_SPLIT_SAMPLER | RPLU_FLAG_LAZY_SWEEP));
+}
+
 // Workspace of one dense run, carved from a 256-byte aligned base.
-DenseWs dense_ws_layout(int dtype, int64_t n, int64_t m, uint32_t flags, bool need_u) {
+DenseWs dense_ws_layout(int dtype, int64_t n, int64_t m, uint32_t flags, bool need_u,
+                        bool allow_step) {
     const size_t es = dtype_size(dtype);
     const bool colmass = (flags & RPLU_FLAG_COLMASS) != 0;
     Carver cv;
     DenseWs w;
+    w.step = allow_step && dense_step_eligible(n, m, flags);
     w.o_st = cv.take(sizeof(StepState));
-    w.o_rm = cv.take((size_t)n * 8);
+    w.o_rm = cv.take((size_t)n * 8 * (w.step ? 2 : 1));   // step form: two buffers
     w.o_rx = (flags & RPLU_FLAG_CPLU) ? cv.take((size_t)n * 8) : 0;
     w.o_ctr = cv.take((size_t)cdf_chunks((int)n) * 8);
     w.o_ctc = cv.take((size_t)cdf_chunks((int)m) * 8);
     const int64_t nbc = (n + DENSE_ROWS_COLMASS - 1) / DENSE_ROWS_COLMASS;
     w.o_cp = colmass ? cv.take((size_t)nbc * m * 8) : 0;
     w.o_u = need_u ? cv.take((size_t)m * es) : 0;
+    if (w.step) {
+        w.groups = (int)((n + DENSE_STEP_ROWS - 1) / DENSE_STEP_ROWS);
+        w.ldur = (m + 3) / 4 * 4;                     // 16-byte aligned rows
+        w.o_sts = cv.take((size_t)w.groups * sizeof(StepState));
+        w.o_ur = cv.take((size_t)w.groups * (size_t)w.ldur * es);
+        w.o_dead = cv.take((size_t)n);
+    }
     w.total = cv.off;
     return w;
 }
@@ -335,7 +350,7 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
     const size_t es = dtype_size(dtype);
     const int64_t kmax = kmax_of(n, m, opts->max_rank);
     const bool colmass = (opts->flags & RPLU_FLAG_COLMASS) != 0;
-    const DenseWs w = dense_ws_layout(dtype, n, m, opts->flags, U == nullptr);
+    const DenseWs w = dense_ws_layout(dtype, n, m, opts->flags, U == nullptr, ctx != nullptr);
 
     DenseArgs a;
     std::memset(&a, 0, sizeof a);        // padding too: the struct keys the graph cache
@@ -373,7 +388,22 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
     a.tol2 = opts->rel_tol * opts->rel_tol;
 
     const bool refresh = (opts->flags & RPLU_FLAG_REFRESH) != 0;
-    launch_state_init(a.st, s, refresh ? 1 : 0);
+    // small runs: draws and sweep of a step in one launch (k_dense_step), the
+    // same results bit for bit; workgroup 0's state is the run's
+    DenseStepArgs d;
+    std::memset(&d, 0, sizeof d);
+    if (w.step) {
+        d.states = (StepState*)(ws + w.o_sts);
+        d.masses = a.rowmass;
+        d.urows = ws + w.o_ur;
+        d.ldur = w.ldur;
+        d.dead = (uint8_t*)(ws + w.o_dead);
+        d.groups = w.groups;
+        a.st = d.states;
+        launch_dense_step_init(a, d, s);
+    } else {
+        launch_state_init(a.st, s, refresh ? 1 : 0);
+    }
     timed(ctx, 3, s, [&] { launch_dense_sweep(a, /*init=*/true, s); });
     if (colmass && a.colmass_out) launch_colmass_reduce(a, false, s);
     hipError_t e = hipGetLastError();
@@ -406,7 +436,19 @@ rplu_status dense_run(rplu_ctx_s* ctx, char* ws, int dtype, int64_t n, int64_t m
     sa.fused = use_fused_pivot(n, m, opts->flags);
 
     const bool graph = ctx != nullptr && !(opts->flags & RPLU_FLAG_NO_GRAPH);
-    const uint64_t key = fnv1a(&sa, sizeof sa, fnv1a(&a, sizeof a, 0x64656e7365ull));
+    uint64_t key = fnv1a(&sa, sizeof sa, fnv1a(&a, sizeof a, 0x64656e7365ull));
+    if (w.step) {
+        key = fnv1a(&d, sizeof d, key);
+        rplu_status rc = run_loop(ctx, a.st, kmax + 1, graph, key, s, [&](hipStream_t q) {
+            timed(ctx, 0, q, [&] { launch_dense_step(a, sa, d, q); });
+        });
+        if (rc) return rc;
+        launch_dense_step_finish(a, d, s);
+        StepState hs;
+        rc = read_state(ctx, a.st, s, &hs);
+        if (rc) return rc;
+        return finish(hs, info, 0, -1);
+    }
     auto step = [&](hipStream_t q) {
         timed(ctx, 1, q, [&] {
             if (sa.fused) {

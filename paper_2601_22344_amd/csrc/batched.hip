@@ -175,7 +175,7 @@ __device__ __forceinline__ void bt_sweep(gmem<T>* __restrict__ S, int64_t lda, i
                         }
                     }
 #pragma unroll
-                    for (int v = 0; v < V; ++v) rp[q] += Sc<T>::mag2(s[q].v[v]);
+                    for (int v = 0; v < V; ++v) rp[q] = Sc<T>::mag2_add(rp[q], s[q].v[v]);
                     if constexpr (!INIT) {
                         gmem<T>* p = rowp[q] + c;
                         if constexpr (FULL) st_pack<T, V>(p, s[q]);
@@ -338,7 +338,7 @@ __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t 
                     }
                     double acc = 0.0;
 #pragma unroll
-                    for (int v = 0; v < V; ++v) acc += Sc<T>::mag2(xk.v[v]);
+                    for (int v = 0; v < V; ++v) acc = Sc<T>::mag2_add(acc, xk.v[v]);
                     part = rem[k] > 0 ? acc : 0.0;
                     if constexpr (!INIT) {
                         if (rem[k] > 0) bt_store<T, V>(S + (int64_t)ri[q] * lda + c, rem[k], xk);

@@ -23,6 +23,10 @@ template <> struct Sc<float> {
     using W = double;
     static constexpr bool cplx = false;
     __device__ __host__ static inline double mag2(float v) { double d = v; return d * d; }
+    // acc + |v|^2 with one rounding (the square of a float is exact in FP64);
+    // every row-mass sum uses it, so that no kernel's sum depends on where
+    // the compiler contracts a multiply and an add
+    __device__ static inline double mag2_add(double acc, float v) { double d = v; return fma(d, d, acc); }
     __device__ static inline W widen(float v) { return (double)v; }
     __device__ static inline float narrow(W v) { return (float)v; }
     __device__ static inline float zero() { return 0.f; }
@@ -36,6 +40,7 @@ template <> struct Sc<double> {
     using W = double;
     static constexpr bool cplx = false;
     __device__ __host__ static inline double mag2(double v) { return v * v; }
+    __device__ static inline double mag2_add(double acc, double v) { return fma(v, v, acc); }
     __device__ static inline W widen(double v) { return v; }
     __device__ static inline double narrow(W v) { return v; }
     __device__ static inline double zero() { return 0.0; }
@@ -53,6 +58,7 @@ template <> struct Sc<cf32> {
         double a = v.re, b = v.im;
         return fma(a, a, b * b);
     }
+    __device__ static inline double mag2_add(double acc, cf32 v) { return acc + mag2(v); }
     __device__ static inline W widen(cf32 v) { return {(double)v.re, (double)v.im}; }
     __device__ static inline cf32 narrow(W v) { return {(float)v.re, (float)v.im}; }
     __device__ static inline cf32 zero() { return {0.f, 0.f}; }
@@ -73,6 +79,7 @@ template <> struct Sc<cf64> {
     using W = cf64;
     static constexpr bool cplx = true;
     __device__ __host__ static inline double mag2(cf64 v) { return fma(v.re, v.re, v.im * v.im); }
+    __device__ static inline double mag2_add(double acc, cf64 v) { return acc + mag2(v); }
     __device__ static inline W widen(cf64 v) { return v; }
     __device__ static inline cf64 narrow(W v) { return v; }
     __device__ static inline cf64 zero() { return {0.0, 0.0}; }

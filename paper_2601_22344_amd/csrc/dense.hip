@@ -180,10 +180,12 @@ __global__ __launch_bounds__(BS) void k_dense_sweep(
                 }
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    const double m2 = Sc<T>::mag2(s[q].v[v]);   // 0 for padding
-                    rp[q] += m2;
-                    if constexpr (COLMASS) cp[v] += m2;
-                    if constexpr (CMAX) rx[q] = m2 > rx[q] ? m2 : rx[q];
+                    rp[q] = Sc<T>::mag2_add(rp[q], s[q].v[v]);   // 0 for padding
+                    if constexpr (COLMASS || CMAX) {
+                        const double m2 = Sc<T>::mag2(s[q].v[v]);
+                        if constexpr (COLMASS) cp[v] += m2;
+                        if constexpr (CMAX) rx[q] = m2 > rx[q] ? m2 : rx[q];
+                    }
                 }
                 if constexpr (!INIT) {
                     T* p = S + (int64_t)(r0 + q) * lda + c;
@@ -456,10 +458,12 @@ __global__ __launch_bounds__(BS) void k_dense_lazy(
                         if constexpr (!FINAL) {
 #pragma unroll
                             for (int v = 0; v < V; ++v) {
-                                const double m2 = Sc<T>::mag2(x[q].v[v]);   // 0 for padding
-                                rp[q] += m2;
-                                if constexpr (COLMASS) cp[v] += m2;
-                                if constexpr (CMAX) rx[q] = m2 > rx[q] ? m2 : rx[q];
+                                rp[q] = Sc<T>::mag2_add(rp[q], x[q].v[v]);   // 0 for padding
+                                if constexpr (COLMASS || CMAX) {
+                                    const double m2 = Sc<T>::mag2(x[q].v[v]);
+                                    if constexpr (COLMASS) cp[v] += m2;
+                                    if constexpr (CMAX) rx[q] = m2 > rx[q] ? m2 : rx[q];
+                                }
                             }
                         }
                     }
@@ -582,18 +586,188 @@ __global__ __launch_bounds__(CDF_THREADS) void k_dense_pivot(const T* __restrict
     const StopInputs in = stop_inputs(pa.st);
     // the window start this step will have (the draw moves it in the state)
     const int tb = (pa.st->flushed == t) ? t : pa.st->t_base;
-    const Philox4 rnd = step_words(pa, t);
-    const int i = pivot_draw_row(sh, pa, t, rnd, in);
+    const int i = pivot_draw_row(sh, pa, t, in);
     if (i < 0) return;
     const T* Si = S + (int64_t)i * lda;
     if constexpr (LAZY) {
         const LazyRowAcc<T> row = lazy_row<T>(S, lda, U, ldu, L, ldl, pa.piv, i, tb, t);
-        pivot_draw_col<T, 0>(sh, pa, t, U + (int64_t)t * ldu, nullptr, nullptr, rnd, row,
+        pivot_draw_col<T, 0>(sh, pa, t, U + (int64_t)t * ldu, nullptr, nullptr, row,
                              [](const T& v) { return v; });
     } else {
-        pivot_draw_col<T, 0>(sh, pa, t, U + (int64_t)t * ldu, nullptr, nullptr, rnd,
+        pivot_draw_col<T, 0>(sh, pa, t, U + (int64_t)t * ldu, nullptr, nullptr,
                              [&](int e) { return Si[e]; }, [](const T& v) { return v; });
     }
+}
+
+// ------------------------------------------------- one launch per step
+//
+// Small matrices (n, m <= DENSE_STEP_MAX): the draws of a step and its sweep
+// in one launch of ceil(n / DENSE_STEP_ROWS) workgroups. A step has two
+// grid-wide dependencies (every row mass before the row draw, the pivot row
+// before the column draw and the update), and in the two-kernel form each
+// costs a launch. Here every workgroup makes both draws itself, on the same
+// inputs with the same arithmetic (pivot_draw_row and pivot_draw_col), so
+// each reaches the same pivot, and then sweeps its own rows: no workgroup
+// waits for another. What keeps it free of races:
+//   * each workgroup has its own copy of the step state (it reads and writes
+//     only that one; slot 0, which workgroup 0 keeps, is read back);
+//   * the row masses alternate between two buffers: step t reads slot t mod 2
+//     and writes slot (t + 1) mod 2;
+//   * the pivot row i is read by every workgroup during step t, so its owner
+//     does not overwrite it: a pivoted row is marked dead, swept no more (its
+//     entries would be exact zeros, its mass 0 and its multipliers +-0, which
+//     is what the owner records), and zeroed in S after the run;
+//   * workgroup 0 writes U(t,:), piv, the trace and the row-mass output; the
+//     others keep their copy of the pivot row in a row of their own.
+// The draws, multipliers, updates and row masses are those of k_dense_pivot
+// and k_dense_sweep bit for bit: the same functions for the draws, and per
+// row the sweep's 512-thread pack mapping, wave sums and wave order.
+constexpr int STEP_HALF = DENSE_THREADS;                 // threads per row (the sweep's)
+
+template <class T, int V>
+__global__ __launch_bounds__(CDF_THREADS) void k_dense_step(
+    T* __restrict__ S, int64_t lda, T* __restrict__ U, int64_t ldu, T* __restrict__ L,
+    int64_t ldl, PivotArgs pa, StepState* __restrict__ states, double* __restrict__ masses,
+    T* __restrict__ urows, int64_t ldur, uint8_t* __restrict__ dead) {
+    using W = typename Sc<T>::W;
+    __shared__ PivotShared sh;
+    __shared__ double red[CDF_THREADS / RPLU_WAVE];
+    __shared__ double pv[3];
+    __shared__ int pvi[2];
+    StepState* st = states + blockIdx.x;
+    if (st->done) return;
+    const int t = st->t;
+    const int n = pa.n, m = pa.m;
+    pa.st = st;
+    pa.rowmass = masses + (int64_t)(t & 1) * n;
+    if (blockIdx.x != 0) {
+        pa.piv = nullptr;
+        pa.trace = nullptr;
+        pa.rowmass_out = nullptr;
+    }
+    T* Ut = blockIdx.x == 0 ? U + (int64_t)t * ldu : urows + (int64_t)blockIdx.x * ldur;
+    const StopInputs in = stop_inputs(st);
+
+    // This workgroup's rows do not depend on the draws: their packs are
+    // loaded first, so that the loads run under the draws. Thread ht of half
+    // h holds the packs at columns (ht + k STEP_HALF) V of rows r0 + 2q + h.
+    constexpr int NQ = DENSE_STEP_ROWS / 2;
+    constexpr int PK = (DENSE_STEP_MAX + STEP_HALF * V - 1) / (STEP_HALF * V);
+    const int h = threadIdx.x / STEP_HALF, ht = threadIdx.x % STEP_HALF;
+    const int r0 = blockIdx.x * DENSE_STEP_ROWS;
+    Pack<T, V> pre[NQ][PK];
+    bool live[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int r = r0 + 2 * q + h;
+        live[q] = r < n && dead[r] == 0;
+        const T* Sr = S + (int64_t)(live[q] ? r : 0) * lda;
+#pragma unroll
+        for (int k = 0; k < PK; ++k) {
+            const int64_t c = (int64_t)(ht + k * STEP_HALF) * V;
+            if (live[q] && c + V <= m) pre[q][k] = ld_s<T, V>(Sr + c);
+            else {
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    pre[q][k].v[v] = (live[q] && c + v < m) ? Sr[c + v] : Sc<T>::zero();
+            }
+        }
+    }
+
+    const int i = pivot_draw_row(sh, pa, t, in);
+    if (i < 0) return;
+    const T* Si = S + (int64_t)i * lda;
+    pivot_draw_col<T, 0>(sh, pa, t, Ut, nullptr, nullptr, [&](int e) { return Si[e]; },
+                         [](const T& v) { return v; });
+    // thread 0 committed the pivot (or recorded an error) in this state
+    if (threadIdx.x == 0) {
+        pvi[0] = st->done;
+        pvi[1] = st->j;
+        pv[0] = st->inv_re;
+        pv[1] = st->inv_im;
+    }
+    __syncthreads();
+    if (pvi[0]) return;
+    const int pj = pvi[1];
+    W inv;
+    if constexpr (Sc<T>::cplx) inv = W{pv[0], pv[1]};
+    else inv = pv[0];
+
+    // the sweep of this workgroup's rows, two at a time (one per half), in
+    // k_dense_sweep's order: packs by increasing column, the ragged pack of
+    // a row (m mod V columns) element by element
+    const int lane = threadIdx.x % RPLU_WAVE, wv = threadIdx.x / RPLU_WAVE;
+    double* mnext = masses + (int64_t)((t + 1) & 1) * n;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int r = r0 + 2 * q + h;
+        const bool valid = r < n;
+        const bool prow = r == i;
+        const bool gone = valid && !prow && !live[q];
+        T l = Sc<T>::zero();
+        if (valid) {
+            if (prow) l = Sc<T>::one();
+            else l = Sc<T>::narrow(wmul(Sc<T>::widen(gone ? Sc<T>::zero() : S[(int64_t)r * lda + pj]), inv));
+            if (L != nullptr && ht == 0) L[(int64_t)t * ldl + r] = l;
+        }
+        double rp = 0.0;
+        if (valid && !prow && !gone) {
+            T* Sr = S + (int64_t)r * lda;
+#pragma unroll
+            for (int k = 0; k < PK; ++k) {
+                const int64_t c = (int64_t)(ht + k * STEP_HALF) * V;
+                if (c >= m) break;
+                const bool full = c + V <= m;
+                Pack<T, V> u, x = pre[q][k];
+                if (full) u = *reinterpret_cast<const Pack<T, V>*>(Ut + c);
+                else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) u.v[v] = (c + v < m) ? Ut[c + v] : Sc<T>::zero();
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    T y = Sc<T>::fms(x.v[v], l, u.v[v]);
+                    if (c + v == pj) y = Sc<T>::zero();
+                    x.v[v] = y;
+                    rp = Sc<T>::mag2_add(rp, y);
+                }
+                if (full) st_s<T, V>(Sr + c, x);
+                else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) if (c + v < m) Sr[c + v] = x.v[v];
+                }
+            }
+        }
+        const double ws = wave_sum(rp);
+        if (lane == 0) red[wv] = ws;
+        __syncthreads();
+        if (valid && ht == 0) {
+            double v = red[h * (STEP_HALF / RPLU_WAVE)];
+#pragma unroll
+            for (int w = 1; w < STEP_HALF / RPLU_WAVE; ++w) v += red[h * (STEP_HALF / RPLU_WAVE) + w];
+            mnext[r] = v;
+            if (prow) dead[r] = 1;
+        }
+        __syncthreads();
+    }
+}
+
+// Before the first step: every workgroup's state zeroed, no row dead.
+__global__ void k_dense_step_init(StepState* __restrict__ states, int groups,
+                                  uint8_t* __restrict__ dead, int n) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < groups) states[g] = StepState{};
+    for (int r = g; r < n; r += gridDim.x * blockDim.x) dead[r] = 0;
+}
+
+// After the run: the pivoted rows of S set to exact zeros (the sweep leaves
+// them as they were at their pivot step).
+template <class T>
+__global__ void k_dense_step_finish(T* __restrict__ S, int64_t lda, int n, int m,
+                                    const uint8_t* __restrict__ dead) {
+    const int r = blockIdx.x;
+    if (r >= n || dead[r] == 0) return;
+    for (int c = threadIdx.x; c < m; c += blockDim.x) S[(int64_t)r * lda + c] = Sc<T>::zero();
 }
 
 // ---------------------------------------------------------------- launchers
@@ -678,6 +852,53 @@ void launch_dense_flush(const DenseArgs& a, hipStream_t s) {
 }
 
 int dense_row_block(bool colmass) { return colmass ? DENSE_ROWS_COLMASS : DENSE_ROWS; }
+
+void launch_dense_step_init(const DenseArgs& a, const DenseStepArgs& d, hipStream_t s) {
+    const int nthr = 256;
+    const int64_t work = a.n > d.groups ? a.n : d.groups;
+    hipLaunchKernelGGL(k_dense_step_init, dim3((unsigned)((work + nthr - 1) / nthr)), dim3(nthr), 0, s,
+                       d.states, d.groups, d.dead, (int)a.n);
+}
+
+template <class T>
+static void step_t(const DenseArgs& a, const SampleArgs& sa, const DenseStepArgs& d, hipStream_t s) {
+    constexpr int VV = 16 / (int)sizeof(T);
+    PivotArgs pa = pivot_args(sa);
+    if (a.vec_ok)
+        hipLaunchKernelGGL((k_dense_step<T, VV>), dim3((unsigned)d.groups), dim3(CDF_THREADS), 0, s,
+                           (T*)a.S, a.lda, (T*)a.U, a.ldu, (T*)a.L, a.ldl, pa, d.states, d.masses,
+                           (T*)d.urows, d.ldur, d.dead);
+    else
+        hipLaunchKernelGGL((k_dense_step<T, 1>), dim3((unsigned)d.groups), dim3(CDF_THREADS), 0, s,
+                           (T*)a.S, a.lda, (T*)a.U, a.ldu, (T*)a.L, a.ldl, pa, d.states, d.masses,
+                           (T*)d.urows, d.ldur, d.dead);
+}
+
+void launch_dense_step(const DenseArgs& a, const SampleArgs& sa, const DenseStepArgs& d,
+                       hipStream_t s) {
+    switch (a.dtype) {
+        case RPLU_R32: step_t<float>(a, sa, d, s); break;
+        case RPLU_R64: step_t<double>(a, sa, d, s); break;
+        case RPLU_C64: step_t<cf32>(a, sa, d, s); break;
+        case RPLU_C128: step_t<cf64>(a, sa, d, s); break;
+    }
+}
+
+template <class T>
+static void step_finish_t(const DenseArgs& a, const DenseStepArgs& d, hipStream_t s) {
+    hipLaunchKernelGGL((k_dense_step_finish<T>), dim3((unsigned)a.n), dim3(256), 0, s, (T*)a.S,
+                       a.lda, (int)a.n, (int)a.m, d.dead);
+}
+
+void launch_dense_step_finish(const DenseArgs& a, const DenseStepArgs& d, hipStream_t s) {
+    switch (a.dtype) {
+        case RPLU_R32: step_finish_t<float>(a, d, s); break;
+        case RPLU_R64: step_finish_t<double>(a, d, s); break;
+        case RPLU_C64: step_finish_t<cf32>(a, d, s); break;
+        case RPLU_C128: step_finish_t<cf64>(a, d, s); break;
+    }
+}
+
 
 void launch_colmass_sum(const double* part, int nb, int64_t m, StepState* st, double* out,
                         int64_t ld_out, int64_t rows_cap, hipStream_t s) {

@@ -52,6 +52,25 @@ struct DenseArgs {
     double tol2;
 };
 
+// The one-launch step of small dense runs (dense.hip, k_dense_step): n and
+// m limit, and rows swept per workgroup.
+constexpr int DENSE_STEP_MAX = 1024;
+constexpr int DENSE_STEP_ROWS = 4;
+
+struct SampleArgs;
+struct DenseStepArgs {
+    StepState* states;   // one private step state per workgroup (slot 0 is read back)
+    double* masses;      // 2 x n: the row masses of steps t (slot t mod 2) and t + 1
+    void* urows;         // workgroups 1..: their own copy of the pivot row (ldur)
+    int64_t ldur;
+    uint8_t* dead;       // n: row already pivoted (its owner no longer sweeps it)
+    int groups;          // workgroups: ceil(n / DENSE_STEP_ROWS)
+};
+void launch_dense_step_init(const DenseArgs& a, const DenseStepArgs& d, hipStream_t s);
+void launch_dense_step(const DenseArgs& a, const SampleArgs& sa, const DenseStepArgs& d,
+                       hipStream_t s);
+void launch_dense_step_finish(const DenseArgs& a, const DenseStepArgs& d, hipStream_t s);
+
 // n and m limit of the fused one-workgroup pivot draw of the dense path
 // (pivot.hpp); above it the draws run as wide kernels. Measured on MI355X:
 // per step the fused draw takes 15.7 us against 18.8 at 512^2 and 20.3

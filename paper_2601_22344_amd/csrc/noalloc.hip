@@ -53,7 +53,7 @@ extern "C" {
 
 size_t rplu_dense_noalloc_bytes(int dtype, int64_t n, int64_t m, uint32_t flags, int has_U) {
     if (dtype_size(dtype) == 0 || n < 1 || m < 1) return 0;
-    return dense_ws_layout(dtype, n, m, flags, has_U == 0).total;
+    return dense_ws_layout(dtype, n, m, flags, has_U == 0, false).total;
 }
 
 rplu_status rplu_dense_noalloc(rplu_dtype dtype, int64_t n, int64_t m, void* A, int64_t lda,
@@ -64,7 +64,7 @@ rplu_status rplu_dense_noalloc(rplu_dtype dtype, int64_t n, int64_t m, void* A, 
     if (rc) return rc;
     if (opts->flags & RPLU_FLAG_KEEP_INPUT)
         return fail(RPLU_E_UNSUPPORTED, "rplu_dense_noalloc: RPLU_FLAG_KEEP_INPUT needs a copy of A");
-    const DenseWs w = dense_ws_layout(dtype, n, m, opts->flags, U == nullptr);
+    const DenseWs w = dense_ws_layout(dtype, n, m, opts->flags, U == nullptr, false);
     if (w.total > (size_t)RPLU_NOALLOC_SCRATCH_BYTES)
         return fail(RPLU_E_ARG,
                     "rplu_dense_noalloc: needs %zu bytes of scratch, the limit is %zu "

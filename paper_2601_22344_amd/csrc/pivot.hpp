@@ -134,8 +134,10 @@ __device__ inline void pivot_commit_col(StepState* st, int t, int j, int m, cons
             st->bj[2 * l] = b.re; st->bj[2 * l + 1] = b.im;
         }
     }
-    piv[2 * t] = i;
-    piv[2 * t + 1] = j;
+    if (piv != nullptr) {               // null: a copy of the step that records nothing
+        piv[2 * t] = i;
+        piv[2 * t + 1] = j;
+    }
     if (trace != nullptr) {
         double* tr = trace + (int64_t)t * RPLU_TRACE_WORDS;
         tr[0] = st->T; tr[1] = st->row_tgt; tr[2] = st->row_lo; tr[3] = st->row_hi;
@@ -401,10 +403,17 @@ __device__ inline void pivot_chunk_totals(PivotShared& sh, double* ct, int len, 
 
 // Whole workgroup: stop test and row draw of step t (= st->t, not done),
 // the chunk totals formed here. Returns the row i in every thread, or -1
-// when the run ends here.
+// when the run ends here. The step's Philox words are formed by the last
+// wave, which holds no chunk while the vector has fewer than 16: its chain
+// of 64-bit products (some thousand cycles) then runs beside the first
+// waves' mass loads instead of before them.
 __device__ inline int pivot_draw_row(PivotShared& sh, const PivotArgs& a, int t,
-                                     const Philox4& rnd, const StopInputs& in) {
-    if (threadIdx.x == 0) { sh.words[0] = rnd.w[0]; sh.words[1] = rnd.w[1]; }
+                                     const StopInputs& in) {
+    if (threadIdx.x == CDF_THREADS - RPLU_WAVE) {
+        const Philox4 rnd = step_words(a, t);
+        sh.words[0] = rnd.w[0];
+        sh.words[1] = rnd.w[1];
+    }
     pivot_chunk_totals(sh, sh.ctr, a.n, [&](int e) { return a.rowmass[e]; },
                        [](double v, int) { return v; });
     const Philox4 w{{sh.words[0], sh.words[1], 0, 0}};
@@ -417,8 +426,7 @@ __device__ inline int pivot_draw_row(PivotShared& sh, const PivotArgs& a, int t,
 // re-reads U(t,:) after the barrier that ends the row pass.
 template <class T, int P, class LoadFn, class ValueFn>
 __device__ inline void pivot_draw_col(PivotShared& sh, const PivotArgs& a, int t, T* Ut,
-                                      const cf64* G, const cf64* B, const Philox4& rnd,
-                                      LoadFn load, ValueFn value) {
+                                      const cf64* G, const cf64* B, LoadFn load, ValueFn value) {
     pivot_chunk_totals(sh, sh.ctc, a.m, load, [&](const decltype(load(0))& ld, int e) {
         const T v = value(ld);
         Ut[e] = v;

@@ -103,8 +103,20 @@ inline void timed(rplu_ctx_s* ctx, int cls, hipStream_t s, F&& launch) {
 // context-free caller (rplu_dense_noalloc) passes ctx == nullptr.
 struct DenseWs {
     size_t o_st, o_rm, o_rx, o_ctr, o_ctc, o_cp, o_u, total;
+    // the one-launch step (k_dense_step): per-workgroup states, the
+    // workgroups' pivot-row copies, the dead-row flags
+    bool step = false;
+    int groups = 0;
+    int64_t ldur = 0;
+    size_t o_sts = 0, o_ur = 0, o_dead = 0;   // (o_rm then holds two buffers)
 };
-DenseWs dense_ws_layout(int dtype, int64_t n, int64_t m, uint32_t flags, bool need_u);
+// Whether a dense run may take the one-launch step (small, and no option
+// that needs the separate kernels).
+bool dense_step_eligible(int64_t n, int64_t m, uint32_t flags);
+// allow_step = false: the layout of the separate kernels only (the
+// context-free entry point).
+DenseWs dense_ws_layout(int dtype, int64_t n, int64_t m, uint32_t flags, bool need_u,
+                        bool allow_step = true);
 rplu_status dense_check(const char* who, int dtype, int64_t n, int64_t m, const void* A,
                         int64_t lda, const rplu_opts* opts, const int32_t* piv, const void* L,
                         int64_t ldl, const void* U, int64_t ldu, const rplu_info* info);
