@@ -70,7 +70,7 @@ def _source_sha(workload: str) -> str:
 
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
 HOT_KERNEL = {"cauchy20k": "k_cauchy_mass", "dense32k": "k_dense_lazy",
-              "dense512": "k_dense_sweep", "batched4096": "k_batched", "cur32k": "k_cur_sweep"}
+              "dense512": "k_dense_step", "batched4096": "k_batched", "cur32k": "k_cur_sweep"}
 CALIBRATION_BYTES = 1 << 30
 
 
@@ -265,8 +265,11 @@ def _setup_dense(torch, rplu, which):
         per_step = [2 * (n - s) * (m - s) * es for s in range(k)]
     live = sum(per_step) / k
     eager_bytes = sum(2 * (n - s) * (m - s) * es for s in range(k)) / k
+    # matrices up to 1024 x 1024 take the one-launch step (draws and sweep)
+    one_launch = n <= 1024 and m <= 1024
     return dict(step=step, k=k, n=n, m=m, kind="dense", dtype=dtype, per_launch=live, verify=verify,
-                eager_per_launch=eager_bytes, sweep="deferred" if lazy else "eager",
+                eager_per_launch=eager_bytes,
+                sweep="deferred" if lazy else ("step" if one_launch else "eager"),
                 live_total=sum(per_step) + n * m * es,
                 config={"workload": desc, "n": n, "m": m, "k": k, "seed": 0})
 
@@ -638,10 +641,13 @@ def _run_workload(args, torch, rplu, workload) -> dict:
                 "count": ("live S^(t) block read at every step, written at every "
                           f"{rplu.RPLU_LAZY_STEPS}th and the last (deferred sweep)"
                           if wl["sweep"] == "deferred" else
+                          "live S^(t) block read and written at every step (the launch also "
+                          "makes both draws of the step)" if wl["sweep"] == "step" else
                           "live S^(t) block read and written at every step"),
                 "eager_equivalent_GBs": (wl["eager_per_launch"] / (hot_ms * 1e-3) / 1e9
                                          if hot_launches and "eager_per_launch" in wl else None)}
-        kernel = {"deferred": "k_dense_lazy", "eager": "k_dense_sweep", "cur": "k_cur_sweep"}[
+        kernel = {"deferred": "k_dense_lazy", "eager": "k_dense_sweep", "step": "k_dense_step",
+                  "cur": "k_cur_sweep"}[
             wl["sweep"]]
         if wl["sweep"] == "cur":
             roof["count"] = ("live rows of A (not yet selected) read once per step, with their "
