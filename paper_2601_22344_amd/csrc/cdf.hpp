@@ -157,13 +157,16 @@ __device__ inline double cdf_levels(CdfShared& sh, const double* __restrict__ ct
     const int G = (K + CDF_GROUP - 1) / CDF_GROUP;
     const int g = threadIdx.x;
     if (g < G) {
+        const int cnt = min(CDF_GROUP, K - g * CDF_GROUP);   // chunks of the group
         double x[CDF_GROUP];                       // loads issued together
 #pragma unroll
         for (int q = 0; q < CDF_GROUP; ++q) x[q] = ct[min(g * CDF_GROUP + q, K - 1)];
         double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < CDF_GROUP; ++q)
-            if (g * CDF_GROUP + q < K) s = s + x[q];
+        for (int q = 0; q < CDF_GROUP; ++q) {      // in order; no pass past the last chunk
+            if (q >= cnt) break;
+            s = s + x[q];
+        }
         sh.goff[g + 1] = s;                        // group total, for now
     }
     __syncthreads();
@@ -202,8 +205,11 @@ __device__ CdfPick cdf_draw(CdfShared& sh, const double* __restrict__ ct, int K,
         const int k0 = g * CDF_GROUP, k1 = min(K, k0 + CDF_GROUP);
         const double myct = ct[min(k0 + lane, K - 1)];   // lane q holds ct[k0 + q]
         double io = 0.0;
+        // only lanes below k1 - k0 are read below, and lane q's sum needs
+        // the chunks before it: the chain stops at the group's last chunk
 #pragma unroll
         for (int q = 0; q < CDF_GROUP - 1; ++q) {
+            if (q >= k1 - k0 - 1) break;
             const double c = uniform_lane(myct, q);
             if (q < lane) io = io + c;
         }

@@ -698,18 +698,29 @@ __global__ __launch_bounds__(CDF_THREADS) void k_dense_step(
     // a row (m mod V columns) element by element
     const int lane = threadIdx.x % RPLU_WAVE, wv = threadIdx.x / RPLU_WAVE;
     double* mnext = masses + (int64_t)((t + 1) & 1) * n;
+    // the multipliers of all the workgroup's rows first: a row's S[r, j] is
+    // read by every wave of its half, and one wave's store of the row's
+    // packs (column j set to 0) must not overtake another wave's read
+    T lq[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int r = r0 + 2 * q + h;
+        lq[q] = Sc<T>::zero();
+        if (r < n) {
+            if (r == i) lq[q] = Sc<T>::one();
+            else lq[q] = Sc<T>::narrow(wmul(Sc<T>::widen(live[q] ? S[(int64_t)r * lda + pj]
+                                                                 : Sc<T>::zero()), inv));
+            if (L != nullptr && ht == 0) L[(int64_t)t * ldl + r] = lq[q];
+        }
+    }
+    __syncthreads();                                  // every S[r, j] read before any store
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int r = r0 + 2 * q + h;
         const bool valid = r < n;
         const bool prow = r == i;
         const bool gone = valid && !prow && !live[q];
-        T l = Sc<T>::zero();
-        if (valid) {
-            if (prow) l = Sc<T>::one();
-            else l = Sc<T>::narrow(wmul(Sc<T>::widen(gone ? Sc<T>::zero() : S[(int64_t)r * lda + pj]), inv));
-            if (L != nullptr && ht == 0) L[(int64_t)t * ldl + r] = l;
-        }
+        const T l = lq[q];
         double rp = 0.0;
         if (valid && !prow && !gone) {
             T* Sr = S + (int64_t)r * lda;

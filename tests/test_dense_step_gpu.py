@@ -59,16 +59,27 @@ def _compare(rplu, A0, tag, flags=0, **kw):
                   rplu.RPLU_FLAG_SPLIT_SAMPLER | rplu.RPLU_FLAG_NO_GRAPH):
         outs.append(_run(rplu, A0, flags | extra, **kw))
     r0, A_0 = outs[0]
-    for r, A in outs[1:]:
-        assert (r.rank, r.stop, r.a_fro2, r.res_fro2) == (r0.rank, r0.stop, r0.a_fro2, r0.res_fro2), \
-            (tag, r.rank, r0.rank, r.stop, r0.stop)
+    bad = []
+    for q, (r, A) in enumerate(outs[1:], 1):
+        if (r.rank, r.stop, r.a_fro2, r.res_fro2) != (r0.rank, r0.stop, r0.a_fro2, r0.res_fro2):
+            bad.append((q, "totals", (r0.rank, r0.stop, r0.a_fro2, r0.res_fro2),
+                        (r.rank, r.stop, r.a_fro2, r.res_fro2)))
         for name in ("piv", "L", "U", "trace", "rowmass"):
             a, b = getattr(r0, name), getattr(r, name)
-            if a is None:
-                assert b is None, (tag, name)
+            if a is None or b is None:
+                if (a is None) != (b is None):
+                    bad.append((q, name, "missing"))
                 continue
-            assert torch.equal(_bits(a), _bits(b)), (tag, name)
-        assert torch.equal(_bits(A_0), _bits(A)), (tag, "final A")
+            if a.shape != b.shape or not torch.equal(_bits(a), _bits(b)):
+                first = None
+                if a.shape == b.shape:
+                    d = (_bits(a) != _bits(b)).nonzero()
+                    first = d[0].tolist() if len(d) else None
+                bad.append((q, name, "first differing index", first))
+        if not torch.equal(_bits(A_0), _bits(A)):
+            bad.append((q, "final A"))
+    # runs: 0 one launch + graph, 1 one launch plain, 2 two kernels + graph, 3 plain
+    assert not bad, (tag, bad)
     print(f"{tag}: rank {r0.rank} stop {r0.stop}", flush=True)
     return r0
 
