@@ -43,6 +43,8 @@ void build_bounds_plan(const CPoint* x, int64_t n, const CPoint* y, int64_t m, d
 // per-run buffers of the bound kernels.
 struct BoundsPlan {
     int n_src_nodes, n_src_leaves, n_tgt_leaves, max_depth;
+    int n_inner;                 // inner source nodes (the length of `inner`)
+    int pad;
     double nu;
     const int32_t* src_perm;     // m
     const int32_t* tgt_perm;     // n

@@ -20,6 +20,8 @@
 //                     (t, stream, q, 0)
 // The accepted row then takes the exact form's kernels: regeneration with
 // the column draw, and the generator update.
+#include <cstring>
+
 #include "common.hpp"
 #include "cdf.hpp"
 #include "launch.hpp"
@@ -91,6 +93,65 @@ __global__ __launch_bounds__(BH_TREE_THREADS) void k_bh_gram_tree(BoundsPlan bp,
     }
 }
 
+// The same bottom-up pass with the matrices, the inner-node list and the
+// child lists in LDS (one load of each from the plan at the start), so that
+// a level costs no memory round trip: the tree pass had spent one per level.
+// Sums and their order are those of k_bh_gram_tree. For plans whose data fit
+// in BH_TREE_LDS bytes.
+constexpr size_t BH_TREE_LDS = 64 * 1024;
+
+template <int P>
+__host__ __device__ inline size_t bh_tree_lds_bytes(int n_nodes, int n_inner, int max_depth) {
+    return (size_t)n_nodes * P * P * sizeof(cf64) + (size_t)n_inner * 5 * sizeof(int32_t) +
+           (size_t)(max_depth + 2) * sizeof(int32_t);
+}
+
+template <int P>
+__global__ __launch_bounds__(BH_TREE_THREADS) void k_bh_gram_tree_lds(BoundsPlan bp,
+                                                                      const StepState* __restrict__ st) {
+    extern __shared__ double lds_raw[];
+    if (st->done) return;
+    const int n_inner = bp.n_inner;
+    cf64* hs = reinterpret_cast<cf64*>(lds_raw);
+    int32_t* node = reinterpret_cast<int32_t*>(hs + (size_t)bp.n_src_nodes * P * P);
+    int32_t* kids = node + n_inner;                   // 4 per inner node, in list order
+    int32_t* loff = kids + 4 * n_inner;
+    cf64* H = (cf64*)bp.H;
+#pragma unroll 4
+    for (int q = threadIdx.x; q < bp.n_src_leaves * P * P; q += BH_TREE_THREADS) {
+        const int s = bp.src_leaves[q / (P * P)];
+        hs[(int64_t)s * P * P + q % (P * P)] = H[(int64_t)s * P * P + q % (P * P)];
+    }
+    for (int q = threadIdx.x; q < n_inner; q += BH_TREE_THREADS) {
+        const int s = bp.inner[q];
+        node[q] = s;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) kids[4 * q + c] = bp.node_child[4 * s + c];
+    }
+    for (int q = threadIdx.x; q < bp.max_depth + 2; q += BH_TREE_THREADS) loff[q] = bp.level_off[q];
+    __syncthreads();
+    for (int d = bp.max_depth; d >= 0; --d) {
+        for (int q = loff[d] + threadIdx.x; q < loff[d + 1]; q += BH_TREE_THREADS) {
+            const int s = node[q];
+            cf64 acc[P * P];
+#pragma unroll
+            for (int e = 0; e < P * P; ++e) acc[e] = cf64{0.0, 0.0};
+            for (int c = 0; c < 4; ++c) {
+                const int ch = kids[4 * q + c];
+                if (ch < 0) break;
+#pragma unroll
+                for (int e = 0; e < P * P; ++e) acc[e] = cadd(acc[e], hs[(int64_t)ch * P * P + e]);
+            }
+#pragma unroll
+            for (int e = 0; e < P * P; ++e) {
+                hs[(int64_t)s * P * P + e] = acc[e];
+                H[(int64_t)s * P * P + e] = acc[e];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <int P>
 __device__ inline void bh_point(const BoundsPlan& bp, const cf64* __restrict__ x,
                                 const cf64* __restrict__ y, const cf64* __restrict__ G,
@@ -154,17 +215,38 @@ __device__ inline double bh_row_mass(const cf64* __restrict__ x, const cf64* __r
     for (int l = 0; l < P; ++l) gi[l] = G[(int64_t)i * P + l];
     const cf64 xi = x[i];
     double v = 0.0;
-    for (int c = threadIdx.x; c < m; c += CDF_THREADS) {
+    // each thread takes columns threadIdx.x + 1024 k, added in order; eight
+    // columns' data are loaded before any is used, so one memory round trip
+    // serves eight columns (a loop of single columns waited on each)
+    auto term = [&](const cf64 (&b)[P], cf64 yc) {
         cf64 s{0.0, 0.0};
 #pragma unroll
         for (int l = 0; l < P; ++l) {
-            const cf64 b = B[(int64_t)l * m + c];
-            s.re = fma(gi[l].re, b.re, s.re);
-            s.re = fma(-gi[l].im, b.im, s.re);
-            s.im = fma(gi[l].re, b.im, s.im);
-            s.im = fma(gi[l].im, b.re, s.im);
+            s.re = fma(gi[l].re, b[l].re, s.re);
+            s.re = fma(-gi[l].im, b[l].im, s.re);
+            s.im = fma(gi[l].re, b[l].im, s.im);
+            s.im = fma(gi[l].im, b[l].re, s.im);
         }
-        v += Sc<cf64>::mag2(cdiv_fast(s, csub(xi, y[c])));
+        return Sc<cf64>::mag2(cdiv_fast(s, csub(xi, yc)));
+    };
+    constexpr int BH_U = 8;
+    int c = threadIdx.x;
+    for (; c + (BH_U - 1) * CDF_THREADS < m; c += BH_U * CDF_THREADS) {
+        cf64 bb[BH_U][P], yy[BH_U];
+#pragma unroll
+        for (int u = 0; u < BH_U; ++u) {
+#pragma unroll
+            for (int l = 0; l < P; ++l) bb[u][l] = B[(int64_t)l * m + c + u * CDF_THREADS];
+            yy[u] = y[c + u * CDF_THREADS];
+        }
+#pragma unroll
+        for (int u = 0; u < BH_U; ++u) v += term(bb[u], yy[u]);
+    }
+    for (; c < m; c += CDF_THREADS) {
+        cf64 b1[P];
+#pragma unroll
+        for (int l = 0; l < P; ++l) b1[l] = B[(int64_t)l * m + c];
+        v += term(b1, y[c]);
     }
     v = wave_sum(v);
     const int lane = threadIdx.x % RPLU_WAVE, w = threadIdx.x / RPLU_WAVE;
@@ -260,10 +342,13 @@ hipError_t upload_bounds_plan(const HostBoundsPlan& P, int64_t n, int p, char* d
         for (int c = 0; c < 4; ++c) (*staging)[2 * ns + 4 * v + c] = P.src[v].child[c];
     }
     BoundsPlan b;
+    std::memset(&b, 0, sizeof b);        // padding too: the plan keys the graph cache
     b.n_src_nodes = ns;
     b.n_src_leaves = (int)P.src_leaves.size();
     b.n_tgt_leaves = (int)P.tl_beg.size();
     b.max_depth = P.max_depth;
+    b.n_inner = (int)P.inner.size();
+    b.pad = 0;
     b.nu = P.nu;
     b.tgt_perm = (const int32_t*)put(P.tgt_perm.data(), P.tgt_perm.size() * 4);
     b.src_perm = (const int32_t*)put(P.src_perm.data(), P.src_perm.size() * 4);
@@ -291,7 +376,12 @@ template <int P>
 static void bounds_p(const BoundsPlan& bp, const CauchyArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_bh_gram_leaves<P>, dim3((unsigned)bp.n_src_leaves), dim3(RPLU_WAVE), 0, s,
                        bp, (const cf64*)a.B, (int)a.m, a.st);
-    hipLaunchKernelGGL(k_bh_gram_tree<P>, dim3(1), dim3(BH_TREE_THREADS), 0, s, bp, a.st);
+    const int n_inner = bp.n_inner;
+    const size_t lds = bh_tree_lds_bytes<P>(bp.n_src_nodes, n_inner, bp.max_depth);
+    if (lds <= BH_TREE_LDS)
+        hipLaunchKernelGGL(k_bh_gram_tree_lds<P>, dim3(1), dim3(BH_TREE_THREADS), lds, s, bp, a.st);
+    else
+        hipLaunchKernelGGL(k_bh_gram_tree<P>, dim3(1), dim3(BH_TREE_THREADS), 0, s, bp, a.st);
     hipLaunchKernelGGL(k_bh_bounds<P>, dim3((unsigned)bp.n_tgt_leaves), dim3(RPLU_WAVE), 0, s, bp,
                        (const cf64*)a.x, (const cf64*)a.y, (const cf64*)a.G, (const cf64*)a.B,
                        (int)a.m, a.st);
