@@ -63,7 +63,14 @@ struct BoundsPlan {
     const int32_t* E_node;
     void* H;                     // n_src_nodes p x p complex FP64 Gram matrices
     double* u;                   // n: the bounds (the row masses of the draws)
+    double* rej_part;            // BH_REJ_CAND x BH_REJ_MAX_SPLIT partial row masses
+    double* rej_cand;            // BH_REJ_CAND x {i, target, lo, hi} of the trials
 };
+
+// The rejection draw evaluates the first BH_REJ_CAND trials at once, each
+// row's mass split over up to BH_REJ_MAX_SPLIT workgroups.
+constexpr int BH_REJ_CAND = 4;
+constexpr int BH_REJ_MAX_SPLIT = 16;
 
 // Bytes of the device plan (256-byte aligned pieces) for a host plan.
 size_t bounds_plan_bytes(const HostBoundsPlan& P, int64_t n, int p);

@@ -13,13 +13,18 @@
 //                     point, the source data as wave-uniform loads
 //   k_rows_draw (sample.hip)  the stop test on sum(u) and the row draw of
 //                     trial 0 (the bounds are the row masses of the draw)
-//   k_bh_reject       one workgroup: rho_i = ||S_i,:||^2 of the drawn row,
-//                     accepted when v u_i < rho_i (v from word w2 of the
-//                     trial's Philox block); otherwise the next trial q draws
-//                     a row from the same CDF with word w0 of counter
-//                     (t, stream, q, 0)
+//   k_bh_reject       rho_i = ||S_i,:||^2 of the drawn row, accepted when
+//                     v u_i < rho_i (v from word w2 of the trial's Philox
+//                     block); otherwise the next trial q draws a row from the
+//                     same CDF with word w0 of counter (t, stream, q, 0). The
+//                     first BH_REJ_CAND trials are evaluated at once, each
+//                     row's mass by S workgroups over a slice of its columns;
+//                     the workgroup that arrives last takes the first trial
+//                     that passes, or goes on with the trials after them
+//                     alone (one workgroup per row)
 // The accepted row then takes the exact form's kernels: regeneration with
 // the column draw, and the generator update.
+#include <algorithm>
 #include <cstring>
 
 #include "common.hpp"
@@ -204,12 +209,13 @@ __global__ __launch_bounds__(RPLU_WAVE) void k_bh_bounds(BoundsPlan bp, const cf
         bh_point<P>(bp, x, y, G, B, m, l, q0 + lane < end, bp.tgt_perm[min(q0 + lane, end - 1)]);
 }
 
-// ||row i||^2 of the Cauchy-like matrix, the row regenerated as in
-// k_cauchy_rowgen_draw; whole workgroup, fixed-order sum, in every thread.
+// sum over the columns j0 <= j < j1 of |S_ij|^2 of the Cauchy-like matrix,
+// the row regenerated as in k_cauchy_rowgen_draw; whole workgroup,
+// fixed-order sum, in every thread.
 template <int P>
 __device__ inline double bh_row_mass(const cf64* __restrict__ x, const cf64* __restrict__ y,
                                      const cf64* __restrict__ G, const cf64* __restrict__ B,
-                                     int m, int i, double* red) {
+                                     int m, int i, int j0, int j1, double* red) {
     cf64 gi[P];
 #pragma unroll
     for (int l = 0; l < P; ++l) gi[l] = G[(int64_t)i * P + l];
@@ -230,8 +236,8 @@ __device__ inline double bh_row_mass(const cf64* __restrict__ x, const cf64* __r
         return Sc<cf64>::mag2(cdiv_fast(s, csub(xi, yc)));
     };
     constexpr int BH_U = 8;
-    int c = threadIdx.x;
-    for (; c + (BH_U - 1) * CDF_THREADS < m; c += BH_U * CDF_THREADS) {
+    int c = j0 + (int)threadIdx.x;
+    for (; c + (BH_U - 1) * CDF_THREADS < j1; c += BH_U * CDF_THREADS) {
         cf64 bb[BH_U][P], yy[BH_U];
 #pragma unroll
         for (int u = 0; u < BH_U; ++u) {
@@ -242,7 +248,7 @@ __device__ inline double bh_row_mass(const cf64* __restrict__ x, const cf64* __r
 #pragma unroll
         for (int u = 0; u < BH_U; ++u) v += term(bb[u], yy[u]);
     }
-    for (; c < m; c += CDF_THREADS) {
+    for (; c < j1; c += CDF_THREADS) {
         cf64 b1[P];
 #pragma unroll
         for (int l = 0; l < P; ++l) b1[l] = B[(int64_t)l * m + c];
@@ -258,6 +264,13 @@ __device__ inline double bh_row_mass(const cf64* __restrict__ x, const cf64* __r
     return r;
 }
 
+// Grid: BH_REJ_CAND x S workgroups (S = gridDim.x / BH_REJ_CAND); workgroup
+// (c, s) draws trial c's row (trial 0's row is the draw kernel's) and sums
+// its masses over the s-th of S equal column slices. The workgroup that
+// arrives last adds each trial's S slices in order and tests the trials in
+// order; past them, it goes on alone as one trial per row sweep. The
+// accepted row, the trial count and the error are those of testing the
+// trials one at a time.
 template <int P>
 __global__ __launch_bounds__(CDF_THREADS) void k_bh_reject(BoundsPlan bp, const cf64* __restrict__ x,
                                                            const cf64* __restrict__ y,
@@ -266,33 +279,87 @@ __global__ __launch_bounds__(CDF_THREADS) void k_bh_reject(BoundsPlan bp, const 
                                                            const double* __restrict__ ct_row) {
     __shared__ CdfShared sh;
     __shared__ double red[CDF_THREADS / RPLU_WAVE];
+    __shared__ int last;
     StepState* st = pa.st;
     if (st->done) return;
     const int t = st->cur;
     if (pa.greedy || pa.forced) {                 // the draw kernel's row stands
-        if (threadIdx.x == 0) { st->trials = 1; st->trials_total += 1; }
+        if (blockIdx.x == 0 && threadIdx.x == 0) { st->trials = 1; st->trials_total += 1; }
         return;
     }
+    const int S = gridDim.x / BH_REJ_CAND;
+    const int c = blockIdx.x / S, s = blockIdx.x % S;
     const int K = cdf_chunks(pa.n);
-    const double T = cdf_levels(sh, ct_row, K);
     int i = st->i;
     double tgt = st->row_tgt, lo = st->row_lo, hi = st->row_hi;
-    for (int q = 0; q < RPLU_BOUND_MAX_TRIALS; ++q) {
-        const Philox4 w = philox4x64_10((uint64_t)t, pa.stream, (uint64_t)q, 0, pa.seed, 0);
-        if (q > 0) {
-            tgt = unit_from_word(w.w[0]) * T;
-            const CdfPick p = cdf_draw(sh, ct_row, K, pa.n, RowMassGlobal{bp.u}, tgt);
-            i = p.idx;
-            lo = p.lo;
-            hi = p.hi;
+    if (c > 0) {
+        const double T = cdf_levels(sh, ct_row, K);
+        const Philox4 w = philox4x64_10((uint64_t)t, pa.stream, (uint64_t)c, 0, pa.seed, 0);
+        tgt = unit_from_word(w.w[0]) * T;
+        const CdfPick p = cdf_draw(sh, ct_row, K, pa.n, RowMassGlobal{bp.u}, tgt);
+        i = p.idx;
+        lo = p.lo;
+        hi = p.hi;
+    }
+    const int j0 = (int)((int64_t)pa.m * s / S), j1 = (int)((int64_t)pa.m * (s + 1) / S);
+    const double part = bh_row_mass<P>(x, y, G, B, pa.m, i, j0, j1, red);
+    if (threadIdx.x == 0) {
+        bp.rej_part[blockIdx.x] = part;
+        if (s == 0) {
+            double* cd = bp.rej_cand + 4 * c;
+            cd[0] = (double)i;
+            cd[1] = tgt;
+            cd[2] = lo;
+            cd[3] = hi;
         }
-        const double rho = bh_row_mass<P>(x, y, G, B, pa.m, i, red);
-        if (unit_from_word(w.w[2]) * bp.u[i] < rho) {
+    }
+    // arrival (bh_row_mass ended on a barrier after the stores' values were
+    // formed; the barrier here orders thread 0's stores): thread 0's
+    // device-scope release fence before its arrival, and in the last
+    // workgroup its acquire fence and the barrier after it order every
+    // later load after all arrivals; the last workgroup clears the counter
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int l = (atomicAdd(&st->arrive, 1u) == gridDim.x - 1) ? 1 : 0;
+        if (l) {
+            __threadfence();
+            st->arrive = 0u;
+        }
+        last = l;
+    }
+    __syncthreads();
+    if (!last) return;
+    for (int q = 0; q < BH_REJ_CAND; ++q) {
+        double rho = 0.0;
+        for (int r = 0; r < S; ++r) rho += bp.rej_part[q * S + r];
+        const double* cd = bp.rej_cand + 4 * q;
+        const int iq = (int)cd[0];
+        const Philox4 w = philox4x64_10((uint64_t)t, pa.stream, (uint64_t)q, 0, pa.seed, 0);
+        if (unit_from_word(w.w[2]) * bp.u[iq] < rho) {
             if (threadIdx.x == 0) {
-                st->i = i;
+                st->i = iq;
+                st->row_tgt = cd[1];
+                st->row_lo = cd[2];
+                st->row_hi = cd[3];
+                st->trials = q + 1;
+                st->trials_total += q + 1;
+            }
+            return;
+        }
+    }
+    const double T = cdf_levels(sh, ct_row, K);
+    for (int q = BH_REJ_CAND; q < RPLU_BOUND_MAX_TRIALS; ++q) {
+        const Philox4 w = philox4x64_10((uint64_t)t, pa.stream, (uint64_t)q, 0, pa.seed, 0);
+        tgt = unit_from_word(w.w[0]) * T;
+        const CdfPick p = cdf_draw(sh, ct_row, K, pa.n, RowMassGlobal{bp.u}, tgt);
+        const double rho = bh_row_mass<P>(x, y, G, B, pa.m, p.idx, 0, pa.m, red);
+        if (unit_from_word(w.w[2]) * bp.u[p.idx] < rho) {
+            if (threadIdx.x == 0) {
+                st->i = p.idx;
                 st->row_tgt = tgt;
-                st->row_lo = lo;
-                st->row_hi = hi;
+                st->row_lo = p.lo;
+                st->row_hi = p.hi;
                 st->trials = q + 1;
                 st->trials_total += q + 1;
             }
@@ -314,7 +381,8 @@ size_t bounds_plan_bytes(const HostBoundsPlan& P, int64_t n, int p) {
            up(P.src_leaves.size() * 4) + up(P.inner.size() * 4) + up(P.level_off.size() * 4) +
            2 * up(P.tl_beg.size() * 4) + up(P.A_off.size() * 4) + up(P.A_node.size() * 4) +
            up(P.A_alpha.size() * 8) + up(P.E_off.size() * 4) + up(P.E_node.size() * 4) +
-           up(ns * (size_t)p * p * 16) + up((size_t)n * 8);
+           up(ns * (size_t)p * p * 16) + up((size_t)n * 8) + up(BH_REJ_CAND * BH_REJ_MAX_SPLIT * 8) +
+           up(BH_REJ_CAND * 4 * 8);
 }
 
 // Copies the host plan into `dev` (bounds_plan_bytes bytes) on stream s and
@@ -368,6 +436,8 @@ hipError_t upload_bounds_plan(const HostBoundsPlan& P, int64_t n, int p, char* d
     b.E_node = (const int32_t*)put(P.E_node.data(), P.E_node.size() * 4);
     b.H = take((size_t)ns * p * p * 16);
     b.u = (double*)take((size_t)n * 8);
+    b.rej_part = (double*)take((size_t)BH_REJ_CAND * BH_REJ_MAX_SPLIT * 8);
+    b.rej_cand = (double*)take((size_t)BH_REJ_CAND * 4 * 8);
     *out = b;
     return e;
 }
@@ -390,7 +460,9 @@ static void bounds_p(const BoundsPlan& bp, const CauchyArgs& a, hipStream_t s) {
 template <int P>
 static void reject_p(const BoundsPlan& bp, const CauchyArgs& a, const SampleArgs& sa,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_bh_reject<P>, dim3(1), dim3(CDF_THREADS), 0, s, bp, (const cf64*)a.x,
+    // slices of at least 1024 columns, at most BH_REJ_MAX_SPLIT per row
+    const int S = (int)std::min<int64_t>(BH_REJ_MAX_SPLIT, std::max<int64_t>(1, (a.m + 1023) / 1024));
+    hipLaunchKernelGGL(k_bh_reject<P>, dim3(BH_REJ_CAND * S), dim3(CDF_THREADS), 0, s, bp, (const cf64*)a.x,
                        (const cf64*)a.y, (const cf64*)a.G, (const cf64*)a.B, pivot_args(sa),
                        (const double*)sa.ct_row);
 }
