@@ -12,7 +12,7 @@ separated sets (p = 1..3), an interleaved cloud (pair-by-pair lists),
 spirals against a cluster (aggregated lists only), a leaf of 70 identical
 targets (more than a wave). Also: the certified tolerance stop (the exact
 residual is within the tolerance), the bound-based C2PLU, the 20000 x 20000
-spirals at k = 60, argument errors.
+spirals at k = 60, steps of more than four trials, argument errors.
 """
 import numpy as np
 import pytest
@@ -89,6 +89,17 @@ def test_bounds_config2_spirals(rplu_lib):
     r = _run(rplu_lib, x, y, G, B, k=60, seed=0, bounds=(5.0, 32))
     o = O.rplu_cauchy(x, y, G, B, k=60, seed=0, bounds=(5.0, 32), keep_masses=True)
     _compare(r, o, "spirals 20000^2")
+
+
+def test_bounds_trials_past_the_first_four(rplu_lib):
+    """Steps that need more than four trials: the device tests the first four
+    trials of a step at once and then goes on one trial at a time. m = 5000
+    columns: each of the first four rows is summed in five column slices."""
+    x, y, G, B = W.cauchy_like_random(1500, 5000, 1, seed=36)
+    r = _run(rplu_lib, x, y, G, B, k=20, seed=7, stream=1, bounds=(50.0, 16))
+    o = O.rplu_cauchy(x, y, G, B, k=20, seed=7, stream=1, bounds=(50.0, 16), keep_masses=True)
+    assert max(o.trials) > 4, o.trials
+    _compare(r, o, "more than four trials")
 
 
 def test_bounds_argument_errors(rplu_lib):
