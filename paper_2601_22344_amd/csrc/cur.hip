@@ -163,8 +163,18 @@ __global__ __launch_bounds__(CDF_THREADS) void k_cur_pivrow_draw(CurArgs a, Pivo
             ri[q] = a.piv[2 * (q0 + q)];
         }
         __syncthreads();
-        for (int q = 0; q < nq; ++q)
-            x = wmsub(Sc<T>::widen(A[(int64_t)ri[q] * a.lda + ec]), zu[q], x);
+        // sixteen rows' entries are loaded before any is used (one memory
+        // round trip for sixteen rows); the updates stay in order
+        constexpr int CUR_U = 16;
+        int q = 0;
+        for (; q + CUR_U <= nq; q += CUR_U) {
+            T v[CUR_U];
+#pragma unroll
+            for (int u = 0; u < CUR_U; ++u) v[u] = A[(int64_t)ri[q + u] * a.lda + ec];
+#pragma unroll
+            for (int u = 0; u < CUR_U; ++u) x = wmsub(Sc<T>::widen(v[u]), zu[q + u], x);
+        }
+        for (; q < nq; ++q) x = wmsub(Sc<T>::widen(A[(int64_t)ri[q] * a.lda + ec]), zu[q], x);
     }
     if (a.selc[ec]) x = wzero(W{});             // selected columns: 0 in the residual
     if (in) ((W*)a.rhat)[e] = x;
