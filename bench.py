@@ -26,8 +26,9 @@ Prints one JSON line. The hot kernel's average launch duration is measured
 with HIP events on the library's stream over the timed region; the CPU
 baseline times the C++ FP64 oracle on a bounded sample of the same workload,
 on all host cores and on one. The default run (cauchy20k) also times
-dense32k and batched4096 in the same process and reports each, with its own
-roofline, under "extra_workloads".
+dense512, dense32k, batched4096, cur32k, cauchy20k_bounds and a serving
+window of --extra-serve-seconds in the same process and reports each, with
+its own roofline where one applies, under "extra_workloads".
 """
 from __future__ import annotations
 
@@ -504,10 +505,13 @@ def main() -> int:
                              "cur32k", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="cauchy20k: skip the dense32k and batched4096 lines the default run "
-                         "adds under extra_workloads")
+                    help="cauchy20k: skip the other workloads' lines the default run adds "
+                         "under extra_workloads")
     ap.add_argument("--extra-steps", type=int, default=3,
-                    help="timed steps of each extra workload")
+                    help="timed steps of each extra workload (dense512: 100)")
+    ap.add_argument("--extra-serve-seconds", type=float, default=10.0,
+                    help="arrival window of the serving line the default run adds "
+                         "(0: no serving line)")
     ap.add_argument("--pivoting", default="rplu", choices=["rplu", "c2plu", "cplu"],
                     help="cauchy20k / dense workloads: c2plu = complete 2-norm pivoting "
                          "(RPLU_FLAG_C2PLU), cplu (dense only) = complete pivoting "
@@ -551,7 +555,8 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     if args.workload == "serve":
-        return _main_serve(args, torch, rplu)
+        print(json.dumps(_run_serve(args, torch, rplu)), flush=True)
+        return 0
     if args.workload == "batched4096":
         out = _run_batched(args, torch, rplu)
     else:
@@ -563,11 +568,20 @@ def main() -> int:
         ex.steps, ex.warmup, ex.no_cpu_baseline = args.extra_steps, 1, True
         torch.cuda.empty_cache()
         extras = {}
-        for name in ("dense32k", "batched4096", "cur32k", "cauchy20k_bounds"):
+        names = ["dense512", "dense32k", "batched4096", "cur32k", "cauchy20k_bounds"]
+        if args.extra_serve_seconds > 0:
+            names.append("serve")
+        for name in names:
             print(f"[bench] extra workload {name}", file=sys.stderr, flush=True)
             ex.workload = name
-            r = _run_batched(ex, torch, rplu) if name == "batched4096" else \
-                _run_workload(ex, torch, rplu, name)
+            ex.steps = 100 if name == "dense512" else args.extra_steps
+            if name == "serve":
+                ex.serve_seconds = args.extra_serve_seconds
+                r = _run_serve(ex, torch, rplu)
+            elif name == "batched4096":
+                r = _run_batched(ex, torch, rplu)
+            else:
+                r = _run_workload(ex, torch, rplu, name)
             for key in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data",
                         "cpu_baseline"):
                 r.pop(key, None)
@@ -749,7 +763,7 @@ def _cauchy_flop(n, m, k):
     return CAUCHY_FLOP_PER_PAIR * n * m * (k + 1)
 
 
-def _main_serve(args, torch, rplu) -> int:
+def _run_serve(args, torch, rplu) -> dict:
     import workloads as W
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)   # noqa: E731
     arrivals = W.serving_arrivals(rate=200.0, duration=args.serve_seconds, seed=5)
@@ -873,8 +887,7 @@ def _main_serve(args, torch, rplu) -> int:
         out["fp64_one_at_a_time"] = {"value": cnt / el, "unit": "approximations/s", "jobs": cnt,
                                      "how": "the first 100 jobs, one after another, dense in FP64"}
     out["cpu_baseline"] = None
-    print(json.dumps(out), flush=True)
-    return 0
+    return out
 
 
 if __name__ == "__main__":
