@@ -256,7 +256,11 @@ __device__ __forceinline__ BPack<T, V> bt_pick(const BPack<T, V>& whole, const B
     return x;
 }
 
-constexpr int BT_NV = 4;   // virtual waves a row may span in the block pass
+constexpr int BT_NV = 4;   // virtual waves of 16-byte packs a row may span in the block pass
+
+// Elements of the pivot row's LDS copy s_u: a row of BT_NV x 64 16-byte
+// packs (1024 FP32, 512 FP64 columns).
+template <class T> constexpr int bt_su() { return BT_NV * RPLU_WAVE * (16 / (int)sizeof(T)); }
 
 // The value of lane 0 (every lane holds the same), in scalar registers.
 __device__ __forceinline__ float uniform_v(float v) {
@@ -264,30 +268,33 @@ __device__ __forceinline__ float uniform_v(float v) {
 }
 __device__ __forceinline__ double uniform_v(double v) { return uniform_d(v); }
 
-// The pass of bt_sweep for rows of NVW <= BT_NV virtual waves (V <= m <= NVW x
-// 64 V columns), where each lane holds at most one pack per virtual wave. A wave
-// takes blocks of RB rows and loads a whole block (RB rows by NVW packs)
-// before any arithmetic, so one memory round trip serves the block instead of
-// one per virtual wave; the pivot row's packs come from its LDS copy s_u
-// (zero past m). Each row keeps the per-lane sums (0 + |x_0|^2 + ... in
-// pack order, exactly 0 for a lane with no column), the wave sums and their
-// sum in virtual-wave order of bt_sweep, so S and the masses are the same
-// bits; lane q holds the running total of row q (the wave sums are the same
-// in every lane).
-template <class T, int RB, int NVW, int V, bool INIT>
+// The pass of bt_sweep for rows the pivot row's LDS copy s_u holds (V <= m
+// <= BT_SU elements), whose lanes hold at most KP packs per virtual wave: NVW
+// virtual waves of KP = 1 pack (m <= NVW x 64 V), or for single-element
+// packs (V = 1, rows not 16-byte aligned) all 8 virtual waves of KP = 1 or
+// 2 packs (m <= 512 KP). A wave takes blocks of RB rows and loads a whole
+// block (RB rows by NVW x KP packs) before any arithmetic, so one memory
+// round trip serves the block instead of one per virtual wave; the pivot
+// row's packs come from s_u. Each row keeps the per-lane sums (0 + |x_0|^2
+// + ... in pack order, exactly 0 for a lane with no column), the wave sums
+// and their sum in virtual-wave order of bt_sweep (a virtual wave past the
+// row's last adds an exact 0 to a total >= +0), so S and the masses are the
+// same bits; lane q holds the running total of row q (the wave sums are the
+// same in every lane).
+template <class T, int RB, int NVW, int KP, int V, bool INIT>
 __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t lda, int m, int pi, int pj,
                                                const T* __restrict__ s_l, const T* __restrict__ s_u,
                                                double* __restrict__ s_rm,
                                                const uint16_t* __restrict__ rows, int nalive) {
+    static_assert(KP == 1 || V == 1, "several packs per virtual wave: single-element packs");
     const int lane = threadIdx.x % RPLU_WAVE, wv = threadIdx.x / RPLU_WAVE;
     const int nblk = (nalive + RB - 1) / RB;
-    int rem[NVW];                         // columns of the row from this lane's pack on
-    int cl[NVW];                          // a whole pack inside the row to load
-#pragma unroll
-    for (int k = 0; k < NVW; ++k) {
-        rem[k] = m - (k * RPLU_WAVE + lane) * V;
-        cl[k] = rem[k] >= V ? m - rem[k] : 0;
-    }
+    // columns of the row from this lane's pack (k, kp) on, and a whole pack
+    // inside the row to load for it (formed where used: as arrays they took
+    // a register each)
+    const int m0 = m - lane * V;
+    auto rem = [&](int k, int kp) { return m0 - (k * RPLU_WAVE + kp * VT_THREADS) * V; };
+    auto cl = [&](int k, int kp) { const int r = rem(k, kp); return r >= V ? m - r : 0; };
     const int mt = m % V, cp = m - mt;
 #pragma unroll 1
     for (int blk = wv; blk < nblk; blk += BT_WAVES) {
@@ -300,7 +307,7 @@ __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t 
             ri[q] = uniform_i(rows[b0 + min(q, nr - 1)]);
             lq[q] = INIT ? Sc<T>::zero() : uniform_v(s_l[ri[q]]);
         }
-        BPack<T, V> x[RB][NVW], xt[RB];
+        BPack<T, V> x[RB][NVW][KP], xt[RB];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
 #pragma unroll
@@ -310,7 +317,9 @@ __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t 
         for (int q = 0; q < RB; ++q) {
             const gmem<T>* rp = S + (int64_t)ri[q] * lda;
 #pragma unroll
-            for (int k = 0; k < NVW; ++k) x[q][k] = ld_pack<T, V>(rp + cl[k]);
+            for (int k = 0; k < NVW; ++k)
+#pragma unroll
+                for (int kp = 0; kp < KP; ++kp) x[q][k][kp] = ld_pack<T, V>(rp + cl(k, kp));
         }
         if (mt != 0) {
 #pragma unroll
@@ -319,30 +328,42 @@ __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t 
         double tot = 0.0;
 #pragma unroll
         for (int k = 0; k < NVW; ++k) {
-            const int c = m - rem[k];
-            const int pv = pj - c;
-            BPack<T, V> uk;
-            if constexpr (!INIT) uk = *reinterpret_cast<const BPack<T, V>*>(s_u + c);
+            int c[KP], pv[KP];
+            BPack<T, V> uk[KP];
+#pragma unroll
+            for (int kp = 0; kp < KP; ++kp) {
+                c[kp] = m - rem(k, kp);
+                pv[kp] = pj - c[kp];
+                // (c < BT_SU for every lane: s_u is read in bounds, and past m
+                // the value goes unused)
+                if constexpr (!INIT) uk[kp] = *reinterpret_cast<const BPack<T, V>*>(s_u + c[kp]);
+            }
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
                 double part = 0.0;
                 if (q < nr) {
-                    BPack<T, V> xk = bt_pick<T, V>(x[q][k], xt[q], rem[k]);
-                    if constexpr (!INIT) {
-                        const bool zr = ri[q] == pi;
-#pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            const T y = Sc<T>::fms(xk.v[v], lq[q], uk.v[v]);
-                            xk.v[v] = ((v == pv) | zr) ? Sc<T>::zero() : y;
-                        }
-                    }
                     double acc = 0.0;
 #pragma unroll
-                    for (int v = 0; v < V; ++v) acc = Sc<T>::mag2_add(acc, xk.v[v]);
-                    part = rem[k] > 0 ? acc : 0.0;
-                    if constexpr (!INIT) {
-                        if (rem[k] > 0) bt_store<T, V>(S + (int64_t)ri[q] * lda + c, rem[k], xk);
+                    for (int kp = 0; kp < KP; ++kp) {
+                        const int rk = m - c[kp];
+                        BPack<T, V> xk = bt_pick<T, V>(x[q][k][kp], xt[q], rk);
+                        if constexpr (!INIT) {
+                            const bool zr = ri[q] == pi;
+#pragma unroll
+                            for (int v = 0; v < V; ++v) {
+                                const T y = Sc<T>::fms(xk.v[v], lq[q], uk[kp].v[v]);
+                                xk.v[v] = ((v == pv[kp]) | zr) ? Sc<T>::zero() : y;
+                            }
+                        }
+                        double a = acc;
+#pragma unroll
+                        for (int v = 0; v < V; ++v) a = Sc<T>::mag2_add(a, xk.v[v]);
+                        acc = rk > 0 ? a : acc;
+                        if constexpr (!INIT) {
+                            if (rk > 0) bt_store<T, V>(S + (int64_t)ri[q] * lda + c[kp], rk, xk);
+                        }
                     }
+                    part = acc;
                 }
                 const double w = wave_sum(part);
                 if (lane == q) tot = (k == 0) ? w : tot + w;
@@ -356,9 +377,11 @@ __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t 
 // 8 spill registers at 1024 threads).
 template <int R> constexpr int bt_packs() { return R == 1 ? 4 : 8; }
 
-// One pass of the sweep: the block pass when rows have V to BT_NV x 64 V
-// columns, with RB = packs / (virtual waves) rows per block; else bt_sweep
-// with R rows in flight.
+// One pass of the sweep: the block pass when the row fits s_u (m <= bt_su),
+// with RB = packs / (virtual waves) rows per block for rows of up to four
+// virtual waves, one row per block for single-element packs over all eight
+// (8 or 16 loads in flight per lane: two or four rows per block spilled
+// registers and ran slower); else bt_sweep with R rows in flight.
 template <class T, int R, int V, bool INIT>
 __device__ __forceinline__ void bt_pass(gmem<T>* __restrict__ S, int64_t lda, int m, int pi, int pj,
                                         const T* __restrict__ s_l, const gmem<T>* __restrict__ Ut,
@@ -366,14 +389,32 @@ __device__ __forceinline__ void bt_pass(gmem<T>* __restrict__ S, int64_t lda, in
                                         double* __restrict__ s_rm, const uint16_t* __restrict__ rows,
                                         int nalive) {
     constexpr int P = bt_packs<R>();
+    constexpr int SUC = bt_su<T>();
     static_assert(BT_NV == 4, "one case per virtual-wave count");
-    switch (m < V ? 0 : (m + RPLU_WAVE * V - 1) / (RPLU_WAVE * V)) {
-        case 1: bt_sweep_block<T, P, 1, V, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive); break;
-        case 2: bt_sweep_block<T, P / 2, 2, V, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive); break;
-        case 3: bt_sweep_block<T, P / 3, 3, V, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive); break;
-        case 4: bt_sweep_block<T, P / 4, 4, V, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive); break;
-        default: bt_sweep<T, R, V, INIT>(S, lda, m, pi, pj, s_l, Ut, s_rm, rows, nalive); break;
+    const int g = m < V ? 0 : (m + RPLU_WAVE * V - 1) / (RPLU_WAVE * V);   // 64-lane groups
+    if (g >= 1 && g <= BT_NV) {
+        switch (g) {
+            case 1: bt_sweep_block<T, P, 1, 1, V, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive); break;
+            case 2: bt_sweep_block<T, P / 2, 2, 1, V, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive); break;
+            case 3: bt_sweep_block<T, P / 3, 3, 1, V, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive); break;
+            default: bt_sweep_block<T, P / 4, 4, 1, V, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive); break;
+        }
+        return;
     }
+    if constexpr (V == 1) {
+        // all 8 virtual waves, one or two columns each per lane
+        if (m <= VT_THREADS && m <= SUC) {
+            bt_sweep_block<T, 1, VT_WAVES, 1, 1, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive);
+            return;
+        }
+        if constexpr (2 * VT_THREADS <= SUC) {
+            if (m <= 2 * VT_THREADS) {
+                bt_sweep_block<T, 1, VT_WAVES, 2, 1, INIT>(S, lda, m, pi, pj, s_l, s_u, s_rm, rows, nalive);
+                return;
+            }
+        }
+    }
+    bt_sweep<T, R, V, INIT>(S, lda, m, pi, pj, s_l, Ut, s_rm, rows, nalive);
 }
 
 // Chunk totals of `len` masses into ct (the waves take chunks in turn) and
@@ -424,8 +465,8 @@ __device__ __forceinline__ CdfPick bt_draw(int len, const double* ct, MassFn& ma
 }
 
 // s_u: the pivot row in LDS for rows that take the block pass (V <= m <=
-// BT_NV x 64 V), zero past m, so the column draw, the pivot entry and the
-// sweep's multiplier packs read LDS instead of the row in memory.
+// bt_su), zero past m, so the column draw, the pivot entry and the sweep's
+// multiplier packs read LDS instead of the row in memory.
 template <class T, int R, int V>
 __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr, BatchInfo* __restrict__ info,
                        double* __restrict__ s_rm, T* __restrict__ s_l, uint16_t* __restrict__ s_alive,
@@ -437,7 +478,7 @@ __device__ __forceinline__ void bt_run(const BatchJob& jb, T* __restrict__ uscr,
     const int64_t lda = jb.lda;
     gmem<T>* Ubase = (gmem<T>*)(jb.U ? (T*)jb.U : uscr);
     const int64_t ldu = jb.U ? jb.ldu : 0;
-    constexpr int SU = BT_NV * RPLU_WAVE * V;
+    constexpr int SU = bt_su<T>();
     const bool lds_row = m >= V && m <= SU;
     for (int r = threadIdx.x; r < n; r += BT_THREADS) {
         s_alive[r] = (uint16_t)r;
@@ -563,7 +604,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batched(const BatchJob* __restri
     uint16_t* s_pos = s_alive + maxn;
     T* myscr = uscratch + (int64_t)blockIdx.x * uscr_ld;
     constexpr int VV = 16 / (int)sizeof(T);
-    __shared__ __align__(16) T s_u[BT_NV * RPLU_WAVE * VV];
+    __shared__ __align__(16) T s_u[bt_su<T>()];
     static_assert(sizeof(BtShared) + sizeof(s_u) <= BT_STATIC_LDS, "static LDS bound of the host check");
     // At most `count` iterations per workgroup (the queue holds count jobs),
     // so the loop ends even if a fetch were ever skipped.

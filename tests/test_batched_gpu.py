@@ -27,21 +27,24 @@ def _instances(dtype, seed=11):
     """Shapes that cover tiny, ragged (m % 4 != 0), one- to eight-wave rows,
     multi-pass rows, unaligned rows (lda * size % 16 != 0) and misaligned
     starts, plus rank-deficient inputs (exhausted before k). The block pass
-    (rows of one pack to four virtual waves: 4..1024 FP32 columns, 2..512
-    FP64, 1..256 unaligned) is taken at and just past each of its limits:
-    m = 2, 3, 4, 256, 512, 768, 769, 1024, 1025 and, unaligned, 256 and 257."""
+    (rows the pivot row's LDS copy holds: 4..1024 FP32 columns, 2..512 FP64;
+    single-element packs for rows not 16-byte aligned, 1..1024 FP32 and
+    1..512 FP64, up to four virtual waves of one column per lane, then all
+    eight of one or two) is taken at and just past each of its limits:
+    m = 2, 3, 4, 256, 512, 768, 769, 1024, 1025 and, unaligned, 256, 257,
+    511, 512, 513, 1023, 1024 and 1025."""
     rng = np.random.default_rng(seed)
     shapes = [(1, 1), (1, 7), (7, 1), (3, 5), (64, 64), (100, 37), (37, 100), (130, 257),
               (257, 130), (513, 20), (20, 513), (997, 1000), (64, 1024), (1024, 64), (40, 3001),
               (33, 2100), (200, 555), (9, 4), (6, 2), (11, 3), (25, 256), (30, 512),
-              (12, 768), (12, 769), (40, 1025)]
+              (12, 768), (12, 769), (40, 1025), (15, 511), (15, 1023)]
     mats, meta = [], []
     for q, (n, m) in enumerate(shapes):
         A = torch.from_numpy(rng.standard_normal((n, m))).to(dtype)
         mats.append(A.to(DEV))
         meta.append(("plain", n, m))
     # unaligned row pitch: lda = m + 1
-    for (n, m) in [(50, 71), (129, 64), (30, 256), (30, 257)]:
+    for (n, m) in [(50, 71), (129, 64), (30, 256), (30, 257), (30, 512), (12, 1024)]:
         buf = torch.zeros((n, m + 1), dtype=dtype)
         buf[:, :m] = torch.from_numpy(rng.standard_normal((n, m))).to(dtype)
         mats.append(buf.to(DEV)[:, :m])
