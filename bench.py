@@ -201,7 +201,8 @@ def _setup_cauchy20k(torch, rplu, bounds=False):
                             "n": n, "m": m, "k": k, "p": 1, "seed": 0, "nu": 5.0, "leaf": 32})
 
     # every all-pairs mass launch (steps t = 0..k, the stop test at k
-    # included) evaluates n * m (row, column) pairs, as the survey counts them
+    # included) evaluates n * m (row, column) pairs: the kernel forms every pair,
+    # pivoted rows and columns included
     pairs = float(n * m)
     return dict(step=step, k=k, n=n, m=m, kind="cauchy", dtype="c128",
                 per_launch=pairs * CAUCHY_FLOP_PER_PAIR, pairs_per_launch=pairs,
