@@ -284,6 +284,24 @@ def rplu_dense(A: np.ndarray, k: int = 0, tol: float = 0.0, seed: int = 0,
                       T0, T, S=S, trace=trace, masses=masses)
 
 
+def factorization_check(A: np.ndarray, L: np.ndarray, U: np.ndarray,
+                        S: Optional[np.ndarray] = None) -> dict:
+    """The three sums of squares of the verification, by their definitions,
+    in FP64 (complex128 for complex data): ||A||_F^2; ||A - L U||_F^2, the
+    error of the rank-k approximation L U (Sec. 2, the error measure); and,
+    with S given, ||A - L U - S||_F^2, which is 0 in exact arithmetic when S
+    is the run's Schur complement (A - L U = A^(k), eq. approximation_update).
+    L U is a library matrix product."""
+    wide = np.complex128 if any(np.iscomplexobj(v) for v in (A, L, U)) else np.float64
+    A = np.asarray(A, dtype=wide)
+    E = A - np.asarray(L, dtype=wide) @ np.asarray(U, dtype=wide)
+    out = {"a_fro2": float(np.sum(squared_magnitude(A))),
+           "err_fro2": float(np.sum(squared_magnitude(E)))}
+    if S is not None:
+        out["schur_gap_fro2"] = float(np.sum(squared_magnitude(E - np.asarray(S, dtype=wide))))
+    return out
+
+
 def schur_closed_form(A: np.ndarray, I: Sequence[int], J: Sequence[int]) -> np.ndarray:
     """Schur complement after pivots on rows I, columns J, by its definition
     A - A[:,J] A[I,J]^{-1} A[I,:] (depends on the sets only; Sec. 4.1, the

@@ -767,6 +767,49 @@ def pin_cur_aaa():
         assert np.max(np.sum(np.abs(S) ** 2, axis=1)) <= eps * eps * M0 * (1 + 1e-3) + 1e-28 * M0
 
 
+def pin_factorization_check():
+    """The verification's sums of squares: exact integer data checked against
+    sums formed term by term in Python integers (tiny sizes, brute force);
+    k = 0 (the error is ||A||^2); and after an oracle run the identity
+    A - L U = S^(k) (eq. approximation_update): the gap is at rounding level
+    and the error equals the run's own ||S||_F^2."""
+    rng = np.random.default_rng(21)
+    for n, m, k in ((3, 4, 2), (5, 2, 1), (1, 1, 1), (4, 6, 3)):
+        L = rng.integers(-3, 4, size=(n, k))
+        U = rng.integers(-3, 4, size=(k, m))
+        D = rng.integers(-2, 3, size=(n, m))
+        A = L @ U + D
+        S = rng.integers(-2, 3, size=(n, m))
+        a2 = sum(int(A[r, c]) ** 2 for r in range(n) for c in range(m))
+        e2 = sum((int(A[r, c]) - sum(int(L[r, q]) * int(U[q, c]) for q in range(k))) ** 2
+                 for r in range(n) for c in range(m))
+        g2 = sum((int(A[r, c]) - sum(int(L[r, q]) * int(U[q, c]) for q in range(k))
+                  - int(S[r, c])) ** 2 for r in range(n) for c in range(m))
+        out = O.factorization_check(A.astype(float), L.astype(float), U.astype(float), S.astype(float))
+        assert (out["a_fro2"], out["err_fro2"], out["schur_gap_fro2"]) == (a2, e2, g2), (out, a2, e2, g2)
+    # complex integers: |z|^2 = re^2 + im^2 term by term
+    Lc = np.array([[1 + 2j], [0 - 1j]])
+    Uc = np.array([[2 - 1j, 1j, 3]])
+    Ac = np.array([[4 + 3j, -2 + 1j, 3 + 6j], [-1 - 2j, 1, 1j]])
+    Ec = Ac - Lc @ Uc
+    e2c = sum(int(z.real) ** 2 + int(z.imag) ** 2 for z in Ec.ravel())
+    a2c = sum(int(z.real) ** 2 + int(z.imag) ** 2 for z in Ac.ravel())
+    out = O.factorization_check(Ac, Lc, Uc)
+    assert (out["a_fro2"], out["err_fro2"]) == (a2c, e2c) and "schur_gap_fro2" not in out
+    # k = 0: nothing approximated
+    A0 = rng.standard_normal((6, 5))
+    out = O.factorization_check(A0, np.zeros((6, 0)), np.zeros((0, 5)))
+    assert out["err_fro2"] == out["a_fro2"] > 0
+    # after a run: A - L U is the Schur complement
+    for seed, cplx in ((3, False), (4, True)):
+        A = W.random_dense(40, 33, seed=seed, complex_=cplx)
+        res = O.rplu_dense(A, k=12, seed=seed)
+        out = O.factorization_check(A, res.L, res.U, res.S)
+        s2 = float(np.sum(np.abs(res.S) ** 2))
+        assert out["schur_gap_fro2"] <= 1e-24 * out["a_fro2"], out
+        assert abs(out["err_fro2"] - s2) <= 1e-10 * s2, (out, s2)
+
+
 ALL_PINS = [
     pin_stall_rule,
     pin_philox_numpy, pin_inverse_cdf_bruteforce, pin_chi2_first_pivot,
@@ -775,5 +818,5 @@ ALL_PINS = [
     pin_eckart_young_floor, pin_mass_bookkeeping, pin_stop_rules,
     pin_nonfinite, pin_cauchy_vs_dense, pin_cauchy_determinant,
     pin_loewner_entries, pin_c2plu, pin_cplu, pin_cur_form, pin_cauchy_bounds,
-    pin_rejection_sampling, pin_cur_aaa,
+    pin_rejection_sampling, pin_cur_aaa, pin_factorization_check,
 ]

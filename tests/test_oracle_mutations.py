@@ -341,6 +341,18 @@ def _bary_conj(zs, t, ft, w):
     return _REAL_BARY(zs, t, ft, np.conj(w))
 
 
+_REAL_CHECK = O.factorization_check
+
+
+def _check_plus(A, L, U, S=None):
+    return _REAL_CHECK(A, -np.asarray(L), U, S)    # A + L U
+
+
+def _check_transposed(A, L, U, S=None):
+    out = _REAL_CHECK(A, L, U, None if S is None else np.asarray(S).T.reshape(np.shape(S)))
+    return out                                      # S read in the wrong order
+
+
 _REAL_GENS = AAA.loewner_gens
 _REAL_BARY = AAA.bary_eval
 
@@ -378,6 +390,8 @@ MUTATIONS = [
     ("aaa_largest_vector", AAA, "aaa_weights", _weights_largest, [pins.pin_cur_aaa]),
     ("aaa_generator_sign", AAA, "loewner_gens", _gens_sign, [pins.pin_cur_aaa]),
     ("aaa_conj_weights", AAA, "bary_eval", _bary_conj, [pins.pin_cur_aaa]),
+    ("check_sign", "factorization_check", _check_plus, [pins.pin_factorization_check]),
+    ("check_schur_order", "factorization_check", _check_transposed, [pins.pin_factorization_check]),
 ]
 
 

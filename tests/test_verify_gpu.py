@@ -1,8 +1,9 @@
-"""FP64 matrix-core verification (rplu_verify) against numpy in FP64.
+"""FP64 matrix-core verification (rplu_verify) against the oracle in FP64.
 
 The kernel forms A - L U tile by tile with v_mfma_f64_16x16x4f64 and reduces
-three squared Frobenius norms; numpy computes the same three numbers from
-the same (widened) values with a library matmul. Sums of squares of the same
+three squared Frobenius norms; the oracle (factorization_check) computes the
+same three numbers from the same (widened) values by their definitions with
+a library matmul. Sums of squares of the same
 terms in another order agree to a few ulps of the total, and the FP64
 products of L U differ by at most k ulps per entry, so 1e-10 relative to
 ||A||^2 (or to the summed magnitudes for the near-zero gap) is a safe bar.
@@ -12,6 +13,7 @@ import pytest
 import torch
 
 import workloads as W
+from oracle import rplu as O
 
 pytestmark = pytest.mark.gpu
 
@@ -20,11 +22,7 @@ DEV = "cuda:0"
 
 def _ref(A, L, U, S):
     A, L, U = (x.detach().cpu().double().numpy() for x in (A, L, U))
-    E = A - L @ U
-    out = {"a_fro2": float(np.sum(A * A)), "err_fro2": float(np.sum(E * E))}
-    if S is not None:
-        G = E - S.detach().cpu().double().numpy()
-        out["schur_gap_fro2"] = float(np.sum(G * G))
+    out = O.factorization_check(A, L, U, None if S is None else S.detach().cpu().double().numpy())
     scale = float(np.sum(np.abs(A) ** 2) + np.sum((np.abs(L) @ np.abs(U)) ** 2))
     return out, scale
 
