@@ -269,7 +269,7 @@ __device__ __forceinline__ float uniform_v(float v) {
 __device__ __forceinline__ double uniform_v(double v) { return uniform_d(v); }
 
 // The pass of bt_sweep for rows the pivot row's LDS copy s_u holds (V <= m
-// <= BT_SU elements), whose lanes hold at most KP packs per virtual wave: NVW
+// <= bt_su elements), whose lanes hold at most KP packs per virtual wave: NVW
 // virtual waves of KP = 1 pack (m <= NVW x 64 V), or for single-element
 // packs (V = 1, rows not 16-byte aligned) all 8 virtual waves of KP = 1 or
 // 2 packs (m <= 512 KP). A wave takes blocks of RB rows and loads a whole
@@ -334,7 +334,7 @@ __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t 
             for (int kp = 0; kp < KP; ++kp) {
                 c[kp] = m - rem(k, kp);
                 pv[kp] = pj - c[kp];
-                // (c < BT_SU for every lane: s_u is read in bounds, and past m
+                // (c < bt_su for every lane: s_u is read in bounds, and past m
                 // the value goes unused)
                 if constexpr (!INIT) uk[kp] = *reinterpret_cast<const BPack<T, V>*>(s_u + c[kp]);
             }
