@@ -214,7 +214,23 @@ __global__ __launch_bounds__(CUR_THREADS) void k_cur_l_gi(CurArgs a, int nbl) {
         const int r = a.piv[2 * s];
         const T* Ar = A + (int64_t)r * a.lda;
         W acc = wzero(W{});
-        for (int q = threadIdx.x; q < a.m; q += CUR_THREADS)
+        // eight columns' entries are loaded before any is used (one memory
+        // round trip for eight); the products are added in column order
+        constexpr int CUR_GU = 8;
+        int q = threadIdx.x;
+        for (; q + (CUR_GU - 1) * CUR_THREADS < a.m; q += CUR_GU * CUR_THREADS) {
+            T av[CUR_GU];
+            W rv[CUR_GU];
+#pragma unroll
+            for (int u = 0; u < CUR_GU; ++u) {
+                av[u] = Ar[q + u * CUR_THREADS];
+                rv[u] = rhat[q + u * CUR_THREADS];
+            }
+#pragma unroll
+            for (int u = 0; u < CUR_GU; ++u)
+                acc = wmad(Sc<T>::widen(av[u]), wconj(wmul(rv[u], inv)), acc);
+        }
+        for (; q < a.m; q += CUR_THREADS)
             acc = wmad(Sc<T>::widen(Ar[q]), wconj(wmul(rhat[q], inv)), acc);
         acc = wg_sum<CUR_THREADS>(acc, red);
         if (threadIdx.x == 0) {
