@@ -167,19 +167,41 @@ __device__ inline void bh_point(const BoundsPlan& bp, const cf64* __restrict__ x
     for (int a = 0; a < P; ++a) g[a] = G[(int64_t)i * P + a];
     double acc = 0.0;
     const cf64* H = (const cf64*)bp.H;
-    for (int e = bp.A_off[l]; e < bp.A_off[l + 1]; ++e) {
-        const cf64* Hs = H + (int64_t)bp.A_node[e] * P * P;
-        // G_i H_s G_i^* = sum_a g_a (sum_c H_ac conj(g_c)), real
+    // G_i H_s G_i^* = sum_a g_a (sum_c H_ac conj(g_c)), real
+    auto form = [&](const cf64* h) {
         double q = 0.0;
 #pragma unroll
         for (int a = 0; a < P; ++a) {
             cf64 w{0.0, 0.0};
 #pragma unroll
-            for (int c = 0; c < P; ++c) w = cmad_conj(Hs[a * P + c], g[c], w);
+            for (int c = 0; c < P; ++c) w = cmad_conj(h[a * P + c], g[c], w);
             q = fma(g[a].re, w.re, fma(-g[a].im, w.im, q));
         }
-        acc = fma(bp.A_alpha[e], q, acc);
+        return q;
+    };
+    // the list's entries in batches: their node indices and weights, then
+    // their matrices, are loaded before any is used (two dependent loads per
+    // entry had each waited a round trip); the terms are added in list order
+    constexpr int BH_E = P == 1 ? 8 : (P == 2 ? 2 : 1);
+    int e = bp.A_off[l];
+    const int e1 = bp.A_off[l + 1];
+    for (; e + BH_E <= e1; e += BH_E) {
+        int nd[BH_E];
+        double al[BH_E];
+#pragma unroll
+        for (int u = 0; u < BH_E; ++u) {
+            nd[u] = bp.A_node[e + u];
+            al[u] = bp.A_alpha[e + u];
+        }
+        cf64 h[BH_E][P * P];
+#pragma unroll
+        for (int u = 0; u < BH_E; ++u)
+#pragma unroll
+            for (int k = 0; k < P * P; ++k) h[u][k] = H[(int64_t)nd[u] * P * P + k];
+#pragma unroll
+        for (int u = 0; u < BH_E; ++u) acc = fma(al[u], form(h[u]), acc);
     }
+    for (; e < e1; ++e) acc = fma(bp.A_alpha[e], form(H + (int64_t)bp.A_node[e] * P * P), acc);
     for (int e = bp.E_off[l]; e < bp.E_off[l + 1]; ++e) {
         const int s = bp.E_node[e];
         for (int q = bp.node_beg[s]; q < bp.node_end[s]; ++q) {
