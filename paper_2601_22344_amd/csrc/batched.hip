@@ -268,6 +268,39 @@ __device__ __forceinline__ float uniform_v(float v) {
 }
 __device__ __forceinline__ double uniform_v(double v) { return uniform_d(v); }
 
+// Four wave sums at once, each with wave_sum's butterfly (v + v(lane ^ 32),
+// then ^ 16, then the rotations inside rows of 16 lanes), so each sum has
+// wave_sum's bits. The first step pairs a with b and c with d through the
+// half-wave swap (its first result holds the two operands' lower halves,
+// the second their upper halves: lanes 0-31 then hold a(l) + a(l + 32),
+// lanes 32-63 b's pair sums); the second step pairs the two results through
+// the row swap (even rows of both operands, then odd rows). The sums end up
+// in rows of 16 lanes: a in lanes 0-15, c in 16-31, b in 32-47, d in 48-63.
+__device__ __forceinline__ double pair_swap32(double a, double b) {
+    const uint64_t x = __builtin_bit_cast(uint64_t, a), y = __builtin_bit_cast(uint64_t, b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)x, (uint32_t)y, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(x >> 32), (uint32_t)(y >> 32), false, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | lo[0]) +
+           __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | lo[1]);
+}
+__device__ __forceinline__ double pair_swap16(double a, double b) {
+    const uint64_t x = __builtin_bit_cast(uint64_t, a), y = __builtin_bit_cast(uint64_t, b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)x, (uint32_t)y, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(x >> 32), (uint32_t)(y >> 32), false, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | lo[0]) +
+           __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | lo[1]);
+}
+__device__ __forceinline__ double wave_sum4(double a, double b, double c, double d) {
+    double v = pair_swap16(pair_swap32(a, b), pair_swap32(c, d));
+    v = v + dpp_d<0x128>(v);     // row_ror:8
+    v = v + dpp_d<0x124>(v);     // row_ror:4
+    v = v + dpp_d<0x122>(v);     // row_ror:2
+    v = v + dpp_d<0x121>(v);     // row_ror:1
+    return v;
+}
+// lanes of the four sums of wave_sum4, in argument order
+constexpr int BT_SUM4_LANE[4] = {0, 32, 16, 48};
+
 // The pass of bt_sweep for rows the pivot row's LDS copy s_u holds (V <= m
 // <= bt_su elements), whose lanes hold at most KP packs per virtual wave: NVW
 // virtual waves of KP = 1 pack (m <= NVW x 64 V), or for single-element
@@ -325,7 +358,25 @@ __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t 
 #pragma unroll
             for (int q = 0; q < RB; ++q) xt[q] = bt_tail<T, V>(S + (int64_t)ri[q] * lda, cp, mt);
         }
-        double tot = 0.0;
+        // the block's wave sums, virtual wave k of row q as sum k RB + q,
+        // are formed four at a time (wave_sum4); each row's total adds its
+        // virtual waves' sums in order, as bt_sweep does
+        constexpr int NS = NVW * RB;
+        double tot[RB];
+        double pend[4];
+        auto flush = [&](int i_last, int cnt) {
+            const double v = wave_sum4(pend[0], cnt > 1 ? pend[1] : 0.0, cnt > 2 ? pend[2] : 0.0,
+                                       cnt > 3 ? pend[3] : 0.0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (u < cnt) {
+                    const int i = i_last - (cnt - 1) + u;
+                    const int kk = i / RB, qq = i % RB;
+                    const double w = uniform_lane(v, BT_SUM4_LANE[u]);
+                    tot[qq] = (kk == 0) ? w : tot[qq] + w;
+                }
+            }
+        };
 #pragma unroll
         for (int k = 0; k < NVW; ++k) {
             int c[KP], pv[KP];
@@ -365,11 +416,15 @@ __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t 
                     }
                     part = acc;
                 }
-                const double w = wave_sum(part);
-                if (lane == q) tot = (k == 0) ? w : tot + w;
+                const int i = k * RB + q;
+                pend[i % 4] = part;
+                if (i % 4 == 3 || i == NS - 1) flush(i, i % 4 + 1);
             }
         }
-        if (lane < nr) s_rm[rows[b0 + lane]] = tot;
+        double mine = tot[0];
+#pragma unroll
+        for (int q = 1; q < RB; ++q) mine = (lane == q) ? tot[q] : mine;
+        if (lane < nr) s_rm[rows[b0 + lane]] = mine;
     }
 }
 
