@@ -406,10 +406,12 @@ __device__ __forceinline__ void bt_sweep_block(gmem<T>* __restrict__ S, int64_t 
                                 xk.v[v] = ((v == pv[kp]) | zr) ? Sc<T>::zero() : y;
                             }
                         }
-                        double a = acc;
+                        // a lane past the row's end holds exact zeros here
+                        // (its pack picked as 0, s_u zero past m, so the
+                        // update leaves +0), and adding 0 to a sum >= +0
+                        // changes no bit: no select needed
 #pragma unroll
-                        for (int v = 0; v < V; ++v) a = Sc<T>::mag2_add(a, xk.v[v]);
-                        acc = rk > 0 ? a : acc;
+                        for (int v = 0; v < V; ++v) acc = Sc<T>::mag2_add(acc, xk.v[v]);
                         if constexpr (!INIT) {
                             if (rk > 0) bt_store<T, V>(S + (int64_t)ri[q] * lda + c[kp], rk, xk);
                         }
